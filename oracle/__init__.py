@@ -1,0 +1,283 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (``icp_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg.  The GPU package never imports this module and
+shares no code with it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+BUILD_DIR = os.path.join(HERE, "_build")
+LIB_PATH = os.path.join(BUILD_DIR, "libicp_oracle.so")
+SOURCES = [os.path.join(HERE, "icp_oracle.c")]
+
+MAX_LEVELS = 4
+BINS = 1024
+BIN_W = 1.0 / 8192.0
+
+INVALID_LIVE, BEHIND, OUTSIDE, INVALID_MODEL, FAR, ANGLE, GATED = range(7)
+LEVEL_OK, TOO_FEW_CORR, ILL_COND, NONFINITE = range(4)
+LAMBDA_CONST, LAMBDA_C_OVER_SQRT_N, LAMBDA_C_OVER_N, LAMBDA_C_OVER_N2 = range(4)
+
+
+def build(force=True):
+    """Compile the oracle with gcc (FP64, no contraction, no fast-math)."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fno-fast-math", "-ffp-contract=off",
+           "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp] + SOURCES + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("levels", C.c_int), ("iters", C.c_int * MAX_LEVELS),
+        ("dist_max", C.c_double), ("cos_angle_max", C.c_double), ("band_beta", C.c_double),
+        ("use_median_filter", C.c_int), ("use_imu_seed", C.c_int), ("lambda_mode", C.c_int),
+        ("lambda_c", C.c_double), ("min_corr", C.c_int), ("ill_cond_eps", C.c_double),
+        ("converge_window", C.c_int),
+    ]
+
+
+class LevelStats(C.Structure):
+    _fields_ = [("iters_run", C.c_int32), ("status", C.c_int32), ("n_gated", C.c_int64),
+                ("n_kept", C.c_int64), ("k_med", C.c_int32), ("pad", C.c_int32), ("rmse", C.c_double)]
+
+
+class IterTrace(C.Structure):
+    _fields_ = [("level", C.c_int32), ("iter", C.c_int32), ("status", C.c_int32), ("k_med", C.c_int32),
+                ("k_lo", C.c_int32), ("k_hi", C.c_int32), ("n_gated", C.c_int64), ("n_kept", C.c_int64),
+                ("x", C.c_double * 6), ("pose", C.c_double * 12)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        d = C.c_double
+        i = C.c_int
+        L.or_params_default.argtypes = [C.POINTER(Params)]
+        L.or_level_intrinsics.argtypes = [P, i, P]
+        L.or_depth_down.argtypes = [P, i, i, P]
+        L.or_live_vn.argtypes = [P, i, i, P, P, P]
+        L.or_model_l0.argtypes = [P, P, i, i, P, P]
+        L.or_model_down.argtypes = [P, P, i, i, P, P]
+        L.or_associate.argtypes = [P, P, P, P, i, i, P, P, d, d, P, P, P, P]
+        L.or_band.argtypes = [P, i, d, P]
+        L.or_bin_of.argtypes = [d]
+        L.or_bin_of.restype = i
+        L.or_pairs.argtypes = [P, P, P, P, i, i, P, P, d, d, P, P, P, P, P]
+        L.or_moments.argtypes = [P, P, P, P, i, i, P, P, d, d, i, i, P, P]
+        L.or_solve_update.argtypes = [P, C.c_int64, P, i, d, i, d, P, P]
+        L.or_solve_update.restype = i
+        L.or_se3_exp.argtypes = [P, P, P, P]
+        L.or_icp_register.argtypes = [P, i, i, P, P, P, P, P, C.POINTER(Params), P, P, P, i]
+        L.or_icp_register.restype = i
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def default_params(**over):
+    p = Params()
+    lib().or_params_default(C.byref(p))
+    for k, v in over.items():
+        if k == "iters":
+            for j in range(MAX_LEVELS):
+                p.iters[j] = int(v[j]) if j < len(v) else 0
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def level_intrinsics(K, level):
+    out = np.zeros(4)
+    lib().or_level_intrinsics(_p(_f64(K)), level, _p(out))
+    return out
+
+
+def pose12(T):
+    """3x4 row-major [R | t] of a 4x4 (or 3x4) pose."""
+    return _f64(np.asarray(T, dtype=np.float64)[:3, :4]).reshape(12).copy()
+
+
+# ---------------------------------------------------------------- stages
+
+def depth_down(D):
+    D = _f32(D)
+    H, W = D.shape
+    out = np.empty((H // 2, W // 2), np.float32)
+    lib().or_depth_down(_p(D), W, H, _p(out))
+    return out
+
+
+def live_vn(D, K):
+    """SoA vertex and normal maps (3, H, W) float32 of one level."""
+    D = _f32(D)
+    H, W = D.shape
+    V = np.empty((3, H, W), np.float32)
+    N = np.empty((3, H, W), np.float32)
+    lib().or_live_vn(_p(D), W, H, _p(_f64(K)), _p(V), _p(N))
+    return V, N
+
+
+def model_l0(vtx, nrm):
+    vtx, nrm = _f32(vtx), _f32(nrm)
+    H, W, _ = vtx.shape
+    V = np.empty((3, H, W), np.float32)
+    N = np.empty((3, H, W), np.float32)
+    lib().or_model_l0(_p(vtx), _p(nrm), W, H, _p(V), _p(N))
+    return V, N
+
+
+def model_down(V, N):
+    V, N = _f32(V), _f32(N)
+    _, H, W = V.shape
+    Vn = np.empty((3, H // 2, W // 2), np.float32)
+    Nn = np.empty((3, H // 2, W // 2), np.float32)
+    lib().or_model_down(_p(V), _p(N), W, H, _p(Vn), _p(Nn))
+    return Vn, Nn
+
+
+def pyramids(depth, vtx, nrm, K, levels):
+    """Per level: dict(D, LV, LN, MV, MN, K)."""
+    out = []
+    D = _f32(depth)
+    MV, MN = model_l0(vtx, nrm)
+    for lvl in range(levels):
+        if lvl > 0:
+            D = depth_down(D)
+            MV, MN = model_down(MV, MN)
+        Kl = level_intrinsics(K, lvl)
+        LV, LN = live_vn(D, Kl)
+        out.append(dict(D=D, LV=LV, LN=LN, MV=MV, MN=MN, K=Kl))
+    return out
+
+
+def associate(lvl, T, dist_max=0.10, cos_max=None):
+    """Per-pixel code, bin, margin (H, W) and the histogram for pose T."""
+    if cos_max is None:
+        cos_max = default_params().cos_angle_max
+    LV, LN, MV, MN = (_f32(lvl[k]) for k in ("LV", "LN", "MV", "MN"))
+    _, H, W = LV.shape
+    code = np.empty((H, W), np.uint8)
+    bins = np.empty((H, W), np.int32)
+    margin = np.empty((H, W), np.float64)
+    hist = np.empty(BINS, np.uint32)
+    lib().or_associate(_p(LV), _p(LN), _p(MV), _p(MN), W, H, _p(_f64(lvl["K"])), _p(pose12(T)),
+                       dist_max, cos_max, _p(code), _p(bins), _p(margin), _p(hist))
+    return code, bins, margin, hist
+
+
+def bin_of(d2):
+    return int(lib().or_bin_of(float(d2)))
+
+
+def pairs(lvl, T, dist_max=0.10, cos_max=None):
+    """Per-pixel code, bin and (GATED pixels) p', q, n_q arrays (H*W, 3)."""
+    if cos_max is None:
+        cos_max = default_params().cos_angle_max
+    LV, LN, MV, MN = (_f32(lvl[k]) for k in ("LV", "LN", "MV", "MN"))
+    _, H, W = LV.shape
+    code = np.empty(H * W, np.uint8)
+    bins = np.empty(H * W, np.int32)
+    pp = np.full((H * W, 3), np.nan)
+    q = np.full((H * W, 3), np.nan)
+    nq = np.full((H * W, 3), np.nan)
+    lib().or_pairs(_p(LV), _p(LN), _p(MV), _p(MN), W, H, _p(_f64(lvl["K"])), _p(pose12(T)), dist_max, cos_max,
+                   _p(code), _p(bins), _p(pp), _p(q), _p(nq))
+    return code, bins, pp, q, nq
+
+
+def band(hist, use_filter=1, beta=1.0):
+    out = np.zeros(4, np.int64)
+    lib().or_band(_p(np.ascontiguousarray(hist, dtype=np.uint32)), use_filter, beta, _p(out))
+    return out
+
+
+def moments(lvl, T, k_lo, k_hi, dist_max=0.10, cos_max=None):
+    if cos_max is None:
+        cos_max = default_params().cos_angle_max
+    LV, LN, MV, MN = (_f32(lvl[k]) for k in ("LV", "LN", "MV", "MN"))
+    _, H, W = LV.shape
+    M = np.zeros(28)
+    n = np.zeros(1, np.int64)
+    lib().or_moments(_p(LV), _p(LN), _p(MV), _p(MN), W, H, _p(_f64(lvl["K"])), _p(pose12(T)),
+                     dist_max, cos_max, int(k_lo), int(k_hi), _p(M), _p(n))
+    return M, int(n[0])
+
+
+def solve_update(M, n, T, lambda_mode=LAMBDA_CONST, lambda_c=5.0, min_corr=6, eps=1e-12):
+    Tout = np.zeros(12)
+    x = np.zeros(6)
+    st = lib().or_solve_update(_p(_f64(M)), int(n), _p(pose12(T)), lambda_mode, lambda_c, min_corr, eps,
+                               _p(Tout), _p(x))
+    P = np.eye(4)
+    P[:3, :4] = Tout.reshape(3, 4)
+    return st, P, x
+
+
+def se3_exp(w, tau):
+    R = np.zeros(9)
+    t = np.zeros(3)
+    lib().or_se3_exp(_p(_f64(w)), _p(_f64(tau)), _p(R), _p(t))
+    return R.reshape(3, 3), t
+
+
+def tri_index(i, j):
+    """Position of entry (i, j), i <= j, in the 28-moment vector."""
+    return i * 7 - i * (i - 1) // 2 + (j - i)
+
+
+def register(depth, vtx, nrm, K, imu_R, init_pose, params=None, trace_cap=64):
+    """Whole registration. Returns (pose 4x4, list of level-stat dicts, trace list)."""
+    p = params if params is not None else default_params()
+    depth, vtx, nrm = _f32(depth), _f32(vtx), _f32(nrm)
+    H, W = depth.shape
+    pose = np.zeros(16)
+    stats = (LevelStats * MAX_LEVELS)()
+    trace = (IterTrace * trace_cap)()
+    nt = lib().or_icp_register(_p(depth), W, H, _p(vtx), _p(nrm), _p(_f64(K)), _p(_f64(imu_R)),
+                               _p(_f64(init_pose)), C.byref(p), _p(pose), C.cast(stats, C.c_void_p),
+                               C.cast(trace, C.c_void_p), trace_cap)
+    st = [dict(iters_run=s.iters_run, status=s.status, n_gated=s.n_gated, n_kept=s.n_kept, k_med=s.k_med,
+               rmse=s.rmse) for s in stats[:p.levels]]
+    tr = []
+    for t in trace[:min(nt, trace_cap)]:
+        P = np.eye(4)
+        P[:3, :4] = np.array(t.pose[:]).reshape(3, 4)
+        tr.append(dict(level=t.level, iter=t.iter, status=t.status, k_med=t.k_med, k_lo=t.k_lo, k_hi=t.k_hi,
+                       n_gated=t.n_gated, n_kept=t.n_kept, x=np.array(t.x[:]), pose=P))
+    return pose.reshape(4, 4), st, tr
+
+
+def register_problem(prob, params=None, trace_cap=64):
+    return register(prob.live_depth, prob.model_vtx, prob.model_nrm, prob.K, prob.imu_R, prob.init_pose,
+                    params, trace_cap)

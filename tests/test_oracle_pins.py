@@ -1,0 +1,407 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: hand-worked
+fixtures, closed forms, exact rational arithmetic, library routines (lstsq,
+expm, partition) and invariants the method must satisfy.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+import synth
+from synth.scene import Plane, centred_intrinsics, render
+from tests.poseutil import pose_err, rot_angle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_rows(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line)
+    return rows
+
+
+# --------------------------------------------------------------- pyramids
+
+def test_depth_pyramid_golden():
+    rows = _golden_rows("pyramid_4x4.txt")
+    depth = np.array([[float(x) for x in r.split()] for r in rows[:4]], np.float32)
+    want = np.array([[float(x) for x in r.split()] for r in rows[4:6]], np.float32)
+    got = oracle.depth_down(depth)
+    assert np.array_equal(got, want)
+
+
+def test_depth_pyramid_invalid_children():
+    d = np.full((4, 4), 2.0, np.float32)
+    d[0, 0] = np.nan
+    d[2, 3] = -1.0
+    d[3, 0] = np.inf
+    got = oracle.depth_down(d)
+    assert got[0, 0] == 0 and got[1, 1] == 0 and got[1, 0] == 0 and got[0, 1] == 2.0
+
+
+def test_model_pyramid_mean_and_normal():
+    V = np.zeros((3, 2, 4), np.float32)
+    N = np.zeros((3, 2, 4), np.float32)
+    # left quad: vertices around (2, 1, 2); normals three times -z and one tilted
+    V[:, 0, 0] = (1, 0, 2)
+    V[:, 0, 1] = (3, 0, 2)
+    V[:, 1, 0] = (1, 2, 2)
+    V[:, 1, 1] = (3, 2, 2)
+    for (v, u) in [(0, 0), (0, 1), (1, 0)]:
+        N[:, v, u] = (0, 0, -1)
+    N[:, 1, 1] = (0.6, 0.0, -0.8)
+    # right quad: one child invalid
+    V[:, :, 2:] = 1.0
+    N[:, :, 2:] = (np.array([0, 0, -1.0], np.float32))[:, None, None]
+    V[1, 1, 3] = np.nan
+    vtx = np.moveaxis(V, 0, -1)
+    nrm = np.moveaxis(N, 0, -1)
+    MV, MN = oracle.model_l0(vtx, nrm)
+    assert np.all(np.isnan(MV[:, 1, 3])) and np.all(np.isnan(MN[:, 1, 3]))
+    Vn, Nn = oracle.model_down(MV, MN)
+    assert np.array_equal(Vn[:, 0, 0], np.array([2, 1, 2], np.float32))
+    s = np.array([0.6, 0.0, -3.8])
+    n = Nn[:, 0, 0].astype(np.float64)
+    assert abs(np.linalg.norm(n) - 1) < 1e-7
+    assert np.linalg.norm(np.cross(n, s)) < 1e-6 * np.linalg.norm(s) and n @ s > 0
+    assert np.all(np.isnan(Vn[:, 0, 1])) and np.all(np.isnan(Nn[:, 0, 1]))
+
+
+def _plane_depth(W, H, K, n, c):
+    pl = Plane(n=np.asarray(n, float) / np.linalg.norm(n), c=c)
+    d, _, _, _ = render([pl], W, H, K, np.eye(4), zmin=0.0, zmax=np.inf)
+    return pl, d.astype(np.float32)
+
+
+def test_live_maps_on_plane():
+    """P1: back-projected vertices lie on the rendered plane and on their pixel
+    rays; forward-difference normals equal the plane normal (facing the camera);
+    the last row and column have no normal."""
+    W, H = 40, 30
+    K = centred_intrinsics(W, H, 35.0)
+    pl, d = _plane_depth(W, H, K, (0.3, -0.2, -1.0), -2.5)
+    V, N = oracle.live_vn(d, K)
+    assert np.array_equal(V[2], d)
+    Vd = V.astype(np.float64)
+    assert np.max(np.abs(np.einsum("k,khw->hw", pl.n, Vd) - pl.c)) < 4e-7 * 4
+    u = np.arange(W)[None, :]
+    v = np.arange(H)[:, None]
+    assert np.max(np.abs(Vd[0] / Vd[2] - (u - K[2]) / K[0])) < 1e-6
+    assert np.max(np.abs(Vd[1] / Vd[2] - (v - K[3]) / K[1])) < 1e-6
+    Ni = N[:, :-1, :-1].astype(np.float64)
+    want = pl.n if pl.n[2] < 0 else -pl.n
+    assert np.max(np.abs(Ni - want[:, None, None])) < 1e-4
+    assert np.all(np.einsum("khw,khw->hw", Ni, Vd[:, :-1, :-1]) < 0)
+    assert np.all(np.isnan(N[:, -1, :])) and np.all(np.isnan(N[:, :, -1]))
+
+
+# --------------------------------------------------------------- bins / band
+
+def test_bin_is_exact_definition():
+    """k is the unique integer with (k w)^2 <= d^2 < ((k+1) w)^2, checked in
+    exact rational arithmetic, including values on and next to bin edges."""
+    rng = np.random.default_rng(5)
+    w = Fraction(1, 8192)
+    vals = list(rng.uniform(0, 0.1, 2000) ** 2)
+    for k in [0, 1, 2, 31, 500, 818, 819]:
+        e = float((k * w) ** 2)
+        vals += [e, np.nextafter(e, 0.0), np.nextafter(e, 1.0)]
+    for d2 in vals:
+        k = oracle.bin_of(d2)
+        f = Fraction(d2)
+        assert (k * w) ** 2 <= f < ((k + 1) * w) ** 2, (d2, k)
+
+
+def test_band_golden():
+    for row in _golden_rows("band_cases.txt"):
+        beta, pairs, want = (s.strip() for s in row.split(";"))
+        hist = np.zeros(oracle.BINS, np.uint32)
+        for pr in pairs.split():
+            k, c = pr.split(":")
+            hist[int(k)] = int(c)
+        got = oracle.band(hist, 1, float(beta))
+        assert list(got) == [int(x) for x in want.split()], row
+
+
+def test_band_median_matches_partition():
+    """The median bin equals the lower median (np.partition) of the multiset of
+    bin indices the histogram counts."""
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        n = int(rng.integers(1, 3000))
+        samples = np.minimum(rng.gamma(2.0, 40.0, n).astype(int), oracle.BINS - 1)
+        hist = np.bincount(samples, minlength=oracle.BINS).astype(np.uint32)
+        N, kmed, klo, khi = oracle.band(hist)
+        m = (n + 1) // 2
+        assert N == n
+        assert kmed == np.partition(samples, m - 1)[m - 1]
+        assert klo == 0 and khi == min(oracle.BINS - 1, 2 * kmed + 1)
+    N, kmed, klo, khi = oracle.band(np.zeros(oracle.BINS, np.uint32))
+    assert N == 0 and kmed == -1 and khi < klo
+    N, kmed, klo, khi = oracle.band(np.bincount([3, 9], minlength=oracle.BINS), use_filter=0)
+    assert (klo, khi) == (0, oracle.BINS - 1)
+
+
+# --------------------------------------------------------------- association
+
+def _tiny_level(W=24, H=18, f=20.0, seed=3, T=None):
+    """One pyramid level of a tiny config-1-like scene (planes plus spheres)."""
+    rng = np.random.default_rng(seed)
+    K = centred_intrinsics(W, H, f)
+    from synth.scene import random_planes, random_spheres
+    prims = random_planes(rng, K, W, H) + random_spheres(rng, K, W, H)
+    T = np.eye(4) if T is None else T
+    _, mv, mn, _ = render(prims, W, H, K, np.eye(4))
+    ld, _, _, _ = render(prims, W, H, K, T)
+    return oracle.pyramids(ld, mv, mn, K, 1)[0]
+
+
+def test_identity_case():
+    """P3: live maps used as model maps at T = I: every live pixel with a vertex
+    and a normal matches itself, d = 0, median bin 0, b = 0, x = 0."""
+    W, H = 32, 24
+    K = centred_intrinsics(W, H, 25.0)
+    d = _tiny_level(W, H, 25.0)["D"]
+    LV, LN = oracle.live_vn(d, K)
+    lvl = oracle.pyramids(d, np.moveaxis(LV, 0, -1), np.moveaxis(LN, 0, -1), K, 1)[0]
+    code, bins, _, hist = oracle.associate(lvl, np.eye(4))
+    has = np.isfinite(LV[0]) & np.isfinite(LN[0])
+    assert has.sum() > 300
+    assert np.all(code[has] == oracle.GATED) and np.all(code[~has] == oracle.INVALID_LIVE)
+    assert np.all(bins[has] == 0) and hist[0] == has.sum() and hist.sum() == has.sum()
+    N, kmed, klo, khi = oracle.band(hist)
+    assert kmed == 0
+    M, n = oracle.moments(lvl, np.eye(4), klo, khi)
+    assert n == has.sum()
+    assert all(M[oracle.tri_index(i, 6)] == 0.0 for i in range(7))
+    st, T1, x = oracle.solve_update(M, n, np.eye(4), lambda_c=0.0)
+    assert st == oracle.LEVEL_OK and np.all(x == 0.0) and np.array_equal(T1, np.eye(4))
+
+
+def test_projection_closed_form():
+    """P4: fronto-parallel plane at z0, model = live, lateral shift of
+    3.25 z0/fx: interior pixels pair with the model pixel three columns to the
+    right at distance 0.25 z0/fx, so every one lands in bin
+    floor(0.25 z0/fx * 8192); the last three columns fall outside the image."""
+    W, H, f, z0 = 40, 20, 130.0, 2.0
+    K = centred_intrinsics(W, H, f)
+    _, d = _plane_depth(W, H, K, (0, 0, -1.0), -z0)
+    LV, LN = oracle.live_vn(d, K)
+    _, mv, mn, _ = render([Plane(n=np.array([0, 0, -1.0]), c=-z0)], W, H, K, np.eye(4))
+    lvl = oracle.pyramids(d, mv, mn, K, 1)[0]
+    T = np.eye(4)
+    T[0, 3] = 3.25 * z0 / f
+    code, bins, margin, hist = oracle.associate(lvl, T)
+    kexp = math.floor(0.25 * z0 / f * 8192)
+    for v in range(H):
+        for u in range(W):
+            if u == W - 1 or v == H - 1:
+                assert code[v, u] == oracle.INVALID_LIVE
+            elif u >= W - 3:
+                assert code[v, u] == oracle.OUTSIDE
+            else:
+                assert code[v, u] == oracle.GATED and bins[v, u] == kexp
+    assert hist[kexp] == (W - 3) * (H - 1) and hist.sum() == hist[kexp]
+    _, _, pp, q, nq = oracle.pairs(lvl, T)
+    g = np.isfinite(pp[:, 0])
+    assert np.allclose(np.linalg.norm(q[g] - pp[g], axis=1), 0.25 * z0 / f, atol=1e-6)
+
+
+# --------------------------------------------------------------- moments / solve
+
+def _kept_pairs(lvl, T):
+    code, bins, pp, q, nq = oracle.pairs(lvl, T)
+    hist = np.bincount(bins[code == oracle.GATED], minlength=oracle.BINS)
+    N, kmed, klo, khi = oracle.band(hist)
+    keep = (code == oracle.GATED) & (bins >= klo) & (bins <= khi)
+    return pp[keep], q[keep], nq[keep], klo, khi
+
+
+def _eq2_matrix(x):
+    """The small-angle transform of Eq. (2), written as printed."""
+    a, b, g, tx, ty, tz = x
+    return np.array([[1, -g, b, tx], [g, 1, -a, ty], [-b, a, 1, tz], [0, 0, 0, 1.0]])
+
+
+def _sym(M):
+    H = np.zeros((7, 7))
+    for i in range(7):
+        for j in range(i, 7):
+            H[i, j] = H[j, i] = M[oracle.tri_index(i, j)]
+    return H
+
+
+def test_moments_reproduce_point_to_plane_objective():
+    """P6: for any increment x, the 28 moments give the Eq. (1) objective of the
+    kept pairs under the Eq. (2) transform: sum (n.(M^ p' - q))^2 =
+    x^T A^T A x - 2 x^T A^T b + b^T b.  Also: A^T A equals the explicit
+    brute-force sum over rows, is symmetric and positive semi-definite."""
+    T = synth.pose_matrix(synth.rot_from_rotvec([0.01, -0.02, 0.015]), [0.01, 0.0, -0.02])
+    lvl = _tiny_level(T=T)
+    pp, q, nq, klo, khi = _kept_pairs(lvl, np.eye(4))
+    assert len(pp) > 50
+    M, n = oracle.moments(lvl, np.eye(4), klo, khi)
+    assert n == len(pp)
+    S = _sym(M)
+    rng = np.random.default_rng(0)
+    for _ in range(60):
+        x = rng.normal(size=6) * np.array([0.05, 0.05, 0.05, 0.1, 0.1, 0.1])
+        Mh = _eq2_matrix(x)
+        r = np.einsum("ik,ik->i", nq, pp @ Mh[:3, :3].T + Mh[:3, 3] - q)
+        xe = np.append(x, -1.0)
+        assert abs(np.sum(r * r) - xe @ S @ xe) <= 1e-10 * max(1.0, np.sum(r * r))
+    A = np.hstack([np.cross(pp, nq), nq])
+    b = np.einsum("ik,ik->i", nq, q - pp)
+    assert np.allclose(S[:6, :6], A.T @ A, rtol=1e-12, atol=1e-12)
+    assert np.allclose(S[:6, 6], A.T @ b, rtol=1e-12, atol=1e-15)
+    ev = np.linalg.eigvalsh(S[:6, :6])
+    assert ev.min() >= -1e-12 * ev.max()
+
+
+@pytest.mark.parametrize("mode,c", [(oracle.LAMBDA_CONST, 0.0), (oracle.LAMBDA_CONST, 5.0),
+                                    (oracle.LAMBDA_C_OVER_SQRT_N, 2.0), (oracle.LAMBDA_C_OVER_N, 1.0),
+                                    (oracle.LAMBDA_C_OVER_N2, 0.2)])
+def test_regularised_solve_matches_lstsq(mode, c):
+    """P7/P8: x minimises Eq. (4), i.e. the least-squares solution (SVD, as in
+    the paper) of [A; sqrt(2 n lambda) P] x = [b; 0] with P = [I3 | 0]; lambda = 0
+    is plain point-to-plane least squares.  The update composes Exp(x) on the
+    left of the pose."""
+    T = synth.pose_matrix(synth.rot_from_rotvec([0.02, 0.01, -0.01]), [0.02, -0.01, 0.01])
+    lvl = _tiny_level(T=T, seed=4)
+    pp, q, nq, klo, khi = _kept_pairs(lvl, np.eye(4))
+    M, n = oracle.moments(lvl, np.eye(4), klo, khi)
+    A = np.hstack([np.cross(pp, nq), nq])
+    b = np.einsum("ik,ik->i", nq, q - pp)
+    lam = {oracle.LAMBDA_CONST: c, oracle.LAMBDA_C_OVER_SQRT_N: c / math.sqrt(n),
+           oracle.LAMBDA_C_OVER_N: c / n, oracle.LAMBDA_C_OVER_N2: c / n ** 2}[mode]
+    P = np.hstack([np.eye(3), np.zeros((3, 3))])
+    As = np.vstack([A, math.sqrt(2 * n * lam) * P])
+    bs = np.concatenate([b, np.zeros(3)])
+    xref = np.linalg.lstsq(As, bs, rcond=None)[0]
+    T0 = synth.pose_matrix(synth.rot_from_rotvec([0.1, 0.2, -0.3]), [0.5, -0.2, 1.0])
+    st, T1, x = oracle.solve_update(M, n, T0, lambda_mode=mode, lambda_c=c)
+    assert st == oracle.LEVEL_OK
+    assert np.allclose(x, xref, rtol=1e-8, atol=1e-12)
+    E = np.zeros((4, 4))
+    E[:3, :3] = np.array([[0, -x[2], x[1]], [x[2], 0, -x[0]], [-x[1], x[0], 0]])
+    E[:3, 3] = x[3:]
+    assert np.allclose(T1, scipy.linalg.expm(E) @ T0, rtol=0, atol=1e-13)
+
+
+def test_solver_flags_degenerate_systems():
+    M = np.zeros(28)
+    st, T1, x = oracle.solve_update(M, 100, np.eye(4), lambda_c=1.0)
+    assert st == oracle.ILL_COND and np.array_equal(T1, np.eye(4))
+    st, _, _ = oracle.solve_update(M, 5, np.eye(4))
+    assert st == oracle.TOO_FEW_CORR
+
+
+def test_se3_exp_matches_expm():
+    """P10: the exponential of the 4x4 twist matrix (scipy expm), RtR = I, det 1."""
+    rng = np.random.default_rng(1)
+    for th in [0.0, 1e-9, 1e-7, 1e-6, 1.1e-6, 1e-5, 1e-3, 0.1, 1.0, 3.0]:
+        for _ in range(5):
+            ax = rng.normal(size=3)
+            w = ax / np.linalg.norm(ax) * th
+            tau = rng.normal(size=3)
+            R, t = oracle.se3_exp(w, tau)
+            E = np.zeros((4, 4))
+            E[:3, :3] = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+            E[:3, 3] = tau
+            X = scipy.linalg.expm(E)
+            assert np.allclose(R, X[:3, :3], rtol=0, atol=2e-15)
+            assert np.allclose(t, X[:3, 3], rtol=0, atol=1e-14 * max(1, np.linalg.norm(tau)))
+            assert np.allclose(R.T @ R, np.eye(3), atol=1e-15) and abs(np.linalg.det(R) - 1) < 1e-15
+
+
+# --------------------------------------------------------------- whole loop
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_truth_recovery_three_planes(seed):
+    """P11: on noiseless renders of three planes in general position the loop
+    converges to the ground-truth motion.  The floor is FP32 storage of the
+    maps; the 2-degree normal gate drops the pixels on plane intersections whose
+    forward-difference normals straddle two planes."""
+    prob = synth.three_plane_problem(seed)
+    p = oracle.default_params(lambda_c=0.0, cos_angle_max=math.cos(math.radians(2.0)))
+    pose, st, _ = oracle.register_problem(prob, p)
+    ang, dt = pose_err(pose, prob.T_gt)
+    assert ang < 1e-6 and dt < 1e-6, (ang, dt)
+    assert all(s["status"] == oracle.LEVEL_OK for s in st)
+
+
+def test_large_lambda_pins_rotation_to_imu():
+    """P9: lambda -> infinity keeps the rotation at the IMU seed; the loop then
+    solves for the translation alone (its last increment vanishes)."""
+    prob = synth.config1_problem(0)
+    p = oracle.default_params(lambda_c=1e12, iters=(30, 5, 4))
+    pose, st, tr = oracle.register_problem(prob, p)
+    assert rot_angle(pose[:3, :3] @ prob.imu_R.T) < 1e-9
+    assert np.linalg.norm(tr[-1]["x"][3:]) < 1e-6
+    assert np.linalg.norm(tr[-1]["x"][:3]) < 1e-12
+
+
+def test_lambda_zero_corrects_imu_error():
+    """Sec. 4.1: without regularisation the IMU error is corrected; with a large
+    lambda the IMU rotation is kept."""
+    prob = synth.config1_problem(0)
+    imu_err = rot_angle(prob.imu_R @ prob.T_gt[:3, :3].T)
+    pose0, _, _ = oracle.register_problem(prob, oracle.default_params(lambda_c=0.0))
+    pose5, _, _ = oracle.register_problem(prob, oracle.default_params(lambda_c=5.0))
+    e0 = pose_err(pose0, prob.T_gt)[0]
+    e5 = pose_err(pose5, prob.T_gt)[0]
+    assert e0 < 0.3 * imu_err and e0 < e5 <= imu_err * 1.01
+
+
+def test_imu_seed_sets_initial_rotation():
+    prob = synth.config1_problem(0)
+    init = synth.pose_matrix(synth.rot_from_rotvec([0.1, 0, 0]), [0.1, 0.2, 0.3])
+    p = oracle.default_params(iters=(0, 0, 0))
+    pose, st, tr = oracle.register(prob.live_depth, prob.model_vtx, prob.model_nrm, prob.K, prob.imu_R, init, p)
+    assert np.array_equal(pose[:3, :3], prob.imu_R) and np.array_equal(pose[:3, 3], init[:3, 3])
+    p = oracle.default_params(iters=(0, 0, 0), use_imu_seed=0)
+    pose, st, tr = oracle.register(prob.live_depth, prob.model_vtx, prob.model_nrm, prob.K, prob.imu_R, init, p)
+    assert np.array_equal(pose, init)
+
+
+def test_convergence_rule_stops_on_settled_median():
+    """P12 (Sec. 3.4): with a window of 3 a level stops right after the first
+    iteration whose median bin equals those of the two before it."""
+    p = oracle.default_params(converge_window=3, iters=(30, 30, 30), lambda_c=0.0)
+    early = 0
+    for seed in range(3):
+        prob = synth.config1_problem(seed)
+        _, st, tr = oracle.register_problem(prob, p, trace_cap=128)
+        for lvl in range(3):
+            ks = [t["k_med"] for t in tr if t["level"] == lvl]
+            stop = next((i for i in range(2, len(ks)) if ks[i] == ks[i - 1] == ks[i - 2]), None)
+            # a median that keeps moving runs the whole cap
+            assert len(ks) == (30 if stop is None else stop + 1), ks
+            assert st[lvl]["iters_run"] == len(ks)
+            early += stop is not None
+    assert early >= 3
+
+
+def test_failure_cases():
+    prob = synth.config1_problem(0)
+    z = np.zeros_like(prob.live_depth)
+    pose, st, _ = oracle.register(z, prob.model_vtx, prob.model_nrm, prob.K, prob.imu_R, prob.init_pose)
+    assert all(s["status"] == oracle.TOO_FEW_CORR and s["iters_run"] == 1 for s in st)
+    assert np.array_equal(pose[:3, :3], prob.imu_R)
+    # a single fronto-parallel plane leaves the in-plane translation free
+    W, H = 40, 30
+    K = centred_intrinsics(W, H, 35.0)
+    _, d = _plane_depth(W, H, K, (0, 0, -1.0), -2.0)
+    _, mv, mn, _ = render([Plane(n=np.array([0, 0, -1.0]), c=-2.0)], W, H, K, np.eye(4))
+    pose, st, _ = oracle.register(d, mv, mn, K, np.eye(3), np.eye(4), oracle.default_params(levels=1))
+    assert st[0]["status"] == oracle.ILL_COND
