@@ -1,0 +1,242 @@
+/*
+ * icp.h -- C ABI of the MI355X (gfx950) tracking hot path of IMU-seeded,
+ * median-filtered, rotation-regularised KinectFusion ICP
+ * (Giancola, Schneider, Wonka, Ghanem, "Integration of Absolute Orientation
+ * Measurements in the KinectFusion Reconstruction pipeline", 2018).
+ *
+ * Problem statement (paper Sec. 1 and Sec. 3, Eq. (1)): find the rigid motion
+ * M = (R, t) in SE(3) that maps the live depth frame onto the model so that the
+ * point-to-plane distances of matched points are minimal.  Here M maps
+ * live-camera coordinates to model-camera coordinates: X_model = R X_live + t.
+ *
+ * Conventions shared by every entry point
+ *   - Images are row-major: pixel (u, v) (column u, row v) is element v*W + u.
+ *   - live_depth: H*W float32 metres on the device; a pixel is valid iff its
+ *     value is finite and > 0.
+ *   - model_vtx, model_nrm: H*W*3 float32 (x, y, z interleaved) on the device,
+ *     in the model camera frame (the predicted maps KinectFusion ray-casts from
+ *     its model); a pixel is valid iff all six values are finite.  Normals are
+ *     unit length and face the camera.
+ *   - Poses are row-major doubles: 4x4 (16 values) in the public calls, 3x4
+ *     [R | t] (12 values) in the stage calls.  imu_R is 3x3 row-major.
+ *   - W and H must be divisible by 2^(levels-1); 1 <= levels <= ICP_MAX_LEVELS;
+ *     W, H <= ICP_MAX_DIM.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device buffers handed to a call must stay alive until the stream work
+ *     that uses them has completed.
+ *   - Return value: ICP_OK (0) or a negative ICP_E* code; icp_strerror() names
+ *     it and icp_last_error() gives the context's last message.  Numerical
+ *     outcomes (too few correspondences, an ill-conditioned system) are not
+ *     errors: they are reported per level in icp_stats and the pose keeps its
+ *     last good value.  No C++ exception crosses this interface.
+ *   - A context is used by one host thread at a time.  It owns all device
+ *     workspace (pyramids, histograms, partial sums, per-problem state).
+ */
+#ifndef ICP_MI355X_H
+#define ICP_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ICP_ABI_VERSION 1
+#define ICP_MAX_LEVELS 4
+#define ICP_MAX_DIM 8192
+#define ICP_HIST_BINS 1024 /* distance histogram: bins of 2^-13 m over [0, 0.125) m */
+
+/* return codes */
+#define ICP_OK 0
+#define ICP_EINVAL (-1)   /* null pointer, bad size or bad parameter */
+#define ICP_ENOMEM (-2)   /* workspace would exceed the context's HBM budget, or allocation failed */
+#define ICP_EDEVICE (-3)  /* a HIP runtime error; icp_last_error() has its text */
+#define ICP_ETIMEOUT (-4) /* a device-side wait gave up (persistent batch kernel) */
+
+/* per-level numerical status (icp_level_stats.status) */
+#define ICP_LEVEL_OK 0
+#define ICP_TOO_FEW_CORR 1 /* fewer than min_corr pairs kept: the level ends, pose unchanged */
+#define ICP_ILL_COND 2     /* an LDL^T pivot <= ill_cond_eps * max diagonal: level ends */
+#define ICP_NONFINITE 3    /* the increment was not finite: level ends */
+
+/* lambda as a function of the kept-pair count n (paper Sec. 3.1, Table 4) */
+#define ICP_LAMBDA_CONST 0
+#define ICP_LAMBDA_C_OVER_SQRT_N 1
+#define ICP_LAMBDA_C_OVER_N 2
+#define ICP_LAMBDA_C_OVER_N2 3
+
+/* per-pixel association codes written by icp_stage_associate */
+#define ICP_PX_INVALID_LIVE 0
+#define ICP_PX_BEHIND 1
+#define ICP_PX_OUTSIDE 2
+#define ICP_PX_INVALID_MODEL 3
+#define ICP_PX_FAR 4
+#define ICP_PX_ANGLE 5
+#define ICP_PX_GATED 6
+
+typedef struct icp_ctx icp_ctx;
+
+typedef struct {
+    double fx, fy, cx, cy; /* level-0 pinhole intrinsics, pixels */
+} icp_intrinsics;
+
+typedef struct {
+    int32_t levels;                 /* pyramid levels (coarse-to-fine, Sec. 3) */
+    int32_t iters[ICP_MAX_LEVELS];  /* ICP iterations per level, level 0 (finest) first;
+                                       KinectFusion's cadence (4,5,10) coarse to fine is
+                                       {10,5,4}, the IMU-seeded one (2,2,3) is {3,2,2} (Sec. 4.4) */
+    double dist_max;                /* pair gate: point-to-point distance < dist_max metres (<= 0.125) */
+    double cos_angle_max;           /* pair gate: (R n_live) . n_model >= this */
+    double band_beta;               /* median filter band (Sec. 3.3): bins
+                                       [floor((1-b) k_med), ceil((1+b)(k_med+1)) - 1]; b >= 0 */
+    int32_t use_median_filter;      /* 0 keeps every gated pair */
+    int32_t use_imu_seed;           /* 1: the initial rotation is imu_R (Sec. 3) */
+    int32_t lambda_mode;            /* ICP_LAMBDA_* */
+    double lambda_c;                /* c >= 0 (Eq. (4)/(5)) */
+    int32_t min_corr;               /* minimum kept pairs for a solve (>= 6) */
+    double ill_cond_eps;            /* LDL^T pivot threshold relative to the max diagonal */
+    int32_t converge_window;        /* 0: fixed cadence; k >= 1: a level stops once the median
+                                       bin is unchanged on k successive iterations (Sec. 3.4) */
+    int32_t reduce_mode;            /* 0: FP32 moment reduction */
+    int32_t tile_px[ICP_MAX_LEVELS];/* pixels per work-group tile per level (multiple of 256);
+                                       0 = chosen by the library */
+} icp_params;
+
+typedef struct {
+    int32_t iters_run;
+    int32_t status;    /* ICP_LEVEL_* of the last iteration run */
+    int64_t n_gated;   /* N: gated pairs (histogram total) of the last iteration run */
+    int64_t n_kept;    /* n: pairs kept by the median band in the last iteration run */
+    int32_t k_med;     /* median bin of the last iteration run (-1: none) */
+    int32_t pad;
+    double rmse;       /* sqrt(b^T b / n) of the last iteration run, metres */
+} icp_level_stats;
+
+typedef struct {
+    icp_level_stats level[ICP_MAX_LEVELS];
+    int32_t status;      /* first non-OK level status, coarse to fine, else ICP_LEVEL_OK */
+    int32_t iters_total; /* iterations run over all levels */
+} icp_stats;
+
+/* one problem of a batch; every pointer is a device pointer except as noted */
+typedef struct {
+    const float* live_depth;
+    const float* model_vtx;
+    const float* model_nrm;
+    int32_t W, H;
+    icp_intrinsics K;
+    double imu_R[9];      /* host values */
+    double init_pose[16]; /* host values */
+} icp_problem;
+
+/* pose (4x4 row-major) and statistics of one registration */
+typedef struct {
+    double pose[16];
+    icp_stats stats;
+} icp_result;
+
+/* ---------------------------------------------------------------- context */
+
+/* ABI version of the loaded library (ICP_ABI_VERSION). */
+int icp_abi_version(void);
+
+/* Text of a return code (static storage). */
+const char* icp_strerror(int code);
+
+/* Last error message of a context (valid until the next call on it). */
+const char* icp_last_error(const icp_ctx* ctx);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+   workspace it may hold (0 = no cap).  *out receives the context. */
+int icp_ctx_create(int device, size_t hbm_budget_bytes, icp_ctx** out);
+
+/* Release a context and its device workspace (synchronises the device first).
+   NULL is ignored. */
+void icp_ctx_destroy(icp_ctx* ctx);
+
+/* Bytes of device workspace the context currently holds. */
+size_t icp_ctx_workspace_bytes(const icp_ctx* ctx);
+
+/* Bytes of workspace a batch of problems of these sizes needs (W, H arrays of
+   length n, host pointers). */
+size_t icp_workspace_bytes(int n, const int32_t* W, const int32_t* H, int levels);
+
+/* Fill *p with the defaults: 3 levels, iterations {10,5,4}, dist_max 0.10 m,
+   20 degree normal gate, band beta 1, median filter on, IMU seed on,
+   lambda = 5 constant (the value of the paper's Freiburg runs, Sec. 5.2),
+   min_corr 6, ill_cond_eps 1e-12, no convergence stop, FP32 reduction. */
+void icp_params_default(icp_params* p);
+
+/* -------------------------------------------------------------- hot path */
+
+/* Register one live depth frame against the model maps (Sec. 3): build the
+   live and model pyramids, seed the pose with the IMU rotation, then per
+   level (coarse to fine) and per iteration run projective association with
+   gates, the distance histogram and median band (Sec. 3.2-3.3), the
+   point-to-plane moment reduction (Eq. (3)), the regularised 6x6 solve
+   (Eq. (5)) and the SE(3) pose update, all on the device.
+   live_depth/model_vtx/model_nrm: device pointers as in the conventions;
+   K, imu_R (3x3), init_pose (4x4), params: host pointers.
+   pose_out (4x4) and stats_out (may be NULL): host pointers, valid on return
+   (the call synchronises `stream`). */
+int icp_register(icp_ctx* ctx, const float* live_depth, int W, int H, const float* model_vtx,
+                 const float* model_nrm, const icp_intrinsics* K, const double* imu_R,
+                 const double* init_pose, const icp_params* params, double* pose_out,
+                 icp_stats* stats_out, void* stream);
+
+/* Same as icp_register but asynchronous: result_dev is a device pointer to
+   one icp_result, written by the stream; nothing is synchronised. */
+int icp_register_async(icp_ctx* ctx, const float* live_depth, int W, int H, const float* model_vtx,
+                       const float* model_nrm, const icp_intrinsics* K, const double* imu_R,
+                       const double* init_pose, const icp_params* params, icp_result* result_dev,
+                       void* stream);
+
+/* Register n independent problems (possibly of different sizes) with shared
+   params in one set of launches: every kernel covers the tiles of all
+   problems.  probs: host array of n problems; results: host array of n,
+   valid on return (synchronises `stream`). */
+int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params,
+                       icp_result* results, void* stream);
+
+/* ------------------------------------------------------ stage access
+   For parity testing of each step against an independent implementation.
+   They use the same kernels and launch configuration as icp_register on one
+   problem held in the context. */
+
+/* Build the live and model pyramids of one problem into the context. */
+int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const float* model_vtx,
+                      const float* model_nrm, const icp_intrinsics* K, int levels, void* stream);
+
+/* Copy level `level` of the prepared pyramids to device buffers (any may be
+   NULL): depth (H_l*W_l), live vertex/normal and model vertex/normal as
+   three planes of H_l*W_l floats (x plane, y plane, z plane).  Synchronises. */
+int icp_stage_level(icp_ctx* ctx, int level, float* depth, float* live_vtx, float* live_nrm,
+                    float* model_vtx, float* model_nrm, void* stream);
+
+/* One association pass (projective lookup, gates, histogram, median band) at
+   `level` for the 3x4 pose12 (host).  code (uint8, H_l*W_l, ICP_PX_* values)
+   and bin (int32, -1 unless gated) are device buffers or NULL; hist (host,
+   ICP_HIST_BINS) and band (host, {N, k_med, k_lo, k_hi}) may be NULL.
+   Synchronises. */
+int icp_stage_associate(icp_ctx* ctx, int level, const double* pose12, const icp_params* params,
+                        uint8_t* code, int32_t* bin, uint32_t* hist, int64_t* band, void* stream);
+
+/* One filter+reduce pass at `level` for pose12 keeping gated pairs with bins
+   in [k_lo, k_hi].  moments (host, 28 doubles: upper triangle of the 7x7
+   [a | b]^T [a | b], row-major) and n (host) receive the reduction.
+   Synchronises. */
+int icp_stage_moments(icp_ctx* ctx, int level, const double* pose12, const icp_params* params,
+                      int k_lo, int k_hi, double* moments, int64_t* n, void* stream);
+
+/* The device solve and update on given moments: pose12_out = Exp(x) pose12_in
+   with x solving Eq. (5).  All pointers host.  *status receives ICP_LEVEL_*.
+   Synchronises. */
+int icp_stage_solve(icp_ctx* ctx, const double* moments, int64_t n, const double* pose12_in,
+                    const icp_params* params, double* pose12_out, double* x_out, int* status,
+                    void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

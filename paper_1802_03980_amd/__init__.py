@@ -1,0 +1,342 @@
+"""MI355X (gfx950) tracking hot path of IMU-seeded, median-filtered,
+regularised KinectFusion ICP (Giancola et al. 2018).
+
+A thin ctypes binding over ``_lib/libicp_mi355x.so`` whose functions carry the
+names of the C ABI in ``include/icp.h``.  It only marshals arguments: device
+memory comes from torch tensors (``data_ptr()``), the stream is torch's current
+HIP stream, and every step of the registration runs in the library's kernels.
+There is no fallback: if the library is missing or no GPU is present, the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libicp_mi355x.so")
+
+ICP_ABI_VERSION = 1
+MAX_LEVELS = 4
+HIST_BINS = 1024
+OK, EINVAL, ENOMEM, EDEVICE, ETIMEOUT = 0, -1, -2, -3, -4
+LEVEL_OK, TOO_FEW_CORR, ILL_COND, NONFINITE = range(4)
+LAMBDA_CONST, LAMBDA_C_OVER_SQRT_N, LAMBDA_C_OVER_N, LAMBDA_C_OVER_N2 = range(4)
+PX_INVALID_LIVE, PX_BEHIND, PX_OUTSIDE, PX_INVALID_MODEL, PX_FAR, PX_ANGLE, PX_GATED = range(7)
+
+# symbols of include/icp.h
+EXPORTS = (
+    "icp_abi_version", "icp_strerror", "icp_last_error", "icp_ctx_create", "icp_ctx_destroy",
+    "icp_ctx_workspace_bytes", "icp_workspace_bytes", "icp_params_default", "icp_register",
+    "icp_register_async", "icp_register_batch", "icp_stage_prepare", "icp_stage_level",
+    "icp_stage_associate", "icp_stage_moments", "icp_stage_solve",
+)
+
+
+class IcpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"icp error {code}: {msg}")
+        self.code = code
+
+
+class icp_intrinsics(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double)]
+
+
+class icp_params(C.Structure):
+    _fields_ = [
+        ("levels", C.c_int32), ("iters", C.c_int32 * MAX_LEVELS), ("dist_max", C.c_double),
+        ("cos_angle_max", C.c_double), ("band_beta", C.c_double), ("use_median_filter", C.c_int32),
+        ("use_imu_seed", C.c_int32), ("lambda_mode", C.c_int32), ("lambda_c", C.c_double),
+        ("min_corr", C.c_int32), ("ill_cond_eps", C.c_double), ("converge_window", C.c_int32),
+        ("reduce_mode", C.c_int32), ("tile_px", C.c_int32 * MAX_LEVELS),
+    ]
+
+
+class icp_level_stats(C.Structure):
+    _fields_ = [("iters_run", C.c_int32), ("status", C.c_int32), ("n_gated", C.c_int64), ("n_kept", C.c_int64),
+                ("k_med", C.c_int32), ("pad", C.c_int32), ("rmse", C.c_double)]
+
+
+class icp_stats(C.Structure):
+    _fields_ = [("level", icp_level_stats * MAX_LEVELS), ("status", C.c_int32), ("iters_total", C.c_int32)]
+
+
+class icp_problem(C.Structure):
+    _fields_ = [("live_depth", C.c_void_p), ("model_vtx", C.c_void_p), ("model_nrm", C.c_void_p),
+                ("W", C.c_int32), ("H", C.c_int32), ("K", icp_intrinsics), ("imu_R", C.c_double * 9),
+                ("init_pose", C.c_double * 16)]
+
+
+class icp_result(C.Structure):
+    _fields_ = [("pose", C.c_double * 16), ("stats", icp_stats)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (loads torch's HIP runtime first)
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                              "python paper_1802_03980_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P, I, D, Z = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+        sig = {
+            "icp_abi_version": (I, []),
+            "icp_strerror": (C.c_char_p, [I]),
+            "icp_last_error": (C.c_char_p, [P]),
+            "icp_ctx_create": (I, [I, Z, C.POINTER(P)]),
+            "icp_ctx_destroy": (None, [P]),
+            "icp_ctx_workspace_bytes": (Z, [P]),
+            "icp_workspace_bytes": (Z, [I, P, P, I]),
+            "icp_params_default": (None, [C.POINTER(icp_params)]),
+            "icp_register": (I, [P, P, I, I, P, P, C.POINTER(icp_intrinsics), P, P, C.POINTER(icp_params), P,
+                                 C.POINTER(icp_stats), P]),
+            "icp_register_async": (I, [P, P, I, I, P, P, C.POINTER(icp_intrinsics), P, P,
+                                       C.POINTER(icp_params), P, P]),
+            "icp_register_batch": (I, [P, I, P, C.POINTER(icp_params), P, P]),
+            "icp_stage_prepare": (I, [P, P, I, I, P, P, C.POINTER(icp_intrinsics), I, P]),
+            "icp_stage_level": (I, [P, I, P, P, P, P, P, P]),
+            "icp_stage_associate": (I, [P, I, P, C.POINTER(icp_params), P, P, P, P, P]),
+            "icp_stage_moments": (I, [P, I, P, C.POINTER(icp_params), I, I, P, P, P]),
+            "icp_stage_solve": (I, [P, P, C.c_int64, P, C.POINTER(icp_params), P, P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        if L.icp_abi_version() != ICP_ABI_VERSION:
+            raise ImportError("libicp_mi355x ABI version mismatch")
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------- helpers
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype_name, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device (HIP) tensor")
+    if str(t.dtype) != f"torch.{dtype_name}":
+        raise TypeError(f"{name} must be {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _f64(a, n, name):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
+    if a.size != n:
+        raise ValueError(f"{name} must have {n} values")
+    return a
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _check(ctx, rc):
+    if rc != OK:
+        L = lib()
+        msg = L.icp_last_error(ctx.handle if isinstance(ctx, Context) else ctx)
+        raise IcpError(rc, (msg or L.icp_strerror(rc)).decode())
+
+
+def stats_to_dict(st, levels=MAX_LEVELS):
+    return dict(status=st.status, iters_total=st.iters_total,
+                levels=[dict(iters_run=s.iters_run, status=s.status, n_gated=s.n_gated, n_kept=s.n_kept,
+                             k_med=s.k_med, rmse=s.rmse) for s in st.level[:levels]])
+
+
+# ---------------------------------------------------------------- API
+
+def icp_params_default(**over):
+    p = icp_params()
+    lib().icp_params_default(C.byref(p))
+    for k, v in over.items():
+        if k in ("iters", "tile_px"):
+            arr = getattr(p, k)
+            for j in range(MAX_LEVELS):
+                arr[j] = int(v[j]) if j < len(v) else 0
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def make_intrinsics(K):
+    fx, fy, cx, cy = (float(v) for v in K)
+    return icp_intrinsics(fx, fy, cx, cy)
+
+
+class Context:
+    """An icp_ctx on one HIP device (created lazily by icp_ctx_create)."""
+
+    def __init__(self, handle, device):
+        self.handle = handle
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.icp_ctx_destroy(self.handle)
+            self.handle = None
+
+    def workspace_bytes(self):
+        return int(lib().icp_ctx_workspace_bytes(self.handle))
+
+
+def icp_ctx_create(device=0, hbm_budget_bytes=0):
+    h = C.c_void_p()
+    rc = lib().icp_ctx_create(int(device), int(hbm_budget_bytes), C.byref(h))
+    if rc != OK:
+        raise IcpError(rc, lib().icp_strerror(rc).decode())
+    return Context(h, device)
+
+
+def icp_workspace_bytes(sizes, levels=3):
+    W = np.array([s[0] for s in sizes], np.int32)
+    H = np.array([s[1] for s in sizes], np.int32)
+    return int(lib().icp_workspace_bytes(len(sizes), _np_ptr(W), _np_ptr(H), levels))
+
+
+def icp_register(ctx, live_depth, model_vtx, model_nrm, K, imu_R, init_pose, params=None, stream=None):
+    """Register one frame; returns (4x4 pose ndarray, stats dict)."""
+    H, W = live_depth.shape
+    p = params if params is not None else icp_params_default()
+    Kc = make_intrinsics(K)
+    R = _f64(imu_R, 9, "imu_R")
+    T0 = _f64(init_pose, 16, "init_pose")
+    pose = np.zeros(16)
+    st = icp_stats()
+    rc = lib().icp_register(ctx.handle, _dev_ptr(live_depth, "float32", "live_depth"), W, H,
+                            _dev_ptr(model_vtx, "float32", "model_vtx"), _dev_ptr(model_nrm, "float32", "model_nrm"),
+                            C.byref(Kc), _np_ptr(R), _np_ptr(T0), C.byref(p), _np_ptr(pose), C.byref(st),
+                            _stream(stream))
+    _check(ctx, rc)
+    return pose.reshape(4, 4), stats_to_dict(st, p.levels)
+
+
+def icp_register_async(ctx, live_depth, model_vtx, model_nrm, K, imu_R, init_pose, result_dev, params=None,
+                       stream=None):
+    """Asynchronous register; result_dev is a uint8 device tensor of at least
+    sizeof(icp_result) bytes that receives the icp_result."""
+    H, W = live_depth.shape
+    p = params if params is not None else icp_params_default()
+    if result_dev.numel() * result_dev.element_size() < C.sizeof(icp_result):
+        raise ValueError("result_dev too small")
+    Kc = make_intrinsics(K)
+    R = _f64(imu_R, 9, "imu_R")
+    T0 = _f64(init_pose, 16, "init_pose")
+    rc = lib().icp_register_async(ctx.handle, _dev_ptr(live_depth, "float32", "live_depth"), W, H,
+                                  _dev_ptr(model_vtx, "float32", "model_vtx"),
+                                  _dev_ptr(model_nrm, "float32", "model_nrm"), C.byref(Kc), _np_ptr(R),
+                                  _np_ptr(T0), C.byref(p), C.c_void_p(result_dev.data_ptr()), _stream(stream))
+    _check(ctx, rc)
+
+
+def result_from_bytes(buf):
+    """Decode an icp_result from host bytes: (4x4 pose, stats dict)."""
+    r = icp_result.from_buffer_copy(bytes(buf))
+    return np.array(r.pose[:]).reshape(4, 4), stats_to_dict(r.stats)
+
+
+def icp_register_batch(ctx, problems, params=None, stream=None):
+    """problems: sequence of dicts with live_depth, model_vtx, model_nrm (device
+    tensors), K, imu_R, init_pose.  Returns a list of (pose, stats)."""
+    p = params if params is not None else icp_params_default()
+    n = len(problems)
+    arr = (icp_problem * n)()
+    for i, q in enumerate(problems):
+        d = q["live_depth"]
+        H, W = d.shape
+        a = arr[i]
+        a.live_depth = _dev_ptr(d, "float32", "live_depth").value
+        a.model_vtx = _dev_ptr(q["model_vtx"], "float32", "model_vtx").value
+        a.model_nrm = _dev_ptr(q["model_nrm"], "float32", "model_nrm").value
+        a.W, a.H = W, H
+        a.K = make_intrinsics(q["K"])
+        a.imu_R[:] = list(_f64(q["imu_R"], 9, "imu_R"))
+        a.init_pose[:] = list(_f64(q["init_pose"], 16, "init_pose"))
+    res = (icp_result * n)()
+    rc = lib().icp_register_batch(ctx.handle, n, C.cast(arr, C.c_void_p), C.byref(p), C.cast(res, C.c_void_p),
+                                  _stream(stream))
+    _check(ctx, rc)
+    return [(np.array(r.pose[:]).reshape(4, 4), stats_to_dict(r.stats, p.levels)) for r in res]
+
+
+# ---------------------------------------------------------------- stage access
+
+def icp_stage_prepare(ctx, live_depth, model_vtx, model_nrm, K, levels=3, stream=None):
+    H, W = live_depth.shape
+    Kc = make_intrinsics(K)
+    rc = lib().icp_stage_prepare(ctx.handle, _dev_ptr(live_depth, "float32", "live_depth"), W, H,
+                                 _dev_ptr(model_vtx, "float32", "model_vtx"),
+                                 _dev_ptr(model_nrm, "float32", "model_nrm"), C.byref(Kc), levels, _stream(stream))
+    _check(ctx, rc)
+
+
+def icp_stage_level(ctx, level, H, W, stream=None):
+    """Level maps as device tensors: depth (H_l, W_l) and four (3, H_l, W_l)."""
+    import torch
+    Hl, Wl = H >> level, W >> level
+    dev = torch.device("cuda", ctx.device)
+    D = torch.empty((Hl, Wl), dtype=torch.float32, device=dev)
+    maps = [torch.empty((3, Hl, Wl), dtype=torch.float32, device=dev) for _ in range(4)]
+    rc = lib().icp_stage_level(ctx.handle, level, C.c_void_p(D.data_ptr()),
+                               *[C.c_void_p(m.data_ptr()) for m in maps], _stream(stream))
+    _check(ctx, rc)
+    return D, maps[0], maps[1], maps[2], maps[3]
+
+
+def icp_stage_associate(ctx, level, pose, H, W, params=None, stream=None):
+    """Per-pixel codes and bins (device tensors), histogram and band (host)."""
+    import torch
+    p = params if params is not None else icp_params_default()
+    Hl, Wl = H >> level, W >> level
+    dev = torch.device("cuda", ctx.device)
+    code = torch.empty((Hl, Wl), dtype=torch.uint8, device=dev)
+    bins = torch.empty((Hl, Wl), dtype=torch.int32, device=dev)
+    hist = np.zeros(HIST_BINS, np.uint32)
+    band = np.zeros(4, np.int64)
+    P12 = _f64(np.asarray(pose, dtype=np.float64)[:3, :4], 12, "pose")
+    rc = lib().icp_stage_associate(ctx.handle, level, _np_ptr(P12), C.byref(p), C.c_void_p(code.data_ptr()),
+                                   C.c_void_p(bins.data_ptr()), _np_ptr(hist), _np_ptr(band), _stream(stream))
+    _check(ctx, rc)
+    return code, bins, hist, band
+
+
+def icp_stage_moments(ctx, level, pose, k_lo, k_hi, params=None, stream=None):
+    p = params if params is not None else icp_params_default()
+    P12 = _f64(np.asarray(pose, dtype=np.float64)[:3, :4], 12, "pose")
+    M = np.zeros(28)
+    n = np.zeros(1, np.int64)
+    rc = lib().icp_stage_moments(ctx.handle, level, _np_ptr(P12), C.byref(p), int(k_lo), int(k_hi), _np_ptr(M),
+                                 _np_ptr(n), _stream(stream))
+    _check(ctx, rc)
+    return M, int(n[0])
+
+
+def icp_stage_solve(ctx, moments, n, pose, params=None, stream=None):
+    p = params if params is not None else icp_params_default()
+    M = _f64(moments, 28, "moments")
+    P12 = _f64(np.asarray(pose, dtype=np.float64)[:3, :4], 12, "pose")
+    out = np.zeros(12)
+    x = np.zeros(6)
+    st = C.c_int(0)
+    rc = lib().icp_stage_solve(ctx.handle, _np_ptr(M), int(n), _np_ptr(P12), C.byref(p), _np_ptr(out), _np_ptr(x),
+                               C.byref(st), _stream(stream))
+    _check(ctx, rc)
+    T = np.eye(4)
+    T[:3, :4] = out.reshape(3, 4)
+    return st.value, T, x

@@ -1,0 +1,572 @@
+// Host side of the C ABI declared in include/icp.h: context, workspace
+// planning, the per-level iteration driver and the stage-access calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "icp.h"
+#include "icp_common.hpp"
+#include "icp_launch.hpp"
+
+struct icp_ctx {
+    int device = 0;
+    size_t budget = 0;
+    void* ws = nullptr;  // device workspace
+    size_t ws_cap = 0;
+    void* hstage = nullptr;  // pinned upload staging
+    size_t hstage_cap = 0;
+    hipEvent_t ev_upload = nullptr;  // upload of the staging buffer finished
+    bool ev_pending = false;
+    std::string err;
+    // stage-access problem (problem 0 of the last icp_stage_prepare)
+    bool stage_ready = false;
+    int stage_levels = 0;
+    ProbDesc stage_desc{};
+    ProbDesc* d_desc = nullptr;
+    int* d_owner[ICP_MAX_LEVELS] = {};
+    int tiles[ICP_MAX_LEVELS] = {};
+    ProbState* d_state = nullptr;
+    double* d_scratch = nullptr;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kScratchBytes = 4096 + 8 * 64;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int fail(icp_ctx* ctx, int code, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int hip_fail(icp_ctx* ctx, hipError_t e, const char* where) {
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(ctx, ICP_EDEVICE, m);
+}
+
+#define HIP_TRY(ctx, expr)                                  \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+int check_params(icp_ctx* ctx, const icp_params* p) {
+    if (!p) return fail(ctx, ICP_EINVAL, "params is NULL");
+    if (p->levels < 1 || p->levels > ICP_MAX_LEVELS) return fail(ctx, ICP_EINVAL, "levels must be in 1..4");
+    for (int l = 0; l < p->levels; ++l) {
+        if (p->iters[l] < 0 || p->iters[l] > 100000) return fail(ctx, ICP_EINVAL, "iters out of range");
+        const int t = p->tile_px[l];
+        if (t != 0 && (t < ICP_WG || t > 65536 || t % ICP_WG != 0))
+            return fail(ctx, ICP_EINVAL, "tile_px must be 0 or a multiple of 256 in [256, 65536]");
+    }
+    if (!(p->dist_max > 0.0 && p->dist_max <= 0.125)) return fail(ctx, ICP_EINVAL, "dist_max must be in (0, 0.125]");
+    if (!(p->cos_angle_max >= -1.0 && p->cos_angle_max <= 1.0))
+        return fail(ctx, ICP_EINVAL, "cos_angle_max must be in [-1, 1]");
+    if (!(p->band_beta >= 0.0 && std::isfinite(p->band_beta))) return fail(ctx, ICP_EINVAL, "band_beta must be >= 0");
+    if (p->lambda_mode < ICP_LAMBDA_CONST || p->lambda_mode > ICP_LAMBDA_C_OVER_N2)
+        return fail(ctx, ICP_EINVAL, "unknown lambda_mode");
+    if (!(p->lambda_c >= 0.0 && std::isfinite(p->lambda_c))) return fail(ctx, ICP_EINVAL, "lambda_c must be >= 0");
+    if (p->min_corr < 1) return fail(ctx, ICP_EINVAL, "min_corr must be >= 1");
+    if (!(p->ill_cond_eps >= 0.0)) return fail(ctx, ICP_EINVAL, "ill_cond_eps must be >= 0");
+    if (p->converge_window < 0) return fail(ctx, ICP_EINVAL, "converge_window must be >= 0");
+    if (p->reduce_mode != 0) return fail(ctx, ICP_EINVAL, "unknown reduce_mode");
+    return ICP_OK;
+}
+
+int check_problem(icp_ctx* ctx, const icp_problem& q, int levels) {
+    if (!q.live_depth || !q.model_vtx || !q.model_nrm) return fail(ctx, ICP_EINVAL, "input pointer is NULL");
+    const int div = 1 << (levels - 1);
+    if (q.W < 1 || q.H < 1 || q.W > ICP_MAX_DIM || q.H > ICP_MAX_DIM)
+        return fail(ctx, ICP_EINVAL, "W and H must be in 1..8192");
+    if (q.W % div || q.H % div) return fail(ctx, ICP_EINVAL, "W and H must be divisible by 2^(levels-1)");
+    const icp_intrinsics& K = q.K;
+    if (!(K.fx > 0 && K.fy > 0 && std::isfinite(K.fx) && std::isfinite(K.fy) && std::isfinite(K.cx) &&
+          std::isfinite(K.cy)))
+        return fail(ctx, ICP_EINVAL, "intrinsics must be finite with fx, fy > 0");
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(q.imu_R[k])) return fail(ctx, ICP_EINVAL, "imu_R not finite");
+    for (int k = 0; k < 12; ++k)
+        if (!std::isfinite(q.init_pose[k])) return fail(ctx, ICP_EINVAL, "init_pose not finite");
+    return ICP_OK;
+}
+
+// Tile size: aim for ~2048 work-groups per pass over the batch (8 per CU).
+int pick_tile(int npx, int nprob, int req) {
+    if (req > 0) return req;
+    const long target = std::max(1L, 2048L / std::max(1, nprob));
+    long t = (npx + target - 1) / target;
+    t = (t + ICP_WG - 1) / ICP_WG * ICP_WG;
+    return (int)std::min(16384L, std::max((long)ICP_WG, t));
+}
+
+// Workspace layout of a batch; offsets are relative to the workspace base.
+struct Plan {
+    size_t off_desc = 0, off_state = 0, off_res = 0, off_scratch = 0, off_owner[ICP_MAX_LEVELS] = {};
+    int tiles[ICP_MAX_LEVELS] = {};
+    int max_npx[ICP_MAX_LEVELS] = {};
+    std::vector<ProbDesc> desc;  // pointers hold offsets until rebased
+    std::vector<int> owner[ICP_MAX_LEVELS];
+    size_t total = 0;
+};
+
+void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int32_t* tile_req, Plan& P) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    P.desc.assign(n, ProbDesc{});
+    P.off_desc = take(sizeof(ProbDesc) * n);
+    P.off_state = take(sizeof(ProbState) * n);
+    P.off_res = take(sizeof(icp_result) * n);
+    P.off_scratch = take(kScratchBytes);
+    for (int l = 0; l < levels; ++l) {
+        P.tiles[l] = 0;
+        P.max_npx[l] = 0;
+        P.owner[l].clear();
+    }
+    for (int p = 0; p < n; ++p) {
+        ProbDesc& d = P.desc[p];
+        d.st = reinterpret_cast<ProbState*>(P.off_state + sizeof(ProbState) * p);
+        for (int l = 0; l < levels; ++l) {
+            LevelDesc& L = d.lv[l];
+            L.W = W[p] >> l;
+            L.H = H[p] >> l;
+            L.npx = L.W * L.H;
+            L.tile_px = pick_tile(L.npx, n, tile_req ? tile_req[l] : 0);
+            L.n_tiles = (L.npx + L.tile_px - 1) / L.tile_px;
+            L.tile_base = P.tiles[l];
+            P.tiles[l] += L.n_tiles;
+            P.max_npx[l] = std::max(P.max_npx[l], L.npx);
+            for (int t = 0; t < L.n_tiles; ++t) P.owner[l].push_back(p);
+            const size_t S = (size_t)L.npx * sizeof(float);
+            L.Dw = l > 0 ? reinterpret_cast<float*>(take(S)) : nullptr;
+            L.LV = reinterpret_cast<float*>(take(3 * S));
+            L.LN = reinterpret_cast<float*>(take(3 * S));
+            L.MV = reinterpret_cast<float*>(take(3 * S));
+            L.MN = reinterpret_cast<float*>(take(3 * S));
+            L.part = reinterpret_cast<float*>(take((size_t)L.n_tiles * ICP_PART_STRIDE * sizeof(float)));
+        }
+    }
+    for (int l = 0; l < levels; ++l) P.off_owner[l] = take(sizeof(int) * std::max(1, P.tiles[l]));
+    P.total = off;
+}
+
+template <typename T>
+T* rebase(T* off, char* base) {
+    return reinterpret_cast<T*>(base + reinterpret_cast<size_t>(off));
+}
+
+int ensure_workspace(icp_ctx* ctx, size_t bytes) {
+    if (ctx->budget && bytes > ctx->budget)
+        return fail(ctx, ICP_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes exceeds the HBM budget");
+    if (bytes <= ctx->ws_cap) return ICP_OK;
+    if (ctx->ws) {
+        HIP_TRY(ctx, hipDeviceSynchronize());
+        HIP_TRY(ctx, hipFree(ctx->ws));
+        ctx->ws = nullptr;
+        ctx->ws_cap = 0;
+        ctx->stage_ready = false;
+    }
+    size_t want = bytes + bytes / 4;
+    if (ctx->budget) want = std::min(want, ctx->budget);
+    hipError_t e = hipMalloc(&ctx->ws, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->ws = nullptr;
+        return fail(ctx, ICP_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    ctx->ws_cap = want;
+    return ICP_OK;
+}
+
+int ensure_stage(icp_ctx* ctx, size_t bytes) {
+    if (ctx->ev_pending) {
+        HIP_TRY(ctx, hipEventSynchronize(ctx->ev_upload));
+        ctx->ev_pending = false;
+    }
+    if (bytes <= ctx->hstage_cap) return ICP_OK;
+    if (ctx->hstage) HIP_TRY(ctx, hipHostFree(ctx->hstage));
+    ctx->hstage = nullptr;
+    ctx->hstage_cap = 0;
+    HIP_TRY(ctx, hipHostMalloc(&ctx->hstage, bytes));
+    ctx->hstage_cap = bytes;
+    return ICP_OK;
+}
+
+KParams kparams(const icp_params* p) {
+    KParams k{};
+    k.d2max = p->dist_max * p->dist_max;
+    k.cos_max = p->cos_angle_max;
+    k.band_beta = p->band_beta;
+    k.lambda_c = p->lambda_c;
+    k.ill_cond_eps = p->ill_cond_eps;
+    k.lambda_mode = p->lambda_mode;
+    k.use_filter = p->use_median_filter;
+    k.min_corr = p->min_corr;
+    k.converge_window = p->converge_window;
+    return k;
+}
+
+// Plan, place and upload a batch; leaves device descriptors ready.
+int stage_batch(icp_ctx* ctx, int n, const icp_problem* probs, int levels, const int32_t* tile_req, Plan& P,
+                hipStream_t s) {
+    std::vector<int32_t> W(n), H(n);
+    for (int p = 0; p < n; ++p) {
+        W[p] = probs[p].W;
+        H[p] = probs[p].H;
+    }
+    make_plan(n, W.data(), H.data(), levels, tile_req, P);
+    int rc = ensure_workspace(ctx, P.total);
+    if (rc) return rc;
+    char* base = static_cast<char*>(ctx->ws);
+    for (int p = 0; p < n; ++p) {
+        ProbDesc& d = P.desc[p];
+        const icp_problem& q = probs[p];
+        d.st = rebase(d.st, base);
+        for (int l = 0; l < levels; ++l) {
+            LevelDesc& L = d.lv[l];
+            const double s2 = std::ldexp(1.0, -l);
+            L.fx = q.K.fx * s2;
+            L.fy = q.K.fy * s2;
+            L.cx = (q.K.cx + 0.5) * s2 - 0.5;
+            L.cy = (q.K.cy + 0.5) * s2 - 0.5;
+            L.Dw = l > 0 ? rebase(L.Dw, base) : nullptr;
+            L.D = l > 0 ? L.Dw : q.live_depth;
+            L.LV = rebase(L.LV, base);
+            L.LN = rebase(L.LN, base);
+            L.MV = rebase(L.MV, base);
+            L.MN = rebase(L.MN, base);
+            L.part = rebase(L.part, base);
+        }
+        d.model_vtx = q.model_vtx;
+        d.model_nrm = q.model_nrm;
+        std::memcpy(d.imu_R, q.imu_R, sizeof(d.imu_R));
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 4; ++j) d.init[4 * i + j] = q.init_pose[4 * i + j];
+    }
+    size_t up = sizeof(ProbDesc) * n;
+    size_t owner_bytes = 0;
+    for (int l = 0; l < levels; ++l) owner_bytes += sizeof(int) * P.owner[l].size();
+    rc = ensure_stage(ctx, up + owner_bytes);
+    if (rc) return rc;
+    char* h = static_cast<char*>(ctx->hstage);
+    std::memcpy(h, P.desc.data(), up);
+    HIP_TRY(ctx, hipMemcpyAsync(base + P.off_desc, h, up, hipMemcpyHostToDevice, s));
+    size_t ho = up;
+    for (int l = 0; l < levels; ++l) {
+        const size_t b = sizeof(int) * P.owner[l].size();
+        std::memcpy(h + ho, P.owner[l].data(), b);
+        HIP_TRY(ctx, hipMemcpyAsync(base + P.off_owner[l], h + ho, b, hipMemcpyHostToDevice, s));
+        ho += b;
+    }
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_upload, s));
+    ctx->ev_pending = true;
+    return ICP_OK;
+}
+
+// Whole registration of a staged batch; results into `res_dev` (device).
+int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* res_dev, hipStream_t s) {
+    char* base = static_cast<char*>(ctx->ws);
+    const ProbDesc* d_desc = reinterpret_cast<const ProbDesc*>(base + P.off_desc);
+    const KParams kp = kparams(prm);
+    HIP_TRY(ctx, icpk::launch_init(d_desc, n, prm->use_imu_seed, s));
+    HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, P.max_npx, s));
+    for (int l = prm->levels - 1; l >= 0; --l) {
+        const int* owner = reinterpret_cast<const int*>(base + P.off_owner[l]);
+        for (int it = 0; it < prm->iters[l]; ++it) {
+            IterCtl ctl{l, it, it == prm->iters[l] - 1 ? 1 : 0, 0};
+            HIP_TRY(ctx, icpk::launch_iteration(d_desc, owner, P.tiles[l], ctl, kp, s));
+        }
+    }
+    HIP_TRY(ctx, icpk::launch_finalize(d_desc, n, res_dev, s));
+    return ICP_OK;
+}
+
+icp_problem one_problem(const float* depth, int W, int H, const float* mv, const float* mn, const icp_intrinsics* K,
+                        const double* imu_R, const double* init_pose) {
+    icp_problem q{};
+    q.live_depth = depth;
+    q.model_vtx = mv;
+    q.model_nrm = mn;
+    q.W = W;
+    q.H = H;
+    if (K) q.K = *K;
+    for (int k = 0; k < 9; ++k) q.imu_R[k] = imu_R ? imu_R[k] : (k % 4 == 0 ? 1.0 : 0.0);
+    for (int k = 0; k < 16; ++k) q.init_pose[k] = init_pose ? init_pose[k] : (k % 5 == 0 ? 1.0 : 0.0);
+    return q;
+}
+
+}  // namespace
+
+extern "C" {
+
+int icp_abi_version(void) { return ICP_ABI_VERSION; }
+
+const char* icp_strerror(int code) {
+    switch (code) {
+        case ICP_OK: return "ok";
+        case ICP_EINVAL: return "invalid argument";
+        case ICP_ENOMEM: return "out of device memory or over the HBM budget";
+        case ICP_EDEVICE: return "HIP runtime error";
+        case ICP_ETIMEOUT: return "device-side wait timed out";
+        default: return "unknown error";
+    }
+}
+
+const char* icp_last_error(const icp_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+void icp_params_default(icp_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->levels = 3;
+    p->iters[0] = 10;
+    p->iters[1] = 5;
+    p->iters[2] = 4;
+    p->dist_max = 0.10;
+    p->cos_angle_max = std::cos(20.0 * M_PI / 180.0);
+    p->band_beta = 1.0;
+    p->use_median_filter = 1;
+    p->use_imu_seed = 1;
+    p->lambda_mode = ICP_LAMBDA_CONST;
+    p->lambda_c = 5.0;
+    p->min_corr = 6;
+    p->ill_cond_eps = 1e-12;
+    p->converge_window = 0;
+    p->reduce_mode = 0;
+}
+
+int icp_ctx_create(int device, size_t hbm_budget_bytes, icp_ctx** out) {
+    if (!out) return ICP_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return ICP_EDEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) return ICP_EDEVICE;
+    icp_ctx* ctx = new icp_ctx();
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes;
+    if (hipEventCreateWithFlags(&ctx->ev_upload, hipEventDisableTiming) != hipSuccess) {
+        delete ctx;
+        return ICP_EDEVICE;
+    }
+    *out = ctx;
+    return ICP_OK;
+}
+
+void icp_ctx_destroy(icp_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->hstage) (void)hipHostFree(ctx->hstage);
+    if (ctx->ev_upload) (void)hipEventDestroy(ctx->ev_upload);
+    delete ctx;
+}
+
+size_t icp_ctx_workspace_bytes(const icp_ctx* ctx) { return ctx ? ctx->ws_cap : 0; }
+
+size_t icp_workspace_bytes(int n, const int32_t* W, const int32_t* H, int levels) {
+    if (n < 1 || !W || !H || levels < 1 || levels > ICP_MAX_LEVELS) return 0;
+    Plan P;
+    make_plan(n, W, H, levels, nullptr, P);
+    return P.total;
+}
+
+int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params, icp_result* results,
+                       void* stream) {
+    if (!ctx) return ICP_EINVAL;
+    if (n < 1 || !probs || !results) return fail(ctx, ICP_EINVAL, "empty batch or NULL array");
+    if (n > 65535) return fail(ctx, ICP_EINVAL, "at most 65535 problems per batch");
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    for (int p = 0; p < n; ++p)
+        if ((rc = check_problem(ctx, probs[p], params->levels))) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Plan P;
+    if ((rc = stage_batch(ctx, n, probs, params->levels, params->tile_px, P, s))) return rc;
+    ctx->stage_ready = false;
+    icp_result* d_res = reinterpret_cast<icp_result*>(static_cast<char*>(ctx->ws) + P.off_res);
+    if ((rc = run_batch(ctx, n, params, P, d_res, s))) return rc;
+    HIP_TRY(ctx, hipMemcpyAsync(results, d_res, sizeof(icp_result) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    return ICP_OK;
+}
+
+int icp_register(icp_ctx* ctx, const float* live_depth, int W, int H, const float* model_vtx,
+                 const float* model_nrm, const icp_intrinsics* K, const double* imu_R, const double* init_pose,
+                 const icp_params* params, double* pose_out, icp_stats* stats_out, void* stream) {
+    if (!ctx) return ICP_EINVAL;
+    if (!K || !imu_R || !init_pose || !pose_out) return fail(ctx, ICP_EINVAL, "NULL host argument");
+    icp_problem q = one_problem(live_depth, W, H, model_vtx, model_nrm, K, imu_R, init_pose);
+    icp_result r;
+    int rc = icp_register_batch(ctx, 1, &q, params, &r, stream);
+    if (rc) return rc;
+    std::memcpy(pose_out, r.pose, sizeof(r.pose));
+    if (stats_out) *stats_out = r.stats;
+    return ICP_OK;
+}
+
+int icp_register_async(icp_ctx* ctx, const float* live_depth, int W, int H, const float* model_vtx,
+                       const float* model_nrm, const icp_intrinsics* K, const double* imu_R, const double* init_pose,
+                       const icp_params* params, icp_result* result_dev, void* stream) {
+    if (!ctx) return ICP_EINVAL;
+    if (!K || !imu_R || !init_pose || !result_dev) return fail(ctx, ICP_EINVAL, "NULL argument");
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    icp_problem q = one_problem(live_depth, W, H, model_vtx, model_nrm, K, imu_R, init_pose);
+    if ((rc = check_problem(ctx, q, params->levels))) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Plan P;
+    if ((rc = stage_batch(ctx, 1, &q, params->levels, params->tile_px, P, s))) return rc;
+    ctx->stage_ready = false;
+    return run_batch(ctx, 1, params, P, result_dev, s);
+}
+
+// ------------------------------------------------------------------ stages
+
+int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const float* model_vtx,
+                      const float* model_nrm, const icp_intrinsics* K, int levels, void* stream) {
+    if (!ctx) return ICP_EINVAL;
+    if (!K) return fail(ctx, ICP_EINVAL, "K is NULL");
+    if (levels < 1 || levels > ICP_MAX_LEVELS) return fail(ctx, ICP_EINVAL, "levels must be in 1..4");
+    icp_problem q = one_problem(live_depth, W, H, model_vtx, model_nrm, K, nullptr, nullptr);
+    int rc = check_problem(ctx, q, levels);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Plan P;
+    if ((rc = stage_batch(ctx, 1, &q, levels, nullptr, P, s))) return rc;
+    char* base = static_cast<char*>(ctx->ws);
+    ctx->d_desc = reinterpret_cast<ProbDesc*>(base + P.off_desc);
+    for (int l = 0; l < levels; ++l) {
+        ctx->d_owner[l] = reinterpret_cast<int*>(base + P.off_owner[l]);
+        ctx->tiles[l] = P.tiles[l];
+    }
+    ctx->d_state = reinterpret_cast<ProbState*>(base + P.off_state);
+    ctx->d_scratch = reinterpret_cast<double*>(base + P.off_scratch);
+    ctx->stage_desc = P.desc[0];
+    ctx->stage_levels = levels;
+    HIP_TRY(ctx, icpk::launch_init(ctx->d_desc, 1, 0, s));
+    HIP_TRY(ctx, icpk::launch_prepare(ctx->d_desc, 1, levels, P.max_npx, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    ctx->stage_ready = true;
+    return ICP_OK;
+}
+
+static int stage_check(icp_ctx* ctx, int level) {
+    if (!ctx) return ICP_EINVAL;
+    if (!ctx->stage_ready) return fail(ctx, ICP_EINVAL, "no prepared stage problem (call icp_stage_prepare)");
+    if (level < 0 || level >= ctx->stage_levels) return fail(ctx, ICP_EINVAL, "level out of range");
+    return ICP_OK;
+}
+
+int icp_stage_level(icp_ctx* ctx, int level, float* depth, float* live_vtx, float* live_nrm, float* model_vtx,
+                    float* model_nrm, void* stream) {
+    int rc = stage_check(ctx, level);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const LevelDesc& L = ctx->stage_desc.lv[level];
+    const size_t S = (size_t)L.npx * sizeof(float);
+    if (depth) HIP_TRY(ctx, hipMemcpyAsync(depth, L.D, S, hipMemcpyDeviceToDevice, s));
+    if (live_vtx) HIP_TRY(ctx, hipMemcpyAsync(live_vtx, L.LV, 3 * S, hipMemcpyDeviceToDevice, s));
+    if (live_nrm) HIP_TRY(ctx, hipMemcpyAsync(live_nrm, L.LN, 3 * S, hipMemcpyDeviceToDevice, s));
+    if (model_vtx) HIP_TRY(ctx, hipMemcpyAsync(model_vtx, L.MV, 3 * S, hipMemcpyDeviceToDevice, s));
+    if (model_nrm) HIP_TRY(ctx, hipMemcpyAsync(model_nrm, L.MN, 3 * S, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    return ICP_OK;
+}
+
+static icpk::PoseArg pose_arg(const double* pose12) {
+    icpk::PoseArg a;
+    std::memcpy(a.v, pose12, sizeof(a.v));
+    return a;
+}
+
+int icp_stage_associate(icp_ctx* ctx, int level, const double* pose12, const icp_params* params, uint8_t* code,
+                        int32_t* bin, uint32_t* hist, int64_t* band, void* stream) {
+    int rc = stage_check(ctx, level);
+    if (rc) return rc;
+    if (!pose12) return fail(ctx, ICP_EINVAL, "pose12 is NULL");
+    if ((rc = check_params(ctx, params))) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const KParams kp = kparams(params);
+    uint32_t* d_hist = reinterpret_cast<uint32_t*>(ctx->d_scratch);
+    HIP_TRY(ctx, icpk::launch_stage_set(ctx->d_desc, pose_arg(pose12), 0, -1, s));
+    IterCtl ctl{level, 0, 0, 0};
+    HIP_TRY(ctx, icpk::launch_stage_pass1(ctx->d_desc, ctx->d_owner[level], ctx->tiles[level], ctl, kp, code, bin,
+                                          d_hist, s));
+    uint32_t hh[ICP_HIST_BINS];
+    int32_t bandv[4];
+    HIP_TRY(ctx, hipMemcpyAsync(hh, d_hist, sizeof(hh), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(bandv, &ctx->d_state->N, sizeof(bandv), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (hist) std::memcpy(hist, hh, sizeof(hh));
+    if (band) {
+        band[0] = (int64_t)(uint32_t)bandv[0];
+        band[1] = bandv[1];
+        band[2] = bandv[2];
+        band[3] = bandv[3];
+    }
+    return ICP_OK;
+}
+
+int icp_stage_moments(icp_ctx* ctx, int level, const double* pose12, const icp_params* params, int k_lo, int k_hi,
+                      double* moments, int64_t* n, void* stream) {
+    int rc = stage_check(ctx, level);
+    if (rc) return rc;
+    if (!pose12 || !moments || !n) return fail(ctx, ICP_EINVAL, "NULL argument");
+    if ((rc = check_params(ctx, params))) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const KParams kp = kparams(params);
+    HIP_TRY(ctx, icpk::launch_stage_set(ctx->d_desc, pose_arg(pose12), k_lo, k_hi, s));
+    IterCtl ctl{level, 0, 0, 1};
+    HIP_TRY(ctx, icpk::launch_stage_pass2(ctx->d_desc, ctx->d_owner[level], ctx->tiles[level], ctl, kp, s));
+    HIP_TRY(ctx, hipMemcpyAsync(moments, ctx->d_state->M, sizeof(double) * ICP_NMOM, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(n, &ctx->d_state->n_last, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    return ICP_OK;
+}
+
+int icp_stage_solve(icp_ctx* ctx, const double* moments, int64_t n, const double* pose12_in, const icp_params* params,
+                    double* pose12_out, double* x_out, int* status, void* stream) {
+    if (!ctx) return ICP_EINVAL;
+    if (!moments || !pose12_in || !pose12_out) return fail(ctx, ICP_EINVAL, "NULL argument");
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!ctx->ws || ctx->ws_cap < kScratchBytes) {
+        if ((rc = ensure_workspace(ctx, kScratchBytes))) return rc;
+        ctx->stage_ready = false;
+        ctx->d_scratch = static_cast<double*>(ctx->ws);
+    }
+    if (!ctx->stage_ready) ctx->d_scratch = static_cast<double*>(ctx->ws);
+    icpk::MomArg M;
+    std::memcpy(M.m, moments, sizeof(M.m));
+    HIP_TRY(ctx, icpk::launch_stage_solve(M, n, pose_arg(pose12_in), kparams(params), ctx->d_scratch, s));
+    double out[19];
+    HIP_TRY(ctx, hipMemcpyAsync(out, ctx->d_scratch, sizeof(out), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    std::memcpy(pose12_out, out, 12 * sizeof(double));
+    if (x_out) std::memcpy(x_out, out + 12, 6 * sizeof(double));
+    if (status) *status = (int)out[18];
+    return ICP_OK;
+}
+
+}  // extern "C"

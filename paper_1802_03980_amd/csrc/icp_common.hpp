@@ -1,0 +1,81 @@
+// Internal layout shared by the kernels and the host side of libicp_mi355x.
+//
+// HBM layout per problem (all float32, level l has W_l x H_l = (W>>l) x (H>>l)):
+//   live depth D_l (level 0 is the caller's buffer), live vertex LV_l and
+//   normal LN_l, model vertex MV_l and normal MN_l, each as three planes of
+//   W_l*H_l floats (x plane, y plane, z plane) so that every per-pixel read is
+//   a unit-stride 4-byte stream across a wavefront.  Invalid entries are NaN
+//   (maps) or 0 (depth).  Per level a problem also owns one 32-float partial
+//   per work-group tile.  The small per-problem state (pose, histogram,
+//   band, tickets, statistics) lives in one ProbState.
+#pragma once
+
+#include <stdint.h>
+
+#include "icp.h"
+
+#define ICP_WG 256              // threads per work-group (four wave64)
+#define ICP_WAVES (ICP_WG / 64)
+#define ICP_PART_STRIDE 32      // floats per tile partial: 28 moments, count, pad
+#define ICP_NMOM 28
+
+struct LevelDesc {
+    int32_t W, H, npx;          // size of the level, npx = W*H
+    int32_t tile_px;            // pixels per tile (multiple of ICP_WG)
+    int32_t n_tiles;            // ceil(npx / tile_px)
+    int32_t tile_base;          // first flat tile of this problem at this level
+    double fx, fy, cx, cy;      // intrinsics of the level
+    const float* D;             // depth (level 0: caller input)
+    float* Dw;                  // writable depth (levels >= 1), same as D there
+    float* LV;                  // live vertex, 3 planes
+    float* LN;                  // live normal
+    float* MV;                  // model vertex
+    float* MN;                  // model normal
+    float* part;                // n_tiles * ICP_PART_STRIDE
+};
+
+struct ProbState {
+    double R[9];                // current pose, row-major rotation
+    double t[3];
+    double M[ICP_NMOM];         // last reduced moments (FP64 sums of tile partials)
+    double x[6];                // last increment
+    int64_t n_last;             // kept pairs of the last reduction
+    uint32_t hist[ICP_HIST_BINS];
+    uint32_t N;                 // gated pairs of the current iteration
+    int32_t k_med, k_lo, k_hi;  // median bin and kept band of the current iteration
+    uint32_t ticket1, ticket2;  // arrival counters of the two passes
+    int32_t level_done;         // the current level has ended (status or convergence)
+    int32_t settled;            // successive iterations with an unchanged median
+    int32_t last_kmed;
+    int32_t last_status;        // status of the last solve
+    icp_stats stats;
+};
+
+struct ProbDesc {
+    LevelDesc lv[ICP_MAX_LEVELS];
+    const float* model_vtx;     // caller's AoS model maps (level 0)
+    const float* model_nrm;
+    double imu_R[9];            // IMU rotation prior, row-major
+    double init[12];            // initial pose, 3x4 row-major [R | t]
+    ProbState* st;
+};
+
+// Scalars of a launch that are the same for every problem in it.
+struct IterCtl {
+    int32_t level;
+    int32_t iter;               // iteration index within the level
+    int32_t last_of_level;      // this is the level's last scheduled iteration
+    int32_t no_update;          // stage calls: reduce only, keep the pose
+};
+
+struct KParams {
+    double d2max;               // dist_max^2
+    double cos_max;
+    double band_beta;
+    double lambda_c;
+    double ill_cond_eps;
+    int32_t lambda_mode;
+    int32_t use_filter;
+    int32_t min_corr;
+    int32_t converge_window;
+};

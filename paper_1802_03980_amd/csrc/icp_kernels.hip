@@ -1,0 +1,553 @@
+// gfx950 kernels of the ICP tracking hot path.
+//
+// Launch shapes: work-groups of 256 threads (four wave64).  Front-end kernels
+// use one thread per output pixel with grid.y = problem.  The two iteration
+// passes use one work-group per tile of `tile_px` consecutive pixels of one
+// problem; a flat tile index spans every problem of the batch and `owner`
+// maps it to its problem.  Each pass ends with an arrival ticket per problem:
+// the last work-group of a problem runs that problem's epilogue (the median
+// band after pass 1, the FP64 solve and pose update after pass 2), so an
+// iteration is two launches whatever the batch size and the pose never leaves
+// the device.
+#include <hip/hip_runtime.h>
+
+#include "icp_device.hpp"
+#include "icp_launch.hpp"
+
+namespace icpk {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ bool depth_ok(float z) { return __builtin_isfinite(z) && z > 0.0f; }
+
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_agent(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------------ init
+
+__global__ __launch_bounds__(ICP_WG) void k_init(const ProbDesc* __restrict__ probs, int use_imu_seed) {
+    const ProbDesc& P = probs[blockIdx.x];
+    ProbState* st = P.st;
+    for (int b = threadIdx.x; b < ICP_HIST_BINS; b += ICP_WG) st->hist[b] = 0u;
+    if (threadIdx.x == 0) {
+        // Sec. 3: the live points are pre-oriented by the IMU rotation
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) st->R[3 * i + j] = use_imu_seed ? P.imu_R[3 * i + j] : P.init[4 * i + j];
+            st->t[i] = P.init[4 * i + 3];
+        }
+        for (int k = 0; k < ICP_NMOM; ++k) st->M[k] = 0.0;
+        for (int k = 0; k < 6; ++k) st->x[k] = 0.0;
+        st->n_last = 0;
+        st->N = 0;
+        st->k_med = -1;
+        st->k_lo = 0;
+        st->k_hi = -1;
+        st->ticket1 = 0;
+        st->ticket2 = 0;
+        st->level_done = 0;
+        st->settled = 0;
+        st->last_kmed = -2;
+        st->last_status = ICP_LEVEL_OK;
+        for (int l = 0; l < ICP_MAX_LEVELS; ++l) {
+            icp_level_stats& S = st->stats.level[l];
+            S.iters_run = 0;
+            S.status = ICP_LEVEL_OK;
+            S.n_gated = 0;
+            S.n_kept = 0;
+            S.k_med = -1;
+            S.pad = 0;
+            S.rmse = 0.0;
+        }
+        st->stats.status = ICP_LEVEL_OK;
+        st->stats.iters_total = 0;
+    }
+}
+
+// ------------------------------------------------------------------ front end
+// Depth pyramid: 2x2 mean of the four children when all four are valid.
+
+__global__ __launch_bounds__(ICP_WG) void k_depth_down(const ProbDesc* __restrict__ probs, int level) {
+    const ProbDesc& P = probs[blockIdx.y];
+    const LevelDesc& F = P.lv[level - 1];
+    const LevelDesc& C = P.lv[level];
+    const int i = blockIdx.x * ICP_WG + threadIdx.x;
+    if (i >= C.npx) return;
+    const int u = i % C.W, v = i / C.W;
+    const float* D = F.D;
+    const float a = D[(2 * v) * F.W + 2 * u], b = D[(2 * v) * F.W + 2 * u + 1];
+    const float c = D[(2 * v + 1) * F.W + 2 * u], d = D[(2 * v + 1) * F.W + 2 * u + 1];
+    float out = 0.0f;
+    if (depth_ok(a) && depth_ok(b) && depth_ok(c) && depth_ok(d))
+        out = (float)(((((double)a + (double)b) + (double)c) + (double)d) * 0.25);
+    C.Dw[i] = out;
+}
+
+// Vertex of pixel (u, v): z ((u - cx)/fx, (v - cy)/fy, 1), stored FP32.
+__device__ __forceinline__ bool back_project(const LevelDesc& L, int u, int v, float* o) {
+    const float z = L.D[v * L.W + u];
+    if (!depth_ok(z)) return false;
+    const double zd = (double)z;
+    o[0] = (float)(zd * (((double)u - L.cx) / L.fx));
+    o[1] = (float)(zd * (((double)v - L.cy) / L.fy));
+    o[2] = z;
+    return true;
+}
+
+// Live vertex map and forward-difference normal map (flipped to face the
+// camera); neighbours' vertices are recomputed with the same arithmetic.
+__global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__ probs, int level) {
+    const LevelDesc& L = probs[blockIdx.y].lv[level];
+    const int i = blockIdx.x * ICP_WG + threadIdx.x;
+    if (i >= L.npx) return;
+    const int S = L.npx;
+    const int u = i % L.W, v = i / L.W;
+    const float qnan = __builtin_nanf("");
+    float p[3] = {qnan, qnan, qnan};
+    float n[3] = {qnan, qnan, qnan};
+    float pr[3], pd[3];
+    if (back_project(L, u, v, p) && u + 1 < L.W && v + 1 < L.H && back_project(L, u + 1, v, pr) &&
+        back_project(L, u, v + 1, pd)) {
+        double e1[3], e2[3];
+        for (int k = 0; k < 3; ++k) {
+            e1[k] = (double)pr[k] - (double)p[k];
+            e2[k] = (double)pd[k] - (double)p[k];
+        }
+        const double c0 = e1[1] * e2[2] - e1[2] * e2[1];
+        const double c1 = e1[2] * e2[0] - e1[0] * e2[2];
+        const double c2 = e1[0] * e2[1] - e1[1] * e2[0];
+        const double len2 = (c0 * c0 + c1 * c1) + c2 * c2;
+        if (len2 > 0.0 && __builtin_isfinite(len2)) {
+            const double len = sqrt(len2);
+            double m0 = c0 / len, m1 = c1 / len, m2 = c2 / len;
+            const double side = (m0 * (double)p[0] + m1 * (double)p[1]) + m2 * (double)p[2];
+            if (side > 0.0) {
+                m0 = -m0;
+                m1 = -m1;
+                m2 = -m2;
+            }
+            n[0] = (float)m0;
+            n[1] = (float)m1;
+            n[2] = (float)m2;
+        }
+    }
+    if (!depth_ok(L.D[i])) p[0] = p[1] = p[2] = qnan;
+    L.LV[i] = p[0];
+    L.LV[S + i] = p[1];
+    L.LV[2 * S + i] = p[2];
+    L.LN[i] = n[0];
+    L.LN[S + i] = n[1];
+    L.LN[2 * S + i] = n[2];
+}
+
+// Model maps, level 0: interleaved input -> planes; a pixel is valid iff all
+// six values are finite, invalid pixels become NaN in all six.
+__global__ __launch_bounds__(ICP_WG) void k_model_l0(const ProbDesc* __restrict__ probs) {
+    const ProbDesc& P = probs[blockIdx.y];
+    const LevelDesc& L = P.lv[0];
+    const int i = blockIdx.x * ICP_WG + threadIdx.x;
+    if (i >= L.npx) return;
+    const int S = L.npx;
+    float v[3], n[3];
+    bool ok = true;
+    for (int k = 0; k < 3; ++k) {
+        v[k] = P.model_vtx[3 * (size_t)i + k];
+        n[k] = P.model_nrm[3 * (size_t)i + k];
+        ok = ok && fin(v[k]) && fin(n[k]);
+    }
+    const float qnan = __builtin_nanf("");
+    for (int k = 0; k < 3; ++k) {
+        L.MV[k * S + i] = ok ? v[k] : qnan;
+        L.MN[k * S + i] = ok ? n[k] : qnan;
+    }
+}
+
+// Model level l from l-1: vertex = mean of the four children, normal = their
+// normalised sum, valid iff all four children are valid.
+__global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restrict__ probs, int level) {
+    const ProbDesc& P = probs[blockIdx.y];
+    const LevelDesc& F = P.lv[level - 1];
+    const LevelDesc& C = P.lv[level];
+    const int i = blockIdx.x * ICP_WG + threadIdx.x;
+    if (i >= C.npx) return;
+    const int SF = F.npx, SC = C.npx;
+    const int u = i % C.W, v = i / C.W;
+    const int ch[4] = {(2 * v) * F.W + 2 * u, (2 * v) * F.W + 2 * u + 1, (2 * v + 1) * F.W + 2 * u,
+                       (2 * v + 1) * F.W + 2 * u + 1};
+    const float qnan = __builtin_nanf("");
+    float vo[3] = {qnan, qnan, qnan}, no[3] = {qnan, qnan, qnan};
+    bool ok = true;
+    for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 3; ++k) ok = ok && fin(F.MV[k * SF + ch[j]]) && fin(F.MN[k * SF + ch[j]]);
+    if (ok) {
+        double s[3];
+        for (int k = 0; k < 3; ++k) {
+            const float* V = F.MV + k * SF;
+            const float* N = F.MN + k * SF;
+            const double m = (((double)V[ch[0]] + (double)V[ch[1]]) + (double)V[ch[2]]) + (double)V[ch[3]];
+            s[k] = (((double)N[ch[0]] + (double)N[ch[1]]) + (double)N[ch[2]]) + (double)N[ch[3]];
+            vo[k] = (float)(m * 0.25);
+        }
+        const double len2 = (s[0] * s[0] + s[1] * s[1]) + s[2] * s[2];
+        if (len2 > 0.0) {
+            const double len = sqrt(len2);
+            for (int k = 0; k < 3; ++k) no[k] = (float)(s[k] / len);
+        } else {
+            vo[0] = vo[1] = vo[2] = qnan;
+        }
+    }
+    for (int k = 0; k < 3; ++k) {
+        C.MV[k * SC + i] = vo[k];
+        C.MN[k * SC + i] = no[k];
+    }
+}
+
+// ------------------------------------------------------------------ pass 1
+// Association, gates and the distance histogram (Sec. 3.2); the last
+// work-group of a problem turns the histogram into the CDF, the median bin
+// and the kept band (Sec. 3.3).
+
+__device__ __forceinline__ void load_pose(const ProbState* st, Pose& T) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) T.r[k] = st->R[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) T.t[k] = st->t[k];
+}
+
+// Median bin k_med = min{k : C_k >= ceil(N/2)} and band from the histogram;
+// run by a whole work-group, histogram read from (and cleared in) `hist`.
+__device__ void median_band(ProbState* st, const KParams& kp, uint32_t* dbg_hist) {
+    __shared__ uint32_t sh_wsum[ICP_WAVES];
+    __shared__ int32_t sh_kmed;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t h[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        h[k] = __hip_atomic_exchange(&st->hist[4 * tid + k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (dbg_hist) dbg_hist[4 * tid + k] = h[k];
+    }
+    const uint32_t own = (h[0] + h[1]) + (h[2] + h[3]);
+    uint32_t incl = own;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) sh_wsum[wave] = incl;
+    if (tid == 0) sh_kmed = -1;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < ICP_WAVES; ++w) {
+        if (w < wave) before += sh_wsum[w];
+        total += sh_wsum[w];
+    }
+    const uint32_t target = (total + 1u) / 2u;
+    uint32_t c = before + incl - own;  // CDF just before this thread's first bin
+    if (total > 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t prev = c;
+            c += h[k];
+            if (prev < target && c >= target) sh_kmed = 4 * tid + k;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int32_t km = sh_kmed;
+        int32_t lo = 0, hi = -1;
+        if (total > 0) {
+            if (kp.use_filter) {
+                const double flo = floor((1.0 - kp.band_beta) * (double)km);
+                const double fhi = ceil((1.0 + kp.band_beta) * (double)(km + 1)) - 1.0;
+                lo = flo < 0.0 ? 0 : (int32_t)flo;
+                hi = fhi > (double)(ICP_HIST_BINS - 1) ? ICP_HIST_BINS - 1 : (int32_t)fhi;
+            } else {
+                hi = ICP_HIST_BINS - 1;
+            }
+        }
+        st->N = total;
+        st->k_med = km;
+        st->k_lo = lo;
+        st->k_hi = hi;
+    }
+}
+
+template <bool kDebug>
+__global__ __launch_bounds__(ICP_WG) void k_pass1(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
+                                                  IterCtl ctl, KParams kp, uint8_t* __restrict__ dbg_code,
+                                                  int32_t* __restrict__ dbg_bin, uint32_t* dbg_hist) {
+    __shared__ uint32_t sh_hist[ICP_HIST_BINS];
+    __shared__ int sh_last;
+    const int g = blockIdx.x;
+    const ProbDesc& P = probs[owner[g]];
+    const LevelDesc& L = P.lv[ctl.level];
+    ProbState* st = P.st;
+    const int tid = threadIdx.x;
+    for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) sh_hist[b] = 0u;
+    __syncthreads();
+    if (!st->level_done) {
+        Pose T;
+        load_pose(st, T);
+        const int base = (g - L.tile_base) * L.tile_px;
+        const int end = min(base + L.tile_px, L.npx);
+        for (int i = base + tid; i < end; i += ICP_WG) {
+            Match m;
+            const int code = associate(L, i, T, kp.d2max, kp.cos_max, m);
+            if (code == kGated) atomicAdd(&sh_hist[m.bin], 1u);
+            if (kDebug) {
+                if (dbg_code) dbg_code[i] = (uint8_t)code;
+                if (dbg_bin) dbg_bin[i] = code == kGated ? m.bin : -1;
+            }
+        }
+    }
+    __syncthreads();
+    for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) {
+        const uint32_t c = sh_hist[b];
+        if (c) atomicAdd(&st->hist[b], c);
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) sh_last = atomicAdd(&st->ticket1, 1u) == (uint32_t)(L.n_tiles - 1);
+    __syncthreads();
+    if (!sh_last) return;
+    __threadfence();
+    if (!st->level_done) median_band(st, kp, dbg_hist);
+    if (tid == 0) st->ticket1 = 0u;
+}
+
+// ------------------------------------------------------------------ pass 2
+// Filter (kept iff gated and its bin lies in the band) and the 28-moment
+// reduction of the kept rows; the last work-group of a problem sums the tile
+// partials in tile order (FP64), solves Eq. (5) and updates the pose.
+
+__device__ void solve_epilogue(ProbState* st, const double* M, int64_t n, const IterCtl& ctl, const KParams& kp) {
+    if (!st->level_done) {
+        for (int k = 0; k < ICP_NMOM; ++k) st->M[k] = M[k];
+        st->n_last = n;
+        if (!ctl.no_update) {
+            double x[6];
+            const int status = solve_regularised(M, n, kp, x);
+            if (status == ICP_LEVEL_OK) compose_exp(x, st->R, st->t);
+            for (int k = 0; k < 6; ++k) st->x[k] = x[k];
+            st->last_status = status;
+            icp_level_stats& S = st->stats.level[ctl.level];
+            S.iters_run = ctl.iter + 1;
+            S.status = status;
+            S.n_gated = st->N;
+            S.n_kept = n;
+            S.k_med = st->k_med;
+            S.rmse = n > 0 ? sqrt(M[ICP_NMOM - 1] / (double)n) : 0.0;
+            st->stats.iters_total += 1;
+            if (status != ICP_LEVEL_OK) {
+                st->level_done = 1;
+                if (st->stats.status == ICP_LEVEL_OK) st->stats.status = status;
+            } else if (kp.converge_window > 0) {
+                // Sec. 3.4: a level has converged once its median bin stays put
+                st->settled = (st->k_med == st->last_kmed) ? st->settled + 1 : 1;
+                st->last_kmed = st->k_med;
+                if (st->settled >= kp.converge_window) st->level_done = 1;
+            }
+        }
+    }
+    if (ctl.last_of_level) {
+        st->level_done = 0;
+        st->settled = 0;
+        st->last_kmed = -2;
+    }
+}
+
+__global__ __launch_bounds__(ICP_WG) void k_pass2(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
+                                                  IterCtl ctl, KParams kp) {
+    __shared__ float sh_red[ICP_WAVES][ICP_PART_STRIDE];
+    __shared__ double sh_sum[ICP_PART_STRIDE][8];
+    __shared__ int sh_last;
+    const int g = blockIdx.x;
+    const ProbDesc& P = probs[owner[g]];
+    const LevelDesc& L = P.lv[ctl.level];
+    ProbState* st = P.st;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = g - L.tile_base;
+    float acc[ICP_NMOM];
+#pragma unroll
+    for (int k = 0; k < ICP_NMOM; ++k) acc[k] = 0.0f;
+    uint32_t cnt = 0;
+    if (!st->level_done) {
+        Pose T;
+        load_pose(st, T);
+        const int klo = st->k_lo, khi = st->k_hi;
+        const int base = tile * L.tile_px;
+        const int end = min(base + L.tile_px, L.npx);
+        for (int i = base + tid; i < end; i += ICP_WG) {
+            Match m;
+            if (associate(L, i, T, kp.d2max, kp.cos_max, m) == kGated && m.bin >= klo && m.bin <= khi) {
+                accumulate_row(m, acc);
+                ++cnt;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < ICP_NMOM; ++k) acc[k] = wave_sum(acc[k]);
+    cnt = wave_sum_u(cnt);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < ICP_NMOM; ++k) sh_red[wave][k] = acc[k];
+        sh_red[wave][ICP_NMOM] = __uint_as_float(cnt);
+    }
+    __syncthreads();
+    if (tid <= ICP_NMOM) {
+        float v;
+        if (tid < ICP_NMOM) {
+            v = (sh_red[0][tid] + sh_red[1][tid]) + (sh_red[2][tid] + sh_red[3][tid]);
+        } else {
+            const uint32_t c = (__float_as_uint(sh_red[0][tid]) + __float_as_uint(sh_red[1][tid])) +
+                               (__float_as_uint(sh_red[2][tid]) + __float_as_uint(sh_red[3][tid]));
+            v = __uint_as_float(c);
+        }
+        st_agent(&L.part[(size_t)tile * ICP_PART_STRIDE + tid], v);
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) sh_last = atomicAdd(&st->ticket2, 1u) == (uint32_t)(L.n_tiles - 1);
+    __syncthreads();
+    if (!sh_last) return;
+    __threadfence();
+    // deterministic FP64 sum of the tile partials: 8 contiguous chunks per value
+    const int j = tid >> 3, c = tid & 7;
+    if (j <= ICP_NMOM) {
+        const int per = (L.n_tiles + 7) / 8;
+        const int t0 = c * per, t1 = min(t0 + per, L.n_tiles);
+        double s = 0.0;
+        for (int t = t0; t < t1; ++t) {
+            const float v = ld_agent(&L.part[(size_t)t * ICP_PART_STRIDE + j]);
+            s += j < ICP_NMOM ? (double)v : (double)__float_as_uint(v);
+        }
+        sh_sum[j][c] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double M[ICP_NMOM];
+        for (int k = 0; k <= ICP_NMOM; ++k) {
+            double s = 0.0;
+            for (int q = 0; q < 8; ++q) s += sh_sum[k][q];
+            if (k < ICP_NMOM) M[k] = s;
+            else sh_sum[k][0] = s;
+        }
+        const int64_t n = (int64_t)sh_sum[ICP_NMOM][0];
+        solve_epilogue(st, M, n, ctl, kp);
+        st->ticket2 = 0u;
+    }
+}
+
+// ------------------------------------------------------------------ results
+
+__global__ void k_finalize(const ProbDesc* __restrict__ probs, int n, icp_result* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const ProbState* st = probs[p].st;
+    icp_result& r = out[p];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) r.pose[4 * i + j] = st->R[3 * i + j];
+        r.pose[4 * i + 3] = st->t[i];
+    }
+    r.pose[12] = r.pose[13] = r.pose[14] = 0.0;
+    r.pose[15] = 1.0;
+    r.stats = st->stats;
+}
+
+// ------------------------------------------------------------------ stage access
+
+__global__ void k_stage_set(const ProbDesc* __restrict__ probs, PoseArg pose, int k_lo, int k_hi) {
+    ProbState* st = probs[0].st;
+    for (int b = threadIdx.x; b < ICP_HIST_BINS; b += blockDim.x) st->hist[b] = 0u;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) st->R[3 * i + j] = pose.v[4 * i + j];
+            st->t[i] = pose.v[4 * i + 3];
+        }
+        st->k_lo = k_lo;
+        st->k_hi = k_hi;
+        st->ticket1 = 0u;
+        st->ticket2 = 0u;
+        st->level_done = 0;
+    }
+}
+
+__global__ void k_stage_solve(MomArg M, int64_t n, PoseArg pose, KParams kp, double* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double R[9], t[3], x[6];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) R[3 * i + j] = pose.v[4 * i + j];
+        t[i] = pose.v[4 * i + 3];
+    }
+    const int status = solve_regularised(M.m, n, kp, x);
+    if (status == ICP_LEVEL_OK) compose_exp(x, R, t);
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) out[4 * i + j] = R[3 * i + j];
+        out[4 * i + 3] = t[i];
+    }
+    for (int k = 0; k < 6; ++k) out[12 + k] = x[k];
+    out[18] = (double)status;
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline unsigned blocks_for(int n) { return (unsigned)((n + ICP_WG - 1) / ICP_WG); }
+
+hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_init, dim3(n), dim3(ICP_WG), 0, s, probs, use_imu_seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, hipStream_t s) {
+    for (int l = 1; l < levels; ++l)
+        hipLaunchKernelGGL(k_depth_down, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
+    for (int l = 0; l < levels; ++l)
+        hipLaunchKernelGGL(k_live_vn, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
+    hipLaunchKernelGGL(k_model_l0, dim3(blocks_for(max_npx[0]), n), dim3(ICP_WG), 0, s, probs);
+    for (int l = 1; l < levels; ++l)
+        hipLaunchKernelGGL(k_model_down, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_iteration(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_pass1<false>, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp, nullptr, nullptr,
+                       nullptr);
+    hipLaunchKernelGGL(k_pass2, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const ProbDesc* probs, int n, icp_result* results, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3((n + 63) / 64), dim3(64), 0, s, probs, n, results);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_set(const ProbDesc* probs, PoseArg pose, int k_lo, int k_hi, hipStream_t s) {
+    hipLaunchKernelGGL(k_stage_set, dim3(1), dim3(ICP_WG), 0, s, probs, pose, k_lo, k_hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_pass1(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
+                              uint8_t* code, int32_t* bin, uint32_t* hist, hipStream_t s) {
+    hipLaunchKernelGGL(k_pass1<true>, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp, code, bin, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_pass2(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_pass2, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_solve(MomArg M, int64_t n, PoseArg pose, const KParams& kp, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_stage_solve, dim3(1), dim3(64), 0, s, M, n, pose, kp, out);
+    return hipGetLastError();
+}
+
+}  // namespace icpk

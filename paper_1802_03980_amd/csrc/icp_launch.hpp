@@ -1,0 +1,38 @@
+// Host-side launchers of the gfx950 kernels (defined in icp_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "icp_common.hpp"
+
+namespace icpk {
+
+struct PoseArg {
+    double v[12];  // 3x4 row-major [R | t]
+};
+
+struct MomArg {
+    double m[ICP_NMOM];
+};
+
+// per problem: seed the pose (IMU rotation or the initial pose), clear the
+// histogram, tickets, flags and statistics
+hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, hipStream_t s);
+// live depth pyramid, live vertex/normal maps, model maps for every level;
+// max_npx[l] is the largest level-l pixel count over the problems
+hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, hipStream_t s);
+// one ICP iteration at ctl.level over `tiles` flat tiles of all problems
+hipError_t launch_iteration(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
+                            hipStream_t s);
+// pose and statistics of every problem into results[n]
+hipError_t launch_finalize(const ProbDesc* probs, int n, icp_result* results, hipStream_t s);
+
+// stage access (problem 0 of `probs`)
+hipError_t launch_stage_set(const ProbDesc* probs, PoseArg pose, int k_lo, int k_hi, hipStream_t s);
+hipError_t launch_stage_pass1(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
+                              uint8_t* code, int32_t* bin, uint32_t* hist, hipStream_t s);
+hipError_t launch_stage_pass2(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
+                              hipStream_t s);
+hipError_t launch_stage_solve(MomArg M, int64_t n, PoseArg pose, const KParams& kp, double* out, hipStream_t s);
+
+}  // namespace icpk

@@ -1,0 +1,64 @@
+"""The C-ABI library loads and exports every entry point include/icp.h declares.
+
+CPU-only: no call here touches a GPU (only pure host functions are called).
+"""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1802_03980_amd as icp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "icp.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(icp_[a-z_]+)\s*\(", src)))
+
+
+def test_library_built():
+    assert os.path.exists(icp.LIB_PATH), "run __graft_entry__.build() first"
+
+
+def test_exports_match_header():
+    declared = _declared()
+    assert declared == sorted(icp.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", icp.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (icp_[a-z_]+)\b", out))
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+
+
+def test_library_loads_and_host_calls():
+    L = icp.lib()
+    assert L.icp_abi_version() == icp.ICP_ABI_VERSION
+    assert L.icp_strerror(icp.EINVAL) == b"invalid argument"
+    p = icp.icp_params_default()
+    assert p.levels == 3 and list(p.iters[:3]) == [10, 5, 4]
+    assert p.lambda_c == 5.0 and p.use_imu_seed == 1 and p.use_median_filter == 1
+    assert abs(p.cos_angle_max - np.cos(np.radians(20))) < 1e-15
+
+
+def test_struct_sizes_match_header_layout():
+    # sizes fixed by natural alignment of the C structs
+    assert C.sizeof(icp.icp_intrinsics) == 32
+    assert C.sizeof(icp.icp_level_stats) == 40
+    assert C.sizeof(icp.icp_stats) == 4 * 40 + 8
+    assert C.sizeof(icp.icp_result) == 16 * 8 + C.sizeof(icp.icp_stats)
+
+
+def test_workspace_bytes_scales_with_pixels():
+    vga = icp.icp_workspace_bytes([(640, 480)])
+    hd = icp.icp_workspace_bytes([(1280, 720)])
+    two = icp.icp_workspace_bytes([(640, 480), (640, 480)])
+    # four 3-plane maps of 4 bytes per pixel over a 3-level pyramid
+    assert vga >= 640 * 480 * 48 * (1 + 0.25 + 0.0625)
+    assert 2.9 < hd / vga < 3.1 and 1.9 < two / vga < 2.1
+    assert icp.lib().icp_workspace_bytes(0, None, None, 3) == 0

@@ -1,0 +1,274 @@
+"""GPU (HIP C-ABI) vs the FP64 oracle, stage by stage and end to end.
+
+Protocol: each stage runs on the same inputs on both sides (the oracle is fed
+the GPU's own maps and pose), so a stage is judged on its own arithmetic.
+  S1 maps: bitwise equal (same FP64 expressions on the same FP32 inputs).
+  S2 codes, bins, histogram: bitwise equal except pixels whose deciding
+     quantity lies within 1e-6 m of its threshold (counted, reported).
+  S3 moments: |gpu - oracle| <= 1e-5 * sum|terms| per entry (FP32 reduction).
+  S4 solve and update: relative 1e-12 (both FP64).
+  End to end: final poses within 1e-5 rad and 1e-5 m.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1802_03980_amd as icp
+import synth
+from tests.poseutil import pose_err
+
+pytestmark = pytest.mark.gpu
+
+EXCUSE_M = 1e-6
+POSE_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return icp.icp_ctx_create(0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def upload(prob):
+    return dev(prob.live_depth), dev(prob.model_vtx), dev(prob.model_nrm)
+
+
+def _same_nan(a, b):
+    return np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(a[~np.isnan(a)], b[~np.isnan(b)])
+
+
+def _gpu_levels(ctx, prob, levels=3):
+    d, mv, mn = upload(prob)
+    icp.icp_stage_prepare(ctx, d, mv, mn, prob.K, levels)
+    out = []
+    for l in range(levels):
+        D, LV, LN, MV, MN = (host(t) for t in icp.icp_stage_level(ctx, l, prob.H, prob.W))
+        out.append(dict(D=D, LV=LV, LN=LN, MV=MV, MN=MN, K=oracle.level_intrinsics(prob.K, l)))
+    return out
+
+
+PROBLEMS = {
+    "cfg1_s0": lambda: synth.config1_problem(0),
+    "cfg1_s1": lambda: synth.config1_problem(1),
+    "cfg4_0": lambda: synth.config4_problem(0),
+}
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_s1_pyramid_maps_bitwise(ctx, name):
+    prob = PROBLEMS[name]()
+    gpu = _gpu_levels(ctx, prob)
+    ref = oracle.pyramids(prob.live_depth, prob.model_vtx, prob.model_nrm, prob.K, 3)
+    for l in range(3):
+        for key in ("D", "LV", "LN", "MV", "MN"):
+            g, o = gpu[l][key], ref[l][key]
+            assert g.shape == o.shape
+            if not _same_nan(g, o):
+                bad = ~((g == o) | (np.isnan(g) & np.isnan(o)))
+                pytest.fail(f"{name} level {l} {key}: {bad.sum()} of {bad.size} entries differ")
+
+
+def _poses_for(prob):
+    seed = np.eye(4)
+    seed[:3, :3] = prob.imu_R
+    off = synth.pose_matrix(synth.rot_from_rotvec([0.004, -0.003, 0.002]), [0.01, -0.005, 0.008]) @ seed
+    return [seed, prob.T_gt, off]
+
+
+def _check_associate(ctx, prob, gpu_lv, level, T, params):
+    code_g, bin_g, hist_g, band_g = icp.icp_stage_associate(ctx, level, T, prob.H, prob.W, params)
+    code_g, bin_g = host(code_g), host(bin_g)
+    code_o, bin_o, margin, hist_o = oracle.associate(gpu_lv[level], T, params.dist_max, params.cos_angle_max)
+    bin_o = np.where(code_o == oracle.GATED, bin_o, -1)
+    diff = (code_g != code_o) | (bin_g != bin_o)
+    excused = diff & (margin < EXCUSE_M)
+    hard = diff & ~excused
+    assert not hard.any(), f"level {level}: {hard.sum()} mismatches beyond the excuse band"
+    assert np.abs(hist_g.astype(np.int64) - hist_o.astype(np.int64)).sum() <= 2 * excused.sum()
+    band_o = oracle.band(hist_o, params.use_median_filter, params.band_beta)
+    if not excused.any():
+        assert list(band_g) == list(band_o)
+    return int(excused.sum()), band_o
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_s2_association_histogram_band(ctx, name):
+    prob = PROBLEMS[name]()
+    gpu_lv = _gpu_levels(ctx, prob)
+    params = icp.icp_params_default()
+    total = 0
+    for T in _poses_for(prob):
+        for level in range(3):
+            ex, _ = _check_associate(ctx, prob, gpu_lv, level, T, params)
+            total += ex
+    print(f"{name}: excused pixels {total}")
+
+
+def _abs_terms(pp, q, nq):
+    A = np.hstack([np.cross(pp, nq), nq, np.einsum("ik,ik->i", nq, q - pp)[:, None]])
+    S = np.abs(A).T @ np.abs(A)
+    return np.array([S[i, j] for i in range(7) for j in range(i, 7)])
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_s3_moments(ctx, name):
+    prob = PROBLEMS[name]()
+    gpu_lv = _gpu_levels(ctx, prob)
+    params = icp.icp_params_default()
+    for T in _poses_for(prob):
+        for level in range(3):
+            _, band = _check_associate(ctx, prob, gpu_lv, level, T, params)
+            klo, khi = int(band[2]), int(band[3])
+            Mg, ng = icp.icp_stage_moments(ctx, level, T, klo, khi, params)
+            Mo, no = oracle.moments(gpu_lv[level], T, klo, khi, params.dist_max, params.cos_angle_max)
+            assert ng == no
+            code, bins, pp, q, nq = oracle.pairs(gpu_lv[level], T, params.dist_max, params.cos_angle_max)
+            keep = (code == oracle.GATED) & (bins >= klo) & (bins <= khi)
+            tol = 1e-5 * _abs_terms(pp[keep], q[keep], nq[keep]) + 1e-30
+            err = np.abs(Mg - Mo)
+            assert np.all(err <= tol), f"level {level}: worst ratio {np.max(err / tol):.3g}"
+
+
+def test_s4_solve_update(ctx):
+    prob = synth.config1_problem(0)
+    lvl = oracle.pyramids(prob.live_depth, prob.model_vtx, prob.model_nrm, prob.K, 1)[0]
+    rng = np.random.default_rng(3)
+    for mode, c in [(icp.LAMBDA_CONST, 0.0), (icp.LAMBDA_CONST, 5.0), (icp.LAMBDA_C_OVER_SQRT_N, 2.0),
+                    (icp.LAMBDA_C_OVER_N, 1.0), (icp.LAMBDA_C_OVER_N2, 0.5)]:
+        params = icp.icp_params_default(lambda_mode=mode, lambda_c=c)
+        T = synth.pose_matrix(synth.rot_from_rotvec(rng.normal(size=3) * 0.02), rng.normal(size=3) * 0.02)
+        M, n = oracle.moments(lvl, T, 0, 1023)
+        st_g, Tg, xg = icp.icp_stage_solve(ctx, M, n, T, params)
+        st_o, To, xo = oracle.solve_update(M, n, T, mode, c)
+        assert st_g == st_o == oracle.LEVEL_OK
+        assert np.allclose(xg, xo, rtol=1e-12, atol=1e-15 * np.abs(xo).max())
+        assert np.allclose(Tg, To, rtol=0, atol=1e-13)
+    # degenerate and too-few cases
+    params = icp.icp_params_default()
+    st_g, Tg, _ = icp.icp_stage_solve(ctx, np.zeros(28), 100, np.eye(4), params)
+    assert st_g == icp.ILL_COND and np.array_equal(Tg, np.eye(4))
+    st_g, _, _ = icp.icp_stage_solve(ctx, np.zeros(28), 3, np.eye(4), params)
+    assert st_g == icp.TOO_FEW_CORR
+
+
+def _oracle_params(p):
+    return oracle.default_params(levels=p.levels, iters=list(p.iters), dist_max=p.dist_max,
+                                 cos_angle_max=p.cos_angle_max, band_beta=p.band_beta,
+                                 use_median_filter=p.use_median_filter, use_imu_seed=p.use_imu_seed,
+                                 lambda_mode=p.lambda_mode, lambda_c=p.lambda_c, min_corr=p.min_corr,
+                                 ill_cond_eps=p.ill_cond_eps, converge_window=p.converge_window)
+
+
+def _register_both(ctx, prob, params):
+    d, mv, mn = upload(prob)
+    Tg, sg = icp.icp_register(ctx, d, mv, mn, prob.K, prob.imu_R, prob.init_pose, params)
+    To, so, _ = oracle.register_problem(prob, _oracle_params(params))
+    return Tg, sg, To, so
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("lam", [5.0, 0.0])
+def test_end_to_end_config1(ctx, seed, lam):
+    prob = synth.config1_problem(seed)
+    params = icp.icp_params_default(lambda_c=lam)
+    Tg, sg, To, so = _register_both(ctx, prob, params)
+    ang, dt = pose_err(Tg, To)
+    assert ang < POSE_TOL and dt < POSE_TOL, (ang, dt)
+    for l in range(3):
+        assert sg["levels"][l]["iters_run"] == so[l]["iters_run"]
+        assert sg["levels"][l]["status"] == so[l]["status"]
+        assert abs(sg["levels"][l]["n_kept"] - so[l]["n_kept"]) <= max(2, 1e-3 * so[l]["n_kept"])
+
+
+def test_end_to_end_vga_room(ctx):
+    seq = synth.RoomSequence(0, n_frames=3)
+    params = icp.icp_params_default()
+    for k in range(2):
+        prob = seq.problem(k)
+        Tg, sg, To, so = _register_both(ctx, prob, params)
+        ang, dt = pose_err(Tg, To)
+        assert ang < POSE_TOL and dt < POSE_TOL, (k, ang, dt)
+        assert sg["status"] == icp.LEVEL_OK
+
+
+def test_convergence_control_matches(ctx):
+    prob = synth.config1_problem(0)
+    params = icp.icp_params_default(converge_window=3, iters=(30, 30, 30), lambda_c=0.0)
+    Tg, sg, To, so = _register_both(ctx, prob, params)
+    ang, dt = pose_err(Tg, To)
+    assert ang < POSE_TOL and dt < POSE_TOL
+    assert [s["iters_run"] for s in sg["levels"]] == [s["iters_run"] for s in so]
+
+
+def test_batch_matches_single(ctx):
+    probs = [synth.config1_problem(0), synth.config4_problem(1), synth.config1_problem(2),
+             synth.config4_problem(3)]
+    params = icp.icp_params_default()
+    items = []
+    keep = []
+    for p in probs:
+        d, mv, mn = upload(p)
+        keep.append((d, mv, mn))
+        items.append(dict(live_depth=d, model_vtx=mv, model_nrm=mn, K=p.K, imu_R=p.imu_R, init_pose=p.init_pose))
+    batch = icp.icp_register_batch(ctx, items, params)
+    for p, (d, mv, mn), (Tb, sb) in zip(probs, keep, batch):
+        Ts, ss = icp.icp_register(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, params)
+        ang, dt = pose_err(Tb, Ts)
+        assert ang < POSE_TOL and dt < POSE_TOL
+        To, so, _ = oracle.register_problem(p, _oracle_params(params))
+        ang, dt = pose_err(Tb, To)
+        assert ang < POSE_TOL and dt < POSE_TOL, (p.name, ang, dt)
+
+
+def test_edge_cases(ctx):
+    prob = synth.config1_problem(0)
+    params = icp.icp_params_default()
+    # all depth invalid: every level reports too few correspondences, pose = seed
+    z = prob.live_depth * 0
+    d, mv, mn = dev(z), dev(prob.model_vtx), dev(prob.model_nrm)
+    Tg, sg = icp.icp_register(ctx, d, mv, mn, prob.K, prob.imu_R, prob.init_pose, params)
+    assert all(s["status"] == icp.TOO_FEW_CORR and s["iters_run"] == 1 for s in sg["levels"])
+    assert np.array_equal(Tg[:3, :3], prob.imu_R)
+    # NaN model maps
+    nanm = np.full_like(prob.model_vtx, np.nan)
+    Tg, sg = icp.icp_register(ctx, dev(prob.live_depth), dev(nanm), dev(nanm), prob.K, prob.imu_R,
+                              prob.init_pose, params)
+    assert sg["status"] == icp.TOO_FEW_CORR
+    # ragged size (tiles do not divide the levels) and 1 / 4 levels
+    for levels, W, H in [(1, 100, 70), (3, 168, 124), (4, 176, 136)]:
+        p = synth.config1_problem(5, W=W, H=H, f=130.0 * W / 160)
+        prm = icp.icp_params_default(levels=levels, iters=[10, 5, 4, 3][:levels])
+        Tg, sg, To, so = _register_both(ctx, p, prm)
+        ang, dt = pose_err(Tg, To)
+        assert ang < POSE_TOL and dt < POSE_TOL, (levels, W, H, ang, dt)
+    # zero iterations: pose is the IMU seed
+    prm = icp.icp_params_default(iters=(0, 0, 0))
+    Tg, sg = icp.icp_register(ctx, d, mv, mn, prob.K, prob.imu_R, prob.init_pose, prm)
+    assert np.array_equal(Tg[:3, :3], prob.imu_R) and sg["iters_total"] == 0
+
+
+def test_invalid_arguments(ctx):
+    prob = synth.config1_problem(0)
+    d, mv, mn = upload(prob)
+    with pytest.raises(icp.IcpError) as e:
+        icp.icp_register(ctx, d[:, :155].contiguous(), mv, mn, prob.K, prob.imu_R, prob.init_pose)
+    assert e.value.code == icp.EINVAL
+    for bad in [dict(levels=0), dict(levels=5), dict(dist_max=0.2), dict(lambda_mode=9), dict(lambda_c=-1.0),
+                dict(tile_px=(100, 0, 0))]:
+        with pytest.raises(icp.IcpError) as e:
+            icp.icp_register(ctx, d, mv, mn, prob.K, prob.imu_R, prob.init_pose, icp.icp_params_default(**bad))
+        assert e.value.code == icp.EINVAL, bad
+    small = icp.icp_ctx_create(0, hbm_budget_bytes=1 << 16)
+    with pytest.raises(icp.IcpError) as e:
+        icp.icp_register(small, d, mv, mn, prob.K, prob.imu_R, prob.init_pose)
+    assert e.value.code == icp.ENOMEM
