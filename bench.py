@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Benchmark of the tracking hot path on the Kinect-scale workload.
+
+Workload: a seeded synthetic 300-frame 640x480 room sequence (fx = fy = 525,
+Kinect depth noise and dropouts, IMU prior = truth + 0.5 deg), giving 299
+independent frame-to-model registrations, each a 3-level pyramid with
+{10,5,4} ICP iterations (finest first), FP32 maps with FP64 decisions.
+
+One step registers all 299 frames in one batched call (every kernel launch
+covers the tiles of all frames).  `value` is registrations per second over
+the timed steps with every input already resident in HBM.  Also reported:
+per-registration latency percentiles of the one-frame-per-call path, the
+roofline of the dominant kernel from HIP events recorded live on its stream,
+the pose error against the FP64 oracle on a sample of frames, and the oracle
+itself timed on the host as a CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
+BYTES_PER_PX_IT = 48           # live vertex+normal and model vertex+normal, FP32 x 3 each
+KERNEL_SOURCES = ("paper_1802_03980_amd/csrc/icp_kernels.hip", "paper_1802_03980_amd/csrc/icp_device.hpp",
+                  "paper_1802_03980_amd/csrc/icp_common.hpp")
+KERNEL_SYMBOL = {"pass1": "k_pass1", "pass2": "k_pass2"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kind):
+    """HBM bytes per pixel of `kind` from the committed counter summary, or
+    None when missing or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{KERNEL_SYMBOL[kind]}_vga299_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_px"])
+    except (KeyError, ValueError):
+        return None
+
+
+def load_or_make(seq, k, cache_dir):
+    """Registration k of the sequence, from the cache directory when present."""
+    if not cache_dir:
+        return seq.problem(k)
+    import synth
+    path = os.path.join(cache_dir, f"room{seq.seed}_{seq.n_frames}_{k:04d}.npz")
+    if os.path.exists(path):
+        z = np.load(path)
+        return synth.Problem(live_depth=z["d"], model_vtx=z["v"], model_nrm=z["n"], K=tuple(z["K"]),
+                             imu_R=z["R"], init_pose=z["T0"], T_gt=z["Tg"], name=f"room/{seq.seed}/{k + 1}")
+    p = seq.problem(k)
+    os.makedirs(cache_dir, exist_ok=True)
+    np.savez(path, d=p.live_depth, v=p.model_vtx, n=p.model_nrm, K=np.array(p.K), R=p.imu_R, T0=p.init_pose,
+             Tg=p.T_gt)
+    return p
+
+
+def rot_err(A, B):
+    R = A[:3, :3] @ B[:3, :3].T
+    s = 0.5 * np.linalg.norm([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]])
+    return math.atan2(s, 0.5 * (np.trace(R) - 1.0))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=300, help="sequence length (registrations = frames - 1)")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline and pose check")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-frame-per-call latency pass")
+    ap.add_argument("--cache-dir", default="", help="reuse generated frames stored here (created if missing)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU; the registrations shard by frame with no "
+              "communication, so runs on more than one GPU are not provided.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1802_03980_amd as icp
+    import synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    # ------------------------------------------------------------- inputs
+    log(f"generating the {args.frames}-frame 640x480 room sequence (seed {args.seed})")
+    seq = synth.RoomSequence(args.seed, n_frames=args.frames)
+    probs, items = [], []
+    t0 = time.time()
+    for k in range(len(seq)):
+        p = load_or_make(seq, k, args.cache_dir)
+        probs.append(p)
+        items.append(dict(live_depth=torch.from_numpy(p.live_depth).to(dev),
+                          model_vtx=torch.from_numpy(p.model_vtx).to(dev),
+                          model_nrm=torch.from_numpy(p.model_nrm).to(dev), K=p.K, imu_R=p.imu_R,
+                          init_pose=p.init_pose))
+        if (k + 1) % 50 == 0:
+            log(f"  {k + 1}/{len(seq)} frames ready ({time.time() - t0:.1f} s)")
+    n = len(items)
+    torch.cuda.synchronize()
+
+    ctx = icp.icp_ctx_create(0)
+    params = icp.icp_params_default()
+    px_it = sum((640 >> l) * (480 >> l) * params.iters[l] for l in range(params.levels))
+
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_calibration_mib} MiB done")
+        del a, b
+
+    # ------------------------------------------------------------- batched path
+    log(f"warmup: {args.warmup} batched steps of {n} registrations")
+    for _ in range(args.warmup):
+        icp.icp_register_batch(ctx, items, params)
+    torch.cuda.synchronize()
+    icp.icp_ctx_set_timing(ctx, True)
+    log(f"timed: {args.steps} batched steps")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    step_ms = []
+    results = None
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        results = icp.icp_register_batch(ctx, items, params)
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    timing = icp.icp_ctx_get_timing(ctx)
+    icp.icp_ctx_set_timing(ctx, False)
+    value = n * args.steps / t_total
+    log(f"batched: {value:.1f} registrations/s, {t_total / args.steps * 1e3:.2f} ms per step")
+
+    # ------------------------------------------------------------- plain path
+    lat = []
+    if not args.no_plain:
+        log("one-frame-per-call pass over the sequence")
+        for it in items:
+            ts = time.perf_counter()
+            icp.icp_register(ctx, it["live_depth"], it["model_vtx"], it["model_nrm"], it["K"], it["imu_R"],
+                             it["init_pose"], params)
+            lat.append((time.perf_counter() - ts) * 1e3)
+    lat = np.array(lat)
+
+    # ------------------------------------------------------------- roofline
+    kinds = {k: v for k, v in timing.items() if k in ("pass1", "pass2") and v["launches"] > 0}
+    dom = max(kinds, key=lambda k: kinds[k]["total_ms"])
+    d = kinds[dom]
+    avg_ms = d["total_ms"] / d["launches"]
+    bytes_per_launch = BYTES_PER_PX_IT * d["pixels"] / d["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    tr = read_traffic(dom)
+    roofline = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if tr is None else round(tr * d["pixels"] / d["launches"]),
+                "avg_launch_ms": round(avg_ms, 5), "launches": d["launches"],
+                "algorithmic_bytes_per_launch": round(bytes_per_launch)}
+    it_ms = sum(timing[k]["total_ms"] for k in ("pass1", "band", "pass2", "solve"))
+    iteration_gbs = BYTES_PER_PX_IT * timing["pass1"]["pixels"] / (it_ms * 1e-3) / 1e9
+    log(f"roofline {dom}: {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of 8 TB/s); "
+        f"whole iteration (all launches) {iteration_gbs:.0f} GB/s")
+
+    # ------------------------------------------------------------- CPU oracle
+    cpu = None
+    pose_err = None
+    if not args.no_cpu:
+        import oracle
+        log(f"CPU oracle sample (about {args.cpu_seconds:.0f} s, {oracle.num_threads()} threads)")
+        ts = time.perf_counter()
+        done = 0
+        errs = []
+        while done < n and (done < 2 or time.perf_counter() - ts < args.cpu_seconds):
+            Tref, _, _ = oracle.register_problem(probs[done])
+            Tg = results[done][0]
+            errs.append((rot_err(Tg, Tref), float(np.linalg.norm(Tg[:3, 3] - Tref[:3, 3]))))
+            done += 1
+        cpu_s = time.perf_counter() - ts
+        cpu = {"value": round(done / cpu_s, 3), "unit": "registrations/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": f"first {done} of {n} registrations of the same sequence, "
+                                           f"{cpu_s:.1f} s, FP64 C oracle with OpenMP over rows"}
+        errs = np.array(errs)
+        pose_err = {"frames_checked": done, "max_rad": float(errs[:, 0].max()), "max_m": float(errs[:, 1].max())}
+        log(f"oracle: {cpu['value']} reg/s; GPU vs oracle max error {pose_err['max_rad']:.2e} rad, "
+            f"{pose_err['max_m']:.2e} m")
+
+    out = {
+        "metric": "ICP registrations/s (VGA,3-level) + p50/p99 latency at <=1e-5 pose err",
+        "value": round(value, 2),
+        "unit": "registrations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_total / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 decisions, f32 maps and moments",
+        "data": "synthetic (seeded room sequence; no dataset)",
+        "config": {"workload": f"Kinect-scale room sequence, {n} frame-to-model registrations of 640x480, "
+                               "3 levels {10,5,4}, lambda 5, median filter",
+                   "registrations_per_step": n, "px_iterations_per_registration": px_it,
+                   "path": "batched (all frames per launch)"},
+        "latency_ms": None if lat.size == 0 else {
+            "path": "one frame per call (icp_register, synchronous)",
+            "p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
+            "registrations_per_s": round(lat.size / (lat.sum() * 1e-3), 2)},
+        "batch_latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
+                             "p99": round(float(np.percentile(step_ms, 99)), 3)},
+        "pose_err_vs_oracle": pose_err,
+        "roofline": roofline,
+        "iteration_roofline": {"achieved": round(iteration_gbs, 1), "unit": "GB/s",
+                               "frac": round(iteration_gbs / HBM_PEAK_GBS, 4),
+                               "note": "48 B per pixel-iteration over the time of all four launches of "
+                                       "each iteration"},
+        "kernel_ms": {k: round(v["total_ms"], 4) for k, v in timing.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

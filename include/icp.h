@@ -94,13 +94,17 @@ typedef struct {
     int32_t use_imu_seed;           /* 1: the initial rotation is imu_R (Sec. 3) */
     int32_t lambda_mode;            /* ICP_LAMBDA_* */
     double lambda_c;                /* c >= 0 (Eq. (4)/(5)) */
-    int32_t min_corr;               /* minimum kept pairs for a solve (>= 6) */
+    int32_t min_corr;               /* minimum kept pairs for a solve (>= 1) */
     double ill_cond_eps;            /* LDL^T pivot threshold relative to the max diagonal */
     int32_t converge_window;        /* 0: fixed cadence; k >= 1: a level stops once the median
                                        bin is unchanged on k successive iterations (Sec. 3.4) */
     int32_t reduce_mode;            /* 0: FP32 moment reduction */
-    int32_t tile_px[ICP_MAX_LEVELS];/* pixels per work-group tile per level (multiple of 256);
-                                       0 = chosen by the library */
+    int32_t pass_mode;              /* 0: single pass over the maps when the band edge falls in a
+                                       window around the previous iteration's edge (two passes
+                                       otherwise; needs band_beta >= 1 or no median filter);
+                                       1: always two passes */
+    int32_t tile_px[ICP_MAX_LEVELS];/* pixels per work-group tile per level (multiple of 1024,
+                                       at most 65536); 0 = chosen by the library */
 } icp_params;
 
 typedef struct {
@@ -165,7 +169,8 @@ size_t icp_workspace_bytes(int n, const int32_t* W, const int32_t* H, int levels
 /* Fill *p with the defaults: 3 levels, iterations {10,5,4}, dist_max 0.10 m,
    20 degree normal gate, band beta 1, median filter on, IMU seed on,
    lambda = 5 constant (the value of the paper's Freiburg runs, Sec. 5.2),
-   min_corr 6, ill_cond_eps 1e-12, no convergence stop, FP32 reduction. */
+   min_corr 6, ill_cond_eps 1e-12, no convergence stop, FP32 reduction,
+   single-pass mode, tiles chosen by the library. */
 void icp_params_default(icp_params* p);
 
 /* -------------------------------------------------------------- hot path */
@@ -198,6 +203,31 @@ int icp_register_async(icp_ctx* ctx, const float* live_depth, int W, int H, cons
    valid on return (synchronises `stream`). */
 int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params,
                        icp_result* results, void* stream);
+
+/* ------------------------------------------------------ kernel timing
+   Tracing for measurement: while enabled, every registration call records
+   HIP events on its own stream around each launch of the front end and of
+   the four launches of every iteration; durations are accumulated per kind
+   once the recorded work has completed (icp_ctx_get_timing waits for it). */
+
+#define ICP_TIME_FRONT_END 0 /* pyramids and vertex/normal maps */
+#define ICP_TIME_PASS1 1     /* association, gates, histogram (and single-pass moments) */
+#define ICP_TIME_BAND 2      /* per-problem median band (and single-pass solve) */
+#define ICP_TIME_PASS2 3     /* band filter and moment reduction */
+#define ICP_TIME_SOLVE 4     /* per-problem FP64 sum of partials, solve, update */
+#define ICP_TIME_KINDS 5
+
+typedef struct {
+    double total_ms;  /* summed launch durations */
+    int64_t launches; /* launches recorded */
+    int64_t pixels;   /* pixels the recorded launches covered (level pixels) */
+} icp_kernel_time;
+
+/* Switch tracing on (1) or off (0); both reset the accumulated times. */
+int icp_ctx_set_timing(icp_ctx* ctx, int enable);
+
+/* Accumulated times per kind into out[ICP_TIME_KINDS] (host). */
+int icp_ctx_get_timing(icp_ctx* ctx, icp_kernel_time* out);
 
 /* ------------------------------------------------------ stage access
    For parity testing of each step against an independent implementation.

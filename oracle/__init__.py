@@ -73,6 +73,7 @@ def lib():
         d = C.c_double
         i = C.c_int
         L.or_params_default.argtypes = [C.POINTER(Params)]
+        L.or_num_threads.restype = C.c_int
         L.or_level_intrinsics.argtypes = [P, i, P]
         L.or_depth_down.argtypes = [P, i, i, P]
         L.or_live_vn.argtypes = [P, i, i, P, P, P]
@@ -115,6 +116,10 @@ def default_params(**over):
         else:
             setattr(p, k, v)
     return p
+
+
+def num_threads():
+    return int(lib().or_num_threads())
 
 
 def level_intrinsics(K, level):

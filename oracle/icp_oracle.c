@@ -30,11 +30,22 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* Histogram of Sec. 3.2: OR_BINS bins of width 2^-13 m over [0, 0.125) m. */
 static const double BIN_W = 1.0 / 8192.0;
 
 static float f_nan(void) { return (float)NAN; }
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 void or_params_default(or_params* p) {
     memset(p, 0, sizeof(*p));

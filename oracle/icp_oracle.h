@@ -76,6 +76,8 @@ typedef struct {
 } or_iter_trace;
 
 void or_params_default(or_params* p);
+/* threads the per-pixel loops use (OpenMP) */
+int or_num_threads(void);
 void or_level_intrinsics(const double K0[4], int level, double Kl[4]);
 
 /* live front end */

@@ -30,7 +30,8 @@ PX_INVALID_LIVE, PX_BEHIND, PX_OUTSIDE, PX_INVALID_MODEL, PX_FAR, PX_ANGLE, PX_G
 EXPORTS = (
     "icp_abi_version", "icp_strerror", "icp_last_error", "icp_ctx_create", "icp_ctx_destroy",
     "icp_ctx_workspace_bytes", "icp_workspace_bytes", "icp_params_default", "icp_register",
-    "icp_register_async", "icp_register_batch", "icp_stage_prepare", "icp_stage_level",
+    "icp_register_async", "icp_register_batch", "icp_ctx_set_timing", "icp_ctx_get_timing",
+    "icp_stage_prepare", "icp_stage_level",
     "icp_stage_associate", "icp_stage_moments", "icp_stage_solve",
 )
 
@@ -51,7 +52,7 @@ class icp_params(C.Structure):
         ("cos_angle_max", C.c_double), ("band_beta", C.c_double), ("use_median_filter", C.c_int32),
         ("use_imu_seed", C.c_int32), ("lambda_mode", C.c_int32), ("lambda_c", C.c_double),
         ("min_corr", C.c_int32), ("ill_cond_eps", C.c_double), ("converge_window", C.c_int32),
-        ("reduce_mode", C.c_int32), ("tile_px", C.c_int32 * MAX_LEVELS),
+        ("reduce_mode", C.c_int32), ("pass_mode", C.c_int32), ("tile_px", C.c_int32 * MAX_LEVELS),
     ]
 
 
@@ -68,6 +69,14 @@ class icp_problem(C.Structure):
     _fields_ = [("live_depth", C.c_void_p), ("model_vtx", C.c_void_p), ("model_nrm", C.c_void_p),
                 ("W", C.c_int32), ("H", C.c_int32), ("K", icp_intrinsics), ("imu_R", C.c_double * 9),
                 ("init_pose", C.c_double * 16)]
+
+
+class icp_kernel_time(C.Structure):
+    _fields_ = [("total_ms", C.c_double), ("launches", C.c_int64), ("pixels", C.c_int64)]
+
+
+TIME_FRONT_END, TIME_PASS1, TIME_BAND, TIME_PASS2, TIME_SOLVE = range(5)
+TIME_KINDS = 5
 
 
 class icp_result(C.Structure):
@@ -101,6 +110,8 @@ def lib():
             "icp_register_async": (I, [P, P, I, I, P, P, C.POINTER(icp_intrinsics), P, P,
                                        C.POINTER(icp_params), P, P]),
             "icp_register_batch": (I, [P, I, P, C.POINTER(icp_params), P, P]),
+            "icp_ctx_set_timing": (I, [P, I]),
+            "icp_ctx_get_timing": (I, [P, P]),
             "icp_stage_prepare": (I, [P, P, I, I, P, P, C.POINTER(icp_intrinsics), I, P]),
             "icp_stage_level": (I, [P, I, P, P, P, P, P, P]),
             "icp_stage_associate": (I, [P, I, P, C.POINTER(icp_params), P, P, P, P, P]),
@@ -273,6 +284,19 @@ def icp_register_batch(ctx, problems, params=None, stream=None):
                                   _stream(stream))
     _check(ctx, rc)
     return [(np.array(r.pose[:]).reshape(4, 4), stats_to_dict(r.stats, p.levels)) for r in res]
+
+
+def icp_ctx_set_timing(ctx, enable):
+    _check(ctx, lib().icp_ctx_set_timing(ctx.handle, 1 if enable else 0))
+
+
+def icp_ctx_get_timing(ctx):
+    """{kind: dict(total_ms, launches, pixels)} per kernel kind."""
+    arr = (icp_kernel_time * TIME_KINDS)()
+    _check(ctx, lib().icp_ctx_get_timing(ctx.handle, C.cast(arr, C.c_void_p)))
+    names = ("front_end", "pass1", "band", "pass2", "solve")
+    return {names[k]: dict(total_ms=arr[k].total_ms, launches=arr[k].launches, pixels=arr[k].pixels)
+            for k in range(TIME_KINDS)}
 
 
 # ---------------------------------------------------------------- stage access

@@ -32,6 +32,16 @@ struct icp_ctx {
     int tiles[ICP_MAX_LEVELS] = {};
     ProbState* d_state = nullptr;
     double* d_scratch = nullptr;
+    // kernel timing
+    struct EvRec {
+        int kind;
+        hipEvent_t a, b;
+        int64_t px;
+    };
+    bool timing = false;
+    std::vector<EvRec> pending;
+    std::vector<hipEvent_t> ev_pool;
+    icp_kernel_time times[ICP_TIME_KINDS] = {};
 };
 
 namespace {
@@ -63,8 +73,8 @@ int check_params(icp_ctx* ctx, const icp_params* p) {
     for (int l = 0; l < p->levels; ++l) {
         if (p->iters[l] < 0 || p->iters[l] > 100000) return fail(ctx, ICP_EINVAL, "iters out of range");
         const int t = p->tile_px[l];
-        if (t != 0 && (t < ICP_WG || t > 65536 || t % ICP_WG != 0))
-            return fail(ctx, ICP_EINVAL, "tile_px must be 0 or a multiple of 256 in [256, 65536]");
+        if (t != 0 && (t < ICP_TILE_QUANTUM || t > 65536 || t % ICP_TILE_QUANTUM != 0))
+            return fail(ctx, ICP_EINVAL, "tile_px must be 0 or a multiple of 1024 in [1024, 65536]");
     }
     if (!(p->dist_max > 0.0 && p->dist_max <= 0.125)) return fail(ctx, ICP_EINVAL, "dist_max must be in (0, 0.125]");
     if (!(p->cos_angle_max >= -1.0 && p->cos_angle_max <= 1.0))
@@ -77,6 +87,7 @@ int check_params(icp_ctx* ctx, const icp_params* p) {
     if (!(p->ill_cond_eps >= 0.0)) return fail(ctx, ICP_EINVAL, "ill_cond_eps must be >= 0");
     if (p->converge_window < 0) return fail(ctx, ICP_EINVAL, "converge_window must be >= 0");
     if (p->reduce_mode != 0) return fail(ctx, ICP_EINVAL, "unknown reduce_mode");
+    if (p->pass_mode != 0 && p->pass_mode != 1) return fail(ctx, ICP_EINVAL, "pass_mode must be 0 or 1");
     return ICP_OK;
 }
 
@@ -97,13 +108,13 @@ int check_problem(icp_ctx* ctx, const icp_problem& q, int levels) {
     return ICP_OK;
 }
 
-// Tile size: aim for ~2048 work-groups per pass over the batch (8 per CU).
+// Tile size: aim for ~8192 work-groups per pass over the batch (32 per CU).
 int pick_tile(int npx, int nprob, int req) {
     if (req > 0) return req;
-    const long target = std::max(1L, 2048L / std::max(1, nprob));
+    const long target = std::max(1L, 8192L / std::max(1, nprob));
     long t = (npx + target - 1) / target;
-    t = (t + ICP_WG - 1) / ICP_WG * ICP_WG;
-    return (int)std::min(16384L, std::max((long)ICP_WG, t));
+    t = (t + ICP_TILE_QUANTUM - 1) / ICP_TILE_QUANTUM * ICP_TILE_QUANTUM;
+    return (int)std::min(16384L, std::max((long)ICP_TILE_QUANTUM, t));
 }
 
 // Workspace layout of a batch; offsets are relative to the workspace base.
@@ -141,19 +152,22 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
             L.W = W[p] >> l;
             L.H = H[p] >> l;
             L.npx = L.W * L.H;
+            L.ps = (L.npx + ICP_PLANE_ALIGN - 1) / ICP_PLANE_ALIGN * ICP_PLANE_ALIGN;
             L.tile_px = pick_tile(L.npx, n, tile_req ? tile_req[l] : 0);
             L.n_tiles = (L.npx + L.tile_px - 1) / L.tile_px;
             L.tile_base = P.tiles[l];
             P.tiles[l] += L.n_tiles;
             P.max_npx[l] = std::max(P.max_npx[l], L.npx);
             for (int t = 0; t < L.n_tiles; ++t) P.owner[l].push_back(p);
-            const size_t S = (size_t)L.npx * sizeof(float);
+            const size_t S = (size_t)L.ps * sizeof(float);
             L.Dw = l > 0 ? reinterpret_cast<float*>(take(S)) : nullptr;
             L.LV = reinterpret_cast<float*>(take(3 * S));
             L.LN = reinterpret_cast<float*>(take(3 * S));
             L.MV = reinterpret_cast<float*>(take(3 * S));
             L.MN = reinterpret_cast<float*>(take(3 * S));
             L.part = reinterpret_cast<float*>(take((size_t)L.n_tiles * ICP_PART_STRIDE * sizeof(float)));
+            L.part1 = reinterpret_cast<float*>(
+                take((size_t)L.n_tiles * ICP_WIN_SLOTS * ICP_PART_STRIDE * sizeof(float)));
         }
     }
     for (int l = 0; l < levels; ++l) P.off_owner[l] = take(sizeof(int) * std::max(1, P.tiles[l]));
@@ -246,6 +260,7 @@ int stage_batch(icp_ctx* ctx, int n, const icp_problem* probs, int levels, const
             L.MV = rebase(L.MV, base);
             L.MN = rebase(L.MN, base);
             L.part = rebase(L.part, base);
+            L.part1 = rebase(L.part1, base);
         }
         d.model_vtx = q.model_vtx;
         d.model_nrm = q.model_nrm;
@@ -273,18 +288,86 @@ int stage_batch(icp_ctx* ctx, int n, const icp_problem* probs, int levels, const
     return ICP_OK;
 }
 
+hipEvent_t take_event(icp_ctx* ctx) {
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Start a timed region on stream s (no-op unless timing is on).
+int time_begin(icp_ctx* ctx, hipStream_t s, icp_ctx::EvRec& r, int kind, int64_t px) {
+    r.kind = -1;
+    if (!ctx->timing) return ICP_OK;
+    r.a = take_event(ctx);
+    r.b = take_event(ctx);
+    if (!r.a || !r.b) return fail(ctx, ICP_EDEVICE, "hipEventCreate failed");
+    HIP_TRY(ctx, hipEventRecord(r.a, s));
+    r.kind = kind;
+    r.px = px;
+    return ICP_OK;
+}
+
+int time_end(icp_ctx* ctx, hipStream_t s, icp_ctx::EvRec& r) {
+    if (r.kind < 0) return ICP_OK;
+    HIP_TRY(ctx, hipEventRecord(r.b, s));
+    ctx->pending.push_back(r);
+    return ICP_OK;
+}
+
+int resolve_timing(icp_ctx* ctx) {
+    for (auto& r : ctx->pending) {
+        HIP_TRY(ctx, hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, r.a, r.b));
+        icp_kernel_time& t = ctx->times[r.kind];
+        t.total_ms += ms;
+        t.launches += 1;
+        t.pixels += r.px;
+        ctx->ev_pool.push_back(r.a);
+        ctx->ev_pool.push_back(r.b);
+    }
+    ctx->pending.clear();
+    return ICP_OK;
+}
+
 // Whole registration of a staged batch; results into `res_dev` (device).
 int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* res_dev, hipStream_t s) {
     char* base = static_cast<char*>(ctx->ws);
     const ProbDesc* d_desc = reinterpret_cast<const ProbDesc*>(base + P.off_desc);
     const KParams kp = kparams(prm);
+    int rc;
+    icp_ctx::EvRec r;
     HIP_TRY(ctx, icpk::launch_init(d_desc, n, prm->use_imu_seed, s));
+    int64_t px0 = 0;
+    for (int p = 0; p < n; ++p) px0 += P.desc[p].lv[0].npx;
+    if ((rc = time_begin(ctx, s, r, ICP_TIME_FRONT_END, px0))) return rc;
     HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, P.max_npx, s));
+    if ((rc = time_end(ctx, s, r))) return rc;
+    // single pass needs the band's lower edge at bin 0
+    const int fused = prm->pass_mode == 0 && (!prm->use_median_filter || prm->band_beta >= 1.0) ? 1 : 0;
     for (int l = prm->levels - 1; l >= 0; --l) {
         const int* owner = reinterpret_cast<const int*>(base + P.off_owner[l]);
+        int64_t px = 0;
+        for (int p = 0; p < n; ++p) px += P.desc[p].lv[l].npx;
         for (int it = 0; it < prm->iters[l]; ++it) {
             IterCtl ctl{l, it, it == prm->iters[l] - 1 ? 1 : 0, 0};
-            HIP_TRY(ctx, icpk::launch_iteration(d_desc, owner, P.tiles[l], ctl, kp, s));
+            if ((rc = time_begin(ctx, s, r, ICP_TIME_PASS1, px))) return rc;
+            HIP_TRY(ctx, icpk::launch_pass1(d_desc, owner, P.tiles[l], ctl, kp, fused, s));
+            if ((rc = time_end(ctx, s, r))) return rc;
+            if ((rc = time_begin(ctx, s, r, ICP_TIME_BAND, 0))) return rc;
+            HIP_TRY(ctx, icpk::launch_band(d_desc, n, ctl, kp, fused, s));
+            if ((rc = time_end(ctx, s, r))) return rc;
+            if ((rc = time_begin(ctx, s, r, ICP_TIME_PASS2, px))) return rc;
+            HIP_TRY(ctx, icpk::launch_pass2(d_desc, owner, P.tiles[l], ctl, kp, s));
+            if ((rc = time_end(ctx, s, r))) return rc;
+            if ((rc = time_begin(ctx, s, r, ICP_TIME_SOLVE, 0))) return rc;
+            HIP_TRY(ctx, icpk::launch_solve(d_desc, n, ctl, kp, s));
+            if ((rc = time_end(ctx, s, r))) return rc;
         }
     }
     HIP_TRY(ctx, icpk::launch_finalize(d_desc, n, res_dev, s));
@@ -371,7 +454,31 @@ void icp_ctx_destroy(icp_ctx* ctx) {
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->hstage) (void)hipHostFree(ctx->hstage);
     if (ctx->ev_upload) (void)hipEventDestroy(ctx->ev_upload);
+    for (auto& r : ctx->pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
+}
+
+int icp_ctx_set_timing(icp_ctx* ctx, int enable) {
+    if (!ctx) return ICP_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    int rc = resolve_timing(ctx);
+    if (rc) return rc;
+    ctx->timing = enable != 0;
+    for (auto& t : ctx->times) t = icp_kernel_time{};
+    return ICP_OK;
+}
+
+int icp_ctx_get_timing(icp_ctx* ctx, icp_kernel_time* out) {
+    if (!ctx || !out) return ICP_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    int rc = resolve_timing(ctx);
+    if (rc) return rc;
+    for (int k = 0; k < ICP_TIME_KINDS; ++k) out[k] = ctx->times[k];
+    return ICP_OK;
 }
 
 size_t icp_ctx_workspace_bytes(const icp_ctx* ctx) { return ctx ? ctx->ws_cap : 0; }
@@ -401,7 +508,7 @@ int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_
     if ((rc = run_batch(ctx, n, params, P, d_res, s))) return rc;
     HIP_TRY(ctx, hipMemcpyAsync(results, d_res, sizeof(icp_result) * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    return ICP_OK;
+    return resolve_timing(ctx);
 }
 
 int icp_register(icp_ctx* ctx, const float* live_depth, int W, int H, const float* model_vtx,
@@ -482,10 +589,14 @@ int icp_stage_level(icp_ctx* ctx, int level, float* depth, float* live_vtx, floa
     const LevelDesc& L = ctx->stage_desc.lv[level];
     const size_t S = (size_t)L.npx * sizeof(float);
     if (depth) HIP_TRY(ctx, hipMemcpyAsync(depth, L.D, S, hipMemcpyDeviceToDevice, s));
-    if (live_vtx) HIP_TRY(ctx, hipMemcpyAsync(live_vtx, L.LV, 3 * S, hipMemcpyDeviceToDevice, s));
-    if (live_nrm) HIP_TRY(ctx, hipMemcpyAsync(live_nrm, L.LN, 3 * S, hipMemcpyDeviceToDevice, s));
-    if (model_vtx) HIP_TRY(ctx, hipMemcpyAsync(model_vtx, L.MV, 3 * S, hipMemcpyDeviceToDevice, s));
-    if (model_nrm) HIP_TRY(ctx, hipMemcpyAsync(model_nrm, L.MN, 3 * S, hipMemcpyDeviceToDevice, s));
+    float* dst[4] = {live_vtx, live_nrm, model_vtx, model_nrm};
+    const float* src[4] = {L.LV, L.LN, L.MV, L.MN};
+    for (int m = 0; m < 4; ++m) {
+        if (!dst[m]) continue;
+        for (int c = 0; c < 3; ++c)  // planes are ps floats apart in the workspace, packed in the output
+            HIP_TRY(ctx, hipMemcpyAsync(dst[m] + (size_t)c * L.npx, src[m] + (size_t)c * L.ps, S,
+                                        hipMemcpyDeviceToDevice, s));
+    }
     HIP_TRY(ctx, hipStreamSynchronize(s));
     return ICP_OK;
 }

@@ -2,12 +2,13 @@
 //
 // HBM layout per problem (all float32, level l has W_l x H_l = (W>>l) x (H>>l)):
 //   live depth D_l (level 0 is the caller's buffer), live vertex LV_l and
-//   normal LN_l, model vertex MV_l and normal MN_l, each as three planes of
-//   W_l*H_l floats (x plane, y plane, z plane) so that every per-pixel read is
-//   a unit-stride 4-byte stream across a wavefront.  Invalid entries are NaN
-//   (maps) or 0 (depth).  Per level a problem also owns one 32-float partial
-//   per work-group tile.  The small per-problem state (pose, histogram,
-//   band, tickets, statistics) lives in one ProbState.
+//   normal LN_l, model vertex MV_l and normal MN_l, each as three planes (x
+//   plane, y plane, z plane) of W_l*H_l floats, consecutive planes `ps` floats
+//   apart (W_l*H_l rounded up to 64, so every plane starts on a 256-byte
+//   boundary and a thread can read four consecutive pixels as one 16-byte
+//   load).  Invalid entries are NaN (maps) or 0 (depth).  Per level a problem
+//   also owns one 32-float partial per work-group tile.  The small per-problem
+//   state (pose, histogram, band, tickets, statistics) lives in one ProbState.
 #pragma once
 
 #include <stdint.h>
@@ -18,10 +19,16 @@
 #define ICP_WAVES (ICP_WG / 64)
 #define ICP_PART_STRIDE 32      // floats per tile partial: 28 moments, count, pad
 #define ICP_NMOM 28
+#define ICP_PX_PER_THREAD 4     // consecutive pixels per thread and round in the passes
+#define ICP_TILE_QUANTUM (ICP_WG * ICP_PX_PER_THREAD)
+#define ICP_PLANE_ALIGN 64      // floats
+#define ICP_WIN 64              // bins of the predicted band-edge window (single-pass mode)
+#define ICP_WIN_SLOTS (ICP_WIN + 1)  // slot 0: rows below the window; slots 1..: one per window bin
 
 struct LevelDesc {
     int32_t W, H, npx;          // size of the level, npx = W*H
-    int32_t tile_px;            // pixels per tile (multiple of ICP_WG)
+    int32_t ps;                 // plane stride in floats (npx rounded up to ICP_PLANE_ALIGN)
+    int32_t tile_px;            // pixels per tile (multiple of ICP_TILE_QUANTUM)
     int32_t n_tiles;            // ceil(npx / tile_px)
     int32_t tile_base;          // first flat tile of this problem at this level
     double fx, fy, cx, cy;      // intrinsics of the level
@@ -31,7 +38,8 @@ struct LevelDesc {
     float* LN;                  // live normal
     float* MV;                  // model vertex
     float* MN;                  // model normal
-    float* part;                // n_tiles * ICP_PART_STRIDE
+    float* part;                // pass-2 partials: n_tiles * ICP_PART_STRIDE
+    float* part1;               // single-pass partials: n_tiles * ICP_WIN_SLOTS * ICP_PART_STRIDE
 };
 
 struct ProbState {
@@ -43,7 +51,8 @@ struct ProbState {
     uint32_t hist[ICP_HIST_BINS];
     uint32_t N;                 // gated pairs of the current iteration
     int32_t k_med, k_lo, k_hi;  // median bin and kept band of the current iteration
-    uint32_t ticket1, ticket2;  // arrival counters of the two passes
+    int32_t pred_hi;            // band upper edge predicted for the next iteration (-1: none)
+    int32_t fused_done;         // this iteration was completed from the single-pass partials
     int32_t level_done;         // the current level has ended (status or convergence)
     int32_t settled;            // successive iterations with an unchanged median
     int32_t last_kmed;

@@ -46,76 +46,185 @@ __device__ __forceinline__ int dist_bin(double d2) {
     return k;
 }
 
+#define ICP_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ const ICP_GLOBAL T* gconst(const T* p) {
+    return (const ICP_GLOBAL T*)p;
+}
+
+// A value that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 struct Pose {
     double r[9];
     double t[3];
 };
 
-struct Match {
-    double p[3];   // live point moved by the current pose, p' = R p + t
-    double d[3];   // q - p'
-    float n[3];    // model normal n_q
-    int bin;
+__device__ __forceinline__ Pose load_pose(const ProbState* st) {
+    Pose T;
+    const ICP_GLOBAL double* R = gconst(st->R);
+    const ICP_GLOBAL double* t = gconst(st->t);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) T.r[k] = uniform(R[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) T.t[k] = uniform(t[k]);
+    return T;
+}
+
+// The maps and geometry of one level held in registers for a pass.
+struct Lvl {
+    const ICP_GLOBAL float* LV;
+    const ICP_GLOBAL float* LN;
+    const ICP_GLOBAL float* MV;
+    const ICP_GLOBAL float* MN;
+    int W, npx, ps;
+    double fx, fy, cx, cy, umax, vmax;
 };
 
-// Projective association of live pixel i (paper Sec. 3): move the live point
-// by the current pose, project it into the model image, round to the nearest
-// pixel, fetch the model point and normal there, then gate on validity,
-// distance and normal agreement.  Returns an ICP_PX_* code.
-__device__ __forceinline__ int associate(const LevelDesc& L, int i, const Pose& T, double d2max, double cos_max,
-                                         Match& m) {
-    const int S = L.npx;
-    const float vx = L.LV[i], vy = L.LV[S + i], vz = L.LV[2 * S + i];
-    const float nx = L.LN[i], ny = L.LN[S + i], nz = L.LN[2 * S + i];
-    if (!(fin(vx) && fin(vy) && fin(vz) && fin(nx) && fin(ny) && fin(nz))) return kInvalidLive;
-    const double px = vx, py = vy, pz = vz;
+__device__ __forceinline__ Lvl load_level(const LevelDesc& L) {
+    Lvl v;
+    v.LV = gconst(L.LV);
+    v.LN = gconst(L.LN);
+    v.MV = gconst(L.MV);
+    v.MN = gconst(L.MN);
+    v.W = L.W;
+    v.npx = L.npx;
+    v.ps = L.ps;
+    v.fx = L.fx;
+    v.fy = L.fy;
+    v.cx = L.cx;
+    v.cy = L.cy;
+    v.umax = (double)(L.W - 1);
+    v.vmax = (double)(L.H - 1);
+    return v;
+}
+
+// Association results of four consecutive pixels; the FP32 row inputs
+// (p', q - p', n_q) are filled for gated pixels only.
+struct Quad {
+    int code[4];
+    int bin[4];
+    float p[4][3];
+    float d[4][3];
+    float n[4][3];
+};
+
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ vf4 ld4(const ICP_GLOBAL float* p) { return *(const ICP_GLOBAL vf4*)p; }
+
+// Projective association of live pixels i..i+3 (i a multiple of 4, paper
+// Sec. 3): move each live point by the current pose, project it into the
+// model image, round to the nearest pixel, fetch the model point and normal
+// there, then gate on validity, distance and normal agreement.  The live
+// vertices arrive as one 16-byte load per plane; the model gathers of the
+// four pixels and the live normals are issued together.
+__device__ __forceinline__ void associate4(const Lvl& L, int i, const Pose& T, double d2max, double cos_max,
+                                           Quad& o) {
+    const int S = L.ps;
+    const vf4 vx = ld4(L.LV + i), vy = ld4(L.LV + S + i), vz = ld4(L.LV + 2 * S + i);
+    const float V[4][3] = {{vx.x, vy.x, vz.x}, {vx.y, vy.y, vz.y}, {vx.z, vy.z, vz.z}, {vx.w, vy.w, vz.w}};
+    double P[4][3];
+    int j[4];
+    bool vok[4];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) m.p[k] = ((T.r[3 * k] * px + T.r[3 * k + 1] * py) + T.r[3 * k + 2] * pz) + T.t[k];
-    if (!(m.p[2] > 0.0)) return kBehind;
-    const double uf = L.fx * (m.p[0] / m.p[2]) + L.cx;
-    const double vf = L.fy * (m.p[1] / m.p[2]) + L.cy;
-    const double uu = floor(uf + 0.5), vv = floor(vf + 0.5);
-    if (!(uu >= 0.0 && uu <= (double)(L.W - 1) && vv >= 0.0 && vv <= (double)(L.H - 1))) return kOutside;
-    const int j = (int)vv * L.W + (int)uu;
-    const float qx = L.MV[j], qy = L.MV[S + j], qz = L.MV[2 * S + j];
-    const float mx = L.MN[j], my = L.MN[S + j], mz = L.MN[2 * S + j];
-    if (!(fin(qx) && fin(qy) && fin(qz) && fin(mx) && fin(my) && fin(mz))) return kInvalidModel;
-    m.d[0] = (double)qx - m.p[0];
-    m.d[1] = (double)qy - m.p[1];
-    m.d[2] = (double)qz - m.p[2];
-    const double d2 = (m.d[0] * m.d[0] + m.d[1] * m.d[1]) + m.d[2] * m.d[2];
-    if (!(d2 < d2max)) return kFar;
-    const double nxd = nx, nyd = ny, nzd = nz;
-    double c = 0.0;
-    {
+    for (int k = 0; k < 4; ++k) {
+        o.code[k] = kInvalidLive;
+        o.bin[k] = -1;
+        j[k] = -1;
+        P[k][0] = P[k][1] = P[k][2] = 0.0;
+        vok[k] = i + k < L.npx && fin(V[k][0]) && fin(V[k][1]) && fin(V[k][2]);
+        if (vok[k]) {
+            const double px = V[k][0], py = V[k][1], pz = V[k][2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                P[k][c] = ((T.r[3 * c] * px + T.r[3 * c + 1] * py) + T.r[3 * c + 2] * pz) + T.t[c];
+            if (!(P[k][2] > 0.0)) {
+                o.code[k] = kBehind;
+            } else {
+                const double uf = L.fx * (P[k][0] / P[k][2]) + L.cx;
+                const double vf = L.fy * (P[k][1] / P[k][2]) + L.cy;
+                const double uu = floor(uf + 0.5), vv = floor(vf + 0.5);
+                if (!(uu >= 0.0 && uu <= L.umax && vv >= 0.0 && vv <= L.vmax)) o.code[k] = kOutside;
+                else j[k] = (int)vv * L.W + (int)uu;
+            }
+        }
+    }
+    const vf4 nx = ld4(L.LN + i), ny = ld4(L.LN + S + i), nz = ld4(L.LN + 2 * S + i);
+    const float N[4][3] = {{nx.x, ny.x, nz.x}, {nx.y, ny.y, nz.y}, {nx.z, ny.z, nz.z}, {nx.w, ny.w, nz.w}};
+    float Q[4][3], M[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int jj = j[k] < 0 ? 0 : j[k];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Q[k][c] = j[k] < 0 ? 0.0f : L.MV[c * S + jj];
+            M[k][c] = j[k] < 0 ? 0.0f : L.MN[c * S + jj];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (!vok[k]) continue;
+        // a live pixel without a normal is invalid whatever its projection
+        if (!(fin(N[k][0]) && fin(N[k][1]) && fin(N[k][2]))) {
+            o.code[k] = kInvalidLive;
+            continue;
+        }
+        if (j[k] < 0) continue;
+        if (!(fin(Q[k][0]) && fin(Q[k][1]) && fin(Q[k][2]) && fin(M[k][0]) && fin(M[k][1]) && fin(M[k][2]))) {
+            o.code[k] = kInvalidModel;
+            continue;
+        }
+        const double d0 = (double)Q[k][0] - P[k][0];
+        const double d1 = (double)Q[k][1] - P[k][1];
+        const double d2 = (double)Q[k][2] - P[k][2];
+        const double dd = (d0 * d0 + d1 * d1) + d2 * d2;
+        if (!(dd < d2max)) {
+            o.code[k] = kFar;
+            continue;
+        }
+        const double nxd = N[k][0], nyd = N[k][1], nzd = N[k][2];
         const double r0 = (T.r[0] * nxd + T.r[1] * nyd) + T.r[2] * nzd;
         const double r1 = (T.r[3] * nxd + T.r[4] * nyd) + T.r[5] * nzd;
         const double r2 = (T.r[6] * nxd + T.r[7] * nyd) + T.r[8] * nzd;
-        c = (r0 * (double)mx + r1 * (double)my) + r2 * (double)mz;
+        const double cv = (r0 * (double)M[k][0] + r1 * (double)M[k][1]) + r2 * (double)M[k][2];
+        if (!(cv >= cos_max)) {
+            o.code[k] = kAngle;
+            continue;
+        }
+        o.code[k] = kGated;
+        o.bin[k] = dist_bin(dd);
+        o.p[k][0] = (float)P[k][0];
+        o.p[k][1] = (float)P[k][1];
+        o.p[k][2] = (float)P[k][2];
+        o.d[k][0] = (float)d0;
+        o.d[k][1] = (float)d1;
+        o.d[k][2] = (float)d2;
+        o.n[k][0] = M[k][0];
+        o.n[k][1] = M[k][1];
+        o.n[k][2] = M[k][2];
     }
-    if (!(c >= cos_max)) return kAngle;
-    m.n[0] = mx;
-    m.n[1] = my;
-    m.n[2] = mz;
-    m.bin = dist_bin(d2);
-    return kGated;
 }
 
 // The row of Eq. (3) for a kept pair and its 28 products.  With the
 // small-angle transform of Eq. (2) applied to p', the residual of Eq. (1) is
 // n . (p' + w x p' + tau - q) = a . x - b, a = [p' x n, n], b = n . (q - p').
-__device__ __forceinline__ void accumulate_row(const Match& m, float (&acc)[ICP_NMOM]) {
-    const float px = (float)m.p[0], py = (float)m.p[1], pz = (float)m.p[2];
-    const float dx = (float)m.d[0], dy = (float)m.d[1], dz = (float)m.d[2];
-    const float nx = m.n[0], ny = m.n[1], nz = m.n[2];
+__device__ __forceinline__ void accumulate_row(const float (&p)[3], const float (&d)[3], const float (&n)[3],
+                                               float (&acc)[ICP_NMOM]) {
     float r[7];
-    r[0] = py * nz - pz * ny;
-    r[1] = pz * nx - px * nz;
-    r[2] = px * ny - py * nx;
-    r[3] = nx;
-    r[4] = ny;
-    r[5] = nz;
-    r[6] = __builtin_fmaf(nz, dz, __builtin_fmaf(ny, dy, nx * dx));
+    r[0] = p[1] * n[2] - p[2] * n[1];
+    r[1] = p[2] * n[0] - p[0] * n[2];
+    r[2] = p[0] * n[1] - p[1] * n[0];
+    r[3] = n[0];
+    r[4] = n[1];
+    r[5] = n[2];
+    r[6] = __builtin_fmaf(n[2], d[2], __builtin_fmaf(n[1], d[1], n[0] * d[0]));
     int k = 0;
 #pragma unroll
     for (int a = 0; a < 7; ++a) {

@@ -1,14 +1,15 @@
 // gfx950 kernels of the ICP tracking hot path.
 //
 // Launch shapes: work-groups of 256 threads (four wave64).  Front-end kernels
-// use one thread per output pixel with grid.y = problem.  The two iteration
-// passes use one work-group per tile of `tile_px` consecutive pixels of one
-// problem; a flat tile index spans every problem of the batch and `owner`
-// maps it to its problem.  Each pass ends with an arrival ticket per problem:
-// the last work-group of a problem runs that problem's epilogue (the median
-// band after pass 1, the FP64 solve and pose update after pass 2), so an
-// iteration is two launches whatever the batch size and the pose never leaves
-// the device.
+// use one thread per output pixel with grid.y = problem.  The two pixel passes
+// use one work-group per tile of `tile_px` consecutive pixels of one problem
+// (four consecutive pixels per thread and round); a flat tile index spans every
+// problem of the batch and `owner` maps it to its problem.  The per-problem
+// steps (median band; FP64 reduction of the tile partials, solve and pose
+// update) run in their own launches with one work-group per problem, so no
+// kernel needs a device-scope fence or an arrival counter: data crosses
+// work-groups only at kernel boundaries.  One ICP iteration of a whole batch
+// is four launches and the pose never leaves the device.
 #include <hip/hip_runtime.h>
 
 #include "icp_device.hpp"
@@ -19,16 +20,6 @@ namespace icpk {
 // ------------------------------------------------------------------ helpers
 
 __device__ __forceinline__ bool depth_ok(float z) { return __builtin_isfinite(z) && z > 0.0f; }
-
-template <typename T>
-__device__ __forceinline__ T ld_agent(const T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <typename T>
-__device__ __forceinline__ void st_agent(T* p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // ------------------------------------------------------------------ init
 
@@ -49,8 +40,8 @@ __global__ __launch_bounds__(ICP_WG) void k_init(const ProbDesc* __restrict__ pr
         st->k_med = -1;
         st->k_lo = 0;
         st->k_hi = -1;
-        st->ticket1 = 0;
-        st->ticket2 = 0;
+        st->pred_hi = -1;
+        st->fused_done = 0;
         st->level_done = 0;
         st->settled = 0;
         st->last_kmed = -2;
@@ -106,7 +97,7 @@ __global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__
     const LevelDesc& L = probs[blockIdx.y].lv[level];
     const int i = blockIdx.x * ICP_WG + threadIdx.x;
     if (i >= L.npx) return;
-    const int S = L.npx;
+    const int S = L.ps;
     const int u = i % L.W, v = i / L.W;
     const float qnan = __builtin_nanf("");
     float p[3] = {qnan, qnan, qnan};
@@ -153,7 +144,7 @@ __global__ __launch_bounds__(ICP_WG) void k_model_l0(const ProbDesc* __restrict_
     const LevelDesc& L = P.lv[0];
     const int i = blockIdx.x * ICP_WG + threadIdx.x;
     if (i >= L.npx) return;
-    const int S = L.npx;
+    const int S = L.ps;
     float v[3], n[3];
     bool ok = true;
     for (int k = 0; k < 3; ++k) {
@@ -176,7 +167,7 @@ __global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restric
     const LevelDesc& C = P.lv[level];
     const int i = blockIdx.x * ICP_WG + threadIdx.x;
     if (i >= C.npx) return;
-    const int SF = F.npx, SC = C.npx;
+    const int SF = F.ps, SC = C.ps;
     const int u = i % C.W, v = i / C.W;
     const int ch[4] = {(2 * v) * F.W + 2 * u, (2 * v) * F.W + 2 * u + 1, (2 * v + 1) * F.W + 2 * u,
                        (2 * v + 1) * F.W + 2 * u + 1};
@@ -209,27 +200,187 @@ __global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restric
 }
 
 // ------------------------------------------------------------------ pass 1
-// Association, gates and the distance histogram (Sec. 3.2); the last
-// work-group of a problem turns the histogram into the CDF, the median bin
-// and the kept band (Sec. 3.3).
+// Association, gates and the distance histogram (Sec. 3.2).  In single-pass
+// mode the rows are also reduced: rows whose bin lies below a window around
+// the band edge predicted from the previous iteration go to per-thread
+// accumulators, rows inside the window to per-bin LDS sums, so that once the
+// band is known the kept rows' moments are a prefix of the tile partials.
 
-__device__ __forceinline__ void load_pose(const ProbState* st, Pose& T) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) T.r[k] = st->R[k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) T.t[k] = st->t[k];
+__device__ __forceinline__ int window_start(int pred_hi) {
+    if (pred_hi < 0) return -1;
+    const int h0 = pred_hi - ICP_WIN / 2;
+    return h0 < 0 ? 0 : (h0 > ICP_HIST_BINS - ICP_WIN ? ICP_HIST_BINS - ICP_WIN : h0);
 }
 
-// Median bin k_med = min{k : C_k >= ceil(N/2)} and band from the histogram;
-// run by a whole work-group, histogram read from (and cleared in) `hist`.
-__device__ void median_band(ProbState* st, const KParams& kp, uint32_t* dbg_hist) {
+// Sum the 28 accumulators and the count over the work-group into `out`
+// (29 floats); every thread calls it.
+__device__ __forceinline__ void block_reduce_row(float (&acc)[ICP_NMOM], float cnt, float (*sh_red)[ICP_PART_STRIDE],
+                                                 float* out) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < ICP_NMOM; ++k) acc[k] = wave_sum(acc[k]);
+    cnt = wave_sum(cnt);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < ICP_NMOM; ++k) sh_red[wave][k] = acc[k];
+        sh_red[wave][ICP_NMOM] = cnt;
+    }
+    __syncthreads();
+    if (tid <= ICP_NMOM) out[tid] = (sh_red[0][tid] + sh_red[1][tid]) + (sh_red[2][tid] + sh_red[3][tid]);
+}
+
+template <bool kDebug, bool kFused>
+__global__ __launch_bounds__(ICP_WG) void k_pass1(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
+                                                  IterCtl ctl, KParams kp, uint8_t* __restrict__ dbg_code,
+                                                  int32_t* __restrict__ dbg_bin) {
+    __shared__ uint32_t sh_hist[ICP_HIST_BINS];
+    __shared__ float sh_win[kFused ? ICP_WIN * (ICP_NMOM + 1) : 1];
+    __shared__ float sh_red[ICP_WAVES][ICP_PART_STRIDE];
+    const int g = blockIdx.x;
+    const ProbDesc& P = probs[owner[g]];
+    const LevelDesc& L = P.lv[ctl.level];
+    const ProbState* st = P.st;
+    const int tid = threadIdx.x;
+    const int tile = g - L.tile_base;
+    if (st->level_done) return;  // uniform: the level has ended for this problem
+    const int h0 = kFused ? window_start(st->pred_hi) : -1;
+    for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) sh_hist[b] = 0u;
+    if (kFused && h0 >= 0)
+        for (int b = tid; b < ICP_WIN * (ICP_NMOM + 1); b += ICP_WG) sh_win[b] = 0.0f;
+    __syncthreads();
+    float acc[ICP_NMOM];
+#pragma unroll
+    for (int k = 0; k < ICP_NMOM; ++k) acc[k] = 0.0f;
+    float cnt = 0.0f;
+    {
+        const Pose T = load_pose(st);
+        const Lvl Lv = load_level(L);
+        const int base = tile * L.tile_px;
+        const int end = min(base + L.tile_px, L.npx);
+        for (int i = base + ICP_PX_PER_THREAD * tid; i < end; i += ICP_TILE_QUANTUM) {
+            Quad q;
+            associate4(Lv, i, T, kp.d2max, kp.cos_max, q);
+#pragma unroll
+            for (int k = 0; k < ICP_PX_PER_THREAD; ++k) {
+                if (kDebug && i + k < end) {
+                    if (dbg_code) dbg_code[i + k] = (uint8_t)q.code[k];
+                    if (dbg_bin) dbg_bin[i + k] = q.bin[k];
+                }
+                if (q.code[k] != kGated) continue;
+                atomicAdd(&sh_hist[q.bin[k]], 1u);
+                if (kFused && h0 >= 0) {
+                    if (q.bin[k] < h0) {
+                        accumulate_row(q.p[k], q.d[k], q.n[k], acc);
+                        cnt += 1.0f;
+                    } else if (q.bin[k] < h0 + ICP_WIN) {
+                        float w[ICP_NMOM];
+#pragma unroll
+                        for (int m = 0; m < ICP_NMOM; ++m) w[m] = 0.0f;
+                        accumulate_row(q.p[k], q.d[k], q.n[k], w);
+                        float* slot = sh_win + (q.bin[k] - h0) * (ICP_NMOM + 1);
+#pragma unroll
+                        for (int m = 0; m < ICP_NMOM; ++m) atomicAdd(slot + m, w[m]);
+                        atomicAdd(slot + ICP_NMOM, 1.0f);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    unsigned int* hist = P.st->hist;
+    for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) {
+        const uint32_t c = sh_hist[b];
+        if (c) atomicAdd(&hist[b], c);
+    }
+    if (kFused && h0 >= 0) {
+        float* part = L.part1 + (size_t)tile * ICP_WIN_SLOTS * ICP_PART_STRIDE;
+        block_reduce_row(acc, cnt, sh_red, part);
+        for (int e = tid; e < ICP_WIN * (ICP_NMOM + 1); e += ICP_WG) {
+            const int b = e / (ICP_NMOM + 1), m = e - b * (ICP_NMOM + 1);
+            part[(b + 1) * ICP_PART_STRIDE + m] = sh_win[e];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ epilogues
+
+// Regularised solve (Eq. (5)), pose update and per-level bookkeeping of one
+// problem; thread 0 only.
+__device__ void solve_epilogue(ProbState* st, const double* M, int64_t n, const IterCtl& ctl, const KParams& kp) {
+    if (st->level_done) return;
+    for (int k = 0; k < ICP_NMOM; ++k) st->M[k] = M[k];
+    st->n_last = n;
+    if (ctl.no_update) return;
+    double x[6];
+    const int status = solve_regularised(M, n, kp, x);
+    if (status == ICP_LEVEL_OK) compose_exp(x, st->R, st->t);
+    for (int k = 0; k < 6; ++k) st->x[k] = x[k];
+    st->last_status = status;
+    icp_level_stats& S = st->stats.level[ctl.level];
+    S.iters_run = ctl.iter + 1;
+    S.status = status;
+    S.n_gated = st->N;
+    S.n_kept = n;
+    S.k_med = st->k_med;
+    S.rmse = n > 0 ? sqrt(M[ICP_NMOM - 1] / (double)n) : 0.0;
+    st->stats.iters_total += 1;
+    if (status != ICP_LEVEL_OK) {
+        st->level_done = 1;
+        if (st->stats.status == ICP_LEVEL_OK) st->stats.status = status;
+    } else if (kp.converge_window > 0) {
+        // Sec. 3.4: a level has converged once its median bin stays put
+        st->settled = (st->k_med == st->last_kmed) ? st->settled + 1 : 1;
+        st->last_kmed = st->k_med;
+        if (st->settled >= kp.converge_window) st->level_done = 1;
+    }
+}
+
+// Deterministic FP64 sums of `nslots` consecutive 32-float slots of every
+// tile partial (tile order, then slot order) into sh_out[0..28]; whole
+// work-group.
+__device__ void sum_partials(const float* part, int n_tiles, int tile_stride, int nslots, double* sh_out) {
+    __shared__ double sh_sum[ICP_NMOM + 1][8];
+    const int tid = threadIdx.x;
+    const int j = tid >> 3, c = tid & 7;
+    if (j <= ICP_NMOM) {
+        const int per = (n_tiles + 7) / 8;
+        const int t0 = c * per, t1 = min(t0 + per, n_tiles);
+        double s = 0.0;
+        for (int t = t0; t < t1; ++t) {
+            const float* q = part + (size_t)t * tile_stride + j;
+            double st = 0.0;
+            for (int k = 0; k < nslots; ++k) st += (double)q[k * ICP_PART_STRIDE];
+            s += st;
+        }
+        sh_sum[j][c] = s;
+    }
+    __syncthreads();
+    if (tid <= ICP_NMOM) {
+        double s = 0.0;
+        for (int q = 0; q < 8; ++q) s += sh_sum[tid][q];
+        sh_out[tid] = s;
+    }
+    __syncthreads();
+}
+
+struct Band {
+    uint32_t N;
+    int32_t k_med, k_lo, k_hi;
+};
+
+// Median bin k_med = min{k : C_k >= ceil(N/2)} of the CDF and the kept band
+// (Sec. 3.3), stored in the state and returned to every thread through LDS;
+// the histogram is cleared for the next iteration.  Whole work-group.
+__device__ Band median_band(ProbState* st, const KParams& kp, uint32_t* dbg_hist) {
     __shared__ uint32_t sh_wsum[ICP_WAVES];
     __shared__ int32_t sh_kmed;
+    __shared__ Band sh_band;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint32_t h[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        h[k] = __hip_atomic_exchange(&st->hist[4 * tid + k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        h[k] = st->hist[4 * tid + k];
+        st->hist[4 * tid + k] = 0u;
         if (dbg_hist) dbg_hist[4 * tid + k] = h[k];
     }
     const uint32_t own = (h[0] + h[1]) + (h[2] + h[3]);
@@ -275,172 +426,93 @@ __device__ void median_band(ProbState* st, const KParams& kp, uint32_t* dbg_hist
         st->k_med = km;
         st->k_lo = lo;
         st->k_hi = hi;
+        sh_band = Band{total, km, lo, hi};
     }
+    __syncthreads();
+    return sh_band;
 }
 
-template <bool kDebug>
-__global__ __launch_bounds__(ICP_WG) void k_pass1(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
-                                                  IterCtl ctl, KParams kp, uint8_t* __restrict__ dbg_code,
-                                                  int32_t* __restrict__ dbg_bin, uint32_t* dbg_hist) {
-    __shared__ uint32_t sh_hist[ICP_HIST_BINS];
-    __shared__ int sh_last;
-    const int g = blockIdx.x;
-    const ProbDesc& P = probs[owner[g]];
+// One work-group per problem: the band; in single-pass mode, when the band
+// edge fell inside the predicted window, the kept rows' moments are summed
+// from the pass-1 partials and the iteration is completed here.
+__global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ probs, IterCtl ctl, KParams kp,
+                                                 int fused, uint32_t* dbg_hist) {
+    __shared__ double sh_M[ICP_NMOM + 1];
+    const ProbDesc& P = probs[blockIdx.x];
     const LevelDesc& L = P.lv[ctl.level];
     ProbState* st = P.st;
-    const int tid = threadIdx.x;
-    for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) sh_hist[b] = 0u;
-    __syncthreads();
-    if (!st->level_done) {
-        Pose T;
-        load_pose(st, T);
-        const int base = (g - L.tile_base) * L.tile_px;
-        const int end = min(base + L.tile_px, L.npx);
-        for (int i = base + tid; i < end; i += ICP_WG) {
-            Match m;
-            const int code = associate(L, i, T, kp.d2max, kp.cos_max, m);
-            if (code == kGated) atomicAdd(&sh_hist[m.bin], 1u);
-            if (kDebug) {
-                if (dbg_code) dbg_code[i] = (uint8_t)code;
-                if (dbg_bin) dbg_bin[i] = code == kGated ? m.bin : -1;
-            }
-        }
+    if (st->level_done) return;
+    const int h0 = fused ? window_start(st->pred_hi) : -1;
+    const Band b = median_band(st, kp, dbg_hist);
+    const bool hit = h0 >= 0 && b.N > 0 && b.k_lo == 0 && b.k_hi >= h0 - 1 && b.k_hi <= h0 + ICP_WIN - 1;
+    if (hit) {
+        sum_partials(L.part1, L.n_tiles, ICP_WIN_SLOTS * ICP_PART_STRIDE, b.k_hi - h0 + 2, sh_M);
+        if (threadIdx.x == 0) solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp);
     }
-    __syncthreads();
-    for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) {
-        const uint32_t c = sh_hist[b];
-        if (c) atomicAdd(&st->hist[b], c);
+    if (threadIdx.x == 0) {
+        st->fused_done = hit ? 1 : 0;
+        if (b.N > 0) st->pred_hi = b.k_hi;
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) sh_last = atomicAdd(&st->ticket1, 1u) == (uint32_t)(L.n_tiles - 1);
-    __syncthreads();
-    if (!sh_last) return;
-    __threadfence();
-    if (!st->level_done) median_band(st, kp, dbg_hist);
-    if (tid == 0) st->ticket1 = 0u;
 }
 
 // ------------------------------------------------------------------ pass 2
 // Filter (kept iff gated and its bin lies in the band) and the 28-moment
-// reduction of the kept rows; the last work-group of a problem sums the tile
-// partials in tile order (FP64), solves Eq. (5) and updates the pose.
-
-__device__ void solve_epilogue(ProbState* st, const double* M, int64_t n, const IterCtl& ctl, const KParams& kp) {
-    if (!st->level_done) {
-        for (int k = 0; k < ICP_NMOM; ++k) st->M[k] = M[k];
-        st->n_last = n;
-        if (!ctl.no_update) {
-            double x[6];
-            const int status = solve_regularised(M, n, kp, x);
-            if (status == ICP_LEVEL_OK) compose_exp(x, st->R, st->t);
-            for (int k = 0; k < 6; ++k) st->x[k] = x[k];
-            st->last_status = status;
-            icp_level_stats& S = st->stats.level[ctl.level];
-            S.iters_run = ctl.iter + 1;
-            S.status = status;
-            S.n_gated = st->N;
-            S.n_kept = n;
-            S.k_med = st->k_med;
-            S.rmse = n > 0 ? sqrt(M[ICP_NMOM - 1] / (double)n) : 0.0;
-            st->stats.iters_total += 1;
-            if (status != ICP_LEVEL_OK) {
-                st->level_done = 1;
-                if (st->stats.status == ICP_LEVEL_OK) st->stats.status = status;
-            } else if (kp.converge_window > 0) {
-                // Sec. 3.4: a level has converged once its median bin stays put
-                st->settled = (st->k_med == st->last_kmed) ? st->settled + 1 : 1;
-                st->last_kmed = st->k_med;
-                if (st->settled >= kp.converge_window) st->level_done = 1;
-            }
-        }
-    }
-    if (ctl.last_of_level) {
-        st->level_done = 0;
-        st->settled = 0;
-        st->last_kmed = -2;
-    }
-}
+// reduction of the kept rows into one partial per tile.
 
 __global__ __launch_bounds__(ICP_WG) void k_pass2(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
                                                   IterCtl ctl, KParams kp) {
     __shared__ float sh_red[ICP_WAVES][ICP_PART_STRIDE];
-    __shared__ double sh_sum[ICP_PART_STRIDE][8];
-    __shared__ int sh_last;
     const int g = blockIdx.x;
     const ProbDesc& P = probs[owner[g]];
     const LevelDesc& L = P.lv[ctl.level];
-    ProbState* st = P.st;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const ProbState* st = P.st;
+    const int tid = threadIdx.x;
     const int tile = g - L.tile_base;
+    if (st->level_done || st->fused_done) return;  // uniform
     float acc[ICP_NMOM];
 #pragma unroll
     for (int k = 0; k < ICP_NMOM; ++k) acc[k] = 0.0f;
-    uint32_t cnt = 0;
-    if (!st->level_done) {
-        Pose T;
-        load_pose(st, T);
-        const int klo = st->k_lo, khi = st->k_hi;
+    float cnt = 0.0f;
+    {
+        const Pose T = load_pose(st);
+        const Lvl Lv = load_level(L);
+        const int klo = __builtin_amdgcn_readfirstlane(st->k_lo);
+        const int khi = __builtin_amdgcn_readfirstlane(st->k_hi);
         const int base = tile * L.tile_px;
         const int end = min(base + L.tile_px, L.npx);
-        for (int i = base + tid; i < end; i += ICP_WG) {
-            Match m;
-            if (associate(L, i, T, kp.d2max, kp.cos_max, m) == kGated && m.bin >= klo && m.bin <= khi) {
-                accumulate_row(m, acc);
-                ++cnt;
+        for (int i = base + ICP_PX_PER_THREAD * tid; i < end; i += ICP_TILE_QUANTUM) {
+            Quad q;
+            associate4(Lv, i, T, kp.d2max, kp.cos_max, q);
+#pragma unroll
+            for (int k = 0; k < ICP_PX_PER_THREAD; ++k) {
+                if (q.code[k] == kGated && q.bin[k] >= klo && q.bin[k] <= khi) {
+                    accumulate_row(q.p[k], q.d[k], q.n[k], acc);
+                    cnt += 1.0f;
+                }
             }
         }
     }
-#pragma unroll
-    for (int k = 0; k < ICP_NMOM; ++k) acc[k] = wave_sum(acc[k]);
-    cnt = wave_sum_u(cnt);
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < ICP_NMOM; ++k) sh_red[wave][k] = acc[k];
-        sh_red[wave][ICP_NMOM] = __uint_as_float(cnt);
+    block_reduce_row(acc, cnt, sh_red, L.part + (size_t)tile * ICP_PART_STRIDE);
+}
+
+// One work-group per problem: FP64 sum of the pass-2 partials in tile order,
+// solve, update; then the end-of-level bookkeeping.
+__global__ __launch_bounds__(ICP_WG) void k_solve(const ProbDesc* __restrict__ probs, IterCtl ctl, KParams kp) {
+    __shared__ double sh_M[ICP_NMOM + 1];
+    const ProbDesc& P = probs[blockIdx.x];
+    const LevelDesc& L = P.lv[ctl.level];
+    ProbState* st = P.st;
+    if (!st->fused_done && !st->level_done) {
+        sum_partials(L.part, L.n_tiles, ICP_PART_STRIDE, 1, sh_M);
+        if (threadIdx.x == 0) solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp);
     }
-    __syncthreads();
-    if (tid <= ICP_NMOM) {
-        float v;
-        if (tid < ICP_NMOM) {
-            v = (sh_red[0][tid] + sh_red[1][tid]) + (sh_red[2][tid] + sh_red[3][tid]);
-        } else {
-            const uint32_t c = (__float_as_uint(sh_red[0][tid]) + __float_as_uint(sh_red[1][tid])) +
-                               (__float_as_uint(sh_red[2][tid]) + __float_as_uint(sh_red[3][tid]));
-            v = __uint_as_float(c);
+    if (threadIdx.x == 0) {
+        st->fused_done = 0;
+        if (ctl.last_of_level) {
+            st->level_done = 0;
+            st->settled = 0;
+            st->last_kmed = -2;
         }
-        st_agent(&L.part[(size_t)tile * ICP_PART_STRIDE + tid], v);
-    }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) sh_last = atomicAdd(&st->ticket2, 1u) == (uint32_t)(L.n_tiles - 1);
-    __syncthreads();
-    if (!sh_last) return;
-    __threadfence();
-    // deterministic FP64 sum of the tile partials: 8 contiguous chunks per value
-    const int j = tid >> 3, c = tid & 7;
-    if (j <= ICP_NMOM) {
-        const int per = (L.n_tiles + 7) / 8;
-        const int t0 = c * per, t1 = min(t0 + per, L.n_tiles);
-        double s = 0.0;
-        for (int t = t0; t < t1; ++t) {
-            const float v = ld_agent(&L.part[(size_t)t * ICP_PART_STRIDE + j]);
-            s += j < ICP_NMOM ? (double)v : (double)__float_as_uint(v);
-        }
-        sh_sum[j][c] = s;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double M[ICP_NMOM];
-        for (int k = 0; k <= ICP_NMOM; ++k) {
-            double s = 0.0;
-            for (int q = 0; q < 8; ++q) s += sh_sum[k][q];
-            if (k < ICP_NMOM) M[k] = s;
-            else sh_sum[k][0] = s;
-        }
-        const int64_t n = (int64_t)sh_sum[ICP_NMOM][0];
-        solve_epilogue(st, M, n, ctl, kp);
-        st->ticket2 = 0u;
     }
 }
 
@@ -472,8 +544,8 @@ __global__ void k_stage_set(const ProbDesc* __restrict__ probs, PoseArg pose, in
         }
         st->k_lo = k_lo;
         st->k_hi = k_hi;
-        st->ticket1 = 0u;
-        st->ticket2 = 0u;
+        st->pred_hi = -1;
+        st->fused_done = 0;
         st->level_done = 0;
     }
 }
@@ -515,11 +587,30 @@ hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* m
     return hipGetLastError();
 }
 
-hipError_t launch_iteration(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_pass1<false>, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp, nullptr, nullptr,
-                       nullptr);
+hipError_t launch_pass1(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp, int fused,
+                        hipStream_t s) {
+    if (fused)
+        hipLaunchKernelGGL((k_pass1<false, true>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp, nullptr,
+                           nullptr);
+    else
+        hipLaunchKernelGGL((k_pass1<false, false>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp, nullptr,
+                           nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_band(const ProbDesc* probs, int n, IterCtl ctl, const KParams& kp, int fused, hipStream_t s) {
+    hipLaunchKernelGGL(k_band, dim3(n), dim3(ICP_WG), 0, s, probs, ctl, kp, fused, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass2(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
+                        hipStream_t s) {
     hipLaunchKernelGGL(k_pass2, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve(const ProbDesc* probs, int n, IterCtl ctl, const KParams& kp, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve, dim3(n), dim3(ICP_WG), 0, s, probs, ctl, kp);
     return hipGetLastError();
 }
 
@@ -535,13 +626,15 @@ hipError_t launch_stage_set(const ProbDesc* probs, PoseArg pose, int k_lo, int k
 
 hipError_t launch_stage_pass1(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
                               uint8_t* code, int32_t* bin, uint32_t* hist, hipStream_t s) {
-    hipLaunchKernelGGL(k_pass1<true>, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp, code, bin, hist);
+    hipLaunchKernelGGL((k_pass1<true, false>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp, code, bin);
+    hipLaunchKernelGGL(k_band, dim3(1), dim3(ICP_WG), 0, s, probs, ctl, kp, 0, hist);
     return hipGetLastError();
 }
 
 hipError_t launch_stage_pass2(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
                               hipStream_t s) {
     hipLaunchKernelGGL(k_pass2, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+    hipLaunchKernelGGL(k_solve, dim3(1), dim3(ICP_WG), 0, s, probs, ctl, kp);
     return hipGetLastError();
 }
 

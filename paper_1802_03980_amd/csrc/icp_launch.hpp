@@ -21,9 +21,14 @@ hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, hipStream
 // live depth pyramid, live vertex/normal maps, model maps for every level;
 // max_npx[l] is the largest level-l pixel count over the problems
 hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, hipStream_t s);
-// one ICP iteration at ctl.level over `tiles` flat tiles of all problems
-hipError_t launch_iteration(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
-                            hipStream_t s);
+// one ICP iteration at ctl.level: pass 1 over `tiles` flat tiles of all
+// problems, the per-problem band, pass 2 over the tiles, the per-problem solve
+hipError_t launch_pass1(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp, int fused,
+                        hipStream_t s);
+hipError_t launch_band(const ProbDesc* probs, int n, IterCtl ctl, const KParams& kp, int fused, hipStream_t s);
+hipError_t launch_pass2(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
+                        hipStream_t s);
+hipError_t launch_solve(const ProbDesc* probs, int n, IterCtl ctl, const KParams& kp, hipStream_t s);
 // pose and statistics of every problem into results[n]
 hipError_t launch_finalize(const ProbDesc* probs, int n, icp_result* results, hipStream_t s);
 

@@ -201,6 +201,23 @@ def test_end_to_end_vga_room(ctx):
         assert sg["status"] == icp.LEVEL_OK
 
 
+@pytest.mark.parametrize("over", [dict(pass_mode=1), dict(pass_mode=0), dict(band_beta=0.5),
+                                  dict(use_median_filter=0), dict(pass_mode=0, lambda_c=0.0)])
+def test_pass_modes_match_oracle(ctx, over):
+    """Single-pass (predicted band window) and two-pass reductions give the
+    oracle's pose; beta < 1 takes the two-pass route automatically."""
+    params = icp.icp_params_default(**over)
+    probs = [synth.config1_problem(3), synth.RoomSequence(1, n_frames=3).problem(1)]
+    for prob in probs:
+        Tg, sg, To, so = _register_both(ctx, prob, params)
+        ang, dt = pose_err(Tg, To)
+        assert ang < POSE_TOL and dt < POSE_TOL, (over, prob.name, ang, dt)
+        for l in range(3):
+            assert sg["levels"][l]["iters_run"] == so[l]["iters_run"]
+            assert sg["levels"][l]["n_kept"] == so[l]["n_kept"] or \
+                abs(sg["levels"][l]["n_kept"] - so[l]["n_kept"]) <= 2
+
+
 def test_convergence_control_matches(ctx):
     prob = synth.config1_problem(0)
     params = icp.icp_params_default(converge_window=3, iters=(30, 30, 30), lambda_c=0.0)
