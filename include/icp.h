@@ -159,6 +159,12 @@ int icp_ctx_create(int device, size_t hbm_budget_bytes, icp_ctx** out);
    NULL is ignored. */
 void icp_ctx_destroy(icp_ctx* ctx);
 
+/* Replay registrations as HIP graphs (1, the default) or launch every kernel
+   eagerly (0).  With graphs, the launches of a registration are captured
+   once per combination of problem sizes, parameters and workspace and
+   replayed on later calls; calls with kernel timing enabled launch eagerly. */
+int icp_ctx_set_graphs(icp_ctx* ctx, int enable);
+
 /* Bytes of device workspace the context currently holds. */
 size_t icp_ctx_workspace_bytes(const icp_ctx* ctx);
 

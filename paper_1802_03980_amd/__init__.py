@@ -30,7 +30,7 @@ PX_INVALID_LIVE, PX_BEHIND, PX_OUTSIDE, PX_INVALID_MODEL, PX_FAR, PX_ANGLE, PX_G
 EXPORTS = (
     "icp_abi_version", "icp_strerror", "icp_last_error", "icp_ctx_create", "icp_ctx_destroy",
     "icp_ctx_workspace_bytes", "icp_workspace_bytes", "icp_params_default", "icp_register",
-    "icp_register_async", "icp_register_batch", "icp_ctx_set_timing", "icp_ctx_get_timing",
+    "icp_register_async", "icp_register_batch", "icp_ctx_set_timing", "icp_ctx_get_timing", "icp_ctx_set_graphs",
     "icp_stage_prepare", "icp_stage_level",
     "icp_stage_associate", "icp_stage_moments", "icp_stage_solve",
 )
@@ -111,6 +111,7 @@ def lib():
                                        C.POINTER(icp_params), P, P]),
             "icp_register_batch": (I, [P, I, P, C.POINTER(icp_params), P, P]),
             "icp_ctx_set_timing": (I, [P, I]),
+            "icp_ctx_set_graphs": (I, [P, I]),
             "icp_ctx_get_timing": (I, [P, P]),
             "icp_stage_prepare": (I, [P, P, I, I, P, P, C.POINTER(icp_intrinsics), I, P]),
             "icp_stage_level": (I, [P, I, P, P, P, P, P, P]),
@@ -262,10 +263,17 @@ def result_from_bytes(buf):
     return np.array(r.pose[:]).reshape(4, 4), stats_to_dict(r.stats)
 
 
-def icp_register_batch(ctx, problems, params=None, stream=None):
-    """problems: sequence of dicts with live_depth, model_vtx, model_nrm (device
-    tensors), K, imu_R, init_pose.  Returns a list of (pose, stats)."""
-    p = params if params is not None else icp_params_default()
+class ProblemArray:
+    """A ctypes icp_problem array built once from problem dicts, reusable in
+    icp_register_batch while its tensors stay alive."""
+
+    def __init__(self, problems):
+        self.n = len(problems)
+        self.arr = _problem_array(problems)
+        self.keep = [(q["live_depth"], q["model_vtx"], q["model_nrm"]) for q in problems]
+
+
+def _problem_array(problems):
     n = len(problems)
     arr = (icp_problem * n)()
     for i, q in enumerate(problems):
@@ -279,11 +287,27 @@ def icp_register_batch(ctx, problems, params=None, stream=None):
         a.K = make_intrinsics(q["K"])
         a.imu_R[:] = list(_f64(q["imu_R"], 9, "imu_R"))
         a.init_pose[:] = list(_f64(q["init_pose"], 16, "init_pose"))
+    return arr
+
+
+def icp_register_batch(ctx, problems, params=None, stream=None):
+    """problems: a ProblemArray or a sequence of dicts with live_depth,
+    model_vtx, model_nrm (device tensors), K, imu_R, init_pose.  Returns a
+    list of (pose, stats)."""
+    p = params if params is not None else icp_params_default()
+    if isinstance(problems, ProblemArray):
+        n, arr = problems.n, problems.arr
+    else:
+        n, arr = len(problems), _problem_array(problems)
     res = (icp_result * n)()
     rc = lib().icp_register_batch(ctx.handle, n, C.cast(arr, C.c_void_p), C.byref(p), C.cast(res, C.c_void_p),
                                   _stream(stream))
     _check(ctx, rc)
     return [(np.array(r.pose[:]).reshape(4, 4), stats_to_dict(r.stats, p.levels)) for r in res]
+
+
+def icp_ctx_set_graphs(ctx, enable):
+    _check(ctx, lib().icp_ctx_set_graphs(ctx.handle, 1 if enable else 0))
 
 
 def icp_ctx_set_timing(ctx, enable):

@@ -42,6 +42,15 @@ struct icp_ctx {
     std::vector<EvRec> pending;
     std::vector<hipEvent_t> ev_pool;
     icp_kernel_time times[ICP_TIME_KINDS] = {};
+    // plan and graph caches (valid for the current workspace allocation)
+    std::vector<int64_t> plan_key;      // shapes + tiling of the cached plan
+    std::vector<int64_t> owners_key;    // plan whose tile owners are in device memory
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;   // private stream used only for capture
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<int64_t> graph_key;
+    void* plan_mem = nullptr;  // the cached Plan (see ctx_plan)
 };
 
 namespace {
@@ -174,6 +183,32 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
     P.total = off;
 }
 
+Plan& ctx_plan(icp_ctx* ctx) {
+    if (!ctx->plan_mem) ctx->plan_mem = new Plan();
+    return *static_cast<Plan*>(ctx->plan_mem);
+}
+
+std::vector<int64_t> plan_signature(int n, const icp_problem* probs, int levels, const int32_t* tile_req) {
+    std::vector<int64_t> k;
+    k.reserve(6 + 2 * (size_t)n);
+    k.push_back(n);
+    k.push_back(levels);
+    for (int l = 0; l < ICP_MAX_LEVELS; ++l) k.push_back(tile_req ? tile_req[l] : 0);
+    for (int p = 0; p < n; ++p) {
+        k.push_back(probs[p].W);
+        k.push_back(probs[p].H);
+    }
+    return k;
+}
+
+void drop_graph(icp_ctx* ctx) {
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_key.clear();
+}
+
 template <typename T>
 T* rebase(T* off, char* base) {
     return reinterpret_cast<T*>(base + reinterpret_cast<size_t>(off));
@@ -190,6 +225,8 @@ int ensure_workspace(icp_ctx* ctx, size_t bytes) {
         ctx->ws_cap = 0;
         ctx->stage_ready = false;
     }
+    ctx->owners_key.clear();
+    drop_graph(ctx);
     size_t want = bytes + bytes / 4;
     if (ctx->budget) want = std::min(want, ctx->budget);
     hipError_t e = hipMalloc(&ctx->ws, want);
@@ -233,12 +270,26 @@ KParams kparams(const icp_params* p) {
 // Plan, place and upload a batch; leaves device descriptors ready.
 int stage_batch(icp_ctx* ctx, int n, const icp_problem* probs, int levels, const int32_t* tile_req, Plan& P,
                 hipStream_t s) {
-    std::vector<int32_t> W(n), H(n);
-    for (int p = 0; p < n; ++p) {
-        W[p] = probs[p].W;
-        H[p] = probs[p].H;
+    std::vector<int64_t> key = plan_signature(n, probs, levels, tile_req);
+    if (key != ctx->plan_key || P.desc.size() != (size_t)n) {
+        std::vector<int32_t> W(n), H(n);
+        for (int p = 0; p < n; ++p) {
+            W[p] = probs[p].W;
+            H[p] = probs[p].H;
+        }
+        make_plan(n, W.data(), H.data(), levels, tile_req, P);
+        ctx->plan_key = key;
+    } else {
+        // same shapes: reset the descriptors' device pointers to offsets
+        std::vector<int32_t> W(n), H(n);
+        for (int p = 0; p < n; ++p) {
+            W[p] = probs[p].W;
+            H[p] = probs[p].H;
+        }
+        Plan fresh;
+        make_plan(n, W.data(), H.data(), levels, tile_req, fresh);
+        P.desc.swap(fresh.desc);
     }
-    make_plan(n, W.data(), H.data(), levels, tile_req, P);
     int rc = ensure_workspace(ctx, P.total);
     if (rc) return rc;
     char* base = static_cast<char*>(ctx->ws);
@@ -268,20 +319,25 @@ int stage_batch(icp_ctx* ctx, int n, const icp_problem* probs, int levels, const
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 4; ++j) d.init[4 * i + j] = q.init_pose[4 * i + j];
     }
-    size_t up = sizeof(ProbDesc) * n;
+    const size_t up = sizeof(ProbDesc) * n;
+    const bool owners = ctx->owners_key != key;
     size_t owner_bytes = 0;
-    for (int l = 0; l < levels; ++l) owner_bytes += sizeof(int) * P.owner[l].size();
+    if (owners)
+        for (int l = 0; l < levels; ++l) owner_bytes += sizeof(int) * P.owner[l].size();
     rc = ensure_stage(ctx, up + owner_bytes);
     if (rc) return rc;
     char* h = static_cast<char*>(ctx->hstage);
     std::memcpy(h, P.desc.data(), up);
     HIP_TRY(ctx, hipMemcpyAsync(base + P.off_desc, h, up, hipMemcpyHostToDevice, s));
-    size_t ho = up;
-    for (int l = 0; l < levels; ++l) {
-        const size_t b = sizeof(int) * P.owner[l].size();
-        std::memcpy(h + ho, P.owner[l].data(), b);
-        HIP_TRY(ctx, hipMemcpyAsync(base + P.off_owner[l], h + ho, b, hipMemcpyHostToDevice, s));
-        ho += b;
+    if (owners) {
+        size_t ho = up;
+        for (int l = 0; l < levels; ++l) {
+            const size_t b = sizeof(int) * P.owner[l].size();
+            std::memcpy(h + ho, P.owner[l].data(), b);
+            HIP_TRY(ctx, hipMemcpyAsync(base + P.off_owner[l], h + ho, b, hipMemcpyHostToDevice, s));
+            ho += b;
+        }
+        ctx->owners_key = key;
     }
     HIP_TRY(ctx, hipEventRecord(ctx->ev_upload, s));
     ctx->ev_pending = true;
@@ -374,6 +430,37 @@ int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* r
     return ICP_OK;
 }
 
+// Launch the whole registration of a staged batch on s, results into the
+// workspace's result array.  Without timing, the launches are captured once
+// per (plan, parameters, workspace) into a HIP graph and replayed.
+int execute(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, hipStream_t s) {
+    char* base = static_cast<char*>(ctx->ws);
+    icp_result* d_res = reinterpret_cast<icp_result*>(base + P.off_res);
+    if (!ctx->use_graphs || ctx->timing) return run_batch(ctx, n, prm, P, d_res, s);
+    std::vector<int64_t> key = ctx->plan_key;
+    key.push_back(reinterpret_cast<int64_t>(ctx->ws));
+    const int64_t* pw = reinterpret_cast<const int64_t*>(prm);
+    for (size_t k = 0; k < sizeof(icp_params) / sizeof(int64_t); ++k) key.push_back(pw[k]);
+    if (key != ctx->graph_key) {
+        drop_graph(ctx);
+        if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        int rc = run_batch(ctx, n, prm, P, d_res, ctx->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+        ctx->graph = g;
+        HIP_TRY(ctx, hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
+        ctx->graph_key = key;
+    }
+    HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, s));
+    return ICP_OK;
+}
+
 icp_problem one_problem(const float* depth, int W, int H, const float* mv, const float* mn, const icp_intrinsics* K,
                         const double* imu_R, const double* init_pose) {
     icp_problem q{};
@@ -459,7 +546,16 @@ void icp_ctx_destroy(icp_ctx* ctx) {
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    drop_graph(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    delete static_cast<Plan*>(ctx->plan_mem);
     delete ctx;
+}
+
+int icp_ctx_set_graphs(icp_ctx* ctx, int enable) {
+    if (!ctx) return ICP_EINVAL;
+    ctx->use_graphs = enable != 0;
+    return ICP_OK;
 }
 
 int icp_ctx_set_timing(icp_ctx* ctx, int enable) {
@@ -501,11 +597,11 @@ int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_
         if ((rc = check_problem(ctx, probs[p], params->levels))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    Plan P;
+    Plan& P = ctx_plan(ctx);
     if ((rc = stage_batch(ctx, n, probs, params->levels, params->tile_px, P, s))) return rc;
     ctx->stage_ready = false;
+    if ((rc = execute(ctx, n, params, P, s))) return rc;
     icp_result* d_res = reinterpret_cast<icp_result*>(static_cast<char*>(ctx->ws) + P.off_res);
-    if ((rc = run_batch(ctx, n, params, P, d_res, s))) return rc;
     HIP_TRY(ctx, hipMemcpyAsync(results, d_res, sizeof(icp_result) * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     return resolve_timing(ctx);
@@ -536,10 +632,13 @@ int icp_register_async(icp_ctx* ctx, const float* live_depth, int W, int H, cons
     if ((rc = check_problem(ctx, q, params->levels))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    Plan P;
+    Plan& P = ctx_plan(ctx);
     if ((rc = stage_batch(ctx, 1, &q, params->levels, params->tile_px, P, s))) return rc;
     ctx->stage_ready = false;
-    return run_batch(ctx, 1, params, P, result_dev, s);
+    if ((rc = execute(ctx, 1, params, P, s))) return rc;
+    icp_result* d_res = reinterpret_cast<icp_result*>(static_cast<char*>(ctx->ws) + P.off_res);
+    HIP_TRY(ctx, hipMemcpyAsync(result_dev, d_res, sizeof(icp_result), hipMemcpyDeviceToDevice, s));
+    return ICP_OK;
 }
 
 // ------------------------------------------------------------------ stages
@@ -554,7 +653,7 @@ int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const
     if (rc) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    Plan P;
+    Plan& P = ctx_plan(ctx);
     if ((rc = stage_batch(ctx, 1, &q, levels, nullptr, P, s))) return rc;
     char* base = static_cast<char*>(ctx->ws);
     ctx->d_desc = reinterpret_cast<ProbDesc*>(base + P.off_desc);

@@ -105,14 +105,14 @@ __device__ __forceinline__ Lvl load_level(const LevelDesc& L) {
     return v;
 }
 
-// Association results of four consecutive pixels; the FP32 row inputs
-// (p', q - p', n_q) are filled for gated pixels only.
-struct Quad {
-    int code[4];
-    int bin[4];
-    float p[4][3];
-    float d[4][3];
-    float n[4][3];
+// Association result of one pixel handed to the caller: the code, the bin
+// (gated pixels) and the FP32 inputs of its row (p', q - p', n_q).
+struct PixelOut {
+    int code;
+    int bin;
+    float p[3];
+    float d[3];
+    float n[3];
 };
 
 typedef float vf4 __attribute__((ext_vector_type(4)));
@@ -122,94 +122,98 @@ __device__ __forceinline__ vf4 ld4(const ICP_GLOBAL float* p) { return *(const I
 // Projective association of live pixels i..i+3 (i a multiple of 4, paper
 // Sec. 3): move each live point by the current pose, project it into the
 // model image, round to the nearest pixel, fetch the model point and normal
-// there, then gate on validity, distance and normal agreement.  The live
-// vertices arrive as one 16-byte load per plane; the model gathers of the
-// four pixels and the live normals are issued together.
+// there, then gate on validity, distance and normal agreement.
+//
+// Written as straight-line code: every quantity is computed for every pixel
+// (NaN inputs propagate and fail every comparison) and the code is selected
+// at the end in the order the checks are defined, so a wavefront runs one
+// path.  Every map stores an invalid pixel as NaN in all three components,
+// so one component decides validity.  The live vertices arrive as one
+// 16-byte load per plane; the model gathers of the four pixels and the live
+// normals are issued together.
+template <class Emit>
 __device__ __forceinline__ void associate4(const Lvl& L, int i, const Pose& T, double d2max, double cos_max,
-                                           Quad& o) {
+                                           Emit&& emit) {
     const int S = L.ps;
     const vf4 vx = ld4(L.LV + i), vy = ld4(L.LV + S + i), vz = ld4(L.LV + 2 * S + i);
     const float V[4][3] = {{vx.x, vy.x, vz.x}, {vx.y, vy.y, vz.y}, {vx.z, vy.z, vz.z}, {vx.w, vy.w, vz.w}};
     double P[4][3];
     int j[4];
-    bool vok[4];
+    bool vok[4], front[4], inside[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        o.code[k] = kInvalidLive;
-        o.bin[k] = -1;
-        j[k] = -1;
-        P[k][0] = P[k][1] = P[k][2] = 0.0;
-        vok[k] = i + k < L.npx && fin(V[k][0]) && fin(V[k][1]) && fin(V[k][2]);
-        if (vok[k]) {
-            const double px = V[k][0], py = V[k][1], pz = V[k][2];
+        vok[k] = (i + k < L.npx) && fin(V[k][2]);
+        const double px = V[k][0], py = V[k][1], pz = V[k][2];
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                P[k][c] = ((T.r[3 * c] * px + T.r[3 * c + 1] * py) + T.r[3 * c + 2] * pz) + T.t[c];
-            if (!(P[k][2] > 0.0)) {
-                o.code[k] = kBehind;
-            } else {
-                const double uf = L.fx * (P[k][0] / P[k][2]) + L.cx;
-                const double vf = L.fy * (P[k][1] / P[k][2]) + L.cy;
-                const double uu = floor(uf + 0.5), vv = floor(vf + 0.5);
-                if (!(uu >= 0.0 && uu <= L.umax && vv >= 0.0 && vv <= L.vmax)) o.code[k] = kOutside;
-                else j[k] = (int)vv * L.W + (int)uu;
-            }
-        }
+        for (int c = 0; c < 3; ++c)
+            P[k][c] = ((T.r[3 * c] * px + T.r[3 * c + 1] * py) + T.r[3 * c + 2] * pz) + T.t[c];
+        front[k] = P[k][2] > 0.0;
+        const double uf = L.fx * (P[k][0] / P[k][2]) + L.cx;
+        const double vf = L.fy * (P[k][1] / P[k][2]) + L.cy;
+        const double uu = floor(uf + 0.5), vv = floor(vf + 0.5);
+        inside[k] = uu >= 0.0 && uu <= L.umax && vv >= 0.0 && vv <= L.vmax;
+        const bool look = vok[k] && front[k] && inside[k];
+        j[k] = look ? (int)vv * L.W + (int)uu : 0;
     }
     const vf4 nx = ld4(L.LN + i), ny = ld4(L.LN + S + i), nz = ld4(L.LN + 2 * S + i);
     const float N[4][3] = {{nx.x, ny.x, nz.x}, {nx.y, ny.y, nz.y}, {nx.z, ny.z, nz.z}, {nx.w, ny.w, nz.w}};
     float Q[4][3], M[4][3];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int jj = j[k] < 0 ? 0 : j[k];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Q[k][c] = j[k] < 0 ? 0.0f : L.MV[c * S + jj];
-            M[k][c] = j[k] < 0 ? 0.0f : L.MN[c * S + jj];
+            Q[k][c] = L.MV[c * S + j[k]];
+            M[k][c] = L.MN[c * S + j[k]];
         }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        if (!vok[k]) continue;
-        // a live pixel without a normal is invalid whatever its projection
-        if (!(fin(N[k][0]) && fin(N[k][1]) && fin(N[k][2]))) {
-            o.code[k] = kInvalidLive;
-            continue;
-        }
-        if (j[k] < 0) continue;
-        if (!(fin(Q[k][0]) && fin(Q[k][1]) && fin(Q[k][2]) && fin(M[k][0]) && fin(M[k][1]) && fin(M[k][2]))) {
-            o.code[k] = kInvalidModel;
-            continue;
-        }
+        const bool nok = fin(N[k][2]);
+        const bool mok = fin(Q[k][2]);
         const double d0 = (double)Q[k][0] - P[k][0];
         const double d1 = (double)Q[k][1] - P[k][1];
         const double d2 = (double)Q[k][2] - P[k][2];
         const double dd = (d0 * d0 + d1 * d1) + d2 * d2;
-        if (!(dd < d2max)) {
-            o.code[k] = kFar;
-            continue;
-        }
+        const bool near = dd < d2max;
         const double nxd = N[k][0], nyd = N[k][1], nzd = N[k][2];
         const double r0 = (T.r[0] * nxd + T.r[1] * nyd) + T.r[2] * nzd;
         const double r1 = (T.r[3] * nxd + T.r[4] * nyd) + T.r[5] * nzd;
         const double r2 = (T.r[6] * nxd + T.r[7] * nyd) + T.r[8] * nzd;
         const double cv = (r0 * (double)M[k][0] + r1 * (double)M[k][1]) + r2 * (double)M[k][2];
-        if (!(cv >= cos_max)) {
-            o.code[k] = kAngle;
-            continue;
-        }
-        o.code[k] = kGated;
-        o.bin[k] = dist_bin(dd);
-        o.p[k][0] = (float)P[k][0];
-        o.p[k][1] = (float)P[k][1];
-        o.p[k][2] = (float)P[k][2];
-        o.d[k][0] = (float)d0;
-        o.d[k][1] = (float)d1;
-        o.d[k][2] = (float)d2;
-        o.n[k][0] = M[k][0];
-        o.n[k][1] = M[k][1];
-        o.n[k][2] = M[k][2];
+        const bool agree = cv >= cos_max;
+        int code = kGated;
+        code = agree ? code : kAngle;
+        code = near ? code : kFar;
+        code = mok ? code : kInvalidModel;
+        code = inside[k] ? code : kOutside;
+        code = front[k] ? code : kBehind;
+        code = (vok[k] && nok) ? code : kInvalidLive;
+        PixelOut o;
+        o.code = code;
+        o.bin = code == kGated ? dist_bin(dd) : -1;
+        o.p[0] = (float)P[k][0];
+        o.p[1] = (float)P[k][1];
+        o.p[2] = (float)P[k][2];
+        o.d[0] = (float)d0;
+        o.d[1] = (float)d1;
+        o.d[2] = (float)d2;
+        o.n[0] = M[k][0];
+        o.n[1] = M[k][1];
+        o.n[2] = M[k][2];
+        emit(k, o);
     }
+}
+
+// The row r = [a | b] of Eq. (3) for a kept pair (see accumulate_row).
+__device__ __forceinline__ void make_row(const float (&p)[3], const float (&d)[3], const float (&n)[3],
+                                         float (&r)[7]) {
+    r[0] = p[1] * n[2] - p[2] * n[1];
+    r[1] = p[2] * n[0] - p[0] * n[2];
+    r[2] = p[0] * n[1] - p[1] * n[0];
+    r[3] = n[0];
+    r[4] = n[1];
+    r[5] = n[2];
+    r[6] = __builtin_fmaf(n[2], d[2], __builtin_fmaf(n[1], d[1], n[0] * d[0]));
 }
 
 // The row of Eq. (3) for a kept pair and its 28 products.  With the

@@ -229,12 +229,72 @@ __device__ __forceinline__ void block_reduce_row(float (&acc)[ICP_NMOM], float c
     if (tid <= ICP_NMOM) out[tid] = (sh_red[0][tid] + sh_red[1][tid]) + (sh_red[2][tid] + sh_red[3][tid]);
 }
 
+#define ICP_STAGE 8  // window rows a wave stages at a time
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The (a, b) entry of the 7x7 upper triangle that moment m holds (row-major).
+__device__ __forceinline__ void moment_pair(int m, int& a, int& b) {
+    a = 0;
+    int rem = m;
+    while (rem >= 7 - a) {
+        rem -= 7 - a;
+        ++a;
+    }
+    b = a + rem;
+}
+
+// Add the window rows of this wave's lanes (those with `inwin`) to the wave's
+// own window sums, in lane order: the rows r = [a | b] are staged in LDS in
+// lane order, then lane m < 28 adds product m of each staged row in turn (lane
+// 28 the count), so the sums do not depend on timing.
+__device__ __forceinline__ void window_add(bool inwin, int bin_off, const float (&p)[3], const float (&d)[3],
+                                           const float (&n)[3], float (*win)[ICP_NMOM + 1], float (*stage)[8]) {
+    const int lane = threadIdx.x & 63;
+    uint64_t m = __ballot(inwin);
+    if (!m) return;
+    int ma, mb;
+    moment_pair(min(lane, ICP_NMOM - 1), ma, mb);
+    while (m) {
+        // the lowest ICP_STAGE pending lanes
+        uint64_t c = m, keep = 0;
+        for (int q = 0; q < ICP_STAGE && c; ++q) {
+            const uint64_t low = c & (~c + 1);
+            keep |= low;
+            c &= c - 1;
+        }
+        if ((keep >> lane) & 1ull) {
+            const int slot = __popcll(keep & ((1ull << lane) - 1ull));
+            float r[7];
+            make_row(p, d, n, r);
+#pragma unroll
+            for (int t = 0; t < 7; ++t) stage[slot][t] = r[t];
+            stage[slot][7] = __int_as_float(bin_off);
+        }
+        wave_sync();
+        const int nst = __popcll(keep);
+        if (lane <= ICP_NMOM) {
+            for (int j = 0; j < nst; ++j) {
+                const int b = __float_as_int(stage[j][7]);
+                win[b][lane] += lane < ICP_NMOM ? stage[j][ma] * stage[j][mb] : 1.0f;
+            }
+        }
+        wave_sync();
+        m &= ~keep;
+    }
+}
+
 template <bool kDebug, bool kFused>
 __global__ __launch_bounds__(ICP_WG) void k_pass1(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
                                                   IterCtl ctl, KParams kp, uint8_t* __restrict__ dbg_code,
                                                   int32_t* __restrict__ dbg_bin) {
     __shared__ uint32_t sh_hist[ICP_HIST_BINS];
-    __shared__ float sh_win[kFused ? ICP_WIN * (ICP_NMOM + 1) : 1];
+    __shared__ float sh_win[kFused ? ICP_WAVES : 1][kFused ? ICP_WIN : 1][ICP_NMOM + 1];
+    __shared__ float sh_stage[kFused ? ICP_WAVES : 1][kFused ? ICP_STAGE : 1][8];
     __shared__ float sh_red[ICP_WAVES][ICP_PART_STRIDE];
     const int g = blockIdx.x;
     const ProbDesc& P = probs[owner[g]];
@@ -246,8 +306,9 @@ __global__ __launch_bounds__(ICP_WG) void k_pass1(const ProbDesc* __restrict__ p
     const int h0 = kFused ? window_start(st->pred_hi) : -1;
     for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) sh_hist[b] = 0u;
     if (kFused && h0 >= 0)
-        for (int b = tid; b < ICP_WIN * (ICP_NMOM + 1); b += ICP_WG) sh_win[b] = 0.0f;
+        for (int b = tid; b < ICP_WAVES * ICP_WIN * (ICP_NMOM + 1); b += ICP_WG) (&sh_win[0][0][0])[b] = 0.0f;
     __syncthreads();
+    const int wave = tid >> 6;
     float acc[ICP_NMOM];
 #pragma unroll
     for (int k = 0; k < ICP_NMOM; ++k) acc[k] = 0.0f;
@@ -258,32 +319,22 @@ __global__ __launch_bounds__(ICP_WG) void k_pass1(const ProbDesc* __restrict__ p
         const int base = tile * L.tile_px;
         const int end = min(base + L.tile_px, L.npx);
         for (int i = base + ICP_PX_PER_THREAD * tid; i < end; i += ICP_TILE_QUANTUM) {
-            Quad q;
-            associate4(Lv, i, T, kp.d2max, kp.cos_max, q);
-#pragma unroll
-            for (int k = 0; k < ICP_PX_PER_THREAD; ++k) {
+            associate4(Lv, i, T, kp.d2max, kp.cos_max, [&](int k, const PixelOut& q) {
                 if (kDebug && i + k < end) {
-                    if (dbg_code) dbg_code[i + k] = (uint8_t)q.code[k];
-                    if (dbg_bin) dbg_bin[i + k] = q.bin[k];
+                    if (dbg_code) dbg_code[i + k] = (uint8_t)q.code;
+                    if (dbg_bin) dbg_bin[i + k] = q.bin;
                 }
-                if (q.code[k] != kGated) continue;
-                atomicAdd(&sh_hist[q.bin[k]], 1u);
+                const bool gated = q.code == kGated;
+                if (gated) atomicAdd(&sh_hist[q.bin], 1u);
                 if (kFused && h0 >= 0) {
-                    if (q.bin[k] < h0) {
-                        accumulate_row(q.p[k], q.d[k], q.n[k], acc);
+                    if (gated && q.bin < h0) {
+                        accumulate_row(q.p, q.d, q.n, acc);
                         cnt += 1.0f;
-                    } else if (q.bin[k] < h0 + ICP_WIN) {
-                        float w[ICP_NMOM];
-#pragma unroll
-                        for (int m = 0; m < ICP_NMOM; ++m) w[m] = 0.0f;
-                        accumulate_row(q.p[k], q.d[k], q.n[k], w);
-                        float* slot = sh_win + (q.bin[k] - h0) * (ICP_NMOM + 1);
-#pragma unroll
-                        for (int m = 0; m < ICP_NMOM; ++m) atomicAdd(slot + m, w[m]);
-                        atomicAdd(slot + ICP_NMOM, 1.0f);
                     }
+                    const bool inwin = gated && q.bin >= h0 && q.bin < h0 + ICP_WIN;
+                    window_add(inwin, q.bin - h0, q.p, q.d, q.n, sh_win[wave], sh_stage[wave]);
                 }
-            }
+            });
         }
     }
     __syncthreads();
@@ -295,9 +346,15 @@ __global__ __launch_bounds__(ICP_WG) void k_pass1(const ProbDesc* __restrict__ p
     if (kFused && h0 >= 0) {
         float* part = L.part1 + (size_t)tile * ICP_WIN_SLOTS * ICP_PART_STRIDE;
         block_reduce_row(acc, cnt, sh_red, part);
-        for (int e = tid; e < ICP_WIN * (ICP_NMOM + 1); e += ICP_WG) {
-            const int b = e / (ICP_NMOM + 1), m = e - b * (ICP_NMOM + 1);
-            part[(b + 1) * ICP_PART_STRIDE + m] = sh_win[e];
+        // slot b+1 holds the prefix sum over window bins 0..b, so the band
+        // kernel needs two slots per tile whatever the band edge
+        __syncthreads();
+        if (tid <= ICP_NMOM) {
+            float run = 0.0f;
+            for (int b = 0; b < ICP_WIN; ++b) {
+                run += (sh_win[0][b][tid] + sh_win[1][b][tid]) + (sh_win[2][b][tid] + sh_win[3][b][tid]);
+                part[(b + 1) * ICP_PART_STRIDE + tid] = run;
+            }
         }
     }
 }
@@ -335,10 +392,10 @@ __device__ void solve_epilogue(ProbState* st, const double* M, int64_t n, const 
     }
 }
 
-// Deterministic FP64 sums of `nslots` consecutive 32-float slots of every
-// tile partial (tile order, then slot order) into sh_out[0..28]; whole
+// Deterministic FP64 sums over the tiles (in tile order) of slot 0 plus, if
+// slot2 > 0, slot `slot2` of every tile partial into sh_out[0..28]; whole
 // work-group.
-__device__ void sum_partials(const float* part, int n_tiles, int tile_stride, int nslots, double* sh_out) {
+__device__ void sum_partials(const float* part, int n_tiles, int tile_stride, int slot2, double* sh_out) {
     __shared__ double sh_sum[ICP_NMOM + 1][8];
     const int tid = threadIdx.x;
     const int j = tid >> 3, c = tid & 7;
@@ -348,9 +405,9 @@ __device__ void sum_partials(const float* part, int n_tiles, int tile_stride, in
         double s = 0.0;
         for (int t = t0; t < t1; ++t) {
             const float* q = part + (size_t)t * tile_stride + j;
-            double st = 0.0;
-            for (int k = 0; k < nslots; ++k) st += (double)q[k * ICP_PART_STRIDE];
-            s += st;
+            double v = (double)q[0];
+            if (slot2 > 0) v += (double)q[slot2 * ICP_PART_STRIDE];
+            s += v;
         }
         sh_sum[j][c] = s;
     }
@@ -446,7 +503,7 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     const Band b = median_band(st, kp, dbg_hist);
     const bool hit = h0 >= 0 && b.N > 0 && b.k_lo == 0 && b.k_hi >= h0 - 1 && b.k_hi <= h0 + ICP_WIN - 1;
     if (hit) {
-        sum_partials(L.part1, L.n_tiles, ICP_WIN_SLOTS * ICP_PART_STRIDE, b.k_hi - h0 + 2, sh_M);
+        sum_partials(L.part1, L.n_tiles, ICP_WIN_SLOTS * ICP_PART_STRIDE, b.k_hi - h0 + 1, sh_M);
         if (threadIdx.x == 0) solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp);
     }
     if (threadIdx.x == 0) {
@@ -481,15 +538,12 @@ __global__ __launch_bounds__(ICP_WG) void k_pass2(const ProbDesc* __restrict__ p
         const int base = tile * L.tile_px;
         const int end = min(base + L.tile_px, L.npx);
         for (int i = base + ICP_PX_PER_THREAD * tid; i < end; i += ICP_TILE_QUANTUM) {
-            Quad q;
-            associate4(Lv, i, T, kp.d2max, kp.cos_max, q);
-#pragma unroll
-            for (int k = 0; k < ICP_PX_PER_THREAD; ++k) {
-                if (q.code[k] == kGated && q.bin[k] >= klo && q.bin[k] <= khi) {
-                    accumulate_row(q.p[k], q.d[k], q.n[k], acc);
+            associate4(Lv, i, T, kp.d2max, kp.cos_max, [&](int, const PixelOut& q) {
+                if (q.code == kGated && q.bin >= klo && q.bin <= khi) {
+                    accumulate_row(q.p, q.d, q.n, acc);
                     cnt += 1.0f;
                 }
-            }
+            });
         }
     }
     block_reduce_row(acc, cnt, sh_red, L.part + (size_t)tile * ICP_PART_STRIDE);
@@ -503,7 +557,7 @@ __global__ __launch_bounds__(ICP_WG) void k_solve(const ProbDesc* __restrict__ p
     const LevelDesc& L = P.lv[ctl.level];
     ProbState* st = P.st;
     if (!st->fused_done && !st->level_done) {
-        sum_partials(L.part, L.n_tiles, ICP_PART_STRIDE, 1, sh_M);
+        sum_partials(L.part, L.n_tiles, ICP_PART_STRIDE, 0, sh_M);
         if (threadIdx.x == 0) solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp);
     }
     if (threadIdx.x == 0) {

@@ -247,6 +247,30 @@ def test_batch_matches_single(ctx):
         assert ang < POSE_TOL and dt < POSE_TOL, (p.name, ang, dt)
 
 
+def test_graph_replays_match_eager(ctx):
+    """Registrations replayed from a captured HIP graph equal the eagerly
+    launched ones bit for bit, replay after replay, with unrelated eager GPU
+    work and synchronisations in between."""
+    seq = synth.RoomSequence(2, n_frames=4)
+    probs = [seq.problem(k) for k in range(3)] + [synth.config1_problem(4)]
+    data = [upload(p) for p in probs]
+    params = icp.icp_params_default()
+    icp.icp_ctx_set_graphs(ctx, False)
+    eager = [icp.icp_register(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, params)
+             for p, (d, mv, mn) in zip(probs, data)]
+    icp.icp_ctx_set_graphs(ctx, True)
+    try:
+        for rep in range(3):
+            for p, (d, mv, mn), (Te, se) in zip(probs, data, eager):
+                Tg, sg = icp.icp_register(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, params)
+                assert np.array_equal(Tg, Te) and sg == se, (rep, p.name)
+                junk = torch.arange(4096, device="cuda", dtype=torch.float32)
+                assert float((junk * 2).sum().item()) == 4095.0 * 4096.0
+                torch.cuda.synchronize()
+    finally:
+        icp.icp_ctx_set_graphs(ctx, True)
+
+
 def test_edge_cases(ctx):
     prob = synth.config1_problem(0)
     params = icp.icp_params_default()
