@@ -240,13 +240,16 @@ int icp_ctx_get_timing(icp_ctx* ctx, icp_kernel_time* out);
    They use the same kernels and launch configuration as icp_register on one
    problem held in the context. */
 
-/* Build the live and model pyramids of one problem into the context. */
+/* Build the live and model pyramids of one problem into the context.  The
+   later stage calls read the caller's level-0 model maps, which must stay
+   alive until the next icp_stage_prepare or registration call. */
 int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const float* model_vtx,
                       const float* model_nrm, const icp_intrinsics* K, int levels, void* stream);
 
 /* Copy level `level` of the prepared pyramids to device buffers (any may be
-   NULL): depth (H_l*W_l), live vertex/normal and model vertex/normal as
-   three planes of H_l*W_l floats (x plane, y plane, z plane).  Synchronises. */
+   NULL): depth (H_l*W_l), live vertex/normal as three planes of H_l*W_l
+   floats (x plane, y plane, z plane), model vertex/normal interleaved
+   (H_l*W_l*3; level 0 is the caller's input).  Synchronises. */
 int icp_stage_level(icp_ctx* ctx, int level, float* depth, float* live_vtx, float* live_nrm,
                     float* model_vtx, float* model_nrm, void* stream);
 

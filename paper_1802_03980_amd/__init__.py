@@ -335,12 +335,14 @@ def icp_stage_prepare(ctx, live_depth, model_vtx, model_nrm, K, levels=3, stream
 
 
 def icp_stage_level(ctx, level, H, W, stream=None):
-    """Level maps as device tensors: depth (H_l, W_l) and four (3, H_l, W_l)."""
+    """Level maps as device tensors: depth (H_l, W_l), live vertex and normal
+    (3, H_l, W_l) planes, model vertex and normal (H_l, W_l, 3) interleaved."""
     import torch
     Hl, Wl = H >> level, W >> level
     dev = torch.device("cuda", ctx.device)
     D = torch.empty((Hl, Wl), dtype=torch.float32, device=dev)
-    maps = [torch.empty((3, Hl, Wl), dtype=torch.float32, device=dev) for _ in range(4)]
+    maps = [torch.empty((3, Hl, Wl), dtype=torch.float32, device=dev) for _ in range(2)]
+    maps += [torch.empty((Hl, Wl, 3), dtype=torch.float32, device=dev) for _ in range(2)]
     rc = lib().icp_stage_level(ctx.handle, level, C.c_void_p(D.data_ptr()),
                                *[C.c_void_p(m.data_ptr()) for m in maps], _stream(stream))
     _check(ctx, rc)

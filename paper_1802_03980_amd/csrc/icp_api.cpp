@@ -172,8 +172,9 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
             L.Dw = l > 0 ? reinterpret_cast<float*>(take(S)) : nullptr;
             L.LV = reinterpret_cast<float*>(take(3 * S));
             L.LN = reinterpret_cast<float*>(take(3 * S));
-            L.MV = reinterpret_cast<float*>(take(3 * S));
-            L.MN = reinterpret_cast<float*>(take(3 * S));
+            const size_t A = (size_t)L.npx * 3 * sizeof(float);
+            L.MVw = l > 0 ? reinterpret_cast<float*>(take(A)) : nullptr;
+            L.MNw = l > 0 ? reinterpret_cast<float*>(take(A)) : nullptr;
             L.part = reinterpret_cast<float*>(take((size_t)L.n_tiles * ICP_PART_STRIDE * sizeof(float)));
             L.part1 = reinterpret_cast<float*>(
                 take((size_t)L.n_tiles * ICP_WIN_SLOTS * ICP_PART_STRIDE * sizeof(float)));
@@ -308,13 +309,13 @@ int stage_batch(icp_ctx* ctx, int n, const icp_problem* probs, int levels, const
             L.D = l > 0 ? L.Dw : q.live_depth;
             L.LV = rebase(L.LV, base);
             L.LN = rebase(L.LN, base);
-            L.MV = rebase(L.MV, base);
-            L.MN = rebase(L.MN, base);
+            L.MVw = l > 0 ? rebase(L.MVw, base) : nullptr;
+            L.MNw = l > 0 ? rebase(L.MNw, base) : nullptr;
+            L.MV = l > 0 ? L.MVw : q.model_vtx;
+            L.MN = l > 0 ? L.MNw : q.model_nrm;
             L.part = rebase(L.part, base);
             L.part1 = rebase(L.part1, base);
         }
-        d.model_vtx = q.model_vtx;
-        d.model_nrm = q.model_nrm;
         std::memcpy(d.imu_R, q.imu_R, sizeof(d.imu_R));
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 4; ++j) d.init[4 * i + j] = q.init_pose[4 * i + j];
@@ -688,14 +689,16 @@ int icp_stage_level(icp_ctx* ctx, int level, float* depth, float* live_vtx, floa
     const LevelDesc& L = ctx->stage_desc.lv[level];
     const size_t S = (size_t)L.npx * sizeof(float);
     if (depth) HIP_TRY(ctx, hipMemcpyAsync(depth, L.D, S, hipMemcpyDeviceToDevice, s));
-    float* dst[4] = {live_vtx, live_nrm, model_vtx, model_nrm};
-    const float* src[4] = {L.LV, L.LN, L.MV, L.MN};
-    for (int m = 0; m < 4; ++m) {
+    float* dst[2] = {live_vtx, live_nrm};
+    const float* src[2] = {L.LV, L.LN};
+    for (int m = 0; m < 2; ++m) {
         if (!dst[m]) continue;
         for (int c = 0; c < 3; ++c)  // planes are ps floats apart in the workspace, packed in the output
             HIP_TRY(ctx, hipMemcpyAsync(dst[m] + (size_t)c * L.npx, src[m] + (size_t)c * L.ps, S,
                                         hipMemcpyDeviceToDevice, s));
     }
+    if (model_vtx) HIP_TRY(ctx, hipMemcpyAsync(model_vtx, L.MV, 3 * S, hipMemcpyDeviceToDevice, s));
+    if (model_nrm) HIP_TRY(ctx, hipMemcpyAsync(model_nrm, L.MN, 3 * S, hipMemcpyDeviceToDevice, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     return ICP_OK;
 }

@@ -2,13 +2,15 @@
 //
 // HBM layout per problem (all float32, level l has W_l x H_l = (W>>l) x (H>>l)):
 //   live depth D_l (level 0 is the caller's buffer), live vertex LV_l and
-//   normal LN_l, model vertex MV_l and normal MN_l, each as three planes (x
-//   plane, y plane, z plane) of W_l*H_l floats, consecutive planes `ps` floats
-//   apart (W_l*H_l rounded up to 64, so every plane starts on a 256-byte
-//   boundary and a thread can read four consecutive pixels as one 16-byte
-//   load).  Invalid entries are NaN (maps) or 0 (depth).  Per level a problem
-//   also owns one 32-float partial per work-group tile.  The small per-problem
-//   state (pose, histogram, band, tickets, statistics) lives in one ProbState.
+//   normal LN_l as three planes (x plane, y plane, z plane) of W_l*H_l floats,
+//   consecutive planes `ps` floats apart (W_l*H_l rounded up to 64, so every
+//   plane starts on a 256-byte boundary and a thread reads four consecutive
+//   pixels as one 16-byte load); model vertex MV_l and normal MN_l interleaved
+//   (x, y, z per pixel: a projective lookup gathers 12 contiguous bytes per
+//   map), level 0 being the caller's buffers.  Invalid entries are NaN (maps)
+//   or 0 (depth).  Per level a problem also owns its tile partials.  The small
+//   per-problem state (pose, histogram, band, statistics) lives in one
+//   ProbState.
 #pragma once
 
 #include <stdint.h>
@@ -35,9 +37,11 @@ struct LevelDesc {
     const float* D;             // depth (level 0: caller input)
     float* Dw;                  // writable depth (levels >= 1), same as D there
     float* LV;                  // live vertex, 3 planes
-    float* LN;                  // live normal
-    float* MV;                  // model vertex
-    float* MN;                  // model normal
+    float* LN;                  // live normal, 3 planes
+    const float* MV;            // model vertex, interleaved (level 0: caller's buffer)
+    const float* MN;            // model normal, interleaved
+    float* MVw;                 // writable model maps (levels >= 1), same as MV/MN there
+    float* MNw;
     float* part;                // pass-2 partials: n_tiles * ICP_PART_STRIDE
     float* part1;               // single-pass partials: n_tiles * ICP_WIN_SLOTS * ICP_PART_STRIDE
 };
@@ -62,8 +66,6 @@ struct ProbState {
 
 struct ProbDesc {
     LevelDesc lv[ICP_MAX_LEVELS];
-    const float* model_vtx;     // caller's AoS model maps (level 0)
-    const float* model_nrm;
     double imu_R[9];            // IMU rotation prior, row-major
     double init[12];            // initial pose, 3x4 row-major [R | t]
     ProbState* st;

@@ -127,10 +127,10 @@ __device__ __forceinline__ vf4 ld4(const ICP_GLOBAL float* p) { return *(const I
 // Written as straight-line code: every quantity is computed for every pixel
 // (NaN inputs propagate and fail every comparison) and the code is selected
 // at the end in the order the checks are defined, so a wavefront runs one
-// path.  Every map stores an invalid pixel as NaN in all three components,
-// so one component decides validity.  The live vertices arrive as one
-// 16-byte load per plane; the model gathers of the four pixels and the live
-// normals are issued together.
+// path.  The live maps store an invalid pixel as NaN in all three components,
+// so one component decides their validity.  The live vertices arrive as one
+// 16-byte load per plane; the model gathers (12 contiguous bytes per map) of
+// the four pixels and the live normals are issued together.
 template <class Emit>
 __device__ __forceinline__ void associate4(const Lvl& L, int i, const Pose& T, double d2max, double cos_max,
                                            Emit&& emit) {
@@ -162,14 +162,16 @@ __device__ __forceinline__ void associate4(const Lvl& L, int i, const Pose& T, d
     for (int k = 0; k < 4; ++k) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Q[k][c] = L.MV[c * S + j[k]];
-            M[k][c] = L.MN[c * S + j[k]];
+            Q[k][c] = L.MV[3 * j[k] + c];
+            M[k][c] = L.MN[3 * j[k] + c];
         }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const bool nok = fin(N[k][2]);
-        const bool mok = fin(Q[k][2]);
+        // the caller's level-0 model maps may be partly NaN: all six decide
+        const bool mok = fin(Q[k][0]) && fin(Q[k][1]) && fin(Q[k][2]) && fin(M[k][0]) && fin(M[k][1]) &&
+                         fin(M[k][2]);
         const double d0 = (double)Q[k][0] - P[k][0];
         const double d1 = (double)Q[k][1] - P[k][1];
         const double d2 = (double)Q[k][2] - P[k][2];

@@ -137,52 +137,33 @@ __global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__
     L.LN[2 * S + i] = n[2];
 }
 
-// Model maps, level 0: interleaved input -> planes; a pixel is valid iff all
-// six values are finite, invalid pixels become NaN in all six.
-__global__ __launch_bounds__(ICP_WG) void k_model_l0(const ProbDesc* __restrict__ probs) {
-    const ProbDesc& P = probs[blockIdx.y];
-    const LevelDesc& L = P.lv[0];
-    const int i = blockIdx.x * ICP_WG + threadIdx.x;
-    if (i >= L.npx) return;
-    const int S = L.ps;
-    float v[3], n[3];
-    bool ok = true;
-    for (int k = 0; k < 3; ++k) {
-        v[k] = P.model_vtx[3 * (size_t)i + k];
-        n[k] = P.model_nrm[3 * (size_t)i + k];
-        ok = ok && fin(v[k]) && fin(n[k]);
-    }
-    const float qnan = __builtin_nanf("");
-    for (int k = 0; k < 3; ++k) {
-        L.MV[k * S + i] = ok ? v[k] : qnan;
-        L.MN[k * S + i] = ok ? n[k] : qnan;
-    }
-}
-
-// Model level l from l-1: vertex = mean of the four children, normal = their
-// normalised sum, valid iff all four children are valid.
+// Model level l from l-1 (interleaved maps): vertex = mean of the four
+// children, normal = their normalised sum, valid iff all four children have
+// six finite values; invalid pixels are NaN in all six.
 __global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restrict__ probs, int level) {
     const ProbDesc& P = probs[blockIdx.y];
     const LevelDesc& F = P.lv[level - 1];
     const LevelDesc& C = P.lv[level];
     const int i = blockIdx.x * ICP_WG + threadIdx.x;
     if (i >= C.npx) return;
-    const int SF = F.ps, SC = C.ps;
     const int u = i % C.W, v = i / C.W;
     const int ch[4] = {(2 * v) * F.W + 2 * u, (2 * v) * F.W + 2 * u + 1, (2 * v + 1) * F.W + 2 * u,
                        (2 * v + 1) * F.W + 2 * u + 1};
     const float qnan = __builtin_nanf("");
-    float vo[3] = {qnan, qnan, qnan}, no[3] = {qnan, qnan, qnan};
+    float cv[4][3], cn[4][3];
     bool ok = true;
     for (int j = 0; j < 4; ++j)
-        for (int k = 0; k < 3; ++k) ok = ok && fin(F.MV[k * SF + ch[j]]) && fin(F.MN[k * SF + ch[j]]);
+        for (int k = 0; k < 3; ++k) {
+            cv[j][k] = F.MV[3 * ch[j] + k];
+            cn[j][k] = F.MN[3 * ch[j] + k];
+            ok = ok && fin(cv[j][k]) && fin(cn[j][k]);
+        }
+    float vo[3] = {qnan, qnan, qnan}, no[3] = {qnan, qnan, qnan};
     if (ok) {
         double s[3];
         for (int k = 0; k < 3; ++k) {
-            const float* V = F.MV + k * SF;
-            const float* N = F.MN + k * SF;
-            const double m = (((double)V[ch[0]] + (double)V[ch[1]]) + (double)V[ch[2]]) + (double)V[ch[3]];
-            s[k] = (((double)N[ch[0]] + (double)N[ch[1]]) + (double)N[ch[2]]) + (double)N[ch[3]];
+            const double m = (((double)cv[0][k] + (double)cv[1][k]) + (double)cv[2][k]) + (double)cv[3][k];
+            s[k] = (((double)cn[0][k] + (double)cn[1][k]) + (double)cn[2][k]) + (double)cn[3][k];
             vo[k] = (float)(m * 0.25);
         }
         const double len2 = (s[0] * s[0] + s[1] * s[1]) + s[2] * s[2];
@@ -194,8 +175,8 @@ __global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restric
         }
     }
     for (int k = 0; k < 3; ++k) {
-        C.MV[k * SC + i] = vo[k];
-        C.MN[k * SC + i] = no[k];
+        C.MVw[3 * i + k] = vo[k];
+        C.MNw[3 * i + k] = no[k];
     }
 }
 
@@ -635,7 +616,6 @@ hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* m
         hipLaunchKernelGGL(k_depth_down, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
     for (int l = 0; l < levels; ++l)
         hipLaunchKernelGGL(k_live_vn, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
-    hipLaunchKernelGGL(k_model_l0, dim3(blocks_for(max_npx[0]), n), dim3(ICP_WG), 0, s, probs);
     for (int l = 1; l < levels; ++l)
         hipLaunchKernelGGL(k_model_down, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
     return hipGetLastError();

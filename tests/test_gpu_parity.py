@@ -47,12 +47,18 @@ def _same_nan(a, b):
     return np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(a[~np.isnan(a)], b[~np.isnan(b)])
 
 
+_ALIVE = []  # the prepared stage problem keeps reading the level-0 model maps
+
+
 def _gpu_levels(ctx, prob, levels=3):
     d, mv, mn = upload(prob)
+    _ALIVE[:] = [d, mv, mn]
     icp.icp_stage_prepare(ctx, d, mv, mn, prob.K, levels)
     out = []
     for l in range(levels):
         D, LV, LN, MV, MN = (host(t) for t in icp.icp_stage_level(ctx, l, prob.H, prob.W))
+        # model maps come back interleaved; the oracle takes planes
+        MV, MN = np.ascontiguousarray(np.moveaxis(MV, -1, 0)), np.ascontiguousarray(np.moveaxis(MN, -1, 0))
         out.append(dict(D=D, LV=LV, LN=LN, MV=MV, MN=MN, K=oracle.level_intrinsics(prob.K, l)))
     return out
 
@@ -285,6 +291,20 @@ def test_edge_cases(ctx):
     Tg, sg = icp.icp_register(ctx, dev(prob.live_depth), dev(nanm), dev(nanm), prob.K, prob.imu_R,
                               prob.init_pose, params)
     assert sg["status"] == icp.TOO_FEW_CORR
+    # model pixels with only some components NaN are invalid as a whole
+    rng = np.random.default_rng(9)
+    pv = prob.model_vtx.copy()
+    pn = prob.model_nrm.copy()
+    pick = rng.random(pv.shape[:2]) < 0.05
+    pv[pick, 1] = np.nan
+    pick = rng.random(pv.shape[:2]) < 0.05
+    pn[pick, 2] = np.nan
+    part = synth.Problem(live_depth=prob.live_depth, model_vtx=pv, model_nrm=pn, K=prob.K, imu_R=prob.imu_R,
+                         init_pose=prob.init_pose, T_gt=prob.T_gt, name="partial-nan")
+    Tg, sg, To, so = _register_both(ctx, part, params)
+    ang, dt = pose_err(Tg, To)
+    assert ang < POSE_TOL and dt < POSE_TOL, (ang, dt)
+    assert [s["n_kept"] for s in sg["levels"]] == [s["n_kept"] for s in so]
     # ragged size (tiles do not divide the levels) and 1 / 4 levels
     for levels, W, H in [(1, 100, 70), (3, 168, 124), (4, 176, 136)]:
         p = synth.config1_problem(5, W=W, H=H, f=130.0 * W / 160)
