@@ -98,7 +98,10 @@ typedef struct {
     double ill_cond_eps;            /* LDL^T pivot threshold relative to the max diagonal */
     int32_t converge_window;        /* 0: fixed cadence; k >= 1: a level stops once the median
                                        bin is unchanged on k successive iterations (Sec. 3.4) */
-    int32_t reduce_mode;            /* 0: FP32 moment reduction */
+    int32_t reduce_mode;            /* 0: FP32 moment reduction; 1: rows centred on the live
+                                       centroid, split into FP16 hi + lo and reduced with
+                                       MFMA (FP32 accumulation), un-centred in FP64 (uses two
+                                       passes) */
     int32_t pass_mode;              /* 0: single pass over the maps when the band edge falls in a
                                        window around the previous iteration's edge (two passes
                                        otherwise; needs band_beta >= 1 or no median filter);

@@ -95,7 +95,7 @@ int check_params(icp_ctx* ctx, const icp_params* p) {
     if (p->min_corr < 1) return fail(ctx, ICP_EINVAL, "min_corr must be >= 1");
     if (!(p->ill_cond_eps >= 0.0)) return fail(ctx, ICP_EINVAL, "ill_cond_eps must be >= 0");
     if (p->converge_window < 0) return fail(ctx, ICP_EINVAL, "converge_window must be >= 0");
-    if (p->reduce_mode != 0) return fail(ctx, ICP_EINVAL, "unknown reduce_mode");
+    if (p->reduce_mode != 0 && p->reduce_mode != 1) return fail(ctx, ICP_EINVAL, "reduce_mode must be 0 or 1");
     if (p->pass_mode != 0 && p->pass_mode != 1) return fail(ctx, ICP_EINVAL, "pass_mode must be 0 or 1");
     return ICP_OK;
 }
@@ -265,6 +265,7 @@ KParams kparams(const icp_params* p) {
     k.use_filter = p->use_median_filter;
     k.min_corr = p->min_corr;
     k.converge_window = p->converge_window;
+    k.reduce_mode = p->reduce_mode;
     return k;
 }
 
@@ -404,9 +405,13 @@ int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* r
     for (int p = 0; p < n; ++p) px0 += P.desc[p].lv[0].npx;
     if ((rc = time_begin(ctx, s, r, ICP_TIME_FRONT_END, px0))) return rc;
     HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, P.max_npx, s));
+    if (prm->reduce_mode == 1) HIP_TRY(ctx, icpk::launch_centroid(d_desc, n, prm->levels, s));
     if ((rc = time_end(ctx, s, r))) return rc;
-    // single pass needs the band's lower edge at bin 0
-    const int fused = prm->pass_mode == 0 && (!prm->use_median_filter || prm->band_beta >= 1.0) ? 1 : 0;
+    // single pass needs the band's lower edge at bin 0 and the FP32 reduction
+    const int fused = prm->pass_mode == 0 && prm->reduce_mode == 0 &&
+                              (!prm->use_median_filter || prm->band_beta >= 1.0)
+                          ? 1
+                          : 0;
     for (int l = prm->levels - 1; l >= 0; --l) {
         const int* owner = reinterpret_cast<const int*>(base + P.off_owner[l]);
         int64_t px = 0;
@@ -668,6 +673,7 @@ int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const
     ctx->stage_levels = levels;
     HIP_TRY(ctx, icpk::launch_init(ctx->d_desc, 1, 0, s));
     HIP_TRY(ctx, icpk::launch_prepare(ctx->d_desc, 1, levels, P.max_npx, s));
+    HIP_TRY(ctx, icpk::launch_centroid(ctx->d_desc, 1, levels, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     ctx->stage_ready = true;
     return ICP_OK;
@@ -719,7 +725,7 @@ int icp_stage_associate(icp_ctx* ctx, int level, const double* pose12, const icp
     hipStream_t s = static_cast<hipStream_t>(stream);
     const KParams kp = kparams(params);
     uint32_t* d_hist = reinterpret_cast<uint32_t*>(ctx->d_scratch);
-    HIP_TRY(ctx, icpk::launch_stage_set(ctx->d_desc, pose_arg(pose12), 0, -1, s));
+    HIP_TRY(ctx, icpk::launch_stage_set(ctx->d_desc, pose_arg(pose12), 0, -1, level, s));
     IterCtl ctl{level, 0, 0, 0};
     HIP_TRY(ctx, icpk::launch_stage_pass1(ctx->d_desc, ctx->d_owner[level], ctx->tiles[level], ctl, kp, code, bin,
                                           d_hist, s));
@@ -747,7 +753,7 @@ int icp_stage_moments(icp_ctx* ctx, int level, const double* pose12, const icp_p
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const KParams kp = kparams(params);
-    HIP_TRY(ctx, icpk::launch_stage_set(ctx->d_desc, pose_arg(pose12), k_lo, k_hi, s));
+    HIP_TRY(ctx, icpk::launch_stage_set(ctx->d_desc, pose_arg(pose12), k_lo, k_hi, level, s));
     IterCtl ctl{level, 0, 0, 1};
     HIP_TRY(ctx, icpk::launch_stage_pass2(ctx->d_desc, ctx->d_owner[level], ctx->tiles[level], ctl, kp, s));
     HIP_TRY(ctx, hipMemcpyAsync(moments, ctx->d_state->M, sizeof(double) * ICP_NMOM, hipMemcpyDeviceToHost, s));

@@ -62,6 +62,8 @@ struct ProbState {
     int32_t last_kmed;
     int32_t last_status;        // status of the last solve
     icp_stats stats;
+    double cen[ICP_MAX_LEVELS][3];  // centroid of each level's valid live vertices
+    double cur_c[3];            // centring point of the current iteration (model frame)
 };
 
 struct ProbDesc {
@@ -89,4 +91,5 @@ struct KParams {
     int32_t use_filter;
     int32_t min_corr;
     int32_t converge_window;
+    int32_t reduce_mode;        // 0: FP32 rows; 1: FP16 hi+lo split MFMA on centred rows
 };

@@ -180,6 +180,41 @@ __global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restric
     }
 }
 
+// Centroid of the valid live vertices of one level (one work-group per
+// problem and level, grid.y = level): the centring point of the split-
+// precision reduction.  Deterministic FP64 sums.
+__global__ __launch_bounds__(ICP_WG) void k_centroid(const ProbDesc* __restrict__ probs) {
+    __shared__ double sh[ICP_WG][4];
+    const ProbDesc& P = probs[blockIdx.x];
+    const int level = blockIdx.y;
+    const LevelDesc& L = P.lv[level];
+    const int tid = threadIdx.x;
+    double sx = 0.0, sy = 0.0, sz = 0.0, n = 0.0;
+    for (int i = tid; i < L.npx; i += ICP_WG) {
+        const float z = L.LV[2 * L.ps + i];
+        if (fin(z)) {
+            sx += (double)L.LV[i];
+            sy += (double)L.LV[L.ps + i];
+            sz += (double)z;
+            n += 1.0;
+        }
+    }
+    sh[tid][0] = sx;
+    sh[tid][1] = sy;
+    sh[tid][2] = sz;
+    sh[tid][3] = n;
+    __syncthreads();
+    for (int w = ICP_WG / 2; w > 0; w >>= 1) {
+        if (tid < w)
+            for (int k = 0; k < 4; ++k) sh[tid][k] += sh[tid + w][k];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        ProbState* st = P.st;
+        for (int k = 0; k < 3; ++k) st->cen[level][k] = sh[0][3] > 0.0 ? sh[0][k] / sh[0][3] : 0.0;
+    }
+}
+
 // ------------------------------------------------------------------ pass 1
 // Association, gates and the distance histogram (Sec. 3.2).  In single-pass
 // mode the rows are also reduced: rows whose bin lies below a window around
@@ -470,6 +505,15 @@ __device__ Band median_band(ProbState* st, const KParams& kp, uint32_t* dbg_hist
     return sh_band;
 }
 
+// Centring point of the split-precision reduction: the level's live centroid
+// moved by the current pose.
+__device__ __forceinline__ void set_centre(ProbState* st, int level) {
+    for (int i = 0; i < 3; ++i)
+        st->cur_c[i] = ((st->R[3 * i] * st->cen[level][0] + st->R[3 * i + 1] * st->cen[level][1]) +
+                        st->R[3 * i + 2] * st->cen[level][2]) +
+                       st->t[i];
+}
+
 // One work-group per problem: the band; in single-pass mode, when the band
 // edge fell inside the predicted window, the kept rows' moments are summed
 // from the pass-1 partials and the iteration is completed here.
@@ -490,6 +534,7 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     if (threadIdx.x == 0) {
         st->fused_done = hit ? 1 : 0;
         if (b.N > 0) st->pred_hi = b.k_hi;
+        if (kp.reduce_mode == 1) set_centre(st, ctl.level);
     }
 }
 
@@ -530,6 +575,141 @@ __global__ __launch_bounds__(ICP_WG) void k_pass2(const ProbDesc* __restrict__ p
     block_reduce_row(acc, cnt, sh_red, L.part + (size_t)tile * ICP_PART_STRIDE);
 }
 
+// Split-precision variant of pass 2 (reduce_mode 1): each kept row
+// r = [(p' - c) x n, n, b, 1], scaled per column by a power of two, is split
+// into FP16 hi = fp16(r) and lo = fp16(r - hi).  Thirty-two rows of
+// X = [hi | lo] (32 x 16) go through one v_mfma_f32_16x16x32_f16 as
+// X^T X with FP32 accumulation; the four 8x8 blocks hi'hi + hi'lo + lo'hi +
+// lo'lo sum to the Gram matrix of the rows.  Lane l supplies column l % 16
+// of eight rows to both operands, so the product does not depend on how the
+// hardware orders the k slots.  Rows are staged through LDS: each round a
+// wave's 256 pixels form eight groups of 32.
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr float kScaleRot = 8.0f;     // |(p' - c) x n| stays well inside FP16 range
+constexpr float kScaleB = 1024.0f;    // |b| < dist_max <= 0.125 m; lifts b's lo part out of FP16 subnormals
+
+__global__ __launch_bounds__(ICP_WG) void k_pass2_mfma(const ProbDesc* __restrict__ probs,
+                                                       const int* __restrict__ owner, IterCtl ctl, KParams kp) {
+    __shared__ _Float16 sh_x[ICP_WAVES][8][16][32];  // [wave][group][column][row in group]
+    __shared__ float sh_d[ICP_WAVES][16][17];
+    __shared__ float sh_red[ICP_WAVES][ICP_PART_STRIDE];
+    const int g = blockIdx.x;
+    const ProbDesc& P = probs[owner[g]];
+    const LevelDesc& L = P.lv[ctl.level];
+    const ProbState* st = P.st;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = g - L.tile_base;
+    if (st->level_done || st->fused_done) return;  // uniform
+    const float c0 = (float)st->cur_c[0], c1 = (float)st->cur_c[1], c2 = (float)st->cur_c[2];
+    f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    {
+        const Pose T = load_pose(st);
+        const Lvl Lv = load_level(L);
+        const int klo = __builtin_amdgcn_readfirstlane(st->k_lo);
+        const int khi = __builtin_amdgcn_readfirstlane(st->k_hi);
+        const int base = tile * L.tile_px;
+        const int end = min(base + L.tile_px, L.npx);
+        const int grp = lane >> 3, q0 = 4 * (lane & 7);
+        // every wave runs the same number of rounds so the wave-level steps stay uniform
+        for (int r0 = base; r0 < end; r0 += ICP_TILE_QUANTUM) {
+            const int i = r0 + ICP_PX_PER_THREAD * tid;
+            _Float16 hv[8][4], lv[8][4];
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) hv[c][k] = lv[c][k] = (_Float16)0.0f;
+            if (i < end) {
+                associate4(Lv, i, T, kp.d2max, kp.cos_max, [&](int k, const PixelOut& q) {
+                    if (!(q.code == kGated && q.bin >= klo && q.bin <= khi)) return;
+                    const float pc[3] = {q.p[0] - c0, q.p[1] - c1, q.p[2] - c2};
+                    float r[7];
+                    make_row(pc, q.d, q.n, r);
+                    float v[8] = {r[0] * kScaleRot, r[1] * kScaleRot, r[2] * kScaleRot, r[3], r[4], r[5],
+                                  r[6] * kScaleB, 1.0f};
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const _Float16 h = (_Float16)v[c];
+                        hv[c][k] = h;
+                        lv[c][k] = (_Float16)(v[c] - (float)h);
+                    }
+                });
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const h4v hh = {hv[c][0], hv[c][1], hv[c][2], hv[c][3]};
+                const h4v ll = {lv[c][0], lv[c][1], lv[c][2], lv[c][3]};
+                *(h4v*)&sh_x[wave][grp][c][q0] = hh;
+                *(h4v*)&sh_x[wave][grp][8 + c][q0] = ll;
+            }
+            wave_sync();
+#pragma unroll
+            for (int G = 0; G < 8; ++G) {
+                const h8v a = *(const h8v*)&sh_x[wave][G][lane & 15][8 * (lane >> 4)];
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, a, acc, 0, 0, 0);
+            }
+            wave_sync();
+        }
+    }
+    // D[4 (l / 16) + t][l % 16] -> LDS, then the 8x8 Gram blocks summed
+#pragma unroll
+    for (int t = 0; t < 4; ++t) sh_d[wave][4 * (lane >> 4) + t][lane & 15] = acc[t];
+    wave_sync();
+    float mom[ICP_NMOM];
+    float cnt = 0.0f;
+    {
+        int k = 0;
+        for (int a = 0; a < 7; ++a)
+            for (int b = a; b < 7; ++b) {
+                const float gsum = (sh_d[wave][a][b] + sh_d[wave][a][8 + b]) +
+                                   (sh_d[wave][8 + a][b] + sh_d[wave][8 + a][8 + b]);
+                const float sa = a < 3 ? kScaleRot : (a == 6 ? kScaleB : 1.0f);
+                const float sb = b < 3 ? kScaleRot : (b == 6 ? kScaleB : 1.0f);
+                mom[k++] = lane == 0 ? gsum / (sa * sb) : 0.0f;
+            }
+        cnt = lane == 0 ? (sh_d[wave][7][7] + sh_d[wave][7][15]) + (sh_d[wave][15][7] + sh_d[wave][15][15]) : 0.0f;
+    }
+    block_reduce_row(mom, cnt, sh_red, L.part + (size_t)tile * ICP_PART_STRIDE);
+}
+
+// Back from centred rows: with a = [ (p' - c) x n + c x n, n ] = J a~,
+// J = [[I, [c]x], [0, I]], the moments are J M~ J^T and J g~ (FP64).
+__device__ void uncentre(double* M, const double* c) {
+    double A[6][6], g[6];
+    for (int i = 0; i < 6; ++i) {
+        for (int j = i; j < 6; ++j) A[i][j] = A[j][i] = M[tri7(i, j)];
+        g[i] = M[tri7(i, 6)];
+    }
+    const double C[3][3] = {{0.0, -c[2], c[1]}, {c[2], 0.0, -c[0]}, {-c[1], c[0], 0.0}};
+    double J[6][6] = {};
+    for (int i = 0; i < 6; ++i) J[i][i] = 1.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) J[i][3 + j] = C[i][j];
+    double T[6][6], B[6][6], h[6];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += J[i][k] * A[k][j];
+            T[i][j] = s;
+        }
+    for (int i = 0; i < 6; ++i) {
+        for (int j = 0; j < 6; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += T[i][k] * J[j][k];
+            B[i][j] = s;
+        }
+        double s = 0.0;
+        for (int k = 0; k < 6; ++k) s += J[i][k] * g[k];
+        h[i] = s;
+    }
+    for (int i = 0; i < 6; ++i) {
+        for (int j = i; j < 6; ++j) M[tri7(i, j)] = B[i][j];
+        M[tri7(i, 6)] = h[i];
+    }
+}
+
 // One work-group per problem: FP64 sum of the pass-2 partials in tile order,
 // solve, update; then the end-of-level bookkeeping.
 __global__ __launch_bounds__(ICP_WG) void k_solve(const ProbDesc* __restrict__ probs, IterCtl ctl, KParams kp) {
@@ -539,7 +719,10 @@ __global__ __launch_bounds__(ICP_WG) void k_solve(const ProbDesc* __restrict__ p
     ProbState* st = P.st;
     if (!st->fused_done && !st->level_done) {
         sum_partials(L.part, L.n_tiles, ICP_PART_STRIDE, 0, sh_M);
-        if (threadIdx.x == 0) solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp);
+        if (threadIdx.x == 0) {
+            if (kp.reduce_mode == 1) uncentre(sh_M, st->cur_c);
+            solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp);
+        }
     }
     if (threadIdx.x == 0) {
         st->fused_done = 0;
@@ -569,7 +752,7 @@ __global__ void k_finalize(const ProbDesc* __restrict__ probs, int n, icp_result
 
 // ------------------------------------------------------------------ stage access
 
-__global__ void k_stage_set(const ProbDesc* __restrict__ probs, PoseArg pose, int k_lo, int k_hi) {
+__global__ void k_stage_set(const ProbDesc* __restrict__ probs, PoseArg pose, int k_lo, int k_hi, int level) {
     ProbState* st = probs[0].st;
     for (int b = threadIdx.x; b < ICP_HIST_BINS; b += blockDim.x) st->hist[b] = 0u;
     if (threadIdx.x == 0) {
@@ -582,6 +765,7 @@ __global__ void k_stage_set(const ProbDesc* __restrict__ probs, PoseArg pose, in
         st->pred_hi = -1;
         st->fused_done = 0;
         st->level_done = 0;
+        set_centre(st, level);
     }
 }
 
@@ -608,6 +792,11 @@ static inline unsigned blocks_for(int n) { return (unsigned)((n + ICP_WG - 1) / 
 
 hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, hipStream_t s) {
     hipLaunchKernelGGL(k_init, dim3(n), dim3(ICP_WG), 0, s, probs, use_imu_seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, hipStream_t s) {
+    hipLaunchKernelGGL(k_centroid, dim3(n, levels), dim3(ICP_WG), 0, s, probs);
     return hipGetLastError();
 }
 
@@ -639,7 +828,10 @@ hipError_t launch_band(const ProbDesc* probs, int n, IterCtl ctl, const KParams&
 
 hipError_t launch_pass2(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_pass2, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+    if (kp.reduce_mode == 1)
+        hipLaunchKernelGGL(k_pass2_mfma, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+    else
+        hipLaunchKernelGGL(k_pass2, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
     return hipGetLastError();
 }
 
@@ -653,8 +845,8 @@ hipError_t launch_finalize(const ProbDesc* probs, int n, icp_result* results, hi
     return hipGetLastError();
 }
 
-hipError_t launch_stage_set(const ProbDesc* probs, PoseArg pose, int k_lo, int k_hi, hipStream_t s) {
-    hipLaunchKernelGGL(k_stage_set, dim3(1), dim3(ICP_WG), 0, s, probs, pose, k_lo, k_hi);
+hipError_t launch_stage_set(const ProbDesc* probs, PoseArg pose, int k_lo, int k_hi, int level, hipStream_t s) {
+    hipLaunchKernelGGL(k_stage_set, dim3(1), dim3(ICP_WG), 0, s, probs, pose, k_lo, k_hi, level);
     return hipGetLastError();
 }
 
@@ -667,7 +859,10 @@ hipError_t launch_stage_pass1(const ProbDesc* probs, const int* owner, int tiles
 
 hipError_t launch_stage_pass2(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_pass2, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+    if (kp.reduce_mode == 1)
+        hipLaunchKernelGGL(k_pass2_mfma, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+    else
+        hipLaunchKernelGGL(k_pass2, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
     hipLaunchKernelGGL(k_solve, dim3(1), dim3(ICP_WG), 0, s, probs, ctl, kp);
     return hipGetLastError();
 }

@@ -18,6 +18,8 @@ struct MomArg {
 // per problem: seed the pose (IMU rotation or the initial pose), clear the
 // histogram, tickets, flags and statistics
 hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, hipStream_t s);
+// centroid of every level's valid live vertices (split-precision reduction)
+hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, hipStream_t s);
 // live depth pyramid, live vertex/normal maps, model maps for every level;
 // max_npx[l] is the largest level-l pixel count over the problems
 hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, hipStream_t s);
@@ -33,7 +35,7 @@ hipError_t launch_solve(const ProbDesc* probs, int n, IterCtl ctl, const KParams
 hipError_t launch_finalize(const ProbDesc* probs, int n, icp_result* results, hipStream_t s);
 
 // stage access (problem 0 of `probs`)
-hipError_t launch_stage_set(const ProbDesc* probs, PoseArg pose, int k_lo, int k_hi, hipStream_t s);
+hipError_t launch_stage_set(const ProbDesc* probs, PoseArg pose, int k_lo, int k_hi, int level, hipStream_t s);
 hipError_t launch_stage_pass1(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
                               uint8_t* code, int32_t* bin, uint32_t* hist, hipStream_t s);
 hipError_t launch_stage_pass2(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,

@@ -126,11 +126,14 @@ def _abs_terms(pp, q, nq):
     return np.array([S[i, j] for i in range(7) for j in range(i, 7)])
 
 
+@pytest.mark.parametrize("reduce_mode", [0, 1])
 @pytest.mark.parametrize("name", list(PROBLEMS))
-def test_s3_moments(ctx, name):
+def test_s3_moments(ctx, name, reduce_mode):
+    """Both reductions (FP32 rows; centred FP16 hi+lo split on MFMA, un-centred
+    in FP64) against the oracle's FP64 sums."""
     prob = PROBLEMS[name]()
     gpu_lv = _gpu_levels(ctx, prob)
-    params = icp.icp_params_default()
+    params = icp.icp_params_default(reduce_mode=reduce_mode)
     for T in _poses_for(prob):
         for level in range(3):
             _, band = _check_associate(ctx, prob, gpu_lv, level, T, params)
@@ -207,6 +210,21 @@ def test_end_to_end_vga_room(ctx):
         assert sg["status"] == icp.LEVEL_OK
 
 
+@pytest.mark.parametrize("lam", [5.0, 0.0])
+def test_end_to_end_split_precision(ctx, lam):
+    """The FP16 hi+lo MFMA reduction reaches the oracle's pose on the small
+    scenes and on VGA room frames."""
+    params = icp.icp_params_default(reduce_mode=1, lambda_c=lam)
+    seq = synth.RoomSequence(0, n_frames=3)
+    for prob in [synth.config1_problem(0), synth.config1_problem(1), seq.problem(0), seq.problem(1)]:
+        Tg, sg, To, so = _register_both(ctx, prob, params)
+        ang, dt = pose_err(Tg, To)
+        assert ang < POSE_TOL and dt < POSE_TOL, (prob.name, ang, dt)
+        for l in range(3):
+            assert sg["levels"][l]["iters_run"] == so[l]["iters_run"]
+            assert abs(sg["levels"][l]["n_kept"] - so[l]["n_kept"]) <= max(2, 1e-3 * so[l]["n_kept"])
+
+
 @pytest.mark.parametrize("over", [dict(pass_mode=1), dict(pass_mode=0), dict(band_beta=0.5),
                                   dict(use_median_filter=0), dict(pass_mode=0, lambda_c=0.0)])
 def test_pass_modes_match_oracle(ctx, over):
@@ -253,14 +271,15 @@ def test_batch_matches_single(ctx):
         assert ang < POSE_TOL and dt < POSE_TOL, (p.name, ang, dt)
 
 
-def test_graph_replays_match_eager(ctx):
+@pytest.mark.parametrize("reduce_mode", [0, 1])
+def test_graph_replays_match_eager(ctx, reduce_mode):
     """Registrations replayed from a captured HIP graph equal the eagerly
     launched ones bit for bit, replay after replay, with unrelated eager GPU
     work and synchronisations in between."""
     seq = synth.RoomSequence(2, n_frames=4)
     probs = [seq.problem(k) for k in range(3)] + [synth.config1_problem(4)]
     data = [upload(p) for p in probs]
-    params = icp.icp_params_default()
+    params = icp.icp_params_default(reduce_mode=reduce_mode)
     icp.icp_ctx_set_graphs(ctx, False)
     eager = [icp.icp_register(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, params)
              for p, (d, mv, mn) in zip(probs, data)]
@@ -325,7 +344,7 @@ def test_invalid_arguments(ctx):
         icp.icp_register(ctx, d[:, :155].contiguous(), mv, mn, prob.K, prob.imu_R, prob.init_pose)
     assert e.value.code == icp.EINVAL
     for bad in [dict(levels=0), dict(levels=5), dict(dist_max=0.2), dict(lambda_mode=9), dict(lambda_c=-1.0),
-                dict(tile_px=(100, 0, 0))]:
+                dict(tile_px=(100, 0, 0)), dict(reduce_mode=2)]:
         with pytest.raises(icp.IcpError) as e:
             icp.icp_register(ctx, d, mv, mn, prob.K, prob.imu_R, prob.init_pose, icp.icp_params_default(**bad))
         assert e.value.code == icp.EINVAL, bad
