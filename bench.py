@@ -11,8 +11,10 @@ covers the tiles of all frames).  `value` is registrations per second over
 the timed steps with every input already resident in HBM.  Also reported:
 per-registration latency percentiles of the one-frame-per-call path, the
 roofline of the dominant kernel from HIP events recorded live on its stream,
-the pose error against the FP64 oracle on a sample of frames, and the oracle
-itself timed on the host as a CPU baseline.
+the pose error against the FP64 oracle on a sample of frames (for the FP32
+reduction and for the FP16 hi+lo split-precision MFMA reduction, whose
+throughput is reported beside it), and the oracle itself timed on the host as
+a CPU baseline.
 """
 from __future__ import annotations
 
@@ -102,6 +104,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline and pose check")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-frame-per-call latency pass")
     ap.add_argument("--cache-dir", default="", help="reuse generated frames stored here (created if missing)")
+    ap.add_argument("--no-split", action="store_true", help="skip the FP16 hi+lo split-precision pass")
+    ap.add_argument("--pose-report", default="", help="write per-frame pose errors vs the oracle to this file")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -173,6 +177,26 @@ def main():
     value = n * args.steps / t_total
     log(f"batched: {value:.1f} registrations/s, {t_total / args.steps * 1e3:.2f} ms per step")
 
+    # ------------------------------------------------------------- split precision
+    split = None
+    results_sp = None
+    if not args.no_split:
+        params_sp = icp.icp_params_default(reduce_mode=1)
+        log("split-precision (FP16 hi+lo MFMA) batched steps")
+        icp.icp_register_batch(ctx, batch, params_sp)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        sp_steps = max(1, min(args.steps, 3))
+        for _ in range(sp_steps):
+            results_sp = icp.icp_register_batch(ctx, batch, params_sp)
+        torch.cuda.synchronize()
+        sp_s = time.perf_counter() - ts
+        split = {"registrations_per_s": round(n * sp_steps / sp_s, 2), "steps": sp_steps,
+                 "ms_per_step": round(sp_s / sp_steps * 1e3, 3),
+                 "note": "moment reduction as FP16 hi+lo split MFMA with FP32 accumulation on centred rows; "
+                         "solve and pose update in FP64; two passes per iteration"}
+        log(f"split precision: {split['registrations_per_s']} registrations/s")
+
     # ------------------------------------------------------------- plain path
     lat = []
     if not args.no_plain:
@@ -217,17 +241,35 @@ def main():
         errs = []
         while done < n and (done < 2 or time.perf_counter() - ts < args.cpu_seconds):
             Tref, _, _ = oracle.register_problem(probs[done])
-            Tg = results[done][0]
-            errs.append((rot_err(Tg, Tref), float(np.linalg.norm(Tg[:3, 3] - Tref[:3, 3]))))
+            e = []
+            for res in (results, results_sp):
+                if res is not None:
+                    Tg = res[done][0]
+                    e += [rot_err(Tg, Tref), float(np.linalg.norm(Tg[:3, 3] - Tref[:3, 3]))]
+            errs.append(e)
             done += 1
         cpu_s = time.perf_counter() - ts
         cpu = {"value": round(done / cpu_s, 3), "unit": "registrations/s", "cores": oracle.num_threads(),
                "kind": "oracle", "sample": f"first {done} of {n} registrations of the same sequence, "
                                            f"{cpu_s:.1f} s, FP64 C oracle with OpenMP over rows"}
         errs = np.array(errs)
-        pose_err = {"frames_checked": done, "max_rad": float(errs[:, 0].max()), "max_m": float(errs[:, 1].max())}
+        pose_err = {"frames_checked": done, "max_rad": float(errs[:, 0].max()), "max_m": float(errs[:, 1].max()),
+                    "p50_rad": float(np.median(errs[:, 0])), "p50_m": float(np.median(errs[:, 1]))}
         log(f"oracle: {cpu['value']} reg/s; GPU vs oracle max error {pose_err['max_rad']:.2e} rad, "
             f"{pose_err['max_m']:.2e} m")
+        if split is not None:
+            split["pose_err_vs_oracle"] = {"frames_checked": done, "max_rad": float(errs[:, 2].max()),
+                                           "max_m": float(errs[:, 3].max()),
+                                           "p50_rad": float(np.median(errs[:, 2])),
+                                           "p50_m": float(np.median(errs[:, 3]))}
+            log(f"split precision vs oracle max error {errs[:, 2].max():.2e} rad, {errs[:, 3].max():.2e} m")
+        if args.pose_report:
+            with open(args.pose_report, "w") as f:
+                f.write("# per-frame pose error vs the FP64 oracle, 640x480 room sequence "
+                        f"(seed {args.seed}), registration k = frame k+1 against the model at frame k\n")
+                f.write("# frame | fp32 rad | fp32 m" + (" | split rad | split m" if split else "") + "\n")
+                for k, e in enumerate(errs):
+                    f.write(f"{k + 1} " + " ".join(f"{v:.2e}" for v in e) + "\n")
 
     out = {
         "metric": "ICP registrations/s (VGA,3-level) + p50/p99 latency at <=1e-5 pose err",
@@ -253,6 +295,7 @@ def main():
         "batch_latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                              "p99": round(float(np.percentile(step_ms, 99)), 3)},
         "pose_err_vs_oracle": pose_err,
+        "split_precision": split,
         "roofline": roofline,
         "iteration_roofline": {"achieved": round(iteration_gbs, 1), "unit": "GB/s",
                                "frac": round(iteration_gbs / HBM_PEAK_GBS, 4),

@@ -21,10 +21,11 @@
 #define ICP_WAVES (ICP_WG / 64)
 #define ICP_PART_STRIDE 32      // floats per tile partial: 28 moments, count, pad
 #define ICP_NMOM 28
-#define ICP_PX_PER_THREAD 4     // consecutive pixels per thread and round in the passes
+#define ICP_PX_PER_THREAD 4
+#define ICP_PASS1_PX 1          // pixels per thread and round in the single-pass kernel     // consecutive pixels per thread and round in the passes
 #define ICP_TILE_QUANTUM (ICP_WG * ICP_PX_PER_THREAD)
 #define ICP_PLANE_ALIGN 64      // floats
-#define ICP_WIN 64              // bins of the predicted band-edge window (single-pass mode)
+#define ICP_WIN 48              // bins of the predicted band-edge window (single-pass mode)
 #define ICP_WIN_SLOTS (ICP_WIN + 1)  // slot 0: rows below the window; slots 1..: one per window bin
 
 struct LevelDesc {

@@ -28,22 +28,40 @@ enum : int {
 __device__ __forceinline__ bool fin(float a) { return __builtin_isfinite(a); }
 
 // Bin of a squared distance: the unique k with (k w)^2 <= d2 < ((k+1) w)^2.
-// k w and its square are exact in FP64 (w = 2^-13, k < 2^13), so the result
-// depends on the value of d2 alone; the FP32 square root only seeds the search.
+// With w = 2^-13, (k w)^2 = k^2 2^-26 exactly, and k^2 is an integer, so k is
+// the integer square root of floor(d2 2^26) (below 2^20 for any gated pair,
+// hence exact in FP32).  The FP32 square root of that integer lands within
+// one of the root; two integer checks settle it.
 __device__ __forceinline__ int dist_bin(double d2) {
-    int k = (int)(__builtin_sqrtf((float)d2) * 8192.0f);
-    k = k > ICP_HIST_BINS - 1 ? ICP_HIST_BINS - 1 : k;
-    while (k > 0) {
-        double e = (double)k * kBinW;
-        if (e * e <= d2) break;
-        --k;
-    }
-    while (k < ICP_HIST_BINS - 1) {
-        double e = (double)(k + 1) * kBinW;
-        if (e * e > d2) break;
-        ++k;
-    }
+    const double D = d2 * 67108864.0;  // times 2^26, exact
+    if (!(D < 1048576.0)) return ICP_HIST_BINS - 1;
+    const int n = (int)D;
+    int k = (int)__builtin_amdgcn_sqrtf((float)n);  // hardware square root, 1 ulp
+    k -= (int)__umul24(k, k) > n ? 1 : 0;
+    k += (int)__umul24(k + 1, k + 1) <= n ? 1 : 0;
     return k;
+}
+
+// floor(f a/b + c + 1/2) with a/b rounded as an IEEE FP64 division rounds it.
+// The quotient comes from a refined reciprocal (error a few FP64 ulps); when
+// f a/b + c + 1/2 lies more than 1e-6 from an integer no rounding of the
+// quotient can move the floor, otherwise the correctly rounded division
+// decides.  `look` false skips the check (the result is not used).
+__device__ __forceinline__ void project_round(double a, double b, double f, double c, double a2, double f2,
+                                              double c2, bool look, double& uu, double& vv) {
+    double r = __builtin_amdgcn_rcp(b);
+    r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
+    r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
+    const double uf = f * (a * r) + c + 0.5;
+    const double vf = f2 * (a2 * r) + c2 + 0.5;
+    uu = floor(uf);
+    vv = floor(vf);
+    const double tu = uf - uu, tv = vf - vv;
+    const bool safe = tu > 1e-6 && tu < 1.0 - 1e-6 && tv > 1e-6 && tv < 1.0 - 1e-6;
+    if (look && !safe) {
+        uu = floor(f * (a / b) + c + 0.5);
+        vv = floor(f2 * (a2 / b) + c2 + 0.5);
+    }
 }
 
 #define ICP_GLOBAL __attribute__((address_space(1)))
@@ -115,10 +133,6 @@ struct PixelOut {
     float n[3];
 };
 
-typedef float vf4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ vf4 ld4(const ICP_GLOBAL float* p) { return *(const ICP_GLOBAL vf4*)p; }
-
 // Projective association of live pixels i..i+3 (i a multiple of 4, paper
 // Sec. 3): move each live point by the current pose, project it into the
 // model image, round to the nearest pixel, fetch the model point and normal
@@ -130,36 +144,83 @@ __device__ __forceinline__ vf4 ld4(const ICP_GLOBAL float* p) { return *(const I
 // path.  The live maps store an invalid pixel as NaN in all three components,
 // so one component decides their validity.  The live vertices arrive as one
 // 16-byte load per plane; the model gathers (12 contiguous bytes per map) of
-// the four pixels and the live normals are issued together.
-template <class Emit>
-__device__ __forceinline__ void associate4(const Lvl& L, int i, const Pose& T, double d2max, double cos_max,
-                                           Emit&& emit) {
+// the four pixels are issued together.  The live planes come in as a
+// LiveQuad so a loop can load the next pixels' planes before this call.
+template <int NPX>
+struct LiveVec;
+template <>
+struct LiveVec<4> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct LiveVec<2> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct LiveVec<1> {
+    typedef float type __attribute__((ext_vector_type(1)));
+};
+
+template <int NPX>
+struct LiveQuad {
+    typedef typename LiveVec<NPX>::type V;
+    V vx, vy, vz, nx, ny, nz;
+};
+
+// Live vertex and normal planes of pixels i..i+NPX-1 (six loads of 4 NPX
+// bytes; i a multiple of NPX).
+template <int NPX>
+__device__ __forceinline__ LiveQuad<NPX> load_live(const Lvl& L, int i) {
+    typedef typename LiveVec<NPX>::type V;
     const int S = L.ps;
-    const vf4 vx = ld4(L.LV + i), vy = ld4(L.LV + S + i), vz = ld4(L.LV + 2 * S + i);
-    const float V[4][3] = {{vx.x, vy.x, vz.x}, {vx.y, vy.y, vz.y}, {vx.z, vy.z, vz.z}, {vx.w, vy.w, vz.w}};
-    double P[4][3];
-    int j[4];
-    bool vok[4], front[4], inside[4];
+    LiveQuad<NPX> q;
+    q.vx = *(const ICP_GLOBAL V*)(L.LV + i);
+    q.vy = *(const ICP_GLOBAL V*)(L.LV + S + i);
+    q.vz = *(const ICP_GLOBAL V*)(L.LV + 2 * S + i);
+    q.nx = *(const ICP_GLOBAL V*)(L.LN + i);
+    q.ny = *(const ICP_GLOBAL V*)(L.LN + S + i);
+    q.nz = *(const ICP_GLOBAL V*)(L.LN + 2 * S + i);
+    return q;
+}
+
+// Pixels at or beyond `lim` count as invalid live pixels (their planes may
+// be any in-bounds data).
+template <int NPX, class Emit>
+__device__ __forceinline__ void associate_px(const Lvl& L, int i, int lim, const LiveQuad<NPX>& lq, const Pose& T,
+                                             double d2max, double cos_max, Emit&& emit) {
+    float V[NPX][3], N[NPX][3];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        vok[k] = (i + k < L.npx) && fin(V[k][2]);
+    for (int k = 0; k < NPX; ++k) {
+        V[k][0] = lq.vx[k];
+        V[k][1] = lq.vy[k];
+        V[k][2] = lq.vz[k];
+    }
+    double P[NPX][3];
+    int j[NPX];
+    bool vok[NPX], front[NPX], inside[NPX];
+#pragma unroll
+    for (int k = 0; k < NPX; ++k) {
+        vok[k] = (i + k < lim) && fin(V[k][2]);
         const double px = V[k][0], py = V[k][1], pz = V[k][2];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             P[k][c] = ((T.r[3 * c] * px + T.r[3 * c + 1] * py) + T.r[3 * c + 2] * pz) + T.t[c];
         front[k] = P[k][2] > 0.0;
-        const double uf = L.fx * (P[k][0] / P[k][2]) + L.cx;
-        const double vf = L.fy * (P[k][1] / P[k][2]) + L.cy;
-        const double uu = floor(uf + 0.5), vv = floor(vf + 0.5);
+        double uu, vv;
+        project_round(P[k][0], P[k][2], L.fx, L.cx, P[k][1], L.fy, L.cy, vok[k] && front[k], uu, vv);
         inside[k] = uu >= 0.0 && uu <= L.umax && vv >= 0.0 && vv <= L.vmax;
         const bool look = vok[k] && front[k] && inside[k];
         j[k] = look ? (int)vv * L.W + (int)uu : 0;
     }
-    const vf4 nx = ld4(L.LN + i), ny = ld4(L.LN + S + i), nz = ld4(L.LN + 2 * S + i);
-    const float N[4][3] = {{nx.x, ny.x, nz.x}, {nx.y, ny.y, nz.y}, {nx.z, ny.z, nz.z}, {nx.w, ny.w, nz.w}};
-    float Q[4][3], M[4][3];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < NPX; ++k) {
+        N[k][0] = lq.nx[k];
+        N[k][1] = lq.ny[k];
+        N[k][2] = lq.nz[k];
+    }
+    float Q[NPX][3], M[NPX][3];
+#pragma unroll
+    for (int k = 0; k < NPX; ++k) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             Q[k][c] = L.MV[3 * j[k] + c];
@@ -167,7 +228,7 @@ __device__ __forceinline__ void associate4(const Lvl& L, int i, const Pose& T, d
         }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < NPX; ++k) {
         const bool nok = fin(N[k][2]);
         // the caller's level-0 model maps may be partly NaN: all six decide
         const bool mok = fin(Q[k][0]) && fin(Q[k][1]) && fin(Q[k][2]) && fin(M[k][0]) && fin(M[k][1]) &&
@@ -204,6 +265,13 @@ __device__ __forceinline__ void associate4(const Lvl& L, int i, const Pose& T, d
         o.n[2] = M[k][2];
         emit(k, o);
     }
+}
+
+// Four pixels i..i+3 of one level, every pixel below npx valid.
+template <class Emit>
+__device__ __forceinline__ void associate4(const Lvl& L, int i, const Pose& T, double d2max, double cos_max,
+                                           Emit&& emit) {
+    associate_px<4>(L, i, L.npx, load_live<4>(L, i), T, d2max, cos_max, emit);
 }
 
 // The row r = [a | b] of Eq. (3) for a kept pair (see accumulate_row).

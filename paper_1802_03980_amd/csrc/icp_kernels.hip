@@ -334,8 +334,23 @@ __global__ __launch_bounds__(ICP_WG) void k_pass1(const ProbDesc* __restrict__ p
         const Lvl Lv = load_level(L);
         const int base = tile * L.tile_px;
         const int end = min(base + L.tile_px, L.npx);
-        for (int i = base + ICP_PX_PER_THREAD * tid; i < end; i += ICP_TILE_QUANTUM) {
-            associate4(Lv, i, T, kp.d2max, kp.cos_max, [&](int k, const PixelOut& q) {
+        // Every lane of the block runs the same rounds (the queue and window
+        // steps work across the wave); a lane past the tile's end loads the
+        // round's first pixels and treats its own as invalid.
+        constexpr int kRound = ICP_WG * ICP_PASS1_PX;  // pixels per round
+        auto ld_index = [&](int r) {
+            const int i = r + ICP_PASS1_PX * tid;
+            return i < end ? i : r;
+        };
+        LiveQuad<ICP_PASS1_PX> cur;
+        if (base < end) cur = load_live<ICP_PASS1_PX>(Lv, ld_index(base));
+        for (int r = base; r < end; r += kRound) {
+            const int i = r + ICP_PASS1_PX * tid;
+            // the next round's live planes are in flight while this round runs
+            // (the last round reloads its own pixels: no branch, so the wait
+            // for this round's data does not also wait for the next round's)
+            const LiveQuad<ICP_PASS1_PX> nxt = load_live<ICP_PASS1_PX>(Lv, ld_index(r + kRound < end ? r + kRound : r));
+            associate_px<ICP_PASS1_PX>(Lv, i, end, cur, T, kp.d2max, kp.cos_max, [&](int k, const PixelOut& q) {
                 if (kDebug && i + k < end) {
                     if (dbg_code) dbg_code[i + k] = (uint8_t)q.code;
                     if (dbg_bin) dbg_bin[i + k] = q.bin;
@@ -351,6 +366,7 @@ __global__ __launch_bounds__(ICP_WG) void k_pass1(const ProbDesc* __restrict__ p
                     window_add(inwin, q.bin - h0, q.p, q.d, q.n, sh_win[wave], sh_stage[wave]);
                 }
             });
+            cur = nxt;
         }
     }
     __syncthreads();
