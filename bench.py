@@ -160,7 +160,6 @@ def main():
     for _ in range(args.warmup):
         icp.icp_register_batch(ctx, batch, params)
     torch.cuda.synchronize()
-    icp.icp_ctx_set_timing(ctx, True)
     log(f"timed: {args.steps} batched steps")
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -172,10 +171,16 @@ def main():
         step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
-    timing = icp.icp_ctx_get_timing(ctx)
-    icp.icp_ctx_set_timing(ctx, False)
     value = n * args.steps / t_total
     log(f"batched: {value:.1f} registrations/s, {t_total / args.steps * 1e3:.2f} ms per step")
+    # per-kernel times: the same steps again, launched eagerly with HIP events
+    # recorded on the launch stream around every kernel (not part of `value`)
+    icp.icp_ctx_set_timing(ctx, True)
+    for _ in range(args.steps):
+        icp.icp_register_batch(ctx, batch, params)
+    torch.cuda.synchronize()
+    timing = icp.icp_ctx_get_timing(ctx)
+    icp.icp_ctx_set_timing(ctx, False)
 
     # ------------------------------------------------------------- split precision
     split = None

@@ -131,6 +131,7 @@ struct Plan {
     size_t off_desc = 0, off_state = 0, off_res = 0, off_scratch = 0, off_owner[ICP_MAX_LEVELS] = {};
     int tiles[ICP_MAX_LEVELS] = {};
     int max_npx[ICP_MAX_LEVELS] = {};
+    int max_vn[ICP_MAX_LEVELS] = {};  // live-map work-groups of the largest level
     std::vector<ProbDesc> desc;  // pointers hold offsets until rebased
     std::vector<int> owner[ICP_MAX_LEVELS];
     size_t total = 0;
@@ -151,6 +152,7 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
     for (int l = 0; l < levels; ++l) {
         P.tiles[l] = 0;
         P.max_npx[l] = 0;
+        P.max_vn[l] = 0;
         P.owner[l].clear();
     }
     for (int p = 0; p < n; ++p) {
@@ -167,6 +169,7 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
             L.tile_base = P.tiles[l];
             P.tiles[l] += L.n_tiles;
             P.max_npx[l] = std::max(P.max_npx[l], L.npx);
+            P.max_vn[l] = std::max(P.max_vn[l], icpk::live_vn_blocks(L.W, L.H));
             for (int t = 0; t < L.n_tiles; ++t) P.owner[l].push_back(p);
             const size_t S = (size_t)L.ps * sizeof(float);
             L.Dw = l > 0 ? reinterpret_cast<float*>(take(S)) : nullptr;
@@ -404,7 +407,7 @@ int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* r
     int64_t px0 = 0;
     for (int p = 0; p < n; ++p) px0 += P.desc[p].lv[0].npx;
     if ((rc = time_begin(ctx, s, r, ICP_TIME_FRONT_END, px0))) return rc;
-    HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, P.max_npx, s));
+    HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, P.max_npx, P.max_vn, s));
     if (prm->reduce_mode == 1) HIP_TRY(ctx, icpk::launch_centroid(d_desc, n, prm->levels, s));
     if ((rc = time_end(ctx, s, r))) return rc;
     // single pass needs the band's lower edge at bin 0 and the FP32 reduction
@@ -672,7 +675,7 @@ int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const
     ctx->stage_desc = P.desc[0];
     ctx->stage_levels = levels;
     HIP_TRY(ctx, icpk::launch_init(ctx->d_desc, 1, 0, s));
-    HIP_TRY(ctx, icpk::launch_prepare(ctx->d_desc, 1, levels, P.max_npx, s));
+    HIP_TRY(ctx, icpk::launch_prepare(ctx->d_desc, 1, levels, P.max_npx, P.max_vn, s));
     HIP_TRY(ctx, icpk::launch_centroid(ctx->d_desc, 1, levels, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     ctx->stage_ready = true;

@@ -71,6 +71,11 @@ __device__ __forceinline__ const ICP_GLOBAL T* gconst(const T* p) {
     return (const ICP_GLOBAL T*)p;
 }
 
+template <typename T>
+__device__ __forceinline__ ICP_GLOBAL T* gmut(T* p) {
+    return (ICP_GLOBAL T*)p;
+}
+
 // A value that is the same in every lane, moved to scalar registers.
 __device__ __forceinline__ double uniform(double v) {
     const long long b = __builtin_bit_cast(long long, v);

@@ -71,70 +71,90 @@ __global__ __launch_bounds__(ICP_WG) void k_depth_down(const ProbDesc* __restric
     const int i = blockIdx.x * ICP_WG + threadIdx.x;
     if (i >= C.npx) return;
     const int u = i % C.W, v = i / C.W;
-    const float* D = F.D;
+    const ICP_GLOBAL float* D = gconst(F.D);
     const float a = D[(2 * v) * F.W + 2 * u], b = D[(2 * v) * F.W + 2 * u + 1];
     const float c = D[(2 * v + 1) * F.W + 2 * u], d = D[(2 * v + 1) * F.W + 2 * u + 1];
     float out = 0.0f;
     if (depth_ok(a) && depth_ok(b) && depth_ok(c) && depth_ok(d))
         out = (float)(((((double)a + (double)b) + (double)c) + (double)d) * 0.25);
-    C.Dw[i] = out;
-}
-
-// Vertex of pixel (u, v): z ((u - cx)/fx, (v - cy)/fy, 1), stored FP32.
-__device__ __forceinline__ bool back_project(const LevelDesc& L, int u, int v, float* o) {
-    const float z = L.D[v * L.W + u];
-    if (!depth_ok(z)) return false;
-    const double zd = (double)z;
-    o[0] = (float)(zd * (((double)u - L.cx) / L.fx));
-    o[1] = (float)(zd * (((double)v - L.cy) / L.fy));
-    o[2] = z;
-    return true;
+    gmut(C.Dw)[i] = out;
 }
 
 // Live vertex map and forward-difference normal map (flipped to face the
-// camera); neighbours' vertices are recomputed with the same arithmetic.
+// camera).  A work-group covers FE_TX x FE_TY pixels; the back-projection
+// quotients (u - cx)/fx and (v - cy)/fy of its columns and rows (one beyond,
+// for the neighbours) are computed once into LDS, so every vertex, own or
+// neighbour's, is z times the same two FP64 quotients.
+#define FE_TX 64
+#define FE_TY 4
 __global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__ probs, int level) {
+    __shared__ double sx[FE_TX + 1], sy[FE_TY + 1];
     const LevelDesc& L = probs[blockIdx.y].lv[level];
-    const int i = blockIdx.x * ICP_WG + threadIdx.x;
-    if (i >= L.npx) return;
-    const int S = L.ps;
-    const int u = i % L.W, v = i / L.W;
+    const int tiles_x = (L.W + FE_TX - 1) / FE_TX;
+    const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+    const int u0 = bx * FE_TX, v0 = by * FE_TY;
+    if (v0 >= L.H) return;  // uniform: grids cover the largest level of the batch
+    const int t = threadIdx.x;
+    if (t <= FE_TX)
+        sx[t] = ((double)(u0 + t) - L.cx) / L.fx;
+    else if (t <= FE_TX + 1 + FE_TY)
+        sy[t - FE_TX - 1] = ((double)(v0 + t - FE_TX - 1) - L.cy) / L.fy;
+    __syncthreads();
+    const int du = t % FE_TX, dv = t / FE_TX;
+    const int u = u0 + du, v = v0 + dv;
+    if (u >= L.W || v >= L.H) return;
+    const ICP_GLOBAL float* D = gconst(L.D);
+    const int i = v * L.W + u;
     const float qnan = __builtin_nanf("");
     float p[3] = {qnan, qnan, qnan};
     float n[3] = {qnan, qnan, qnan};
-    float pr[3], pd[3];
-    if (back_project(L, u, v, p) && u + 1 < L.W && v + 1 < L.H && back_project(L, u + 1, v, pr) &&
-        back_project(L, u, v + 1, pd)) {
-        double e1[3], e2[3];
-        for (int k = 0; k < 3; ++k) {
-            e1[k] = (double)pr[k] - (double)p[k];
-            e2[k] = (double)pd[k] - (double)p[k];
-        }
-        const double c0 = e1[1] * e2[2] - e1[2] * e2[1];
-        const double c1 = e1[2] * e2[0] - e1[0] * e2[2];
-        const double c2 = e1[0] * e2[1] - e1[1] * e2[0];
-        const double len2 = (c0 * c0 + c1 * c1) + c2 * c2;
-        if (len2 > 0.0 && __builtin_isfinite(len2)) {
-            const double len = sqrt(len2);
-            double m0 = c0 / len, m1 = c1 / len, m2 = c2 / len;
-            const double side = (m0 * (double)p[0] + m1 * (double)p[1]) + m2 * (double)p[2];
-            if (side > 0.0) {
-                m0 = -m0;
-                m1 = -m1;
-                m2 = -m2;
+    const float z = D[i];
+    const bool ok = depth_ok(z);
+    if (ok) {
+        const double zd = (double)z;
+        p[0] = (float)(zd * sx[du]);
+        p[1] = (float)(zd * sy[dv]);
+        p[2] = z;
+    }
+    if (ok && u + 1 < L.W && v + 1 < L.H) {
+        const float zr = D[i + 1], zb = D[i + L.W];
+        if (depth_ok(zr) && depth_ok(zb)) {
+            const double zrd = (double)zr, zbd = (double)zb;
+            const float pr[3] = {(float)(zrd * sx[du + 1]), (float)(zrd * sy[dv]), zr};
+            const float pd[3] = {(float)(zbd * sx[du]), (float)(zbd * sy[dv + 1]), zb};
+            double e1[3], e2[3];
+            for (int k = 0; k < 3; ++k) {
+                e1[k] = (double)pr[k] - (double)p[k];
+                e2[k] = (double)pd[k] - (double)p[k];
             }
-            n[0] = (float)m0;
-            n[1] = (float)m1;
-            n[2] = (float)m2;
+            const double c0 = e1[1] * e2[2] - e1[2] * e2[1];
+            const double c1 = e1[2] * e2[0] - e1[0] * e2[2];
+            const double c2 = e1[0] * e2[1] - e1[1] * e2[0];
+            const double len2 = (c0 * c0 + c1 * c1) + c2 * c2;
+            if (len2 > 0.0 && __builtin_isfinite(len2)) {
+                const double len = sqrt(len2);
+                double m0 = c0 / len, m1 = c1 / len, m2 = c2 / len;
+                const double side = (m0 * (double)p[0] + m1 * (double)p[1]) + m2 * (double)p[2];
+                if (side > 0.0) {
+                    m0 = -m0;
+                    m1 = -m1;
+                    m2 = -m2;
+                }
+                n[0] = (float)m0;
+                n[1] = (float)m1;
+                n[2] = (float)m2;
+            }
         }
     }
-    if (!depth_ok(L.D[i])) p[0] = p[1] = p[2] = qnan;
-    L.LV[i] = p[0];
-    L.LV[S + i] = p[1];
-    L.LV[2 * S + i] = p[2];
-    L.LN[i] = n[0];
-    L.LN[S + i] = n[1];
-    L.LN[2 * S + i] = n[2];
+    const int S = L.ps;
+    ICP_GLOBAL float* LV = gmut(L.LV);
+    ICP_GLOBAL float* LN = gmut(L.LN);
+    LV[i] = p[0];
+    LV[S + i] = p[1];
+    LV[2 * S + i] = p[2];
+    LN[i] = n[0];
+    LN[S + i] = n[1];
+    LN[2 * S + i] = n[2];
 }
 
 // Model level l from l-1 (interleaved maps): vertex = mean of the four
@@ -152,10 +172,12 @@ __global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restric
     const float qnan = __builtin_nanf("");
     float cv[4][3], cn[4][3];
     bool ok = true;
+    const ICP_GLOBAL float* MV = gconst(F.MV);
+    const ICP_GLOBAL float* MN = gconst(F.MN);
     for (int j = 0; j < 4; ++j)
         for (int k = 0; k < 3; ++k) {
-            cv[j][k] = F.MV[3 * ch[j] + k];
-            cn[j][k] = F.MN[3 * ch[j] + k];
+            cv[j][k] = MV[3 * ch[j] + k];
+            cn[j][k] = MN[3 * ch[j] + k];
             ok = ok && fin(cv[j][k]) && fin(cn[j][k]);
         }
     float vo[3] = {qnan, qnan, qnan}, no[3] = {qnan, qnan, qnan};
@@ -174,9 +196,11 @@ __global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restric
             vo[0] = vo[1] = vo[2] = qnan;
         }
     }
+    ICP_GLOBAL float* MVo = gmut(C.MVw);
+    ICP_GLOBAL float* MNo = gmut(C.MNw);
     for (int k = 0; k < 3; ++k) {
-        C.MVw[3 * i + k] = vo[k];
-        C.MNw[3 * i + k] = no[k];
+        MVo[3 * i + k] = vo[k];
+        MNo[3 * i + k] = no[k];
     }
 }
 
@@ -816,11 +840,14 @@ hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, hipStream_t s) {
+int live_vn_blocks(int W, int H) { return ((W + FE_TX - 1) / FE_TX) * ((H + FE_TY - 1) / FE_TY); }
+
+hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, const int* max_vn_blocks,
+                          hipStream_t s) {
     for (int l = 1; l < levels; ++l)
         hipLaunchKernelGGL(k_depth_down, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
     for (int l = 0; l < levels; ++l)
-        hipLaunchKernelGGL(k_live_vn, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
+        hipLaunchKernelGGL(k_live_vn, dim3(max_vn_blocks[l], n), dim3(ICP_WG), 0, s, probs, l);
     for (int l = 1; l < levels; ++l)
         hipLaunchKernelGGL(k_model_down, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
     return hipGetLastError();

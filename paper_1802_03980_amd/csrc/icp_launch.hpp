@@ -22,7 +22,10 @@ hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, hipStream
 hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, hipStream_t s);
 // live depth pyramid, live vertex/normal maps, model maps for every level;
 // max_npx[l] is the largest level-l pixel count over the problems
-hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, hipStream_t s);
+// live-map work-groups of a W x H level (one per 64 x 4 pixels)
+int live_vn_blocks(int W, int H);
+hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, const int* max_vn_blocks,
+                          hipStream_t s);
 // one ICP iteration at ctl.level: pass 1 over `tiles` flat tiles of all
 // problems, the per-problem band, pass 2 over the tiles, the per-problem solve
 hipError_t launch_pass1(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp, int fused,
