@@ -108,12 +108,20 @@ def main():
     ap.add_argument("--pose-report", default="", help="write per-frame pose errors vs the oracle to this file")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
+    ap.add_argument("--workload", choices=("room", "serve"), default="room",
+                    help="room: batched VGA room sequence (default); serve: the frame server on 32 camera streams")
+    ap.add_argument("--serve-frames", type=int, default=600, help="frames per stream (serve)")
+    ap.add_argument("--serve-period", type=int, default=30, help="distinct frames per stream (serve)")
+    ap.add_argument("--serve-sweep", default="1,4,16,64", help="arrival-rate multipliers of the saturation sweep")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU; the registrations shard by frame with no "
               "communication, so runs on more than one GPU are not provided.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serve":
+        serve_main(args)
+        return
 
     import torch
 
@@ -308,6 +316,145 @@ def main():
                                        "each iteration"},
         "kernel_ms": {k: round(v["total_ms"], 4) for k, v in timing.items()},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+# ----------------------------------------------------------------- serving
+
+SERVE_TILES = (4096, 2048, 1024, 0)  # fixed per level: a frame's result does not depend on its batch-mates
+
+
+def _make_stream_frames(job):
+    from synth.streams import CameraStream
+    i, W, H, period, seed = job
+    s = CameraStream(i, W, H, seed=seed, period=period)
+    return [s.depth(k) for k in range(period)], [s.imu_rel(k) for k in range(period)], s.K
+
+
+def _serve_run(icp, streams, rate_hz, n_frames, params, max_batch, seed):
+    """Poisson arrivals at rate_hz per stream; returns per-frame latencies and
+    the served rate."""
+    import threading
+    rng = np.random.default_rng(seed)
+    sched = []
+    for i in range(len(streams)):
+        t = np.cumsum(rng.exponential(1.0 / rate_hz, size=n_frames))
+        sched += [(float(t[k]), i, k) for k in range(n_frames)]
+    sched.sort()
+    srv = icp.Server(icp.icp_server_config_default(params=params, max_batch=max_batch, slots=2))
+    ids = [srv.open_stream(st["W"], st["H"], st["K"]) for st in streams]
+    total = len(sched)
+    lat, bsz = [], []
+    errors = []
+    outstanding = [0] * len(streams)  # submitted, not yet served (bounded: the client holds back)
+    lock = threading.Lock()
+    start = icp.icp_server_clock() + 0.05
+
+    def feeder():
+        try:
+            for t, i, k in sched:
+                due = start + t
+                while True:
+                    d = due - icp.icp_server_clock()
+                    if d <= 0:
+                        break
+                    time.sleep(min(d, 0.002) if d > 0.0005 else 0)
+                while outstanding[i] >= 16 and not errors:
+                    time.sleep(0.0002)
+                with lock:
+                    outstanding[i] += 1
+                st = streams[i]
+                j = k % len(st["depth"])
+                srv.submit(ids[i], st["depth"][j], st["imu"][j] if k > 0 else np.eye(3), tag=k, t_submit=due)
+        except Exception as e:  # surfaced below
+            errors.append(e)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    got = 0
+    t_first = t_last = None
+    quiet_since = time.time()
+    while got < total:
+        res = srv.poll(1024, timeout_ms=200)
+        if not res:
+            if time.time() - quiet_since > 30.0 or (errors and not th.is_alive()):
+                break
+            continue
+        quiet_since = time.time()
+        for r in res:
+            with lock:
+                outstanding[ids.index(r["stream_id"])] -= 1
+            if r["status"] != 0:
+                errors.append(RuntimeError(f"frame status {r['status']}"))
+            lat.append(r["t_done"] - r["t_submit"])
+            bsz.append(r["batch_size"])
+            t_first = r["t_done"] if t_first is None else min(t_first, r["t_done"])
+            t_last = r["t_done"] if t_last is None else max(t_last, r["t_done"])
+        got += len(res)
+    th.join()
+    ctr = srv.counters()
+    srv.close()
+    if errors:
+        raise errors[0]
+    if got < total:
+        raise RuntimeError(f"served {got} of {total} frames")
+    lat = np.array(lat) * 1e3
+    span = (t_last - start) if t_last else float("nan")
+    return {"rate_hz_per_stream": rate_hz, "frames": total, "served_per_s": round(total / span, 1),
+            "offered_per_s": round(rate_hz * len(streams), 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_batch": round(float(np.mean(bsz)), 2), "batches": ctr["batches"],
+            "gpu_busy_frac": round(ctr["busy_s"] / span, 3) if span == span else None,
+            "resident_mb": round(ctr["resident_bytes"] / 2**20, 1),
+            "workspace_mb": round(ctr["workspace_bytes"] / 2**20, 1)}
+
+
+def serve_main(args):
+    """Frame server on 32 camera streams (7 x 320x240, 13 x 640x480, 6 x
+    848x480, 6 x 1280x720), frame-to-frame tracking, Poisson arrivals at 30 Hz
+    per stream, then a saturation sweep of the arrival rate."""
+    import multiprocessing as mp
+
+    from synth.streams import serving_mix
+    mix = serving_mix(32)
+    jobs = [(i, W, H, args.serve_period, args.seed) for i, (W, H) in enumerate(mix)]
+    log(f"generating {len(jobs)} camera streams, {args.serve_period} distinct frames each")
+    t0 = time.time()
+    # frames are made before the GPU is touched (forked workers)
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        made = pool.map(_make_stream_frames, jobs)
+    streams = [dict(W=W, H=H, depth=d, imu=r, K=K) for (i, W, H, _, _), (d, r, K) in zip(jobs, made)]
+    log(f"  done in {time.time() - t0:.1f} s")
+
+    import torch
+
+    import paper_1802_03980_amd as icp
+    torch.cuda.set_device(0)
+    params = icp.icp_params_default(tile_px=SERVE_TILES)
+    px_frame = sum(st["W"] * st["H"] for st in streams) / len(streams)
+    log("warm-up")
+    _serve_run(icp, streams, 30.0, 3, params, 64, args.seed)
+    log(f"serving {args.serve_frames} frames per stream at 30 Hz per stream")
+    base = _serve_run(icp, streams, 30.0, args.serve_frames, params, 64, args.seed)
+    log(f"  {base}")
+    sweep = []
+    for m in [float(x) for x in args.serve_sweep.split(",") if x]:
+        n = max(30, min(args.serve_frames, int(30 * m * 4)))  # about 4 s of arrivals, at least 30 frames
+        r = _serve_run(icp, streams, 30.0 * m, n, params, 64, args.seed + 1)
+        log(f"  x{m:g}: {r}")
+        sweep.append(r)
+    out = {
+        "metric": "served frame registrations/s + p50/p99 latency (32 mixed-resolution streams)",
+        "value": base["served_per_s"], "unit": "registrations/s", "n_gpus": 1,
+        "higher_is_better": True, "data": "synthetic (seeded camera streams; no dataset)",
+        "dtype": "f64 decisions, f32 maps and moments",
+        "config": {"workload": "32 streams: 7 x 320x240, 13 x 640x480, 6 x 848x480, 6 x 1280x720; "
+                               f"{args.serve_frames} frames each ({args.serve_period} distinct, periodic path); "
+                               "Poisson arrivals at 30 Hz per stream; frame-to-frame; 3 levels {10,5,4}",
+                   "mean_px_per_frame": round(px_frame), "tiles": list(SERVE_TILES[:3])},
+        "latency_ms": {"p50": base["p50_ms"], "p99": base["p99_ms"], "from": "arrival to result on the host"},
+        "at_30hz": base, "saturation_sweep": sweep,
     }
     print(json.dumps(out), flush=True)
 

@@ -278,6 +278,96 @@ int icp_stage_solve(icp_ctx* ctx, const double* moments, int64_t n, const double
                     const icp_params* params, double* pose12_out, double* x_out, int* status,
                     void* stream);
 
+/* ---------------------------------------------------------------- model maps */
+
+/* Vertex and normal maps of one depth image at full resolution, written
+   interleaved (H*W*3 float32 each, device): the same back-projection and
+   forward-difference normals (facing the camera, NaN where invalid) that the
+   registration computes for its live frame at level 0 (paper Sec. 3, the
+   KinectFusion surface measurement).  With them the previous frame of a
+   stream serves as the model of the next one (frame-to-frame tracking).
+   depth: H*W float32 on the device.  Asynchronous on `stream`. */
+int icp_live_maps(icp_ctx* ctx, const float* depth, int W, int H, const icp_intrinsics* K, float* vtx,
+                  float* nrm, void* stream);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A frame server tracks many camera streams frame to frame on one GPU with
+   continuous batching.  Each open stream keeps on the device its depth slot
+   and its model maps (the vertex / normal maps of its previous frame, built
+   with icp_live_maps' arithmetic).  Frames are submitted with the IMU rotation
+   of the frame relative to the stream's previous frame (the registration's
+   imu_R, paper Sec. 3: the prior that seeds the rotation); init_pose is the
+   identity.  A scheduler thread launches one batched registration for every
+   stream with a waiting frame and no frame on the GPU (oldest request first,
+   at most max_batch), on one of `slots` HIP streams, so frames that arrive
+   while a batch runs go into the next batch as soon as a slot is free.  The
+   first frame of a stream only builds its model maps (pose = identity).
+
+   Admission: icp_server_open_stream fails with ICP_ENOMEM when the resident
+   state of every open stream plus, per slot, the workspace of the largest
+   batch the open streams can form would exceed hbm_budget_bytes (0: no
+   limit).  All calls may come from any host thread; results are taken with
+   icp_server_poll.  A HIP failure inside the scheduler makes every later call
+   return it. */
+typedef struct icp_server icp_server;
+
+typedef struct {
+    int32_t device;
+    int32_t max_batch;          /* most frames per batch, 1..4096 (default 64) */
+    int32_t slots;              /* batches in flight at once, 1..4 (default 2) */
+    int32_t use_graphs;         /* replay repeated batch shapes as HIP graphs (default 0) */
+    size_t hbm_budget_bytes;    /* admission budget; 0 = unlimited */
+    icp_params params;          /* registration parameters of every stream */
+} icp_server_config;
+
+typedef struct {
+    int32_t stream_id;
+    int32_t status;             /* ICP_OK, or the error that stopped this frame */
+    uint64_t frame;             /* 0-based index of the frame in its stream */
+    uint64_t tag;               /* the caller's tag */
+    double pose_rel[16];        /* the frame's camera in the previous frame's camera (4x4) */
+    double pose_world[16];      /* chained: the frame's camera in the stream's first camera */
+    icp_stats stats;
+    double t_submit;            /* icp_server_clock() seconds: request arrival */
+    double t_start;             /* its batch was launched */
+    double t_done;              /* its batch was seen complete */
+    int32_t batch_size;         /* frames in its batch */
+    int32_t pad;
+} icp_server_result;
+
+typedef struct {
+    uint64_t batches;
+    uint64_t frames;            /* results published */
+    uint64_t registrations;     /* frames that were registered (not first frames) */
+    double busy_s;              /* sum over batches of launch-to-completion time */
+    size_t resident_bytes;      /* device state of the open streams */
+    size_t workspace_bytes;     /* per-slot batch workspace accounted by admission, all slots */
+    int32_t streams_open;
+    int32_t pad;
+} icp_server_counters;
+
+void icp_server_config_default(icp_server_config* cfg);
+/* The server clock (seconds, monotonic) used for t_submit / t_start / t_done. */
+double icp_server_clock(void);
+int icp_server_create(const icp_server_config* cfg, icp_server** out);
+/* Waits for batches on the GPU, then frees everything (pending frames are dropped). */
+void icp_server_destroy(icp_server* srv);
+const char* icp_server_last_error(icp_server* srv);
+/* Admit a W x H stream with intrinsics K; *stream_id receives its id. */
+int icp_server_open_stream(icp_server* srv, int W, int H, const icp_intrinsics* K, int* stream_id);
+/* Frames already submitted are still served; the state is freed after the last. */
+int icp_server_close_stream(icp_server* srv, int stream_id);
+/* Queue the stream's next frame: depth_host (H*W float32, host memory, copied
+   before the call returns), imu_rel_R (3x3 row-major, host), a caller tag and
+   the arrival time on icp_server_clock() (<= 0: now). */
+int icp_server_submit(icp_server* srv, int stream_id, const float* depth_host, const double* imu_rel_R,
+                      uint64_t tag, double t_submit);
+/* Move up to max finished results into out; waits up to timeout_ms for the
+   first (0: no wait, < 0: forever).  Returns the count (>= 0) or an error. */
+int icp_server_poll(icp_server* srv, icp_server_result* out, int max, int timeout_ms);
+int icp_server_get_counters(icp_server* srv, icp_server_counters* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,10 @@ EXPORTS = (
     "icp_ctx_workspace_bytes", "icp_workspace_bytes", "icp_params_default", "icp_register",
     "icp_register_async", "icp_register_batch", "icp_ctx_set_timing", "icp_ctx_get_timing", "icp_ctx_set_graphs",
     "icp_stage_prepare", "icp_stage_level",
-    "icp_stage_associate", "icp_stage_moments", "icp_stage_solve",
+    "icp_stage_associate", "icp_stage_moments", "icp_stage_solve", "icp_live_maps",
+    "icp_server_config_default", "icp_server_clock", "icp_server_create", "icp_server_destroy",
+    "icp_server_last_error", "icp_server_open_stream", "icp_server_close_stream", "icp_server_submit",
+    "icp_server_poll", "icp_server_get_counters",
 )
 
 
@@ -83,6 +86,24 @@ class icp_result(C.Structure):
     _fields_ = [("pose", C.c_double * 16), ("stats", icp_stats)]
 
 
+class icp_server_config(C.Structure):
+    _fields_ = [("device", C.c_int32), ("max_batch", C.c_int32), ("slots", C.c_int32), ("use_graphs", C.c_int32),
+                ("hbm_budget_bytes", C.c_size_t), ("params", icp_params)]
+
+
+class icp_server_result(C.Structure):
+    _fields_ = [("stream_id", C.c_int32), ("status", C.c_int32), ("frame", C.c_uint64), ("tag", C.c_uint64),
+                ("pose_rel", C.c_double * 16), ("pose_world", C.c_double * 16), ("stats", icp_stats),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("batch_size", C.c_int32), ("pad", C.c_int32)]
+
+
+class icp_server_counters(C.Structure):
+    _fields_ = [("batches", C.c_uint64), ("frames", C.c_uint64), ("registrations", C.c_uint64),
+                ("busy_s", C.c_double), ("resident_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t),
+                ("streams_open", C.c_int32), ("pad", C.c_int32)]
+
+
 _lib = None
 
 
@@ -118,6 +139,17 @@ def lib():
             "icp_stage_associate": (I, [P, I, P, C.POINTER(icp_params), P, P, P, P, P]),
             "icp_stage_moments": (I, [P, I, P, C.POINTER(icp_params), I, I, P, P, P]),
             "icp_stage_solve": (I, [P, P, C.c_int64, P, C.POINTER(icp_params), P, P, P, P]),
+            "icp_live_maps": (I, [P, P, I, I, C.POINTER(icp_intrinsics), P, P, P]),
+            "icp_server_config_default": (None, [C.POINTER(icp_server_config)]),
+            "icp_server_clock": (D, []),
+            "icp_server_create": (I, [C.POINTER(icp_server_config), C.POINTER(P)]),
+            "icp_server_destroy": (None, [P]),
+            "icp_server_last_error": (C.c_char_p, [P]),
+            "icp_server_open_stream": (I, [P, I, I, C.POINTER(icp_intrinsics), C.POINTER(I)]),
+            "icp_server_close_stream": (I, [P, I]),
+            "icp_server_submit": (I, [P, I, P, P, C.c_uint64, D]),
+            "icp_server_poll": (I, [P, P, I, I]),
+            "icp_server_get_counters": (I, [P, C.POINTER(icp_server_counters)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -390,3 +422,99 @@ def icp_stage_solve(ctx, moments, n, pose, params=None, stream=None):
     T = np.eye(4)
     T[:3, :4] = out.reshape(3, 4)
     return st.value, T, x
+
+
+# ---------------------------------------------------------------- model maps
+
+def icp_live_maps(ctx, depth, K, stream=None):
+    """Interleaved (H, W, 3) vertex and normal maps of a device depth image."""
+    import torch
+    H, W = depth.shape
+    dev = torch.device("cuda", ctx.device)
+    vtx = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    nrm = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    Kc = make_intrinsics(K)
+    rc = lib().icp_live_maps(ctx.handle, _dev_ptr(depth, "float32", "depth"), W, H, C.byref(Kc),
+                             C.c_void_p(vtx.data_ptr()), C.c_void_p(nrm.data_ptr()), _stream(stream))
+    _check(ctx, rc)
+    return vtx, nrm
+
+
+# ---------------------------------------------------------------- serving
+
+def icp_server_config_default(**over):
+    cfg = icp_server_config()
+    lib().icp_server_config_default(C.byref(cfg))
+    for k, v in over.items():
+        if k == "params":
+            cfg.params = v
+        else:
+            setattr(cfg, k, v)
+    return cfg
+
+
+def icp_server_clock():
+    return lib().icp_server_clock()
+
+
+def server_result_dict(r):
+    return dict(stream_id=r.stream_id, status=r.status, frame=r.frame, tag=r.tag,
+                pose_rel=np.array(r.pose_rel[:]).reshape(4, 4), pose_world=np.array(r.pose_world[:]).reshape(4, 4),
+                stats=stats_to_dict(r.stats), t_submit=r.t_submit, t_start=r.t_start, t_done=r.t_done,
+                batch_size=r.batch_size)
+
+
+class Server:
+    """Frame server (icp_server_*): frame-to-frame tracking of many camera
+    streams with continuous batching; see include/icp.h."""
+
+    def __init__(self, config=None, **over):
+        cfg = config if config is not None else icp_server_config_default(**over)
+        h = C.c_void_p()
+        rc = lib().icp_server_create(C.byref(cfg), C.byref(h))
+        if rc != OK:
+            raise IcpError(rc, "icp_server_create failed")
+        self.handle = h
+        self.config = cfg
+
+    def _check(self, rc):
+        if rc < 0:
+            msg = lib().icp_server_last_error(self.handle)
+            raise IcpError(rc, msg.decode() if msg else "")
+        return rc
+
+    def open_stream(self, W, H, K):
+        sid = C.c_int(-1)
+        Kc = make_intrinsics(K)
+        self._check(lib().icp_server_open_stream(self.handle, W, H, C.byref(Kc), C.byref(sid)))
+        return sid.value
+
+    def close_stream(self, sid):
+        self._check(lib().icp_server_close_stream(self.handle, sid))
+
+    def submit(self, sid, depth, imu_rel_R, tag=0, t_submit=0.0):
+        d = np.ascontiguousarray(depth, dtype=np.float32)
+        R = np.ascontiguousarray(imu_rel_R, dtype=np.float64).reshape(9)
+        self._check(lib().icp_server_submit(self.handle, sid, d.ctypes.data_as(C.c_void_p),
+                                            R.ctypes.data_as(C.c_void_p), int(tag), float(t_submit)))
+
+    def poll(self, max_results=256, timeout_ms=0):
+        buf = (icp_server_result * max_results)()
+        n = self._check(lib().icp_server_poll(self.handle, C.cast(buf, C.c_void_p), max_results, int(timeout_ms)))
+        return [server_result_dict(buf[i]) for i in range(n)]
+
+    def counters(self):
+        c = icp_server_counters()
+        self._check(lib().icp_server_get_counters(self.handle, C.byref(c)))
+        return {k: getattr(c, k) for k, _ in icp_server_counters._fields_ if k != "pad"}
+
+    def close(self):
+        if self.handle:
+            lib().icp_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

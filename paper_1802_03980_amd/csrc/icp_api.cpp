@@ -11,6 +11,7 @@
 
 #include "icp.h"
 #include "icp_common.hpp"
+#include "icp_internal.hpp"
 #include "icp_launch.hpp"
 
 struct icp_ctx {
@@ -51,6 +52,7 @@ struct icp_ctx {
     hipGraphExec_t graph_exec = nullptr;
     std::vector<int64_t> graph_key;
     void* plan_mem = nullptr;  // the cached Plan (see ctx_plan)
+    MapsDesc* d_jobs = nullptr;  // icp_live_maps job descriptor (device)
 };
 
 namespace {
@@ -558,6 +560,7 @@ void icp_ctx_destroy(icp_ctx* ctx) {
     drop_graph(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete static_cast<Plan*>(ctx->plan_mem);
+    if (ctx->d_jobs) (void)hipFree(ctx->d_jobs);
     delete ctx;
 }
 
@@ -627,6 +630,28 @@ int icp_register(icp_ctx* ctx, const float* live_depth, int W, int H, const floa
     if (rc) return rc;
     std::memcpy(pose_out, r.pose, sizeof(r.pose));
     if (stats_out) *stats_out = r.stats;
+    return ICP_OK;
+}
+
+int icp_live_maps(icp_ctx* ctx, const float* depth, int W, int H, const icp_intrinsics* K, float* vtx, float* nrm,
+                  void* stream) {
+    if (!ctx) return ICP_EINVAL;
+    if (!depth || !K || !vtx || !nrm) return fail(ctx, ICP_EINVAL, "NULL argument");
+    if (W < 1 || H < 1 || W > ICP_MAX_DIM || H > ICP_MAX_DIM) return fail(ctx, ICP_EINVAL, "W and H must be in 1..8192");
+    if (!(K->fx > 0 && K->fy > 0 && std::isfinite(K->fx) && std::isfinite(K->fy) && std::isfinite(K->cx) &&
+          std::isfinite(K->cy)))
+        return fail(ctx, ICP_EINVAL, "intrinsics must be finite with fx, fy > 0");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!ctx->d_jobs) HIP_TRY(ctx, hipMalloc(&ctx->d_jobs, sizeof(MapsDesc)));
+    int rc = ensure_stage(ctx, sizeof(MapsDesc));
+    if (rc) return rc;
+    MapsDesc* J = static_cast<MapsDesc*>(ctx->hstage);
+    *J = MapsDesc{depth, vtx, nrm, W, H, K->fx, K->fy, K->cx, K->cy};
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_jobs, J, sizeof(MapsDesc), hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_upload, s));
+    ctx->ev_pending = true;
+    HIP_TRY(ctx, icpk::launch_depth_to_maps(ctx->d_jobs, 1, icpk::live_vn_blocks(W, H), s));
     return ICP_OK;
 }
 
@@ -792,3 +817,37 @@ int icp_stage_solve(icp_ctx* ctx, const double* moments, int64_t n, const double
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ library-internal
+
+namespace icpi {
+
+int register_batch_async(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params, icp_result* h_res,
+                         hipStream_t s) {
+    if (!ctx) return ICP_EINVAL;
+    if (n < 1 || !probs || !h_res) return fail(ctx, ICP_EINVAL, "empty batch or NULL array");
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    for (int p = 0; p < n; ++p)
+        if ((rc = check_problem(ctx, probs[p], params->levels))) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    Plan& P = ctx_plan(ctx);
+    if ((rc = stage_batch(ctx, n, probs, params->levels, params->tile_px, P, s))) return rc;
+    ctx->stage_ready = false;
+    if ((rc = execute(ctx, n, params, P, s))) return rc;
+    icp_result* d_res = reinterpret_cast<icp_result*>(static_cast<char*>(ctx->ws) + P.off_res);
+    HIP_TRY(ctx, hipMemcpyAsync(h_res, d_res, sizeof(icp_result) * n, hipMemcpyDeviceToHost, s));
+    return ICP_OK;
+}
+
+int reserve_workspace(icp_ctx* ctx, size_t bytes) {
+    if (!ctx) return ICP_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    return ensure_workspace(ctx, bytes);
+}
+
+int validate_params(icp_ctx* ctx, const icp_params* params) { return check_params(ctx, params); }
+
+const char* error(icp_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+}  // namespace icpi

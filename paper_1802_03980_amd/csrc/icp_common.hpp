@@ -47,6 +47,15 @@ struct LevelDesc {
     float* part1;               // single-pass partials: n_tiles * ICP_WIN_SLOTS * ICP_PART_STRIDE
 };
 
+// One depth image turned into interleaved vertex / normal maps.
+struct MapsDesc {
+    const float* depth;
+    float* mv;
+    float* mn;
+    int32_t W, H;
+    double fx, fy, cx, cy;
+};
+
 struct ProbState {
     double R[9];                // current pose, row-major rotation
     double t[3];

@@ -87,27 +87,22 @@ __global__ __launch_bounds__(ICP_WG) void k_depth_down(const ProbDesc* __restric
 // neighbour's, is z times the same two FP64 quotients.
 #define FE_TX 64
 #define FE_TY 4
-__global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__ probs, int level) {
-    __shared__ double sx[FE_TX + 1], sy[FE_TY + 1];
-    const LevelDesc& L = probs[blockIdx.y].lv[level];
-    const int tiles_x = (L.W + FE_TX - 1) / FE_TX;
-    const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
-    const int u0 = bx * FE_TX, v0 = by * FE_TY;
-    if (v0 >= L.H) return;  // uniform: grids cover the largest level of the batch
+
+__device__ __forceinline__ void fe_quotients(double* sx, double* sy, int u0, int v0, double fx, double fy, double cx,
+                                             double cy) {
     const int t = threadIdx.x;
     if (t <= FE_TX)
-        sx[t] = ((double)(u0 + t) - L.cx) / L.fx;
+        sx[t] = ((double)(u0 + t) - cx) / fx;
     else if (t <= FE_TX + 1 + FE_TY)
-        sy[t - FE_TX - 1] = ((double)(v0 + t - FE_TX - 1) - L.cy) / L.fy;
-    __syncthreads();
-    const int du = t % FE_TX, dv = t / FE_TX;
-    const int u = u0 + du, v = v0 + dv;
-    if (u >= L.W || v >= L.H) return;
-    const ICP_GLOBAL float* D = gconst(L.D);
-    const int i = v * L.W + u;
+        sy[t - FE_TX - 1] = ((double)(v0 + t - FE_TX - 1) - cy) / fy;
+}
+
+// Vertex p and normal n of pixel (u, v) = (u0 + du, v0 + dv); NaN when invalid.
+__device__ __forceinline__ void live_px(const ICP_GLOBAL float* D, int W, int H, const double* sx, const double* sy,
+                                        int du, int dv, int u, int v, float (&p)[3], float (&n)[3]) {
     const float qnan = __builtin_nanf("");
-    float p[3] = {qnan, qnan, qnan};
-    float n[3] = {qnan, qnan, qnan};
+    for (int k = 0; k < 3; ++k) p[k] = n[k] = qnan;
+    const int i = v * W + u;
     const float z = D[i];
     const bool ok = depth_ok(z);
     if (ok) {
@@ -116,8 +111,8 @@ __global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__
         p[1] = (float)(zd * sy[dv]);
         p[2] = z;
     }
-    if (ok && u + 1 < L.W && v + 1 < L.H) {
-        const float zr = D[i + 1], zb = D[i + L.W];
+    if (ok && u + 1 < W && v + 1 < H) {
+        const float zr = D[i + 1], zb = D[i + W];
         if (depth_ok(zr) && depth_ok(zb)) {
             const double zrd = (double)zr, zbd = (double)zb;
             const float pr[3] = {(float)(zrd * sx[du + 1]), (float)(zrd * sy[dv]), zr};
@@ -146,7 +141,23 @@ __global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__
             }
         }
     }
-    const int S = L.ps;
+}
+
+__global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__ probs, int level) {
+    __shared__ double sx[FE_TX + 1], sy[FE_TY + 1];
+    const LevelDesc& L = probs[blockIdx.y].lv[level];
+    const int tiles_x = (L.W + FE_TX - 1) / FE_TX;
+    const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+    const int u0 = bx * FE_TX, v0 = by * FE_TY;
+    if (v0 >= L.H) return;  // uniform: grids cover the largest level of the batch
+    fe_quotients(sx, sy, u0, v0, L.fx, L.fy, L.cx, L.cy);
+    __syncthreads();
+    const int du = threadIdx.x % FE_TX, dv = threadIdx.x / FE_TX;
+    const int u = u0 + du, v = v0 + dv;
+    if (u >= L.W || v >= L.H) return;
+    float p[3], n[3];
+    live_px(gconst(L.D), L.W, L.H, sx, sy, du, dv, u, v, p, n);
+    const int S = L.ps, i = v * L.W + u;
     ICP_GLOBAL float* LV = gmut(L.LV);
     ICP_GLOBAL float* LN = gmut(L.LN);
     LV[i] = p[0];
@@ -155,6 +166,31 @@ __global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__
     LN[i] = n[0];
     LN[S + i] = n[1];
     LN[2 * S + i] = n[2];
+}
+
+// The same vertex and normal maps of full-resolution depth images, written
+// interleaved (H x W x 3): the model maps of frame-to-frame tracking.
+__global__ __launch_bounds__(ICP_WG) void k_depth_to_maps(const MapsDesc* __restrict__ jobs) {
+    __shared__ double sx[FE_TX + 1], sy[FE_TY + 1];
+    const MapsDesc& J = jobs[blockIdx.y];
+    const int tiles_x = (J.W + FE_TX - 1) / FE_TX;
+    const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+    const int u0 = bx * FE_TX, v0 = by * FE_TY;
+    if (v0 >= J.H) return;
+    fe_quotients(sx, sy, u0, v0, J.fx, J.fy, J.cx, J.cy);
+    __syncthreads();
+    const int du = threadIdx.x % FE_TX, dv = threadIdx.x / FE_TX;
+    const int u = u0 + du, v = v0 + dv;
+    if (u >= J.W || v >= J.H) return;
+    float p[3], n[3];
+    live_px(gconst(J.depth), J.W, J.H, sx, sy, du, dv, u, v, p, n);
+    const int i = v * J.W + u;
+    ICP_GLOBAL float* MV = gmut(J.mv);
+    ICP_GLOBAL float* MN = gmut(J.mn);
+    for (int k = 0; k < 3; ++k) {
+        MV[3 * i + k] = p[k];
+        MN[3 * i + k] = n[k];
+    }
 }
 
 // Model level l from l-1 (interleaved maps): vertex = mean of the four
@@ -850,6 +886,11 @@ hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* m
         hipLaunchKernelGGL(k_live_vn, dim3(max_vn_blocks[l], n), dim3(ICP_WG), 0, s, probs, l);
     for (int l = 1; l < levels; ++l)
         hipLaunchKernelGGL(k_model_down, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_depth_to_maps(const MapsDesc* jobs, int n, int max_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_depth_to_maps, dim3(max_blocks, n), dim3(ICP_WG), 0, s, jobs);
     return hipGetLastError();
 }
 

@@ -22,6 +22,8 @@ hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, hipStream
 hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, hipStream_t s);
 // live depth pyramid, live vertex/normal maps, model maps for every level;
 // max_npx[l] is the largest level-l pixel count over the problems
+// interleaved vertex / normal maps of n depth images (grid: max_blocks x n)
+hipError_t launch_depth_to_maps(const MapsDesc* jobs, int n, int max_blocks, hipStream_t s);
 // live-map work-groups of a W x H level (one per 64 x 4 pixels)
 int live_vn_blocks(int W, int H);
 hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, const int* max_vn_blocks,

@@ -1,0 +1,196 @@
+"""Frame server (continuous batching of frame-to-frame registrations) and the
+model-map entry point it builds on.
+
+  - icp_live_maps equals the oracle's level-0 live vertex / normal maps bit
+    for bit (same FP64 expressions on the same FP32 depth).
+  - Every served frame equals the same registration run alone through
+    icp_register (model maps of the previous frame from icp_live_maps, the
+    frame's relative IMU prior, identity start, same parameters), whatever
+    else shared its batch: bit for bit, and so within 1e-5 rad / 1e-5 m.
+  - A sample of served frames matches the FP64 oracle run on the same inputs
+    (the oracle builds its own model maps from the previous depth).
+  - Admission by HBM budget; first frames; result bookkeeping.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1802_03980_amd as icp
+import synth
+from synth.streams import CameraStream
+from tests.poseutil import pose_err
+
+pytestmark = pytest.mark.gpu
+
+POSE_TOL = 1e-5
+TILES = (2048, 1024, 1024, 0)  # fixed tiling: a frame is tiled the same alone and in any batch
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return icp.icp_ctx_create(0)
+
+
+def _params():
+    return icp.icp_params_default(tile_px=TILES)
+
+
+def _oracle_params(p):
+    return oracle.default_params(levels=p.levels, iters=list(p.iters), dist_max=p.dist_max,
+                                 cos_angle_max=p.cos_angle_max, band_beta=p.band_beta,
+                                 use_median_filter=p.use_median_filter, use_imu_seed=p.use_imu_seed,
+                                 lambda_mode=p.lambda_mode, lambda_c=p.lambda_c, min_corr=p.min_corr,
+                                 ill_cond_eps=p.ill_cond_eps, converge_window=p.converge_window)
+
+
+def _interleave(V, N):
+    return np.ascontiguousarray(np.moveaxis(V, 0, -1)), np.ascontiguousarray(np.moveaxis(N, 0, -1))
+
+
+@pytest.mark.parametrize("case", ["cfg1", "stream_qvga"])
+def test_live_maps_match_oracle(ctx, case):
+    if case == "cfg1":
+        p = synth.config1_problem(2)
+        depth, K = p.live_depth, p.K
+    else:
+        s = CameraStream(3, 320, 240, period=4)
+        depth, K = s.depth(1), s.K
+    d = torch.from_numpy(depth).cuda()
+    vtx, nrm = icp.icp_live_maps(ctx, d, K)
+    torch.cuda.synchronize()
+    V, N = oracle.live_vn(depth, K)
+    Vi, Ni = _interleave(V, N)
+    g_v, g_n = vtx.cpu().numpy(), nrm.cpu().numpy()
+    assert np.array_equal(np.isnan(g_v), np.isnan(Vi)) and np.array_equal(np.isnan(g_n), np.isnan(Ni))
+    assert np.array_equal(g_v[~np.isnan(g_v)], Vi[~np.isnan(Vi)])
+    assert np.array_equal(g_n[~np.isnan(g_n)], Ni[~np.isnan(Ni)])
+
+
+def _alone(ctx, s, k, params):
+    """Registration k of stream s run by itself through icp_register."""
+    prev = torch.from_numpy(s.depth(k - 1)).cuda()
+    cur = torch.from_numpy(s.depth(k)).cuda()
+    mv, mn = icp.icp_live_maps(ctx, prev, s.K)
+    return icp.icp_register(ctx, cur, mv, mn, s.K, s.imu_rel(k), np.eye(4), params)
+
+
+def _serve(streams, n_frames, params, order_seed=0, max_batch=64, slots=2):
+    """Submit every stream's frames in a shuffled interleaving, a few at a
+    time, and collect all results."""
+    frames = [[s.depth(k) for k in range(n_frames)] for s in streams]  # render before serving
+    srv = icp.Server(icp.icp_server_config_default(params=params, max_batch=max_batch, slots=slots))
+    try:
+        ids = [srv.open_stream(s.W, s.H, s.K) for s in streams]
+        rng = np.random.default_rng(order_seed)
+        nxt = [0] * len(streams)
+        results = []
+        total = len(streams) * n_frames
+        while sum(nxt) < len(streams) * n_frames:
+            burst = rng.integers(2, 2 * len(streams) + 1)
+            for _ in range(burst):
+                live = [i for i in range(len(streams)) if nxt[i] < n_frames]
+                if not live:
+                    break
+                i = int(rng.choice(live))
+                k = nxt[i]
+                R = np.eye(3) if k == 0 else streams[i].imu_rel(k)
+                srv.submit(ids[i], frames[i][k], R, tag=1000 * i + k)
+                nxt[i] += 1
+            results += srv.poll(256, timeout_ms=0)
+        while len(results) < total:
+            got = srv.poll(256, timeout_ms=20000)
+            assert got, "server stalled"
+            results += got
+        counters = srv.counters()
+    finally:
+        srv.close()
+    return ids, results, counters
+
+
+def test_server_alone_vs_mix(ctx):
+    params = _params()
+    streams = [CameraStream(0, 160, 120, period=8), CameraStream(1, 320, 240, period=8),
+               CameraStream(2, 160, 120, period=8), CameraStream(3, 640, 480, period=8)]
+    n_frames = 5
+    ids, results, counters = _serve(streams, n_frames, params)
+    assert len(results) == len(streams) * n_frames
+    assert counters["frames"] == len(results) and counters["registrations"] == len(streams) * (n_frames - 1)
+    by = {(r["stream_id"], r["frame"]): r for r in results}
+    assert max(r["batch_size"] for r in results) > 1, "no two frames shared a batch"
+    for i, s in enumerate(streams):
+        world = np.eye(4)
+        for k in range(n_frames):
+            r = by[(ids[i], k)]
+            assert r["status"] == icp.OK and r["tag"] == 1000 * i + k
+            assert r["t_submit"] <= r["t_start"] <= r["t_done"]
+            if k == 0:
+                assert np.array_equal(r["pose_rel"], np.eye(4))
+                continue
+            T, st = _alone(ctx, s, k, params)
+            ang, dt = pose_err(r["pose_rel"], T)
+            assert ang < POSE_TOL and dt < POSE_TOL, (i, k, ang, dt)
+            assert np.array_equal(r["pose_rel"], T), (i, k, "served result differs from the alone run")
+            assert r["stats"]["levels"][0]["n_kept"] == st["levels"][0]["n_kept"]
+            world = world @ T
+            assert np.allclose(r["pose_world"], world, rtol=0, atol=1e-12)
+
+
+def test_server_matches_oracle_sample(ctx):
+    params = _params()
+    streams = [CameraStream(7, 320, 240, period=6), CameraStream(8, 160, 120, period=6)]
+    ids, results, _ = _serve(streams, 4, params, order_seed=3)
+    by = {(r["stream_id"], r["frame"]): r for r in results}
+    op = _oracle_params(params)
+    for i, s in enumerate(streams):
+        for k in (1, 3):
+            V, N = oracle.live_vn(s.depth(k - 1), s.K)
+            mv, mn = _interleave(V, N)
+            To, _, _ = oracle.register(s.depth(k), mv, mn, s.K, s.imu_rel(k), np.eye(4), op)
+            ang, dt = pose_err(by[(ids[i], k)]["pose_rel"], To)
+            assert ang < POSE_TOL and dt < POSE_TOL, (i, k, ang, dt)
+            # sanity: near the true inter-frame motion (noisy low-resolution frames)
+            ang_t, dt_t = pose_err(To, s.truth_rel(k))
+            assert ang_t < np.radians(2.0) and dt_t < 0.03, (i, k, ang_t, dt_t)
+
+
+def test_server_admission_by_budget():
+    params = _params()
+    cfg = icp.icp_server_config_default(params=params, max_batch=8, slots=2)
+    K = synth.centred_intrinsics(640, 480, 525.0)
+    # the budget of one VGA stream and its two batch workspaces, not of two streams
+    ws1 = icp.icp_workspace_bytes([(640, 480)])
+    ws2 = icp.icp_workspace_bytes([(640, 480), (640, 480)])
+    cfg.hbm_budget_bytes = int(640 * 480 * 28 + 4096 + 2 * 1.25 * ws1 + 0.5 * (2 * 1.25 * (ws2 - ws1)))
+    srv = icp.Server(cfg)
+    try:
+        a = srv.open_stream(640, 480, K)
+        with pytest.raises(icp.IcpError) as e:
+            srv.open_stream(640, 480, K)
+        assert e.value.code == icp.ENOMEM
+        c0 = srv.counters()
+        assert c0["streams_open"] == 1 and c0["resident_bytes"] > 0
+        srv.close_stream(a)
+        b = srv.open_stream(640, 480, K)  # admitted once the first left
+        assert b != a
+        with pytest.raises(icp.IcpError) as e:
+            srv.submit(a, np.zeros((480, 640), np.float32), np.eye(3))
+        assert e.value.code == icp.EINVAL
+    finally:
+        srv.close()
+
+
+def test_server_rejects_bad_arguments():
+    srv = icp.Server(icp.icp_server_config_default(params=_params()))
+    try:
+        K = synth.centred_intrinsics(160, 120, 130.0)
+        with pytest.raises(icp.IcpError) as e:
+            srv.open_stream(161, 120, K)  # not divisible by 2^(levels-1)
+        assert e.value.code == icp.EINVAL
+        sid = srv.open_stream(160, 120, K)
+        with pytest.raises(icp.IcpError) as e:
+            srv.submit(sid, np.zeros((120, 160), np.float32), np.full((3, 3), np.nan))
+        assert e.value.code == icp.EINVAL
+        assert srv.poll(8, timeout_ms=0) == []
+    finally:
+        srv.close()
