@@ -213,6 +213,18 @@ int icp_register_async(icp_ctx* ctx, const float* live_depth, int W, int H, cons
 int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params,
                        icp_result* results, void* stream);
 
+/* Tile-size autotuner for a batch: for each level, coarsest first, time the
+   whole batched registration (HIP events on `stream`, `reps` runs each, the
+   median) for every tile size in {1024, 2048, 4096, 8192, 16384} with the
+   other levels at their best so far, and keep the fastest.  tile_px_out
+   (ICP_MAX_LEVELS entries; unused levels 0) can be copied into
+   icp_params.tile_px; *best_ms (may be NULL) receives the time of one
+   registration of the batch with them.  The tile size sets how many pixels
+   one work-group reduces into one partial sum (it changes the FP32 rounding
+   of the moments, not which pixels are used).  Synchronises. */
+int icp_autotune_tiles(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params, int reps,
+                       int32_t* tile_px_out, double* best_ms, void* stream);
+
 /* ------------------------------------------------------ kernel timing
    Tracing for measurement: while enabled, every registration call records
    HIP events on its own stream around each launch of the front end and of

@@ -32,7 +32,7 @@ EXPORTS = (
     "icp_ctx_workspace_bytes", "icp_workspace_bytes", "icp_params_default", "icp_register",
     "icp_register_async", "icp_register_batch", "icp_ctx_set_timing", "icp_ctx_get_timing", "icp_ctx_set_graphs",
     "icp_stage_prepare", "icp_stage_level",
-    "icp_stage_associate", "icp_stage_moments", "icp_stage_solve", "icp_live_maps",
+    "icp_stage_associate", "icp_stage_moments", "icp_stage_solve", "icp_live_maps", "icp_autotune_tiles",
     "icp_server_config_default", "icp_server_clock", "icp_server_create", "icp_server_destroy",
     "icp_server_last_error", "icp_server_open_stream", "icp_server_close_stream", "icp_server_submit",
     "icp_server_poll", "icp_server_get_counters",
@@ -140,6 +140,7 @@ def lib():
             "icp_stage_moments": (I, [P, I, P, C.POINTER(icp_params), I, I, P, P, P]),
             "icp_stage_solve": (I, [P, P, C.c_int64, P, C.POINTER(icp_params), P, P, P, P]),
             "icp_live_maps": (I, [P, P, I, I, C.POINTER(icp_intrinsics), P, P, P]),
+            "icp_autotune_tiles": (I, [P, I, P, C.POINTER(icp_params), I, P, C.POINTER(D), P]),
             "icp_server_config_default": (None, [C.POINTER(icp_server_config)]),
             "icp_server_clock": (D, []),
             "icp_server_create": (I, [C.POINTER(icp_server_config), C.POINTER(P)]),
@@ -336,6 +337,22 @@ def icp_register_batch(ctx, problems, params=None, stream=None):
                                   _stream(stream))
     _check(ctx, rc)
     return [(np.array(r.pose[:]).reshape(4, 4), stats_to_dict(r.stats, p.levels)) for r in res]
+
+
+def icp_autotune_tiles(ctx, problems, params=None, reps=3, stream=None):
+    """Per-level tile sizes picked by timing the batch (see include/icp.h);
+    returns (tile_px tuple of MAX_LEVELS, ms per registration of the batch)."""
+    p = params if params is not None else icp_params_default()
+    if isinstance(problems, ProblemArray):
+        n, arr = problems.n, problems.arr
+    else:
+        n, arr = len(problems), _problem_array(problems)
+    out = (C.c_int32 * MAX_LEVELS)()
+    ms = C.c_double(0.0)
+    rc = lib().icp_autotune_tiles(ctx.handle, n, C.cast(arr, C.c_void_p), C.byref(p), int(reps),
+                                  C.cast(out, C.c_void_p), C.byref(ms), _stream(stream))
+    _check(ctx, rc)
+    return tuple(out[:]), ms.value
 
 
 def icp_ctx_set_graphs(ctx, enable):

@@ -619,6 +619,67 @@ int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_
     return resolve_timing(ctx);
 }
 
+int icp_autotune_tiles(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params, int reps,
+                       int32_t* tile_px_out, double* best_ms, void* stream) {
+    if (!ctx) return ICP_EINVAL;
+    if (n < 1 || !probs || !tile_px_out || reps < 1 || reps > 100)
+        return fail(ctx, ICP_EINVAL, "autotune: empty batch, NULL output or reps outside 1..100");
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<icp_result> res(n);
+    icp_params p = *params;
+    for (int l = 0; l < ICP_MAX_LEVELS; ++l)
+        if (l >= p.levels) p.tile_px[l] = 0;
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(ctx, hipEventCreate(&a));
+    HIP_TRY(ctx, hipEventCreate(&b));
+    auto time_once = [&](const icp_params& q, double& ms) -> int {
+        std::vector<double> t;
+        int r = icp_register_batch(ctx, n, probs, &q, res.data(), stream);  // warm: plan, workspace, graph
+        for (int k = 0; k < reps && r == ICP_OK; ++k) {
+            if (hipEventRecord(a, s) != hipSuccess) return fail(ctx, ICP_EDEVICE, "hipEventRecord");
+            r = icp_register_batch(ctx, n, probs, &q, res.data(), stream);
+            if (r) break;
+            if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess)
+                return fail(ctx, ICP_EDEVICE, "hipEventSynchronize");
+            float f = 0.0f;
+            (void)hipEventElapsedTime(&f, a, b);
+            t.push_back(f);
+        }
+        if (r) return r;
+        std::sort(t.begin(), t.end());
+        ms = t[t.size() / 2];
+        return ICP_OK;
+    };
+    static const int kCand[] = {1024, 2048, 4096, 8192, 16384};
+    double best = 0.0;
+    for (int l = 0; l < p.levels && rc == ICP_OK; ++l) p.tile_px[l] = p.tile_px[l] ? p.tile_px[l] : 4096;
+    for (int l = p.levels - 1; l >= 0 && rc == ICP_OK; --l) {
+        int pick = p.tile_px[l];
+        double pick_ms = 1e300;
+        for (int c : kCand) {
+            icp_params q = p;
+            q.tile_px[l] = c;
+            double ms = 0.0;
+            if ((rc = time_once(q, ms))) break;
+            if (ms < pick_ms) {
+                pick_ms = ms;
+                pick = c;
+            }
+        }
+        p.tile_px[l] = pick;
+        best = pick_ms;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    for (int l = 0; l < ICP_MAX_LEVELS; ++l) tile_px_out[l] = l < p.levels ? p.tile_px[l] : 0;
+    if (best_ms) *best_ms = best;
+    return ICP_OK;
+}
+
 int icp_register(icp_ctx* ctx, const float* live_depth, int W, int H, const float* model_vtx,
                  const float* model_nrm, const icp_intrinsics* K, const double* imu_R, const double* init_pose,
                  const icp_params* params, double* pose_out, icp_stats* stats_out, void* stream) {

@@ -352,3 +352,20 @@ def test_invalid_arguments(ctx):
     with pytest.raises(icp.IcpError) as e:
         icp.icp_register(small, d, mv, mn, prob.K, prob.imu_R, prob.init_pose)
     assert e.value.code == icp.ENOMEM
+
+
+def test_autotuned_tiles_match_oracle(ctx):
+    """The autotuner returns candidate tile sizes, and the batch registered
+    with them reaches the oracle's poses."""
+    probs = [synth.config1_problem(5), synth.config4_problem(2), synth.config1_problem(6)]
+    keep = [upload(p) for p in probs]
+    items = [dict(live_depth=d, model_vtx=mv, model_nrm=mn, K=p.K, imu_R=p.imu_R, init_pose=p.init_pose)
+             for p, (d, mv, mn) in zip(probs, keep)]
+    params = icp.icp_params_default()
+    tiles, ms = icp.icp_autotune_tiles(ctx, items, params, reps=1)
+    assert all(t in (1024, 2048, 4096, 8192, 16384) for t in tiles[:3]) and tiles[3] == 0 and ms > 0
+    tuned = icp.icp_params_default(tile_px=tiles)
+    for p, (Tb, sb) in zip(probs, icp.icp_register_batch(ctx, items, tuned)):
+        To, so, _ = oracle.register_problem(p, _oracle_params(tuned))
+        ang, dt = pose_err(Tb, To)
+        assert ang < POSE_TOL and dt < POSE_TOL, (p.name, ang, dt)
