@@ -151,6 +151,8 @@ struct PixelOut {
 // 16-byte load per plane; the model gathers (12 contiguous bytes per map) of
 // the four pixels are issued together.  The live planes come in as a
 // LiveQuad so a loop can load the next pixels' planes before this call.
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
 template <int NPX>
 struct LiveVec;
 template <>

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(ICP_WG) void k_depth_down(const ProbDesc* __restric
 // for the neighbours) are computed once into LDS, so every vertex, own or
 // neighbour's, is z times the same two FP64 quotients.
 #define FE_TX 64
-#define FE_TY 4
+#define FE_TY 16  // rows per work-group: each thread takes every fourth row
 
 __device__ __forceinline__ void fe_quotients(double* sx, double* sy, int u0, int v0, double fx, double fy, double cx,
                                              double cy) {
@@ -152,20 +152,25 @@ __global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__
     if (v0 >= L.H) return;  // uniform: grids cover the largest level of the batch
     fe_quotients(sx, sy, u0, v0, L.fx, L.fy, L.cx, L.cy);
     __syncthreads();
-    const int du = threadIdx.x % FE_TX, dv = threadIdx.x / FE_TX;
-    const int u = u0 + du, v = v0 + dv;
-    if (u >= L.W || v >= L.H) return;
-    float p[3], n[3];
-    live_px(gconst(L.D), L.W, L.H, sx, sy, du, dv, u, v, p, n);
-    const int S = L.ps, i = v * L.W + u;
+    const int du = threadIdx.x % FE_TX;
+    const int u = u0 + du;
+    if (u >= L.W) return;
+    const int S = L.ps;
     ICP_GLOBAL float* LV = gmut(L.LV);
     ICP_GLOBAL float* LN = gmut(L.LN);
-    LV[i] = p[0];
-    LV[S + i] = p[1];
-    LV[2 * S + i] = p[2];
-    LN[i] = n[0];
-    LN[S + i] = n[1];
-    LN[2 * S + i] = n[2];
+    for (int dv = threadIdx.x / FE_TX; dv < FE_TY; dv += ICP_WG / FE_TX) {
+        const int v = v0 + dv;
+        if (v >= L.H) break;
+        float p[3], n[3];
+        live_px(gconst(L.D), L.W, L.H, sx, sy, du, dv, u, v, p, n);
+        const int i = v * L.W + u;
+        LV[i] = p[0];
+        LV[S + i] = p[1];
+        LV[2 * S + i] = p[2];
+        LN[i] = n[0];
+        LN[S + i] = n[1];
+        LN[2 * S + i] = n[2];
+    }
 }
 
 // The same vertex and normal maps of full-resolution depth images, written
@@ -179,64 +184,107 @@ __global__ __launch_bounds__(ICP_WG) void k_depth_to_maps(const MapsDesc* __rest
     if (v0 >= J.H) return;
     fe_quotients(sx, sy, u0, v0, J.fx, J.fy, J.cx, J.cy);
     __syncthreads();
-    const int du = threadIdx.x % FE_TX, dv = threadIdx.x / FE_TX;
-    const int u = u0 + du, v = v0 + dv;
-    if (u >= J.W || v >= J.H) return;
-    float p[3], n[3];
-    live_px(gconst(J.depth), J.W, J.H, sx, sy, du, dv, u, v, p, n);
-    const int i = v * J.W + u;
+    const int du = threadIdx.x % FE_TX;
+    const int u = u0 + du;
+    if (u >= J.W) return;
     ICP_GLOBAL float* MV = gmut(J.mv);
     ICP_GLOBAL float* MN = gmut(J.mn);
-    for (int k = 0; k < 3; ++k) {
-        MV[3 * i + k] = p[k];
-        MN[3 * i + k] = n[k];
+    for (int dv = threadIdx.x / FE_TX; dv < FE_TY; dv += ICP_WG / FE_TX) {
+        const int v = v0 + dv;
+        if (v >= J.H) break;
+        float p[3], n[3];
+        live_px(gconst(J.depth), J.W, J.H, sx, sy, du, dv, u, v, p, n);
+        const int i = v * J.W + u;
+        for (int k = 0; k < 3; ++k) {
+            MV[3 * i + k] = p[k];
+            MN[3 * i + k] = n[k];
+        }
     }
 }
 
 // Model level l from l-1 (interleaved maps): vertex = mean of the four
 // children, normal = their normalised sum, valid iff all four children have
 // six finite values; invalid pixels are NaN in all six.
+__device__ __forceinline__ void model_px(const float (&cv)[4][3], const float (&cn)[4][3], float (&vo)[3],
+                                         float (&no)[3]) {
+    const float qnan = __builtin_nanf("");
+    bool ok = true;
+    for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 3; ++k) ok = ok && fin(cv[j][k]) && fin(cn[j][k]);
+    for (int k = 0; k < 3; ++k) vo[k] = no[k] = qnan;
+    if (!ok) return;
+    double s[3];
+    for (int k = 0; k < 3; ++k) {
+        const double m = (((double)cv[0][k] + (double)cv[1][k]) + (double)cv[2][k]) + (double)cv[3][k];
+        s[k] = (((double)cn[0][k] + (double)cn[1][k]) + (double)cn[2][k]) + (double)cn[3][k];
+        vo[k] = (float)(m * 0.25);
+    }
+    const double len2 = (s[0] * s[0] + s[1] * s[1]) + s[2] * s[2];
+    if (len2 > 0.0) {
+        const double len = sqrt(len2);
+        for (int k = 0; k < 3; ++k) no[k] = (float)(s[k] / len);
+    } else {
+        vo[0] = vo[1] = vo[2] = qnan;
+    }
+}
+
+// One thread per pair of output pixels (u, u+1), u even: each child row of
+// the pair is 12 consecutive floats per map, read as three 16-byte loads when
+// the maps are 16-byte aligned (any caller buffer at level 0 is accepted: an
+// unaligned one takes the scalar loads).
 __global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restrict__ probs, int level) {
     const ProbDesc& P = probs[blockIdx.y];
     const LevelDesc& F = P.lv[level - 1];
     const LevelDesc& C = P.lv[level];
-    const int i = blockIdx.x * ICP_WG + threadIdx.x;
-    if (i >= C.npx) return;
-    const int u = i % C.W, v = i / C.W;
-    const int ch[4] = {(2 * v) * F.W + 2 * u, (2 * v) * F.W + 2 * u + 1, (2 * v + 1) * F.W + 2 * u,
-                       (2 * v + 1) * F.W + 2 * u + 1};
-    const float qnan = __builtin_nanf("");
-    float cv[4][3], cn[4][3];
-    bool ok = true;
+    const int half = (C.W + 1) >> 1;  // pairs per row
+    const int t = blockIdx.x * ICP_WG + threadIdx.x;
+    if (t >= half * C.H) return;
+    const int v = t / half, u = 2 * (t % half);
+    const bool two = u + 1 < C.W;
     const ICP_GLOBAL float* MV = gconst(F.MV);
     const ICP_GLOBAL float* MN = gconst(F.MN);
-    for (int j = 0; j < 4; ++j)
-        for (int k = 0; k < 3; ++k) {
-            cv[j][k] = MV[3 * ch[j] + k];
-            cn[j][k] = MN[3 * ch[j] + k];
-            ok = ok && fin(cv[j][k]) && fin(cn[j][k]);
-        }
-    float vo[3] = {qnan, qnan, qnan}, no[3] = {qnan, qnan, qnan};
-    if (ok) {
-        double s[3];
-        for (int k = 0; k < 3; ++k) {
-            const double m = (((double)cv[0][k] + (double)cv[1][k]) + (double)cv[2][k]) + (double)cv[3][k];
-            s[k] = (((double)cn[0][k] + (double)cn[1][k]) + (double)cn[2][k]) + (double)cn[3][k];
-            vo[k] = (float)(m * 0.25);
-        }
-        const double len2 = (s[0] * s[0] + s[1] * s[1]) + s[2] * s[2];
-        if (len2 > 0.0) {
-            const double len = sqrt(len2);
-            for (int k = 0; k < 3; ++k) no[k] = (float)(s[k] / len);
+    const bool vec = two && ((reinterpret_cast<uintptr_t>(F.MV) | reinterpret_cast<uintptr_t>(F.MN)) & 15) == 0;
+    float rv[2][12], rn[2][12];  // [child row][4 children x 3 components]
+    for (int r = 0; r < 2; ++r) {
+        const int base = 3 * ((2 * v + r) * F.W + 2 * u);
+        if (vec) {
+            for (int q = 0; q < 3; ++q) {
+                const vf4 a = *(const ICP_GLOBAL vf4*)(MV + base + 4 * q);
+                const vf4 b = *(const ICP_GLOBAL vf4*)(MN + base + 4 * q);
+                for (int c = 0; c < 4; ++c) {
+                    rv[r][4 * q + c] = a[c];
+                    rn[r][4 * q + c] = b[c];
+                }
+            }
         } else {
-            vo[0] = vo[1] = vo[2] = qnan;
+            const int cnt = two ? 12 : 6;
+            for (int c = 0; c < 12; ++c) {
+                rv[r][c] = c < cnt ? MV[base + c] : 0.0f;
+                rn[r][c] = c < cnt ? MN[base + c] : 0.0f;
+            }
         }
     }
     ICP_GLOBAL float* MVo = gmut(C.MVw);
     ICP_GLOBAL float* MNo = gmut(C.MNw);
-    for (int k = 0; k < 3; ++k) {
-        MVo[3 * i + k] = vo[k];
-        MNo[3 * i + k] = no[k];
+    for (int o = 0; o < (two ? 2 : 1); ++o) {
+        float cv[4][3], cn[4][3];
+        for (int k = 0; k < 3; ++k) {
+            cv[0][k] = rv[0][6 * o + k];
+            cv[1][k] = rv[0][6 * o + 3 + k];
+            cv[2][k] = rv[1][6 * o + k];
+            cv[3][k] = rv[1][6 * o + 3 + k];
+            cn[0][k] = rn[0][6 * o + k];
+            cn[1][k] = rn[0][6 * o + 3 + k];
+            cn[2][k] = rn[1][6 * o + k];
+            cn[3][k] = rn[1][6 * o + 3 + k];
+        }
+        float vo[3], no[3];
+        model_px(cv, cn, vo, no);
+        const int i = v * C.W + u + o;
+        for (int k = 0; k < 3; ++k) {
+            MVo[3 * i + k] = vo[k];
+            MNo[3 * i + k] = no[k];
+        }
     }
 }
 
@@ -878,14 +926,16 @@ hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, hipStream_t
 
 int live_vn_blocks(int W, int H) { return ((W + FE_TX - 1) / FE_TX) * ((H + FE_TY - 1) / FE_TY); }
 
+int model_pairs(int W, int H) { return ((W + 1) / 2) * H; }
+
 hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, const int* max_vn_blocks,
-                          hipStream_t s) {
+                          const int* max_model_pairs, hipStream_t s) {
     for (int l = 1; l < levels; ++l)
         hipLaunchKernelGGL(k_depth_down, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
     for (int l = 0; l < levels; ++l)
         hipLaunchKernelGGL(k_live_vn, dim3(max_vn_blocks[l], n), dim3(ICP_WG), 0, s, probs, l);
     for (int l = 1; l < levels; ++l)
-        hipLaunchKernelGGL(k_model_down, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
+        hipLaunchKernelGGL(k_model_down, dim3(blocks_for(max_model_pairs[l]), n), dim3(ICP_WG), 0, s, probs, l);
     return hipGetLastError();
 }
 

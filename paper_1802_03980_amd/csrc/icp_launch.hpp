@@ -26,8 +26,10 @@ hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, hipStream_t
 hipError_t launch_depth_to_maps(const MapsDesc* jobs, int n, int max_blocks, hipStream_t s);
 // live-map work-groups of a W x H level (one per 64 x 4 pixels)
 int live_vn_blocks(int W, int H);
+// model-pyramid threads of a W x H level (one per pair of pixels in a row)
+int model_pairs(int W, int H);
 hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, const int* max_vn_blocks,
-                          hipStream_t s);
+                          const int* max_model_pairs, hipStream_t s);
 // one ICP iteration at ctl.level: pass 1 over `tiles` flat tiles of all
 // problems, the per-problem band, pass 2 over the tiles, the per-problem solve
 hipError_t launch_pass1(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp, int fused,
