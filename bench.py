@@ -108,9 +108,9 @@ def main():
     ap.add_argument("--pose-report", default="", help="write per-frame pose errors vs the oracle to this file")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
-    ap.add_argument("--workload", choices=("room", "batch64", "serve"), default="room",
+    ap.add_argument("--workload", choices=("room", "batch64", "serve", "sweep"), default="room",
                     help="room: batched VGA room sequence (default); batch64: 64 uneven problems in one batch; "
-                         "serve: the frame server on 32 camera streams")
+                         "serve: the frame server on 32 camera streams; sweep: robustness and lambda sweeps")
     ap.add_argument("--oracle-sample", type=int, default=16, help="problems checked against the oracle (batch64)")
     ap.add_argument("--serve-frames", type=int, default=600, help="frames per stream (serve)")
     ap.add_argument("--serve-period", type=int, default=30, help="distinct frames per stream (serve)")
@@ -126,6 +126,9 @@ def main():
         return
     if args.workload == "batch64":
         batch64_main(args)
+        return
+    if args.workload == "sweep":
+        sweep_main(args)
         return
 
     import torch
@@ -248,6 +251,21 @@ def main():
     log(f"roofline {dom}: {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of 8 TB/s); "
         f"whole iteration (all launches) {iteration_gbs:.0f} GB/s")
 
+    # ------------------------------------------------------------- read ceiling
+    # what a plain library reduction reads per second on this GPU (context for
+    # the roofline fraction, which is taken against the 8 TB/s peak)
+    probe = torch.ones(1 << 30, dtype=torch.float32, device=dev)
+    probe.sum()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        probe.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    read_probe_gbs = 5 * probe.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del probe
+    log(f"read probe (torch sum over 4 GiB): {read_probe_gbs:.0f} GB/s")
+
     # ------------------------------------------------------------- CPU oracle
     cpu = None
     pose_err = None
@@ -320,6 +338,7 @@ def main():
                                "note": "48 B per pixel-iteration over the time of all four launches of "
                                        "each iteration"},
         "kernel_ms": {k: round(v["total_ms"], 4) for k, v in timing.items()},
+        "hbm_read_probe_gbs": round(read_probe_gbs, 1),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -446,6 +465,84 @@ def batch64_main(args):
         "pose_err_vs_oracle": errs,
     }
     print(json.dumps(out), flush=True)
+
+
+# ----------------------------------------------------------------- robustness sweeps
+
+SWEEP_ANGLES = (5, 10, 15, 20, 30, 45, 60)
+
+
+def _make_sweep_problem(job):
+    import synth
+    ang, k = job
+    return synth.config1_problem(seed=1000 * ang + k, W=320, H=240, f=260.0, rot_deg=float(ang), trans_m=0.02)
+
+
+def sweep_main(args):
+    """Failure rate against the inter-frame rotation, with and without the IMU
+    seed (320x240 scenes of the single-pair type, 64 per angle; failure = more
+    than 5 deg or 5 cm from the true motion), and the error against the true
+    motion over the room sequence for each lambda form."""
+    import multiprocessing as mp
+    jobs = [(a, k) for a in SWEEP_ANGLES for k in range(64)]
+    log(f"generating {len(jobs)} sweep problems")
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        probs = pool.map(_make_sweep_problem, jobs)
+
+    import torch
+
+    import paper_1802_03980_amd as icp
+    import synth
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ctx = icp.icp_ctx_create(0)
+
+    def items_of(ps):
+        return [dict(live_depth=torch.from_numpy(p.live_depth).to(dev), model_vtx=torch.from_numpy(p.model_vtx).to(dev),
+                     model_nrm=torch.from_numpy(p.model_nrm).to(dev), K=p.K, imu_R=p.imu_R, init_pose=p.init_pose)
+                for p in ps]
+
+    def errors(res, ps):
+        out = []
+        for (T, _), p in zip(res, ps):
+            out.append((math.degrees(rot_err(T, p.T_gt)), float(np.linalg.norm(T[:3, 3] - p.T_gt[:3, 3]))))
+        return np.array(out)
+
+    angular = []
+    for a in SWEEP_ANGLES:
+        ps = [p for (ang, _), p in zip(jobs, probs) if ang == a]
+        items = items_of(ps)
+        row = {"angle_deg": a, "problems": len(ps)}
+        for seed_on in (1, 0):
+            e = errors(icp.icp_register_batch(ctx, items, icp.icp_params_default(use_imu_seed=seed_on)), ps)
+            fail = (e[:, 0] > 5.0) | (e[:, 1] > 0.05)
+            key = "imu_seed" if seed_on else "no_seed"
+            row[key] = {"failure_rate": round(float(fail.mean()), 4),
+                        "median_rot_err_deg": round(float(np.median(e[:, 0])), 4),
+                        "median_trans_err_m": round(float(np.median(e[:, 1])), 5)}
+        log(f"  {row}")
+        angular.append(row)
+
+    log("room sequence, lambda forms")
+    seq = synth.RoomSequence(args.seed, n_frames=args.frames)
+    rps = [load_or_make(seq, k, args.cache_dir) for k in range(len(seq))]
+    items = items_of(rps)
+    forms = [("c", icp.LAMBDA_CONST, c) for c in (0.0, 1.0, 5.0, 25.0, 100.0)]
+    forms += [("c/sqrt(n)", icp.LAMBDA_C_OVER_SQRT_N, 500.0), ("c/n", icp.LAMBDA_C_OVER_N, 5.0e4),
+              ("c/n^2", icp.LAMBDA_C_OVER_N2, 5.0e8)]
+    lam = []
+    for name, mode, c in forms:
+        e = errors(icp.icp_register_batch(ctx, items, icp.icp_params_default(lambda_mode=mode, lambda_c=c)), rps)
+        r = {"form": name, "c": c, "rmse_rot_deg": round(float(np.sqrt(np.mean(e[:, 0] ** 2))), 5),
+             "rmse_trans_m": round(float(np.sqrt(np.mean(e[:, 1] ** 2))), 6),
+             "max_rot_deg": round(float(e[:, 0].max()), 4), "max_trans_m": round(float(e[:, 1].max()), 5)}
+        log(f"  {r}")
+        lam.append(r)
+    print(json.dumps({"workload": "robustness sweeps", "angular": angular, "lambda_forms": lam,
+                      "notes": "failure = rotation error > 5 deg or translation error > 5 cm against the true "
+                               "motion; IMU prior 0.5 deg off the truth; lambda errors are per-frame "
+                               f"frame-to-model errors against the true motion over {len(rps)} room registrations"}),
+          flush=True)
 
 
 # ----------------------------------------------------------------- serving
