@@ -311,15 +311,17 @@ int icp_live_maps(icp_ctx* ctx, const float* depth, int W, int H, const icp_intr
    of the frame relative to the stream's previous frame (the registration's
    imu_R, paper Sec. 3: the prior that seeds the rotation); init_pose is the
    identity.  A scheduler thread launches one batched registration for every
-   stream with a waiting frame and no frame on the GPU (oldest request first,
-   at most max_batch), on one of `slots` HIP streams, so frames that arrive
-   while a batch runs go into the next batch as soon as a slot is free.  The
-   first frame of a stream only builds its model maps (pose = identity).
+   stream with waiting frames and no batch on the GPU (oldest request first,
+   up to frames_in_flight consecutive frames per stream, at most max_batch),
+   on one of `slots` HIP streams, so frames that arrive while a batch runs go
+   into the next batch as soon as a slot is free.  The first frame of a
+   stream only builds its model maps (pose = identity).
 
    Admission: icp_server_open_stream fails with ICP_ENOMEM when the resident
    state of every open stream plus, per slot, the workspace of the largest
    batch the open streams can form would exceed hbm_budget_bytes (0: no
-   limit).  All calls may come from any host thread; results are taken with
+   limit); a stream's resident state is (frames_in_flight + 1) x 28 bytes per
+   pixel.  All calls may come from any host thread; results are taken with
    icp_server_poll.  A HIP failure inside the scheduler makes every later call
    return it. */
 typedef struct icp_server icp_server;
@@ -329,6 +331,9 @@ typedef struct {
     int32_t max_batch;          /* most frames per batch, 1..4096 (default 64) */
     int32_t slots;              /* batches in flight at once, 1..4 (default 2) */
     int32_t use_graphs;         /* replay repeated batch shapes as HIP graphs (default 0) */
+    int32_t frames_in_flight;   /* most consecutive frames of one stream in one batch, 1..7 (default 2);
+                                   a stream holds frames_in_flight + 1 frame slots on the device */
+    int32_t pad;
     size_t hbm_budget_bytes;    /* admission budget; 0 = unlimited */
     icp_params params;          /* registration parameters of every stream */
 } icp_server_config;

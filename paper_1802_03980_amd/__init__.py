@@ -88,7 +88,8 @@ class icp_result(C.Structure):
 
 class icp_server_config(C.Structure):
     _fields_ = [("device", C.c_int32), ("max_batch", C.c_int32), ("slots", C.c_int32), ("use_graphs", C.c_int32),
-                ("hbm_budget_bytes", C.c_size_t), ("params", icp_params)]
+                ("frames_in_flight", C.c_int32), ("pad", C.c_int32), ("hbm_budget_bytes", C.c_size_t),
+                ("params", icp_params)]
 
 
 class icp_server_result(C.Structure):

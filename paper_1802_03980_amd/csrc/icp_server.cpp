@@ -1,18 +1,21 @@
 // Frame server: frame-to-frame tracking of many camera streams on one GPU with
 // continuous batching.
 //
-// Each open stream keeps its state on the device: the depth slot of the frame
-// being registered and the model maps (interleaved vertex / normal maps of the
-// stream's previous frame).  Callers submit frames (host depth + the IMU
+// Each open stream keeps its state on the device: a ring of R frame slots,
+// each a depth image and its interleaved vertex / normal maps (the model of
+// the stream's next frame).  Callers submit frames (host depth + the IMU
 // rotation of the frame relative to the previous one); a scheduler thread
-// forms a batch from every stream that has a waiting frame and no frame on
-// the GPU, oldest request first, and launches it on one of `slots` HIP
-// streams, each with its own context and workspace.  Frames that arrive while
-// batches run wait for the next free slot, so with two slots one batch is
-// staged and launched while the other is still on the GPU.  A batch is one
-// batched registration (all frames with a model) followed by one launch that
-// turns every frame's depth into the model maps of its stream's next frame.
-// Results are taken with icp_server_poll.
+// forms a batch from every stream that has waiting frames and no batch on the
+// GPU, oldest request first, taking up to R-1 consecutive frames of a stream,
+// and launches it on one of `slots` HIP streams, each with its own context
+// and workspace.  Frames that arrive while batches run wait for the next free
+// slot, so with two slots one batch is staged and launched while the other is
+// still on the GPU.  A batch uploads its depths, turns every depth into the
+// maps of its ring slot, then registers every frame but a stream's first
+// against the maps of the frame before it (in the same batch or an earlier,
+// finished one).  Frame k lives in ring slot k mod R: the batch's frames and
+// the maps they read occupy at most R distinct slots, and any older frame's
+// slot is no longer read.  Results are taken with icp_server_poll.
 //
 // Streams are admitted against an HBM budget: the resident state of every
 // open stream plus, per slot, the workspace of the largest batch the open
@@ -49,16 +52,18 @@ struct Request {
     float* depth = nullptr;  // pinned copy of the caller's depth, from the stream's pool
 };
 
+constexpr int kMaxRing = 8;
+
 struct Stream {
     int id = -1;
     int W = 0, H = 0;
     icp_intrinsics K{};
-    float* d_depth = nullptr;  // frame being registered
-    float* d_mv = nullptr;     // model maps: previous frame's vertices and normals, H x W x 3
-    float* d_mn = nullptr;
-    size_t bytes = 0;          // device bytes held
-    bool has_model = false;
-    bool in_flight = false;
+    int ring = 2;                       // frame slots
+    float* d_depth[kMaxRing] = {};      // depth of the frame in each slot, H x W
+    float* d_mv[kMaxRing] = {};         // its vertex / normal maps, H x W x 3
+    float* d_mn[kMaxRing] = {};
+    size_t bytes = 0;                   // device bytes held
+    bool in_flight = false;             // a batch with this stream's frames is on the GPU
     bool closing = false;
     uint64_t submitted = 0;
     double world[16] = {};     // pose of the last served frame in the stream's first camera
@@ -139,16 +144,18 @@ size_t batch_workspace(const std::vector<Stream*>& ss, int max_batch, int levels
     return b + b / 4;
 }
 
-size_t stream_bytes(int W, int H) {
+size_t stream_bytes(int W, int H, int ring) {
     const size_t px = (size_t)W * H;
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-    return al(px * 4) + 2 * al(px * 12);
+    return (size_t)ring * (al(px * 4) + 2 * al(px * 12));
 }
 
 void free_stream(Stream* st) {
-    if (st->d_depth) (void)hipFree(st->d_depth);
-    if (st->d_mv) (void)hipFree(st->d_mv);
-    if (st->d_mn) (void)hipFree(st->d_mn);
+    for (int r = 0; r < kMaxRing; ++r) {
+        if (st->d_depth[r]) (void)hipFree(st->d_depth[r]);
+        if (st->d_mv[r]) (void)hipFree(st->d_mv[r]);
+        if (st->d_mn[r]) (void)hipFree(st->d_mn[r]);
+    }
     for (float* p : st->pool) (void)hipHostFree(p);
     for (Request& r : st->pending)
         if (r.depth) (void)hipHostFree(r.depth);
@@ -181,12 +188,15 @@ void finish_slot(icp_server* S, Slot& sl) {
             eye4(r.pose_world);
         }
         std::memcpy(st->world, r.pose_world, sizeof(st->world));
-        st->has_model = true;
-        st->in_flight = false;
         st->pool.push_back(rq.depth);
         S->done.push_back(r);
         S->ctr.frames += 1;
         if (sl.reg[i] >= 0) S->ctr.registrations += 1;
+    }
+    for (int i = 0; i < nb; ++i) {
+        Stream* st = sl.streams[i];
+        if (!st->in_flight) continue;  // already released (a stream appears once per frame)
+        st->in_flight = false;
         if (st->closing && st->pending.empty()) {
             S->resident -= st->bytes;
             S->streams[st->id] = nullptr;
@@ -212,34 +222,38 @@ int launch_slot(icp_server* S, Slot& sl) {
     for (int i = 0; i < nb; ++i) {
         Stream* st = sl.streams[i];
         const Request& rq = sl.reqs[i];
-        hipError_t e = hipMemcpyAsync(st->d_depth, rq.depth, sizeof(float) * st->W * st->H, hipMemcpyHostToDevice,
-                                      sl.stream);
+        const int cur = (int)(rq.frame % st->ring);
+        hipError_t e = hipMemcpyAsync(st->d_depth[cur], rq.depth, sizeof(float) * st->W * st->H,
+                                      hipMemcpyHostToDevice, sl.stream);
         if (e != hipSuccess) return srv_fail(S, ICP_EDEVICE, std::string("depth upload: ") + hipGetErrorString(e));
-        if (st->has_model) {
+        if (rq.frame > 0) {
+            const int prev = (int)((rq.frame - 1) % st->ring);
             icp_problem q{};
-            q.live_depth = st->d_depth;
+            q.live_depth = st->d_depth[cur];
             q.W = st->W;
             q.H = st->H;
-            q.model_vtx = st->d_mv;
-            q.model_nrm = st->d_mn;
+            q.model_vtx = st->d_mv[prev];
+            q.model_nrm = st->d_mn[prev];
             q.K = st->K;
             std::memcpy(q.imu_R, rq.prior, sizeof(q.imu_R));
             eye4(q.init_pose);
             sl.reg[i] = (int)sl.probs.size();
             sl.probs.push_back(q);
         }
-        sl.h_jobs[i] = MapsDesc{st->d_depth, st->d_mv, st->d_mn, st->W, st->H, st->K.fx, st->K.fy, st->K.cx, st->K.cy};
+        sl.h_jobs[i] = MapsDesc{st->d_depth[cur], st->d_mv[cur], st->d_mn[cur], st->W, st->H,
+                                st->K.fx,         st->K.fy,     st->K.cx,     st->K.cy};
         max_blocks = std::max(max_blocks, icpk::live_vn_blocks(st->W, st->H));
     }
+    // the maps of every frame of the batch (the model of the frame after it), before the registrations read them
+    hipError_t e = hipMemcpyAsync(sl.d_jobs, sl.h_jobs, sizeof(MapsDesc) * nb, hipMemcpyHostToDevice, sl.stream);
+    if (e == hipSuccess) e = icpk::launch_depth_to_maps(sl.d_jobs, nb, max_blocks, sl.stream);
+    if (e != hipSuccess) return srv_fail(S, ICP_EDEVICE, std::string("maps: ") + hipGetErrorString(e));
     if (!sl.probs.empty()) {
         int rc = icpi::register_batch_async(sl.ctx, (int)sl.probs.size(), sl.probs.data(), &prm, sl.h_res, sl.stream);
         if (rc) return srv_fail(S, rc, std::string("batch: ") + icpi::error(sl.ctx));
     }
-    // the model maps of each stream's next frame, after this batch has read the current ones
-    hipError_t e = hipMemcpyAsync(sl.d_jobs, sl.h_jobs, sizeof(MapsDesc) * nb, hipMemcpyHostToDevice, sl.stream);
-    if (e == hipSuccess) e = icpk::launch_depth_to_maps(sl.d_jobs, nb, max_blocks, sl.stream);
-    if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
-    if (e != hipSuccess) return srv_fail(S, ICP_EDEVICE, std::string("maps: ") + hipGetErrorString(e));
+    e = hipEventRecord(sl.done, sl.stream);
+    if (e != hipSuccess) return srv_fail(S, ICP_EDEVICE, std::string("event: ") + hipGetErrorString(e));
     return ICP_OK;
 }
 
@@ -282,13 +296,34 @@ void scheduler(icp_server* S) {
                       [](Stream* a, Stream* b) { return a->pending.front().t_submit < b->pending.front().t_submit; });
             if ((int)ready.size() > S->cfg.max_batch) ready.resize(S->cfg.max_batch);
             Slot& sl = *free_slot;
-            sl.streams = ready;
+            sl.streams.clear();
             sl.reqs.clear();
-            for (Stream* st : ready) {
-                sl.reqs.push_back(st->pending.front());
-                st->pending.pop_front();
-                st->in_flight = true;
+            // one frame of every ready stream first, then more frames of the same
+            // streams (up to ring-1 consecutive ones) while the batch has room
+            for (int take = 0; take < kMaxRing && (int)sl.reqs.size() < S->cfg.max_batch; ++take)
+                for (Stream* st : ready) {
+                    if ((int)sl.reqs.size() >= S->cfg.max_batch) break;
+                    if (take >= st->ring - 1 || st->pending.empty()) continue;
+                    sl.streams.push_back(st);
+                    sl.reqs.push_back(st->pending.front());
+                    st->pending.pop_front();
+                    st->in_flight = true;
+                }
+            // keep each stream's frames consecutive and in order
+            std::vector<size_t> ord(sl.reqs.size());
+            for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
+            std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+                if (sl.streams[a] != sl.streams[b]) return sl.streams[a]->id < sl.streams[b]->id;
+                return sl.reqs[a].frame < sl.reqs[b].frame;
+            });
+            std::vector<Stream*> s2;
+            std::vector<Request> r2;
+            for (size_t q : ord) {
+                s2.push_back(sl.streams[q]);
+                r2.push_back(sl.reqs[q]);
             }
+            sl.streams.swap(s2);
+            sl.reqs.swap(r2);
             sl.busy = true;
             sl.t_start = clock_s();
             const size_t need = S->ws_need;
@@ -349,6 +384,7 @@ void icp_server_config_default(icp_server_config* cfg) {
     cfg->max_batch = 64;
     cfg->slots = 2;
     cfg->use_graphs = 0;
+    cfg->frames_in_flight = 2;
     cfg->hbm_budget_bytes = 0;
     icp_params_default(&cfg->params);
 }
@@ -358,7 +394,9 @@ double icp_server_clock(void) { return clock_s(); }
 int icp_server_create(const icp_server_config* cfg, icp_server** out) {
     if (!cfg || !out) return ICP_EINVAL;
     *out = nullptr;
-    if (cfg->max_batch < 1 || cfg->max_batch > 4096 || cfg->slots < 1 || cfg->slots > 4) return ICP_EINVAL;
+    if (cfg->max_batch < 1 || cfg->max_batch > 4096 || cfg->slots < 1 || cfg->slots > 4 ||
+        cfg->frames_in_flight < 1 || cfg->frames_in_flight > kMaxRing - 1)
+        return ICP_EINVAL;
     icp_server* S = new icp_server();
     S->cfg = *cfg;
     S->slots.resize(cfg->slots);
@@ -434,7 +472,8 @@ int icp_server_open_stream(icp_server* S, int W, int H, const icp_intrinsics* K,
     st->W = W;
     st->H = H;
     st->K = *K;
-    st->bytes = stream_bytes(W, H);
+    st->ring = S->cfg.frames_in_flight + 1;
+    st->bytes = stream_bytes(W, H, st->ring);
     eye4(st->world);
     // admission: resident state of all streams + per-slot workspace of the largest batch
     std::vector<Stream*> with = S->streams;
@@ -449,12 +488,13 @@ int icp_server_open_stream(icp_server* S, int W, int H, const icp_intrinsics* K,
     }
     (void)hipSetDevice(S->cfg.device);
     const size_t px = (size_t)W * H;
-    if (hipMalloc(&st->d_depth, px * 4) != hipSuccess || hipMalloc(&st->d_mv, px * 12) != hipSuccess ||
-        hipMalloc(&st->d_mn, px * 12) != hipSuccess) {
-        (void)hipGetLastError();
-        free_stream(st);
-        return srv_fail(S, ICP_ENOMEM, "device allocation of the stream state failed");
-    }
+    for (int r = 0; r < st->ring; ++r)
+        if (hipMalloc(&st->d_depth[r], px * 4) != hipSuccess || hipMalloc(&st->d_mv[r], px * 12) != hipSuccess ||
+            hipMalloc(&st->d_mn[r], px * 12) != hipSuccess) {
+            (void)hipGetLastError();
+            free_stream(st);
+            return srv_fail(S, ICP_ENOMEM, "device allocation of the stream state failed");
+        }
     st->id = (int)S->streams.size();
     S->streams.push_back(st);
     S->resident += st->bytes;

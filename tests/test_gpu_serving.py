@@ -75,11 +75,12 @@ def _alone(ctx, s, k, params):
     return icp.icp_register(ctx, cur, mv, mn, s.K, s.imu_rel(k), np.eye(4), params)
 
 
-def _serve(streams, n_frames, params, order_seed=0, max_batch=64, slots=2):
+def _serve(streams, n_frames, params, order_seed=0, max_batch=64, slots=2, frames_in_flight=2):
     """Submit every stream's frames in a shuffled interleaving, a few at a
     time, and collect all results."""
     frames = [[s.depth(k) for k in range(n_frames)] for s in streams]  # render before serving
-    srv = icp.Server(icp.icp_server_config_default(params=params, max_batch=max_batch, slots=slots))
+    srv = icp.Server(icp.icp_server_config_default(params=params, max_batch=max_batch, slots=slots,
+                                                   frames_in_flight=frames_in_flight))
     try:
         ids = [srv.open_stream(s.W, s.H, s.K) for s in streams]
         rng = np.random.default_rng(order_seed)
@@ -108,12 +109,13 @@ def _serve(streams, n_frames, params, order_seed=0, max_batch=64, slots=2):
     return ids, results, counters
 
 
-def test_server_alone_vs_mix(ctx):
+@pytest.mark.parametrize("in_flight", [1, 3])
+def test_server_alone_vs_mix(ctx, in_flight):
     params = _params()
     streams = [CameraStream(0, 160, 120, period=8), CameraStream(1, 320, 240, period=8),
                CameraStream(2, 160, 120, period=8), CameraStream(3, 640, 480, period=8)]
-    n_frames = 5
-    ids, results, counters = _serve(streams, n_frames, params)
+    n_frames = 7
+    ids, results, counters = _serve(streams, n_frames, params, frames_in_flight=in_flight)
     assert len(results) == len(streams) * n_frames
     assert counters["frames"] == len(results) and counters["registrations"] == len(streams) * (n_frames - 1)
     by = {(r["stream_id"], r["frame"]): r for r in results}
@@ -158,10 +160,12 @@ def test_server_admission_by_budget():
     params = _params()
     cfg = icp.icp_server_config_default(params=params, max_batch=8, slots=2)
     K = synth.centred_intrinsics(640, 480, 525.0)
-    # the budget of one VGA stream and its two batch workspaces, not of two streams
+    # the budget of one VGA stream (its frame slots) and its two batch
+    # workspaces, not of two streams
+    ring = cfg.frames_in_flight + 1
     ws1 = icp.icp_workspace_bytes([(640, 480)])
     ws2 = icp.icp_workspace_bytes([(640, 480), (640, 480)])
-    cfg.hbm_budget_bytes = int(640 * 480 * 28 + 4096 + 2 * 1.25 * ws1 + 0.5 * (2 * 1.25 * (ws2 - ws1)))
+    cfg.hbm_budget_bytes = int(ring * 640 * 480 * 28 + 4096 + 2 * 1.25 * ws1 + 0.5 * (2 * 1.25 * (ws2 - ws1)))
     srv = icp.Server(cfg)
     try:
         a = srv.open_stream(640, 480, K)
