@@ -251,20 +251,21 @@ def main():
     log(f"roofline {dom}: {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of 8 TB/s); "
         f"whole iteration (all launches) {iteration_gbs:.0f} GB/s")
 
-    # ------------------------------------------------------------- read ceiling
-    # what a plain library reduction reads per second on this GPU (context for
+    # ------------------------------------------------------------- copy reference
+    # bytes read + written per second by a plain 1 GiB device copy (context for
     # the roofline fraction, which is taken against the 8 TB/s peak)
-    probe = torch.ones(1 << 30, dtype=torch.float32, device=dev)
-    probe.sum()
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(5):
-        probe.sum()
+        dst.copy_(src)
     e1.record()
     torch.cuda.synchronize()
-    read_probe_gbs = 5 * probe.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del probe
-    log(f"read probe (torch sum over 4 GiB): {read_probe_gbs:.0f} GB/s")
+    copy_gbs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    log(f"device copy reference: {copy_gbs:.0f} GB/s (read + write)")
 
     # ------------------------------------------------------------- CPU oracle
     cpu = None
@@ -338,7 +339,7 @@ def main():
                                "note": "48 B per pixel-iteration over the time of all four launches of "
                                        "each iteration"},
         "kernel_ms": {k: round(v["total_ms"], 4) for k, v in timing.items()},
-        "hbm_read_probe_gbs": round(read_probe_gbs, 1),
+        "device_copy_gbs": round(copy_gbs, 1),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
