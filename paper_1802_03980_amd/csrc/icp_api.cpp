@@ -135,6 +135,7 @@ struct Plan {
     int max_npx[ICP_MAX_LEVELS] = {};
     int max_vn[ICP_MAX_LEVELS] = {};  // live-map work-groups of the largest level
     int max_mp[ICP_MAX_LEVELS] = {};  // model-pyramid threads of the largest level
+    int max_q[ICP_MAX_LEVELS] = {};   // quotient-table entries (W + H + 2) of the largest level
     std::vector<ProbDesc> desc;  // pointers hold offsets until rebased
     std::vector<int> owner[ICP_MAX_LEVELS];
     size_t total = 0;
@@ -157,6 +158,7 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
         P.max_npx[l] = 0;
         P.max_vn[l] = 0;
         P.max_mp[l] = 0;
+        P.max_q[l] = 0;
         P.owner[l].clear();
     }
     for (int p = 0; p < n; ++p) {
@@ -175,6 +177,7 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
             P.max_npx[l] = std::max(P.max_npx[l], L.npx);
             P.max_vn[l] = std::max(P.max_vn[l], icpk::live_vn_blocks(L.W, L.H));
             P.max_mp[l] = std::max(P.max_mp[l], icpk::model_pairs(L.W, L.H));
+            P.max_q[l] = std::max(P.max_q[l], L.W + L.H + 2);
             for (int t = 0; t < L.n_tiles; ++t) P.owner[l].push_back(p);
             const size_t S = (size_t)L.ps * sizeof(float);
             L.Dw = l > 0 ? reinterpret_cast<float*>(take(S)) : nullptr;
@@ -183,6 +186,8 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
             const size_t A = (size_t)L.npx * 3 * sizeof(float);
             L.MVw = l > 0 ? reinterpret_cast<float*>(take(A)) : nullptr;
             L.MNw = l > 0 ? reinterpret_cast<float*>(take(A)) : nullptr;
+            L.XQ = reinterpret_cast<double*>(take((size_t)(L.W + 1) * sizeof(double)));
+            L.YQ = reinterpret_cast<double*>(take((size_t)(L.H + 1) * sizeof(double)));
             L.part = reinterpret_cast<float*>(take((size_t)L.n_tiles * ICP_PART_STRIDE * sizeof(float)));
             L.part1 = reinterpret_cast<float*>(
                 take((size_t)L.n_tiles * ICP_WIN_SLOTS * ICP_PART_STRIDE * sizeof(float)));
@@ -322,6 +327,8 @@ int stage_batch(icp_ctx* ctx, int n, const icp_problem* probs, int levels, const
             L.MNw = l > 0 ? rebase(L.MNw, base) : nullptr;
             L.MV = l > 0 ? L.MVw : q.model_vtx;
             L.MN = l > 0 ? L.MNw : q.model_nrm;
+            L.XQ = rebase(L.XQ, base);
+            L.YQ = rebase(L.YQ, base);
             L.part = rebase(L.part, base);
             L.part1 = rebase(L.part1, base);
         }
@@ -412,7 +419,7 @@ int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* r
     int64_t px0 = 0;
     for (int p = 0; p < n; ++p) px0 += P.desc[p].lv[0].npx;
     if ((rc = time_begin(ctx, s, r, ICP_TIME_FRONT_END, px0))) return rc;
-    HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, P.max_npx, P.max_vn, P.max_mp, s));
+    HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, P.max_npx, P.max_vn, P.max_mp, P.max_q, false, s));
     if (prm->reduce_mode == 1) HIP_TRY(ctx, icpk::launch_centroid(d_desc, n, prm->levels, s));
     if ((rc = time_end(ctx, s, r))) return rc;
     // single pass needs the band's lower edge at bin 0 and the FP32 reduction
@@ -764,7 +771,7 @@ int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const
     ctx->stage_desc = P.desc[0];
     ctx->stage_levels = levels;
     HIP_TRY(ctx, icpk::launch_init(ctx->d_desc, 1, 0, s));
-    HIP_TRY(ctx, icpk::launch_prepare(ctx->d_desc, 1, levels, P.max_npx, P.max_vn, P.max_mp, s));
+    HIP_TRY(ctx, icpk::launch_prepare(ctx->d_desc, 1, levels, P.max_npx, P.max_vn, P.max_mp, P.max_q, true, s));
     HIP_TRY(ctx, icpk::launch_centroid(ctx->d_desc, 1, levels, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     ctx->stage_ready = true;

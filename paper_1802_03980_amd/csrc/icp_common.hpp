@@ -43,6 +43,8 @@ struct LevelDesc {
     const float* MN;            // model normal, interleaved
     float* MVw;                 // writable model maps (levels >= 1), same as MV/MN there
     float* MNw;
+    double* XQ;                 // back-projection quotients (u - cx)/fx, u = 0..W
+    double* YQ;                 // (v - cy)/fy, v = 0..H
     float* part;                // pass-2 partials: n_tiles * ICP_PART_STRIDE
     float* part1;               // single-pass partials: n_tiles * ICP_WIN_SLOTS * ICP_PART_STRIDE
 };

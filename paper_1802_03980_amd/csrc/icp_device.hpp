@@ -102,23 +102,30 @@ __device__ __forceinline__ Pose load_pose(const ProbState* st) {
 
 // The maps and geometry of one level held in registers for a pass.
 struct Lvl {
-    const ICP_GLOBAL float* LV;
-    const ICP_GLOBAL float* LN;
+    const ICP_GLOBAL float* D;    // live depth of the level
+    const ICP_GLOBAL float* LN;   // live normal planes
+    const ICP_GLOBAL double* XQ;  // (u - cx) / fx, u = 0..W
+    const ICP_GLOBAL double* YQ;  // (v - cy) / fy, v = 0..H
     const ICP_GLOBAL float* MV;
     const ICP_GLOBAL float* MN;
-    int W, npx, ps;
+    int W, H, npx, ps;
+    float invW;
     double fx, fy, cx, cy, umax, vmax;
 };
 
 __device__ __forceinline__ Lvl load_level(const LevelDesc& L) {
     Lvl v;
-    v.LV = gconst(L.LV);
+    v.D = gconst(L.D);
     v.LN = gconst(L.LN);
+    v.ps = L.ps;
+    v.XQ = gconst(L.XQ);
+    v.YQ = gconst(L.YQ);
     v.MV = gconst(L.MV);
     v.MN = gconst(L.MN);
     v.W = L.W;
+    v.H = L.H;
     v.npx = L.npx;
-    v.ps = L.ps;
+    v.invW = 1.0f / (float)L.W;
     v.fx = L.fx;
     v.fy = L.fy;
     v.cx = L.cx;
@@ -149,58 +156,110 @@ struct PixelOut {
 // path.  The live maps store an invalid pixel as NaN in all three components,
 // so one component decides their validity.  The live vertices arrive as one
 // 16-byte load per plane; the model gathers (12 contiguous bytes per map) of
-// the four pixels are issued together.  The live planes come in as a
-// LiveQuad so a loop can load the next pixels' planes before this call.
+// the pixels are issued together.  The live vertex of each pixel is rebuilt
+// from the level's depth with the front end's arithmetic and its normal is
+// read from the stored normal planes: 16 bytes of live data per pixel instead
+// of 24.
 typedef float vf4 __attribute__((ext_vector_type(4)));
 
+__device__ __forceinline__ bool depth_ok(float z) { return __builtin_isfinite(z) && z > 0.0f; }
+
+// Live vertex p and forward-difference normal n (flipped to face the camera)
+// of a pixel with depth z, from its right and lower neighbours' depths and the
+// back-projection quotients x0 = (u - cx)/fx, x1 = (u + 1 - cx)/fx,
+// y0 = (v - cy)/fy, y1 = (v + 1 - cy)/fy; NaN where invalid.  The one
+// arithmetic of the live maps: the front-end kernels and the pixel passes
+// both call it, so the maps they see are the same bits.
+__device__ __forceinline__ void live_vertex(float z, double x0, double y0, float (&p)[3]) {
+    const float qnan = __builtin_nanf("");
+    const bool ok = depth_ok(z);
+    const double zd = (double)z;
+    p[0] = ok ? (float)(zd * x0) : qnan;
+    p[1] = ok ? (float)(zd * y0) : qnan;
+    p[2] = ok ? z : qnan;
+}
+
+__device__ __forceinline__ void live_from_depth(float z, float zr, float zb, bool has_r, bool has_b, double x0,
+                                                double x1, double y0, double y1, float (&p)[3], float (&n)[3]) {
+    const float qnan = __builtin_nanf("");
+    for (int k = 0; k < 3; ++k) n[k] = qnan;
+    live_vertex(z, x0, y0, p);
+    const bool ok = depth_ok(z);
+    if (ok && has_r && has_b && depth_ok(zr) && depth_ok(zb)) {
+        const double zrd = (double)zr, zbd = (double)zb;
+        const float pr[3] = {(float)(zrd * x1), (float)(zrd * y0), zr};
+        const float pd[3] = {(float)(zbd * x0), (float)(zbd * y1), zb};
+        double e1[3], e2[3];
+        for (int k = 0; k < 3; ++k) {
+            e1[k] = (double)pr[k] - (double)p[k];
+            e2[k] = (double)pd[k] - (double)p[k];
+        }
+        const double c0 = e1[1] * e2[2] - e1[2] * e2[1];
+        const double c1 = e1[2] * e2[0] - e1[0] * e2[2];
+        const double c2 = e1[0] * e2[1] - e1[1] * e2[0];
+        const double len2 = (c0 * c0 + c1 * c1) + c2 * c2;
+        if (len2 > 0.0 && __builtin_isfinite(len2)) {
+            const double len = sqrt(len2);
+            double m0 = c0 / len, m1 = c1 / len, m2 = c2 / len;
+            const double side = (m0 * (double)p[0] + m1 * (double)p[1]) + m2 * (double)p[2];
+            if (side > 0.0) {
+                m0 = -m0;
+                m1 = -m1;
+                m2 = -m2;
+            }
+            n[0] = (float)m0;
+            n[1] = (float)m1;
+            n[2] = (float)m2;
+        }
+    }
+}
+
+// Row and column of pixel i (an FP32 estimate of i / W, corrected by one).
+__device__ __forceinline__ void pixel_uv(const Lvl& L, int i, int& u, int& v) {
+    v = (int)((float)i * L.invW);
+    v -= v * L.W > i ? 1 : 0;
+    v += (v + 1) * L.W <= i ? 1 : 0;
+    u = i - v * L.W;
+}
+
+// What a pixel's live vertex and normal come from: its depth (the vertex is
+// rebuilt from it with the front end's arithmetic) and its stored normal (the
+// normal needs two neighbours and a square root and three divisions: cheaper
+// to read than to rebuild every iteration).  A loop loads the next round's
+// before running this one.
 template <int NPX>
-struct LiveVec;
-template <>
-struct LiveVec<4> {
-    typedef float type __attribute__((ext_vector_type(4)));
-};
-template <>
-struct LiveVec<2> {
-    typedef float type __attribute__((ext_vector_type(2)));
-};
-template <>
-struct LiveVec<1> {
-    typedef float type __attribute__((ext_vector_type(1)));
+struct LiveIn {
+    float z[NPX], n[NPX][3];
 };
 
 template <int NPX>
-struct LiveQuad {
-    typedef typename LiveVec<NPX>::type V;
-    V vx, vy, vz, nx, ny, nz;
-};
-
-// Live vertex and normal planes of pixels i..i+NPX-1 (six loads of 4 NPX
-// bytes; i a multiple of NPX).
-template <int NPX>
-__device__ __forceinline__ LiveQuad<NPX> load_live(const Lvl& L, int i) {
-    typedef typename LiveVec<NPX>::type V;
-    const int S = L.ps;
-    LiveQuad<NPX> q;
-    q.vx = *(const ICP_GLOBAL V*)(L.LV + i);
-    q.vy = *(const ICP_GLOBAL V*)(L.LV + S + i);
-    q.vz = *(const ICP_GLOBAL V*)(L.LV + 2 * S + i);
-    q.nx = *(const ICP_GLOBAL V*)(L.LN + i);
-    q.ny = *(const ICP_GLOBAL V*)(L.LN + S + i);
-    q.nz = *(const ICP_GLOBAL V*)(L.LN + 2 * S + i);
+__device__ __forceinline__ LiveIn<NPX> load_live(const Lvl& L, int i) {
+    LiveIn<NPX> q;
+#pragma unroll
+    for (int k = 0; k < NPX; ++k) {
+        const int j = min(i + k, L.npx - 1);  // pixels past the end read the last one (and count as invalid)
+        q.z[k] = L.D[j];
+        q.n[k][0] = L.LN[j];
+        q.n[k][1] = L.LN[L.ps + j];
+        q.n[k][2] = L.LN[2 * L.ps + j];
+    }
     return q;
 }
 
 // Pixels at or beyond `lim` count as invalid live pixels (their planes may
 // be any in-bounds data).
 template <int NPX, class Emit>
-__device__ __forceinline__ void associate_px(const Lvl& L, int i, int lim, const LiveQuad<NPX>& lq, const Pose& T,
+__device__ __forceinline__ void associate_px(const Lvl& L, int i, int lim, const LiveIn<NPX>& lq, const Pose& T,
                                              double d2max, double cos_max, Emit&& emit) {
     float V[NPX][3], N[NPX][3];
 #pragma unroll
     for (int k = 0; k < NPX; ++k) {
-        V[k][0] = lq.vx[k];
-        V[k][1] = lq.vy[k];
-        V[k][2] = lq.vz[k];
+        int u, v;
+        pixel_uv(L, min(i + k, L.npx - 1), u, v);
+        live_vertex(lq.z[k], L.XQ[u], L.YQ[v], V[k]);
+        N[k][0] = lq.n[k][0];
+        N[k][1] = lq.n[k][1];
+        N[k][2] = lq.n[k][2];
     }
     double P[NPX][3];
     int j[NPX];
@@ -218,12 +277,6 @@ __device__ __forceinline__ void associate_px(const Lvl& L, int i, int lim, const
         inside[k] = uu >= 0.0 && uu <= L.umax && vv >= 0.0 && vv <= L.vmax;
         const bool look = vok[k] && front[k] && inside[k];
         j[k] = look ? (int)vv * L.W + (int)uu : 0;
-    }
-#pragma unroll
-    for (int k = 0; k < NPX; ++k) {
-        N[k][0] = lq.nx[k];
-        N[k][1] = lq.ny[k];
-        N[k][2] = lq.nz[k];
     }
     float Q[NPX][3], M[NPX][3];
 #pragma unroll

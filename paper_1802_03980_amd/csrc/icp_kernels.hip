@@ -19,8 +19,6 @@ namespace icpk {
 
 // ------------------------------------------------------------------ helpers
 
-__device__ __forceinline__ bool depth_ok(float z) { return __builtin_isfinite(z) && z > 0.0f; }
-
 // ------------------------------------------------------------------ init
 
 __global__ __launch_bounds__(ICP_WG) void k_init(const ProbDesc* __restrict__ probs, int use_imu_seed) {
@@ -100,50 +98,27 @@ __device__ __forceinline__ void fe_quotients(double* sx, double* sy, int u0, int
 // Vertex p and normal n of pixel (u, v) = (u0 + du, v0 + dv); NaN when invalid.
 __device__ __forceinline__ void live_px(const ICP_GLOBAL float* D, int W, int H, const double* sx, const double* sy,
                                         int du, int dv, int u, int v, float (&p)[3], float (&n)[3]) {
-    const float qnan = __builtin_nanf("");
-    for (int k = 0; k < 3; ++k) p[k] = n[k] = qnan;
     const int i = v * W + u;
+    const bool has_r = u + 1 < W, has_b = v + 1 < H;
     const float z = D[i];
-    const bool ok = depth_ok(z);
-    if (ok) {
-        const double zd = (double)z;
-        p[0] = (float)(zd * sx[du]);
-        p[1] = (float)(zd * sy[dv]);
-        p[2] = z;
-    }
-    if (ok && u + 1 < W && v + 1 < H) {
-        const float zr = D[i + 1], zb = D[i + W];
-        if (depth_ok(zr) && depth_ok(zb)) {
-            const double zrd = (double)zr, zbd = (double)zb;
-            const float pr[3] = {(float)(zrd * sx[du + 1]), (float)(zrd * sy[dv]), zr};
-            const float pd[3] = {(float)(zbd * sx[du]), (float)(zbd * sy[dv + 1]), zb};
-            double e1[3], e2[3];
-            for (int k = 0; k < 3; ++k) {
-                e1[k] = (double)pr[k] - (double)p[k];
-                e2[k] = (double)pd[k] - (double)p[k];
-            }
-            const double c0 = e1[1] * e2[2] - e1[2] * e2[1];
-            const double c1 = e1[2] * e2[0] - e1[0] * e2[2];
-            const double c2 = e1[0] * e2[1] - e1[1] * e2[0];
-            const double len2 = (c0 * c0 + c1 * c1) + c2 * c2;
-            if (len2 > 0.0 && __builtin_isfinite(len2)) {
-                const double len = sqrt(len2);
-                double m0 = c0 / len, m1 = c1 / len, m2 = c2 / len;
-                const double side = (m0 * (double)p[0] + m1 * (double)p[1]) + m2 * (double)p[2];
-                if (side > 0.0) {
-                    m0 = -m0;
-                    m1 = -m1;
-                    m2 = -m2;
-                }
-                n[0] = (float)m0;
-                n[1] = (float)m1;
-                n[2] = (float)m2;
-            }
-        }
-    }
+    const float zr = has_r ? D[i + 1] : 0.0f;
+    const float zb = has_b ? D[i + W] : 0.0f;
+    live_from_depth(z, zr, zb, has_r, has_b, sx[du], sx[du + 1], sy[dv], sy[dv + 1], p, n);
 }
 
-__global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__ probs, int level) {
+// Back-projection quotient tables of a level: XQ[u] = (u - cx)/fx for
+// u = 0..W and YQ[v] = (v - cy)/fy for v = 0..H (the same FP64 divisions as
+// fe_quotients), read by the pixel passes.
+__global__ __launch_bounds__(ICP_WG) void k_quotients(const ProbDesc* __restrict__ probs, int level) {
+    const LevelDesc& L = probs[blockIdx.y].lv[level];
+    const int t = blockIdx.x * ICP_WG + threadIdx.x;
+    if (t <= L.W)
+        gmut(L.XQ)[t] = ((double)t - L.cx) / L.fx;
+    else if (t <= L.W + 1 + L.H)
+        gmut(L.YQ)[t - L.W - 1] = ((double)(t - L.W - 1) - L.cy) / L.fy;
+}
+
+__global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__ probs, int level, int with_vertex) {
     __shared__ double sx[FE_TX + 1], sy[FE_TY + 1];
     const LevelDesc& L = probs[blockIdx.y].lv[level];
     const int tiles_x = (L.W + FE_TX - 1) / FE_TX;
@@ -164,9 +139,11 @@ __global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__
         float p[3], n[3];
         live_px(gconst(L.D), L.W, L.H, sx, sy, du, dv, u, v, p, n);
         const int i = v * L.W + u;
-        LV[i] = p[0];
-        LV[S + i] = p[1];
-        LV[2 * S + i] = p[2];
+        if (with_vertex) {
+            LV[i] = p[0];
+            LV[S + i] = p[1];
+            LV[2 * S + i] = p[2];
+        }
         LN[i] = n[0];
         LN[S + i] = n[1];
         LN[2 * S + i] = n[2];
@@ -298,11 +275,13 @@ __global__ __launch_bounds__(ICP_WG) void k_centroid(const ProbDesc* __restrict_
     const LevelDesc& L = P.lv[level];
     const int tid = threadIdx.x;
     double sx = 0.0, sy = 0.0, sz = 0.0, n = 0.0;
+    const ICP_GLOBAL float* D = gconst(L.D);
     for (int i = tid; i < L.npx; i += ICP_WG) {
-        const float z = L.LV[2 * L.ps + i];
-        if (fin(z)) {
-            sx += (double)L.LV[i];
-            sy += (double)L.LV[L.ps + i];
+        const float z = D[i];
+        if (depth_ok(z)) {
+            const int v = i / L.W, u = i - v * L.W;
+            sx += (double)(float)((double)z * L.XQ[u]);
+            sy += (double)(float)((double)z * L.YQ[v]);
             sz += (double)z;
             n += 1.0;
         }
@@ -413,7 +392,7 @@ __device__ __forceinline__ void window_add(bool inwin, int bin_off, const float 
 }
 
 template <bool kDebug, bool kFused>
-__global__ __launch_bounds__(ICP_WG) void k_pass1(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
+__global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) void k_pass1(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
                                                   IterCtl ctl, KParams kp, uint8_t* __restrict__ dbg_code,
                                                   int32_t* __restrict__ dbg_bin) {
     __shared__ uint32_t sh_hist[ICP_HIST_BINS];
@@ -450,14 +429,14 @@ __global__ __launch_bounds__(ICP_WG) void k_pass1(const ProbDesc* __restrict__ p
             const int i = r + ICP_PASS1_PX * tid;
             return i < end ? i : r;
         };
-        LiveQuad<ICP_PASS1_PX> cur;
+        LiveIn<ICP_PASS1_PX> cur;
         if (base < end) cur = load_live<ICP_PASS1_PX>(Lv, ld_index(base));
         for (int r = base; r < end; r += kRound) {
             const int i = r + ICP_PASS1_PX * tid;
             // the next round's live planes are in flight while this round runs
             // (the last round reloads its own pixels: no branch, so the wait
             // for this round's data does not also wait for the next round's)
-            const LiveQuad<ICP_PASS1_PX> nxt = load_live<ICP_PASS1_PX>(Lv, ld_index(r + kRound < end ? r + kRound : r));
+            const LiveIn<ICP_PASS1_PX> nxt = load_live<ICP_PASS1_PX>(Lv, ld_index(r + kRound < end ? r + kRound : r));
             associate_px<ICP_PASS1_PX>(Lv, i, end, cur, T, kp.d2max, kp.cos_max, [&](int k, const PixelOut& q) {
                 if (kDebug && i + k < end) {
                     if (dbg_code) dbg_code[i + k] = (uint8_t)q.code;
@@ -929,11 +908,14 @@ int live_vn_blocks(int W, int H) { return ((W + FE_TX - 1) / FE_TX) * ((H + FE_T
 int model_pairs(int W, int H) { return ((W + 1) / 2) * H; }
 
 hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, const int* max_vn_blocks,
-                          const int* max_model_pairs, hipStream_t s) {
+                          const int* max_model_pairs, const int* max_quot, bool with_live_maps, hipStream_t s) {
     for (int l = 1; l < levels; ++l)
         hipLaunchKernelGGL(k_depth_down, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
     for (int l = 0; l < levels; ++l)
-        hipLaunchKernelGGL(k_live_vn, dim3(max_vn_blocks[l], n), dim3(ICP_WG), 0, s, probs, l);
+        hipLaunchKernelGGL(k_quotients, dim3(blocks_for(max_quot[l]), n), dim3(ICP_WG), 0, s, probs, l);
+    for (int l = 0; l < levels; ++l)
+        hipLaunchKernelGGL(k_live_vn, dim3(max_vn_blocks[l], n), dim3(ICP_WG), 0, s, probs, l,
+                           with_live_maps ? 1 : 0);
     for (int l = 1; l < levels; ++l)
         hipLaunchKernelGGL(k_model_down, dim3(blocks_for(max_model_pairs[l]), n), dim3(ICP_WG), 0, s, probs, l);
     return hipGetLastError();
