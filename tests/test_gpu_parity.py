@@ -67,6 +67,7 @@ PROBLEMS = {
     "cfg1_s0": lambda: synth.config1_problem(0),
     "cfg1_s1": lambda: synth.config1_problem(1),
     "cfg4_0": lambda: synth.config4_problem(0),
+    "odd_41x31_at_l2": lambda: synth.config1_problem(7, W=164, H=124, f=133.0),
 }
 
 
@@ -324,13 +325,27 @@ def test_edge_cases(ctx):
     ang, dt = pose_err(Tg, To)
     assert ang < POSE_TOL and dt < POSE_TOL, (ang, dt)
     assert [s["n_kept"] for s in sg["levels"]] == [s["n_kept"] for s in so]
-    # ragged size (tiles do not divide the levels) and 1 / 4 levels
-    for levels, W, H in [(1, 100, 70), (3, 168, 124), (4, 176, 136)]:
+    # ragged size (tiles do not divide the levels), odd widths and heights at
+    # the coarse levels (pixel pairs of the model pyramid, row/column lookup of
+    # the rebuilt vertices), 1 / 2 / 4 levels
+    for levels, W, H in [(1, 100, 70), (3, 168, 124), (4, 176, 136), (2, 162, 122), (3, 164, 124)]:
         p = synth.config1_problem(5, W=W, H=H, f=130.0 * W / 160)
         prm = icp.icp_params_default(levels=levels, iters=[10, 5, 4, 3][:levels])
         Tg, sg, To, so = _register_both(ctx, p, prm)
         ang, dt = pose_err(Tg, To)
         assert ang < POSE_TOL and dt < POSE_TOL, (levels, W, H, ang, dt)
+    # level-0 model maps at an address that is not 16-byte aligned (the model
+    # pyramid then reads them with scalar loads)
+    flat_v = torch.empty(prob.model_vtx.size + 1, dtype=torch.float32, device="cuda")
+    flat_n = torch.empty(prob.model_nrm.size + 1, dtype=torch.float32, device="cuda")
+    flat_v[1:] = dev(prob.model_vtx.reshape(-1))
+    flat_n[1:] = dev(prob.model_nrm.reshape(-1))
+    mv_u, mn_u = flat_v[1:].view(prob.model_vtx.shape), flat_n[1:].view(prob.model_nrm.shape)
+    assert mv_u.data_ptr() % 16 != 0
+    Tg, sg = icp.icp_register(ctx, dev(prob.live_depth), mv_u, mn_u, prob.K, prob.imu_R, prob.init_pose, params)
+    To, so, _ = oracle.register_problem(prob, _oracle_params(params))
+    ang, dt = pose_err(Tg, To)
+    assert ang < POSE_TOL and dt < POSE_TOL, ("unaligned model maps", ang, dt)
     # zero iterations: pose is the IMU seed
     prm = icp.icp_params_default(iters=(0, 0, 0))
     Tg, sg = icp.icp_register(ctx, d, mv, mn, prob.K, prob.imu_R, prob.init_pose, prm)
