@@ -45,7 +45,9 @@ class Params(C.Structure):
         ("dist_max", C.c_double), ("cos_angle_max", C.c_double), ("band_beta", C.c_double),
         ("use_median_filter", C.c_int), ("use_imu_seed", C.c_int), ("lambda_mode", C.c_int),
         ("lambda_c", C.c_double), ("min_corr", C.c_int), ("ill_cond_eps", C.c_double),
-        ("converge_window", C.c_int),
+        ("converge_window", C.c_int), ("depth_filter", C.c_int), ("filter_radius", C.c_int),
+        ("filter_sigma_px", C.c_double), ("filter_sigma_m", C.c_double), ("normal_mode", C.c_int),
+        ("normal_radius", C.c_int),
     ]
 
 
@@ -77,6 +79,8 @@ def lib():
         L.or_level_intrinsics.argtypes = [P, i, P]
         L.or_depth_down.argtypes = [P, i, i, P]
         L.or_live_vn.argtypes = [P, i, i, P, P, P]
+        L.or_bilateral.argtypes = [P, i, i, i, d, d, P]
+        L.or_live_vn_box.argtypes = [P, i, i, P, i, P, P]
         L.or_model_l0.argtypes = [P, P, i, i, P, P]
         L.or_model_down.argtypes = [P, P, i, i, P, P]
         L.or_associate.argtypes = [P, P, P, P, i, i, P, P, d, d, P, P, P, P]
@@ -150,6 +154,25 @@ def live_vn(D, K):
     V = np.empty((3, H, W), np.float32)
     N = np.empty((3, H, W), np.float32)
     lib().or_live_vn(_p(D), W, H, _p(_f64(K)), _p(V), _p(N))
+    return V, N
+
+
+def bilateral(D, r=3, sigma_px=4.5, sigma_m=0.05):
+    """Bilateral smoothing of a depth image (Gaussian spatial, biweight range)."""
+    D = _f32(D)
+    H, W = D.shape
+    out = np.empty((H, W), np.float32)
+    lib().or_bilateral(_p(D), W, H, int(r), C.c_double(sigma_px), C.c_double(sigma_m), _p(out))
+    return out
+
+
+def live_vn_box(D, K, r=2):
+    """Vertex planes and box-average 3D-gradient normal planes (3, H, W)."""
+    D = _f32(D)
+    H, W = D.shape
+    V = np.empty((3, H, W), np.float32)
+    N = np.empty((3, H, W), np.float32)
+    lib().or_live_vn_box(_p(D), W, H, _p(_f64(K)), int(r), _p(V), _p(N))
     return V, N
 
 

@@ -63,6 +63,12 @@ void or_params_default(or_params* p) {
     p->min_corr = 6;
     p->ill_cond_eps = 1e-12;
     p->converge_window = 0;
+    p->depth_filter = 0;
+    p->filter_radius = 3;
+    p->filter_sigma_px = 4.5;
+    p->filter_sigma_m = 0.05;
+    p->normal_mode = 0;
+    p->normal_radius = 2;
 }
 
 /* Level l pixel (u, v) averages level-(l-1) pixels 2u..2u+1, 2v..2v+1; its
@@ -149,6 +155,121 @@ void or_live_vn(const float* D, int W, int H, const double K[4], float* V, float
             N[i] = (float)n[0]; /* stored FP32 */
             N[S + i] = (float)n[1];
             N[2 * S + i] = (float)n[2];
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * The paper's front end (Sec. 3.3: normals by an integral-image method, on
+ * KinectFusion's smoothed depth).  Readings taken:
+ *  - Smoothing is a bilateral filter over the (2r+1)^2 window: weight of a
+ *    valid neighbour q of a valid pixel p = exp(-(du^2 + dv^2) / (2 s^2))
+ *    (spatial Gaussian, s in pixels) times (1 - (dz/c)^2)^2 for
+ *    |dz| = |z_q - z_p| < c, else 0 (a biweight range kernel: polynomial, so
+ *    any implementation reproduces it exactly); out = sum(w z) / sum(w),
+ *    sums in FP64 in row-major window order; invalid pixels stay invalid.
+ *  - Normals: the average 3D gradient of the integral-image method with a
+ *    fixed smoothing box: the horizontal tangent is the sum of the vertices in
+ *    the right half of the (2r+1)^2 box minus the sum in the left half (rows
+ *    v-r..v+r, columns u+1..u+r and u-r..u-1), the vertical one the lower half
+ *    minus the upper half; n = normalise(h x g), flipped to face the camera.
+ *    The box sums are written out directly (an integral image gives the same
+ *    sums faster); the pixel is invalid unless its whole box is inside the
+ *    image and valid.
+ * ------------------------------------------------------------------------- */
+void or_bilateral(const float* D, int W, int H, int r, double sigma_px, double sigma_m, float* out) {
+    int n = 2 * r + 1;
+    double* ws = (double*)malloc((size_t)n * n * sizeof(double));
+    for (int dv = -r; dv <= r; ++dv)
+        for (int du = -r; du <= r; ++du)
+            ws[(dv + r) * n + (du + r)] = exp(-(double)(du * du + dv * dv) / (2.0 * sigma_px * sigma_px));
+#pragma omp parallel for schedule(static)
+    for (int v = 0; v < H; ++v) {
+        for (int u = 0; u < W; ++u) {
+            size_t i = (size_t)v * W + u;
+            float z = D[i];
+            if (!depth_ok(z)) {
+                out[i] = 0.0f;
+                continue;
+            }
+            double sw = 0.0, swz = 0.0;
+            for (int dv = -r; dv <= r; ++dv) {
+                int y = v + dv;
+                if (y < 0 || y >= H) continue;
+                for (int du = -r; du <= r; ++du) {
+                    int x = u + du;
+                    if (x < 0 || x >= W) continue;
+                    float zq = D[(size_t)y * W + x];
+                    if (!depth_ok(zq)) continue;
+                    double dz = (double)zq - (double)z;
+                    if (!(fabs(dz) < sigma_m)) continue;
+                    double t = dz / sigma_m;
+                    double a = 1.0 - t * t;
+                    double w = ws[(dv + r) * n + (du + r)] * (a * a);
+                    sw += w;
+                    swz += w * (double)zq;
+                }
+            }
+            out[i] = (float)(swz / sw);
+        }
+    }
+    free(ws);
+}
+
+void or_live_vn_box(const float* D, int W, int H, const double K[4], int r, float* V, float* N) {
+    size_t S = (size_t)W * H;
+    for (int v = 0; v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            size_t i = (size_t)v * W + u;
+            float p[3];
+            live_vertex(D, W, u, v, K, p);
+            V[i] = p[0];
+            V[S + i] = p[1];
+            V[2 * S + i] = p[2];
+        }
+#pragma omp parallel for schedule(static)
+    for (int v = 0; v < H; ++v) {
+        for (int u = 0; u < W; ++u) {
+            size_t i = (size_t)v * W + u;
+            N[i] = N[S + i] = N[2 * S + i] = f_nan();
+            if (u - r < 0 || u + r >= W || v - r < 0 || v + r >= H) continue;
+            int ok = 1;
+            double h[3] = {0, 0, 0}, g[3] = {0, 0, 0};
+            for (int k = 0; k < 3 && ok; ++k) {
+                double right = 0.0, left = 0.0, low = 0.0, up = 0.0;
+                for (int dv = -r; dv <= r && ok; ++dv)
+                    for (int du = -r; du <= r; ++du) {
+                        float x = V[(size_t)k * S + (size_t)(v + dv) * W + (u + du)];
+                        if (!isfinite(x)) {
+                            ok = 0;
+                            break;
+                        }
+                        if (du > 0) right += (double)x;
+                        if (du < 0) left += (double)x;
+                        if (dv > 0) low += (double)x;
+                        if (dv < 0) up += (double)x;
+                    }
+                h[k] = right - left;
+                g[k] = low - up;
+            }
+            if (!ok) continue;
+            double c[3];
+            c[0] = h[1] * g[2] - h[2] * g[1];
+            c[1] = h[2] * g[0] - h[0] * g[2];
+            c[2] = h[0] * g[1] - h[1] * g[0];
+            double len2 = (c[0] * c[0] + c[1] * c[1]) + c[2] * c[2];
+            if (!(len2 > 0.0) || !isfinite(len2)) continue;
+            double len = sqrt(len2);
+            double nn[3] = {c[0] / len, c[1] / len, c[2] / len};
+            double side = (nn[0] * (double)V[i] + nn[1] * (double)V[S + i]) + nn[2] * (double)V[2 * S + i];
+            if (side > 0.0) {
+                nn[0] = -nn[0];
+                nn[1] = -nn[1];
+                nn[2] = -nn[2];
+            }
+            N[i] = (float)nn[0];
+            N[S + i] = (float)nn[1];
+            N[2 * S + i] = (float)nn[2];
         }
     }
 }
@@ -548,9 +669,17 @@ int or_icp_register(const float* depth, int W, int H, const float* model_vtx, co
         MN[l] = (float*)malloc(3 * S * sizeof(float));
         or_level_intrinsics(K, l, Kl[l]);
     }
-    memcpy(D[0], depth, (size_t)W * H * sizeof(float));
+    if (p->depth_filter)
+        or_bilateral(depth, W, H, p->filter_radius, p->filter_sigma_px, p->filter_sigma_m, D[0]);
+    else
+        memcpy(D[0], depth, (size_t)W * H * sizeof(float));
     for (int l = 1; l < L; ++l) or_depth_down(D[l - 1], Wl[l - 1], Hl[l - 1], D[l]);
-    for (int l = 0; l < L; ++l) or_live_vn(D[l], Wl[l], Hl[l], Kl[l], LV[l], LN[l]);
+    for (int l = 0; l < L; ++l) {
+        if (p->normal_mode == 1)
+            or_live_vn_box(D[l], Wl[l], Hl[l], Kl[l], p->normal_radius, LV[l], LN[l]);
+        else
+            or_live_vn(D[l], Wl[l], Hl[l], Kl[l], LV[l], LN[l]);
+    }
     or_model_l0(model_vtx, model_nrm, W, H, MV[0], MN[0]);
     for (int l = 1; l < L; ++l) or_model_down(MV[l - 1], MN[l - 1], Wl[l - 1], Hl[l - 1], MV[l], MN[l]);
 

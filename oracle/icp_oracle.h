@@ -56,6 +56,12 @@ typedef struct {
     double ill_cond_eps;        /* LDLT pivot threshold relative to max diagonal */
     int converge_window;        /* 0: fixed cadence; k: stop a level once the median
                                    bin was equal on k successive iterations */
+    int depth_filter;           /* 1: bilateral smoothing of the level-0 depth first */
+    int filter_radius;          /* its window is (2r+1)^2 pixels */
+    double filter_sigma_px;     /* spatial Gaussian sigma, pixels */
+    double filter_sigma_m;      /* range kernel cut-off, metres */
+    int normal_mode;            /* 0: forward differences; 1: box-average 3D gradients */
+    int normal_radius;          /* the boxes of normal_mode 1 span (2r+1) pixels */
 } or_params;
 
 typedef struct {
@@ -83,6 +89,10 @@ void or_level_intrinsics(const double K0[4], int level, double Kl[4]);
 /* live front end */
 void or_depth_down(const float* D, int W, int H, float* Dn);
 void or_live_vn(const float* D, int W, int H, const double K[4], float* V, float* N);
+/* bilateral smoothing of a depth image (see the definition in icp_oracle.c) */
+void or_bilateral(const float* D, int W, int H, int r, double sigma_px, double sigma_m, float* out);
+/* vertex map and box-average 3D-gradient normals (normal_mode 1) */
+void or_live_vn_box(const float* D, int W, int H, const double K[4], int r, float* V, float* N);
 /* model maps */
 void or_model_l0(const float* vtx_aos, const float* nrm_aos, int W, int H, float* V, float* N);
 void or_model_down(const float* V, const float* N, int W, int H, float* Vn, float* Nn);
