@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define ICP_ABI_VERSION 1
+#define ICP_ABI_VERSION 2
 #define ICP_MAX_LEVELS 4
 #define ICP_MAX_DIM 8192
 #define ICP_HIST_BINS 1024 /* distance histogram: bins of 2^-13 m over [0, 0.125) m */
@@ -108,6 +108,19 @@ typedef struct {
                                        1: always two passes */
     int32_t tile_px[ICP_MAX_LEVELS];/* pixels per work-group tile per level (multiple of 1024,
                                        at most 65536); 0 = chosen by the library */
+    /* live front end (Sec. 3.3: normals by an integral-image method on smoothed depth) */
+    int32_t depth_filter;           /* 1: bilateral smoothing of the level-0 depth before the pyramid:
+                                       weights exp(-(du^2+dv^2)/(2 s^2)) (s = filter_sigma_px) times
+                                       (1-(dz/c)^2)^2 for |dz| < c = filter_sigma_m, over the
+                                       (2 filter_radius + 1)^2 window; default 0 */
+    int32_t filter_radius;          /* 1..7 (default 3) */
+    double filter_sigma_px;         /* > 0 (default 4.5) */
+    double filter_sigma_m;          /* > 0 (default 0.05) */
+    int32_t normal_mode;            /* 0: forward-difference normals (default); 1: average 3D
+                                       gradients over a (2 normal_radius + 1)^2 box (right half
+                                       minus left half, lower minus upper), invalid unless the
+                                       whole box is valid and inside the image */
+    int32_t normal_radius;          /* 1..7 (default 2) */
 } icp_params;
 
 typedef struct {
@@ -255,11 +268,13 @@ int icp_ctx_get_timing(icp_ctx* ctx, icp_kernel_time* out);
    They use the same kernels and launch configuration as icp_register on one
    problem held in the context. */
 
-/* Build the live and model pyramids of one problem into the context.  The
-   later stage calls read the caller's level-0 model maps, which must stay
-   alive until the next icp_stage_prepare or registration call. */
+/* Build the live and model pyramids of one problem into the context, with
+   the front end of params (depth_filter, normal_mode and their constants; NULL:
+   defaults).  The later stage calls read the caller's level-0 model maps, which
+   must stay alive until the next icp_stage_prepare or registration call. */
 int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const float* model_vtx,
-                      const float* model_nrm, const icp_intrinsics* K, int levels, void* stream);
+                      const float* model_nrm, const icp_intrinsics* K, int levels, const icp_params* params,
+                      void* stream);
 
 /* Copy level `level` of the prepared pyramids to device buffers (any may be
    NULL): depth (H_l*W_l), live vertex/normal as three planes of H_l*W_l
@@ -321,7 +336,8 @@ int icp_live_maps(icp_ctx* ctx, const float* depth, int W, int H, const icp_intr
    state of every open stream plus, per slot, the workspace of the largest
    batch the open streams can form would exceed hbm_budget_bytes (0: no
    limit); a stream's resident state is (frames_in_flight + 1) x 28 bytes per
-   pixel.  All calls may come from any host thread; results are taken with
+   pixel.  The server uses the default front end (params.depth_filter and
+   params.normal_mode 0; other values are rejected at creation).  All calls may come from any host thread; results are taken with
    icp_server_poll.  A HIP failure inside the scheduler makes every later call
    return it. */
 typedef struct icp_server icp_server;

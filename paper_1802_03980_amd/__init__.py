@@ -18,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libicp_mi355x.so")
 
-ICP_ABI_VERSION = 1
+ICP_ABI_VERSION = 2
 MAX_LEVELS = 4
 HIST_BINS = 1024
 OK, EINVAL, ENOMEM, EDEVICE, ETIMEOUT = 0, -1, -2, -3, -4
@@ -56,6 +56,8 @@ class icp_params(C.Structure):
         ("use_imu_seed", C.c_int32), ("lambda_mode", C.c_int32), ("lambda_c", C.c_double),
         ("min_corr", C.c_int32), ("ill_cond_eps", C.c_double), ("converge_window", C.c_int32),
         ("reduce_mode", C.c_int32), ("pass_mode", C.c_int32), ("tile_px", C.c_int32 * MAX_LEVELS),
+        ("depth_filter", C.c_int32), ("filter_radius", C.c_int32), ("filter_sigma_px", C.c_double),
+        ("filter_sigma_m", C.c_double), ("normal_mode", C.c_int32), ("normal_radius", C.c_int32),
     ]
 
 
@@ -135,7 +137,7 @@ def lib():
             "icp_ctx_set_timing": (I, [P, I]),
             "icp_ctx_set_graphs": (I, [P, I]),
             "icp_ctx_get_timing": (I, [P, P]),
-            "icp_stage_prepare": (I, [P, P, I, I, P, P, C.POINTER(icp_intrinsics), I, P]),
+            "icp_stage_prepare": (I, [P, P, I, I, P, P, C.POINTER(icp_intrinsics), I, P, P]),
             "icp_stage_level": (I, [P, I, P, P, P, P, P, P]),
             "icp_stage_associate": (I, [P, I, P, C.POINTER(icp_params), P, P, P, P, P]),
             "icp_stage_moments": (I, [P, I, P, C.POINTER(icp_params), I, I, P, P, P]),
@@ -375,12 +377,14 @@ def icp_ctx_get_timing(ctx):
 
 # ---------------------------------------------------------------- stage access
 
-def icp_stage_prepare(ctx, live_depth, model_vtx, model_nrm, K, levels=3, stream=None):
+def icp_stage_prepare(ctx, live_depth, model_vtx, model_nrm, K, levels=3, params=None, stream=None):
     H, W = live_depth.shape
     Kc = make_intrinsics(K)
+    prm = C.byref(params) if params is not None else None
     rc = lib().icp_stage_prepare(ctx.handle, _dev_ptr(live_depth, "float32", "live_depth"), W, H,
                                  _dev_ptr(model_vtx, "float32", "model_vtx"),
-                                 _dev_ptr(model_nrm, "float32", "model_nrm"), C.byref(Kc), levels, _stream(stream))
+                                 _dev_ptr(model_nrm, "float32", "model_nrm"), C.byref(Kc), levels, prm,
+                                 _stream(stream))
     _check(ctx, rc)
 
 

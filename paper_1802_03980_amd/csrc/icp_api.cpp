@@ -99,6 +99,14 @@ int check_params(icp_ctx* ctx, const icp_params* p) {
     if (p->converge_window < 0) return fail(ctx, ICP_EINVAL, "converge_window must be >= 0");
     if (p->reduce_mode != 0 && p->reduce_mode != 1) return fail(ctx, ICP_EINVAL, "reduce_mode must be 0 or 1");
     if (p->pass_mode != 0 && p->pass_mode != 1) return fail(ctx, ICP_EINVAL, "pass_mode must be 0 or 1");
+    if (p->depth_filter != 0 && p->depth_filter != 1) return fail(ctx, ICP_EINVAL, "depth_filter must be 0 or 1");
+    if (p->depth_filter &&
+        (p->filter_radius < 1 || p->filter_radius > ICP_FILTER_MAX_R || !(p->filter_sigma_px > 0.0) ||
+         !std::isfinite(p->filter_sigma_px) || !(p->filter_sigma_m > 0.0) || !std::isfinite(p->filter_sigma_m)))
+        return fail(ctx, ICP_EINVAL, "filter_radius must be in 1..7 and the filter sigmas > 0");
+    if (p->normal_mode != 0 && p->normal_mode != 1) return fail(ctx, ICP_EINVAL, "normal_mode must be 0 or 1");
+    if (p->normal_mode == 1 && (p->normal_radius < 1 || p->normal_radius > ICP_FILTER_MAX_R))
+        return fail(ctx, ICP_EINVAL, "normal_radius must be in 1..7");
     return ICP_OK;
 }
 
@@ -180,7 +188,7 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
             P.max_q[l] = std::max(P.max_q[l], L.W + L.H + 2);
             for (int t = 0; t < L.n_tiles; ++t) P.owner[l].push_back(p);
             const size_t S = (size_t)L.ps * sizeof(float);
-            L.Dw = l > 0 ? reinterpret_cast<float*>(take(S)) : nullptr;
+            L.Dw = reinterpret_cast<float*>(take(S));  // level 0: the filtered depth, when filtering
             L.LV = reinterpret_cast<float*>(take(3 * S));
             L.LN = reinterpret_cast<float*>(take(3 * S));
             const size_t A = (size_t)L.npx * 3 * sizeof(float);
@@ -267,6 +275,25 @@ int ensure_stage(icp_ctx* ctx, size_t bytes) {
     return ICP_OK;
 }
 
+// The bilateral filter's spatial weights exp(-(du^2 + dv^2) / (2 s^2)) in
+// row-major window order, evaluated on the host once per call.
+FrontEnd front_end(const icp_params* p) {
+    FrontEnd fe{};
+    fe.depth_filter = p->depth_filter;
+    fe.filter_radius = p->filter_radius;
+    fe.normal_mode = p->normal_mode;
+    fe.normal_radius = p->normal_radius;
+    fe.sigma_m = p->filter_sigma_m;
+    if (p->depth_filter) {
+        const int r = p->filter_radius, n = 2 * r + 1;
+        const double sp = p->filter_sigma_px;
+        for (int dv = -r; dv <= r; ++dv)
+            for (int du = -r; du <= r; ++du)
+                fe.ws[(dv + r) * n + (du + r)] = std::exp(-(double)(du * du + dv * dv) / (2.0 * sp * sp));
+    }
+    return fe;
+}
+
 KParams kparams(const icp_params* p) {
     KParams k{};
     k.d2max = p->dist_max * p->dist_max;
@@ -283,8 +310,8 @@ KParams kparams(const icp_params* p) {
 }
 
 // Plan, place and upload a batch; leaves device descriptors ready.
-int stage_batch(icp_ctx* ctx, int n, const icp_problem* probs, int levels, const int32_t* tile_req, Plan& P,
-                hipStream_t s) {
+int stage_batch(icp_ctx* ctx, int n, const icp_problem* probs, int levels, const int32_t* tile_req,
+                int depth_filter, Plan& P, hipStream_t s) {
     std::vector<int64_t> key = plan_signature(n, probs, levels, tile_req);
     if (key != ctx->plan_key || P.desc.size() != (size_t)n) {
         std::vector<int32_t> W(n), H(n);
@@ -319,8 +346,8 @@ int stage_batch(icp_ctx* ctx, int n, const icp_problem* probs, int levels, const
             L.fy = q.K.fy * s2;
             L.cx = (q.K.cx + 0.5) * s2 - 0.5;
             L.cy = (q.K.cy + 0.5) * s2 - 0.5;
-            L.Dw = l > 0 ? rebase(L.Dw, base) : nullptr;
-            L.D = l > 0 ? L.Dw : q.live_depth;
+            L.Dw = rebase(L.Dw, base);
+            L.D = (l > 0 || depth_filter) ? L.Dw : q.live_depth;
             L.LV = rebase(L.LV, base);
             L.LN = rebase(L.LN, base);
             L.MVw = l > 0 ? rebase(L.MVw, base) : nullptr;
@@ -332,6 +359,7 @@ int stage_batch(icp_ctx* ctx, int n, const icp_problem* probs, int levels, const
             L.part = rebase(L.part, base);
             L.part1 = rebase(L.part1, base);
         }
+        d.depth_in = q.live_depth;
         std::memcpy(d.imu_R, q.imu_R, sizeof(d.imu_R));
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 4; ++j) d.init[4 * i + j] = q.init_pose[4 * i + j];
@@ -419,7 +447,8 @@ int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* r
     int64_t px0 = 0;
     for (int p = 0; p < n; ++p) px0 += P.desc[p].lv[0].npx;
     if ((rc = time_begin(ctx, s, r, ICP_TIME_FRONT_END, px0))) return rc;
-    HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, P.max_npx, P.max_vn, P.max_mp, P.max_q, false, s));
+    HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, P.max_npx, P.max_vn, P.max_mp, P.max_q, false,
+                                      front_end(prm), s));
     if (prm->reduce_mode == 1) HIP_TRY(ctx, icpk::launch_centroid(d_desc, n, prm->levels, s));
     if ((rc = time_end(ctx, s, r))) return rc;
     // single pass needs the band's lower edge at bin 0 and the FP32 reduction
@@ -533,6 +562,12 @@ void icp_params_default(icp_params* p) {
     p->ill_cond_eps = 1e-12;
     p->converge_window = 0;
     p->reduce_mode = 0;
+    p->depth_filter = 0;
+    p->filter_radius = 3;
+    p->filter_sigma_px = 4.5;
+    p->filter_sigma_m = 0.05;
+    p->normal_mode = 0;
+    p->normal_radius = 2;
 }
 
 int icp_ctx_create(int device, size_t hbm_budget_bytes, icp_ctx** out) {
@@ -620,7 +655,7 @@ int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     Plan& P = ctx_plan(ctx);
-    if ((rc = stage_batch(ctx, n, probs, params->levels, params->tile_px, P, s))) return rc;
+    if ((rc = stage_batch(ctx, n, probs, params->levels, params->tile_px, params->depth_filter, P, s))) return rc;
     ctx->stage_ready = false;
     if ((rc = execute(ctx, n, params, P, s))) return rc;
     icp_result* d_res = reinterpret_cast<icp_result*>(static_cast<char*>(ctx->ws) + P.off_res);
@@ -738,7 +773,7 @@ int icp_register_async(icp_ctx* ctx, const float* live_depth, int W, int H, cons
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     Plan& P = ctx_plan(ctx);
-    if ((rc = stage_batch(ctx, 1, &q, params->levels, params->tile_px, P, s))) return rc;
+    if ((rc = stage_batch(ctx, 1, &q, params->levels, params->tile_px, params->depth_filter, P, s))) return rc;
     ctx->stage_ready = false;
     if ((rc = execute(ctx, 1, params, P, s))) return rc;
     icp_result* d_res = reinterpret_cast<icp_result*>(static_cast<char*>(ctx->ws) + P.off_res);
@@ -749,17 +784,22 @@ int icp_register_async(icp_ctx* ctx, const float* live_depth, int W, int H, cons
 // ------------------------------------------------------------------ stages
 
 int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const float* model_vtx,
-                      const float* model_nrm, const icp_intrinsics* K, int levels, void* stream) {
+                      const float* model_nrm, const icp_intrinsics* K, int levels, const icp_params* params,
+                      void* stream) {
     if (!ctx) return ICP_EINVAL;
     if (!K) return fail(ctx, ICP_EINVAL, "K is NULL");
     if (levels < 1 || levels > ICP_MAX_LEVELS) return fail(ctx, ICP_EINVAL, "levels must be in 1..4");
-    icp_problem q = one_problem(live_depth, W, H, model_vtx, model_nrm, K, nullptr, nullptr);
-    int rc = check_problem(ctx, q, levels);
+    icp_params dflt;
+    icp_params_default(&dflt);
+    const icp_params* prm = params ? params : &dflt;
+    int rc = check_params(ctx, prm);
     if (rc) return rc;
+    icp_problem q = one_problem(live_depth, W, H, model_vtx, model_nrm, K, nullptr, nullptr);
+    if ((rc = check_problem(ctx, q, levels))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     Plan& P = ctx_plan(ctx);
-    if ((rc = stage_batch(ctx, 1, &q, levels, nullptr, P, s))) return rc;
+    if ((rc = stage_batch(ctx, 1, &q, levels, nullptr, prm->depth_filter, P, s))) return rc;
     char* base = static_cast<char*>(ctx->ws);
     ctx->d_desc = reinterpret_cast<ProbDesc*>(base + P.off_desc);
     for (int l = 0; l < levels; ++l) {
@@ -771,7 +811,8 @@ int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const
     ctx->stage_desc = P.desc[0];
     ctx->stage_levels = levels;
     HIP_TRY(ctx, icpk::launch_init(ctx->d_desc, 1, 0, s));
-    HIP_TRY(ctx, icpk::launch_prepare(ctx->d_desc, 1, levels, P.max_npx, P.max_vn, P.max_mp, P.max_q, true, s));
+    HIP_TRY(ctx, icpk::launch_prepare(ctx->d_desc, 1, levels, P.max_npx, P.max_vn, P.max_mp, P.max_q, true,
+                                      front_end(prm), s));
     HIP_TRY(ctx, icpk::launch_centroid(ctx->d_desc, 1, levels, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     ctx->stage_ready = true;
@@ -903,7 +944,7 @@ int register_batch_async(icp_ctx* ctx, int n, const icp_problem* probs, const ic
         if ((rc = check_problem(ctx, probs[p], params->levels))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     Plan& P = ctx_plan(ctx);
-    if ((rc = stage_batch(ctx, n, probs, params->levels, params->tile_px, P, s))) return rc;
+    if ((rc = stage_batch(ctx, n, probs, params->levels, params->tile_px, params->depth_filter, P, s))) return rc;
     ctx->stage_ready = false;
     if ((rc = execute(ctx, n, params, P, s))) return rc;
     icp_result* d_res = reinterpret_cast<icp_result*>(static_cast<char*>(ctx->ws) + P.off_res);

@@ -49,6 +49,16 @@ struct LevelDesc {
     float* part1;               // single-pass partials: n_tiles * ICP_WIN_SLOTS * ICP_PART_STRIDE
 };
 
+// Front-end options of a batch: the bilateral filter's spatial weights (row-major
+// over the (2r+1)^2 window, computed on the host) and range cut-off, and the
+// normal mode.
+#define ICP_FILTER_MAX_R 7
+struct FrontEnd {
+    int32_t depth_filter, filter_radius, normal_mode, normal_radius;
+    double sigma_m;
+    double ws[(2 * ICP_FILTER_MAX_R + 1) * (2 * ICP_FILTER_MAX_R + 1)];
+};
+
 // One depth image turned into interleaved vertex / normal maps.
 struct MapsDesc {
     const float* depth;
@@ -83,6 +93,7 @@ struct ProbDesc {
     double imu_R[9];            // IMU rotation prior, row-major
     double init[12];            // initial pose, 3x4 row-major [R | t]
     ProbState* st;
+    const float* depth_in;      // the caller's level-0 depth (lv[0].D is its filtered copy when filtering)
 };
 
 // Scalars of a launch that are the same for every problem in it.

@@ -106,6 +106,109 @@ __device__ __forceinline__ void live_px(const ICP_GLOBAL float* D, int W, int H,
     live_from_depth(z, zr, zb, has_r, has_b, sx[du], sx[du + 1], sy[dv], sy[dv + 1], p, n);
 }
 
+// Bilateral smoothing of the level-0 depth into the level's workspace plane:
+// over the (2r+1)^2 window in row-major order, valid neighbours within the
+// range cut-off add ws * (1 - (dz/c)^2)^2 to the weight sum and that times z
+// to the weighted sum (FP64); out = sum(w z) / sum(w); invalid pixels stay 0.
+__global__ __launch_bounds__(ICP_WG) void k_bilateral(const ProbDesc* __restrict__ probs, FrontEnd fe) {
+    const ProbDesc& P = probs[blockIdx.y];
+    const LevelDesc& L = P.lv[0];
+    const int i = blockIdx.x * ICP_WG + threadIdx.x;
+    if (i >= L.npx) return;
+    const ICP_GLOBAL float* D = gconst(P.depth_in);
+    const int u = i % L.W, v = i / L.W, r = fe.filter_radius, n = 2 * r + 1;
+    const float z = D[i];
+    float out = 0.0f;
+    if (depth_ok(z)) {
+        double sw = 0.0, swz = 0.0;
+        for (int dv = -r; dv <= r; ++dv) {
+            const int y = v + dv;
+            if (y < 0 || y >= L.H) continue;
+            for (int du = -r; du <= r; ++du) {
+                const int x = u + du;
+                if (x < 0 || x >= L.W) continue;
+                const float zq = D[y * L.W + x];
+                if (!depth_ok(zq)) continue;
+                const double dz = (double)zq - (double)z;
+                if (!(fabs(dz) < fe.sigma_m)) continue;
+                const double t = dz / fe.sigma_m;
+                const double a = 1.0 - t * t;
+                const double w = fe.ws[(dv + r) * n + (du + r)] * (a * a);
+                sw += w;
+                swz += w * (double)zq;
+            }
+        }
+        out = (float)(swz / sw);
+    }
+    gmut(L.Dw)[i] = out;
+}
+
+// Box-average 3D-gradient normals (normal_mode 1): for the (2r+1)^2 box around
+// the pixel, the tangents are (right half - left half) and (lower half -
+// upper half) of the vertex sums, each a row-major FP64 sum of the FP32
+// vertices; n = normalise(h x g), flipped to face the camera; invalid unless
+// the whole box lies inside the image and is valid.
+__global__ __launch_bounds__(ICP_WG) void k_live_n_box(const ProbDesc* __restrict__ probs, int level, int r) {
+    const LevelDesc& L = probs[blockIdx.y].lv[level];
+    const int i = blockIdx.x * ICP_WG + threadIdx.x;
+    if (i >= L.npx) return;
+    const int u = i % L.W, v = i / L.W;
+    const ICP_GLOBAL float* D = gconst(L.D);
+    const ICP_GLOBAL double* XQ = gconst(L.XQ);
+    const ICP_GLOBAL double* YQ = gconst(L.YQ);
+    const float qnan = __builtin_nanf("");
+    float n[3] = {qnan, qnan, qnan};
+    if (u - r >= 0 && u + r < L.W && v - r >= 0 && v + r < L.H) {
+        double right[3] = {0, 0, 0}, left[3] = {0, 0, 0}, low[3] = {0, 0, 0}, up[3] = {0, 0, 0};
+        bool ok = true;
+        for (int dv = -r; dv <= r && ok; ++dv)
+            for (int du = -r; du <= r; ++du) {
+                float q[3];
+                live_vertex(D[(v + dv) * L.W + (u + du)], XQ[u + du], YQ[v + dv], q);
+                if (!fin(q[2])) {
+                    ok = false;
+                    break;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    if (du > 0) right[k] += (double)q[k];
+                    if (du < 0) left[k] += (double)q[k];
+                    if (dv > 0) low[k] += (double)q[k];
+                    if (dv < 0) up[k] += (double)q[k];
+                }
+            }
+        if (ok) {
+            double h[3], g[3];
+            for (int k = 0; k < 3; ++k) {
+                h[k] = right[k] - left[k];
+                g[k] = low[k] - up[k];
+            }
+            const double c0 = h[1] * g[2] - h[2] * g[1];
+            const double c1 = h[2] * g[0] - h[0] * g[2];
+            const double c2 = h[0] * g[1] - h[1] * g[0];
+            const double len2 = (c0 * c0 + c1 * c1) + c2 * c2;
+            if (len2 > 0.0 && __builtin_isfinite(len2)) {
+                const double len = sqrt(len2);
+                double m0 = c0 / len, m1 = c1 / len, m2 = c2 / len;
+                float p[3];
+                live_vertex(D[i], XQ[u], YQ[v], p);
+                const double side = (m0 * (double)p[0] + m1 * (double)p[1]) + m2 * (double)p[2];
+                if (side > 0.0) {
+                    m0 = -m0;
+                    m1 = -m1;
+                    m2 = -m2;
+                }
+                n[0] = (float)m0;
+                n[1] = (float)m1;
+                n[2] = (float)m2;
+            }
+        }
+    }
+    ICP_GLOBAL float* LN = gmut(L.LN);
+    LN[i] = n[0];
+    LN[L.ps + i] = n[1];
+    LN[2 * L.ps + i] = n[2];
+}
+
 // Back-projection quotient tables of a level: XQ[u] = (u - cx)/fx for
 // u = 0..W and YQ[v] = (v - cy)/fy for v = 0..H (the same FP64 divisions as
 // fe_quotients), read by the pixel passes.
@@ -908,14 +1011,23 @@ int live_vn_blocks(int W, int H) { return ((W + FE_TX - 1) / FE_TX) * ((H + FE_T
 int model_pairs(int W, int H) { return ((W + 1) / 2) * H; }
 
 hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, const int* max_vn_blocks,
-                          const int* max_model_pairs, const int* max_quot, bool with_live_maps, hipStream_t s) {
+                          const int* max_model_pairs, const int* max_quot, bool with_live_maps, const FrontEnd& fe,
+                          hipStream_t s) {
+    if (fe.depth_filter)
+        hipLaunchKernelGGL(k_bilateral, dim3(blocks_for(max_npx[0]), n), dim3(ICP_WG), 0, s, probs, fe);
     for (int l = 1; l < levels; ++l)
         hipLaunchKernelGGL(k_depth_down, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
     for (int l = 0; l < levels; ++l)
         hipLaunchKernelGGL(k_quotients, dim3(blocks_for(max_quot[l]), n), dim3(ICP_WG), 0, s, probs, l);
-    for (int l = 0; l < levels; ++l)
-        hipLaunchKernelGGL(k_live_vn, dim3(max_vn_blocks[l], n), dim3(ICP_WG), 0, s, probs, l,
-                           with_live_maps ? 1 : 0);
+    for (int l = 0; l < levels; ++l) {
+        // live vertex planes (stage access) and forward-difference normals
+        if (with_live_maps || fe.normal_mode == 0)
+            hipLaunchKernelGGL(k_live_vn, dim3(max_vn_blocks[l], n), dim3(ICP_WG), 0, s, probs, l,
+                               with_live_maps ? 1 : 0);
+        if (fe.normal_mode == 1)
+            hipLaunchKernelGGL(k_live_n_box, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l,
+                               fe.normal_radius);
+    }
     for (int l = 1; l < levels; ++l)
         hipLaunchKernelGGL(k_model_down, dim3(blocks_for(max_model_pairs[l]), n), dim3(ICP_WG), 0, s, probs, l);
     return hipGetLastError();

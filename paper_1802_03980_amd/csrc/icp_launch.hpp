@@ -28,12 +28,15 @@ hipError_t launch_depth_to_maps(const MapsDesc* jobs, int n, int max_blocks, hip
 int live_vn_blocks(int W, int H);
 // model-pyramid threads of a W x H level (one per pair of pixels in a row)
 int model_pairs(int W, int H);
-// Front end of every problem: depth pyramid, back-projection quotient tables,
-// live normal planes, model pyramid, and (with_live_maps) the live vertex
-// planes, which only the stage-access calls read (the pixel passes rebuild
-// the vertices from depth).
+// Front end of every problem: optional bilateral filter of the caller's depth
+// into the level-0 workspace plane, depth pyramid,
+// back-projection quotient tables, live normal planes (forward differences or
+// box gradients), model pyramid, and (with_live_maps) the live vertex planes,
+// which only the stage-access calls read (the pixel passes rebuild the
+// vertices from depth).
 hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, const int* max_vn_blocks,
-                          const int* max_model_pairs, const int* max_quot, bool with_live_maps, hipStream_t s);
+                          const int* max_model_pairs, const int* max_quot, bool with_live_maps, const FrontEnd& fe,
+                          hipStream_t s);
 // one ICP iteration at ctl.level: pass 1 over `tiles` flat tiles of all
 // problems, the per-problem band, pass 2 over the tiles, the per-problem solve
 hipError_t launch_pass1(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp, int fused,

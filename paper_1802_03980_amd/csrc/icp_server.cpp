@@ -414,6 +414,8 @@ int icp_server_create(const icp_server_config* cfg, icp_server** out) {
         }
     }
     if (rc == ICP_OK) rc = icpi::validate_params(S->slots[0].ctx, &cfg->params);
+    // the served model maps are built with the default front end, so the live frames must be too
+    if (rc == ICP_OK && (cfg->params.depth_filter != 0 || cfg->params.normal_mode != 0)) rc = ICP_EINVAL;
     if (rc != ICP_OK) {
         for (Slot& sl : S->slots) {
             if (sl.ctx) icp_ctx_destroy(sl.ctx);

@@ -63,3 +63,17 @@ def test_workspace_bytes_scales_with_pixels():
     assert vga >= 640 * 480 * (24 * (1 + 0.25 + 0.0625) + 28 * (0.25 + 0.0625))
     assert 2.9 < hd / vga < 3.1 and 1.9 < two / vga < 2.1
     assert icp.lib().icp_workspace_bytes(0, None, None, 3) == 0
+
+
+def test_public_struct_sizes_match_the_c_compiler(tmp_path):
+    """Every struct the binding mirrors has the size the C compiler gives it."""
+    names = ["icp_intrinsics", "icp_params", "icp_level_stats", "icp_stats", "icp_problem", "icp_result",
+             "icp_kernel_time", "icp_server_config", "icp_server_result", "icp_server_counters"]
+    src = tmp_path / "sz.c"
+    src.write_text("#include <stdio.h>\n#include \"icp.h\"\nint main(void) {\n" +
+                   "".join(f'  printf("%zu\\n", sizeof({n}));\n' for n in names) + "  return 0;\n}\n")
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    sizes = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    for n, sz in zip(names, sizes):
+        assert C.sizeof(getattr(icp, n)) == sz, n

@@ -85,6 +85,47 @@ def test_s1_pyramid_maps_bitwise(ctx, name):
                 pytest.fail(f"{name} level {l} {key}: {bad.sum()} of {bad.size} entries differ")
 
 
+FRONT_ENDS = {"filter": dict(depth_filter=1), "box_normals": dict(normal_mode=1),
+              "both": dict(depth_filter=1, normal_mode=1, normal_radius=3)}
+
+
+@pytest.mark.parametrize("mode", list(FRONT_ENDS))
+def test_s1_front_end_modes_bitwise(ctx, mode):
+    """The bilateral filter and the box-gradient normals give the oracle's maps
+    bit for bit at every level."""
+    prob = synth.config1_problem(4)
+    params = icp.icp_params_default(**FRONT_ENDS[mode])
+    d, mv, mn = upload(prob)
+    _ALIVE[:] = [d, mv, mn]
+    icp.icp_stage_prepare(ctx, d, mv, mn, prob.K, 3, params)
+    D = prob.live_depth
+    if params.depth_filter:
+        D = oracle.bilateral(D, params.filter_radius, params.filter_sigma_px, params.filter_sigma_m)
+    for l in range(3):
+        if l > 0:
+            D = oracle.depth_down(D)
+        Kl = oracle.level_intrinsics(prob.K, l)
+        if params.normal_mode:
+            V, N = oracle.live_vn_box(D, Kl, params.normal_radius)
+        else:
+            V, N = oracle.live_vn(D, Kl)
+        Dg, LV, LN, _, _ = (host(t) for t in icp.icp_stage_level(ctx, l, prob.H, prob.W))
+        for key, g, o in (("D", Dg, D), ("LV", LV, V), ("LN", LN, N)):
+            assert _same_nan(g, o), f"{mode} level {l} {key}"
+
+
+@pytest.mark.parametrize("mode", list(FRONT_ENDS))
+def test_end_to_end_front_end_modes(ctx, mode):
+    params = icp.icp_params_default(**FRONT_ENDS[mode])
+    for prob in [synth.config1_problem(1), synth.RoomSequence(0, n_frames=2).problem(0)]:
+        Tg, sg, To, so = _register_both(ctx, prob, params)
+        ang, dt = pose_err(Tg, To)
+        assert ang < POSE_TOL and dt < POSE_TOL, (mode, prob.name, ang, dt)
+        for l in range(3):
+            assert sg["levels"][l]["iters_run"] == so[l]["iters_run"]
+            assert abs(sg["levels"][l]["n_kept"] - so[l]["n_kept"]) <= max(2, 1e-3 * so[l]["n_kept"])
+
+
 def _poses_for(prob):
     seed = np.eye(4)
     seed[:3, :3] = prob.imu_R
@@ -176,7 +217,10 @@ def _oracle_params(p):
                                  cos_angle_max=p.cos_angle_max, band_beta=p.band_beta,
                                  use_median_filter=p.use_median_filter, use_imu_seed=p.use_imu_seed,
                                  lambda_mode=p.lambda_mode, lambda_c=p.lambda_c, min_corr=p.min_corr,
-                                 ill_cond_eps=p.ill_cond_eps, converge_window=p.converge_window)
+                                 ill_cond_eps=p.ill_cond_eps, converge_window=p.converge_window,
+                                 depth_filter=p.depth_filter, filter_radius=p.filter_radius,
+                                 filter_sigma_px=p.filter_sigma_px, filter_sigma_m=p.filter_sigma_m,
+                                 normal_mode=p.normal_mode, normal_radius=p.normal_radius)
 
 
 def _register_both(ctx, prob, params):
@@ -359,7 +403,8 @@ def test_invalid_arguments(ctx):
         icp.icp_register(ctx, d[:, :155].contiguous(), mv, mn, prob.K, prob.imu_R, prob.init_pose)
     assert e.value.code == icp.EINVAL
     for bad in [dict(levels=0), dict(levels=5), dict(dist_max=0.2), dict(lambda_mode=9), dict(lambda_c=-1.0),
-                dict(tile_px=(100, 0, 0)), dict(reduce_mode=2)]:
+                dict(tile_px=(100, 0, 0)), dict(reduce_mode=2), dict(depth_filter=1, filter_radius=8),
+                dict(normal_mode=2), dict(normal_mode=1, normal_radius=0)]:
         with pytest.raises(icp.IcpError) as e:
             icp.icp_register(ctx, d, mv, mn, prob.K, prob.imu_R, prob.init_pose, icp.icp_params_default(**bad))
         assert e.value.code == icp.EINVAL, bad

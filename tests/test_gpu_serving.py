@@ -41,7 +41,10 @@ def _oracle_params(p):
                                  cos_angle_max=p.cos_angle_max, band_beta=p.band_beta,
                                  use_median_filter=p.use_median_filter, use_imu_seed=p.use_imu_seed,
                                  lambda_mode=p.lambda_mode, lambda_c=p.lambda_c, min_corr=p.min_corr,
-                                 ill_cond_eps=p.ill_cond_eps, converge_window=p.converge_window)
+                                 ill_cond_eps=p.ill_cond_eps, converge_window=p.converge_window,
+                                 depth_filter=p.depth_filter, filter_radius=p.filter_radius,
+                                 filter_sigma_px=p.filter_sigma_px, filter_sigma_m=p.filter_sigma_m,
+                                 normal_mode=p.normal_mode, normal_radius=p.normal_radius)
 
 
 def _interleave(V, N):
