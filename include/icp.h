@@ -117,9 +117,10 @@ typedef struct {
     double filter_sigma_px;         /* > 0 (default 4.5) */
     double filter_sigma_m;          /* > 0 (default 0.05) */
     int32_t normal_mode;            /* 0: forward-difference normals (default); 1: average 3D
-                                       gradients over a (2 normal_radius + 1)^2 box (right half
-                                       minus left half, lower minus upper), invalid unless the
-                                       whole box is valid and inside the image */
+                                       gradients over a (2 normal_radius + 1)^2 box (mean of the
+                                       valid vertices of the right half minus the left half,
+                                       lower minus upper); needs a valid pixel, the box inside the
+                                       image and half of each half box valid */
     int32_t normal_radius;          /* 1..7 (default 2) */
 } icp_params;
 

@@ -169,13 +169,15 @@ void or_live_vn(const float* D, int W, int H, const double K[4], float* V, float
  *    any implementation reproduces it exactly); out = sum(w z) / sum(w),
  *    sums in FP64 in row-major window order; invalid pixels stay invalid.
  *  - Normals: the average 3D gradient of the integral-image method with a
- *    fixed smoothing box: the horizontal tangent is the sum of the vertices in
- *    the right half of the (2r+1)^2 box minus the sum in the left half (rows
- *    v-r..v+r, columns u+1..u+r and u-r..u-1), the vertical one the lower half
- *    minus the upper half; n = normalise(h x g), flipped to face the camera.
- *    The box sums are written out directly (an integral image gives the same
- *    sums faster); the pixel is invalid unless its whole box is inside the
- *    image and valid.
+ *    fixed smoothing box: the horizontal tangent is the mean of the valid
+ *    vertices in the right half of the (2r+1)^2 box minus the mean over the
+ *    left half (rows v-r..v+r, columns u+1..u+r and u-r..u-1), the vertical
+ *    one the lower half minus the upper half; n = normalise(h x g), flipped to
+ *    face the camera.  Like the method's valid-count integral images, the
+ *    means run over the valid pixels only; the pixel needs a valid vertex, a
+ *    box inside the image and at least half of each half box valid.  The box
+ *    sums are written out directly (an integral image gives the same sums
+ *    faster), in row-major order.
  * ------------------------------------------------------------------------- */
 void or_bilateral(const float* D, int W, int H, int r, double sigma_px, double sigma_m, float* out) {
     int n = 2 * r + 1;
@@ -233,26 +235,33 @@ void or_live_vn_box(const float* D, int W, int H, const double K[4], int r, floa
             size_t i = (size_t)v * W + u;
             N[i] = N[S + i] = N[2 * S + i] = f_nan();
             if (u - r < 0 || u + r >= W || v - r < 0 || v + r >= H) continue;
-            int ok = 1;
-            double h[3] = {0, 0, 0}, g[3] = {0, 0, 0};
-            for (int k = 0; k < 3 && ok; ++k) {
-                double right = 0.0, left = 0.0, low = 0.0, up = 0.0;
-                for (int dv = -r; dv <= r && ok; ++dv)
-                    for (int du = -r; du <= r; ++du) {
-                        float x = V[(size_t)k * S + (size_t)(v + dv) * W + (u + du)];
-                        if (!isfinite(x)) {
-                            ok = 0;
-                            break;
-                        }
-                        if (du > 0) right += (double)x;
-                        if (du < 0) left += (double)x;
-                        if (dv > 0) low += (double)x;
-                        if (dv < 0) up += (double)x;
+            if (!isfinite(V[2 * S + i])) continue;
+            /* valid pixels of each half box, and the vertex sums over them */
+            int nr = 0, nl = 0, nd = 0, nu = 0;
+            double sr[3] = {0, 0, 0}, sl[3] = {0, 0, 0}, sd[3] = {0, 0, 0}, su[3] = {0, 0, 0};
+            for (int dv = -r; dv <= r; ++dv)
+                for (int du = -r; du <= r; ++du) {
+                    size_t j = (size_t)(v + dv) * W + (u + du);
+                    if (!isfinite(V[2 * S + j])) continue;
+                    for (int k = 0; k < 3; ++k) {
+                        double x = (double)V[(size_t)k * S + j];
+                        if (du > 0) sr[k] += x;
+                        if (du < 0) sl[k] += x;
+                        if (dv > 0) sd[k] += x;
+                        if (dv < 0) su[k] += x;
                     }
-                h[k] = right - left;
-                g[k] = low - up;
+                    nr += du > 0;
+                    nl += du < 0;
+                    nd += dv > 0;
+                    nu += dv < 0;
+                }
+            int need = (r * (2 * r + 1) + 1) / 2;
+            if (nr < need || nl < need || nd < need || nu < need) continue;
+            double h[3], g[3];
+            for (int k = 0; k < 3; ++k) {
+                h[k] = sr[k] / nr - sl[k] / nl;
+                g[k] = sd[k] / nd - su[k] / nu;
             }
-            if (!ok) continue;
             double c[3];
             c[0] = h[1] * g[2] - h[2] * g[1];
             c[1] = h[2] * g[0] - h[0] * g[2];

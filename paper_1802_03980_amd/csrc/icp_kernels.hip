@@ -144,10 +144,11 @@ __global__ __launch_bounds__(ICP_WG) void k_bilateral(const ProbDesc* __restrict
 }
 
 // Box-average 3D-gradient normals (normal_mode 1): for the (2r+1)^2 box around
-// the pixel, the tangents are (right half - left half) and (lower half -
-// upper half) of the vertex sums, each a row-major FP64 sum of the FP32
-// vertices; n = normalise(h x g), flipped to face the camera; invalid unless
-// the whole box lies inside the image and is valid.
+// the pixel, the tangents are (mean over the right half - mean over the left
+// half) and (lower - upper) of the valid vertices, each half sum a row-major
+// FP64 sum of the FP32 vertices; n = normalise(h x g), flipped to face the
+// camera; the pixel needs a valid vertex, a box inside the image and at least
+// half of each half box valid.
 __global__ __launch_bounds__(ICP_WG) void k_live_n_box(const ProbDesc* __restrict__ probs, int level, int r) {
     const LevelDesc& L = probs[blockIdx.y].lv[level];
     const int i = blockIdx.x * ICP_WG + threadIdx.x;
@@ -158,29 +159,34 @@ __global__ __launch_bounds__(ICP_WG) void k_live_n_box(const ProbDesc* __restric
     const ICP_GLOBAL double* YQ = gconst(L.YQ);
     const float qnan = __builtin_nanf("");
     float n[3] = {qnan, qnan, qnan};
-    if (u - r >= 0 && u + r < L.W && v - r >= 0 && v + r < L.H) {
-        double right[3] = {0, 0, 0}, left[3] = {0, 0, 0}, low[3] = {0, 0, 0}, up[3] = {0, 0, 0};
-        bool ok = true;
-        for (int dv = -r; dv <= r && ok; ++dv)
+    float p[3];
+    live_vertex(D[i], XQ[u], YQ[v], p);
+    if (u - r >= 0 && u + r < L.W && v - r >= 0 && v + r < L.H && fin(p[2])) {
+        double sr[3] = {0, 0, 0}, sl[3] = {0, 0, 0}, sd[3] = {0, 0, 0}, su[3] = {0, 0, 0};
+        int nr = 0, nl = 0, nd = 0, nu = 0;
+        for (int dv = -r; dv <= r; ++dv)
             for (int du = -r; du <= r; ++du) {
                 float q[3];
                 live_vertex(D[(v + dv) * L.W + (u + du)], XQ[u + du], YQ[v + dv], q);
-                if (!fin(q[2])) {
-                    ok = false;
-                    break;
-                }
+                if (!fin(q[2])) continue;
                 for (int k = 0; k < 3; ++k) {
-                    if (du > 0) right[k] += (double)q[k];
-                    if (du < 0) left[k] += (double)q[k];
-                    if (dv > 0) low[k] += (double)q[k];
-                    if (dv < 0) up[k] += (double)q[k];
+                    const double x = (double)q[k];
+                    if (du > 0) sr[k] += x;
+                    if (du < 0) sl[k] += x;
+                    if (dv > 0) sd[k] += x;
+                    if (dv < 0) su[k] += x;
                 }
+                nr += du > 0;
+                nl += du < 0;
+                nd += dv > 0;
+                nu += dv < 0;
             }
-        if (ok) {
+        const int need = (r * (2 * r + 1) + 1) / 2;
+        if (nr >= need && nl >= need && nd >= need && nu >= need) {
             double h[3], g[3];
             for (int k = 0; k < 3; ++k) {
-                h[k] = right[k] - left[k];
-                g[k] = low[k] - up[k];
+                h[k] = sr[k] / nr - sl[k] / nl;
+                g[k] = sd[k] / nd - su[k] / nu;
             }
             const double c0 = h[1] * g[2] - h[2] * g[1];
             const double c1 = h[2] * g[0] - h[0] * g[2];
@@ -189,8 +195,6 @@ __global__ __launch_bounds__(ICP_WG) void k_live_n_box(const ProbDesc* __restric
             if (len2 > 0.0 && __builtin_isfinite(len2)) {
                 const double len = sqrt(len2);
                 double m0 = c0 / len, m1 = c1 / len, m2 = c2 / len;
-                float p[3];
-                live_vertex(D[i], XQ[u], YQ[v], p);
                 const double side = (m0 * (double)p[0] + m1 * (double)p[1]) + m2 * (double)p[2];
                 if (side > 0.0) {
                     m0 = -m0;

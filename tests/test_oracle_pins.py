@@ -150,11 +150,22 @@ def test_box_normals_on_plane_and_holes():
     inner = N[:, r:H - r, r:W - r].astype(np.float64)
     assert np.max(np.abs(inner - want[:, None, None])) < 1e-5
     assert np.all(np.isnan(N[:, :r, :])) and np.all(np.isnan(N[:, :, -r:]))
+    # holes: a pixel keeps its normal while half of each half box is valid;
+    # the means over valid pixels still give the plane normal
     d2 = d.copy()
     d2[15, 20] = 0.0
+    d2[15, 21] = 0.0
     _, N2 = oracle.live_vn_box(d2, K, r)
-    lost = np.isnan(N2[0]) & ~np.isnan(N[0])
-    assert lost.sum() == (2 * r + 1) ** 2 and lost[15 - r:16 + r, 20 - r:21 + r].all()
+    assert np.isnan(N2[0, 15, 20]) and np.isnan(N2[0, 15, 21])
+    ok = ~np.isnan(N2[0])
+    assert ok[14, 20] and ok[16, 21]
+    assert np.max(np.abs(N2[:, ok].astype(np.float64) - want[:, None])) < 1e-5
+    d3 = d.copy()
+    d3[10:20, 19:22] = 0.0  # an invalid block, columns 19..21
+    _, N3 = oracle.live_vn_box(d3, K, r)
+    assert np.isnan(N3[0, 15, 18])  # right half (columns 19..20) all invalid
+    assert not np.isnan(N3[0, 15, 17])  # right half (columns 18..19): 5 of 10 valid, enough
+
 
 
 def test_paper_front_end_registration():
