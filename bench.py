@@ -112,6 +112,9 @@ def main():
                     help="room: batched VGA room sequence (default); batch64: 64 uneven problems in one batch; "
                          "serve: the frame server on 32 camera streams; sweep: robustness and lambda sweeps")
     ap.add_argument("--oracle-sample", type=int, default=16, help="problems checked against the oracle (batch64)")
+    ap.add_argument("--front-end", choices=("kinfu", "paper"), default="kinfu",
+                    help="kinfu: raw depth, forward-difference normals (default); paper: bilateral filter and "
+                         "box-average 3D-gradient normals")
     ap.add_argument("--serve-frames", type=int, default=600, help="frames per stream (serve)")
     ap.add_argument("--serve-period", type=int, default=30, help="distinct frames per stream (serve)")
     ap.add_argument("--serve-sweep", default="1,4,16,64", help="arrival-rate multipliers of the saturation sweep")
@@ -157,7 +160,8 @@ def main():
     torch.cuda.synchronize()
 
     ctx = icp.icp_ctx_create(0)
-    params = icp.icp_params_default()
+    front = dict(depth_filter=1, normal_mode=1) if args.front_end == "paper" else {}
+    params = icp.icp_params_default(**front)
     batch = icp.ProblemArray(items)
     px_it = sum((640 >> l) * (480 >> l) * params.iters[l] for l in range(params.levels))
 
@@ -202,7 +206,7 @@ def main():
     split = None
     results_sp = None
     if not args.no_split:
-        params_sp = icp.icp_params_default(reduce_mode=1)
+        params_sp = icp.icp_params_default(reduce_mode=1, **front)
         log("split-precision (FP16 hi+lo MFMA) batched steps")
         icp.icp_register_batch(ctx, batch, params_sp)
         torch.cuda.synchronize()
@@ -277,7 +281,7 @@ def main():
         done = 0
         errs = []
         while done < n and (done < 2 or time.perf_counter() - ts < args.cpu_seconds):
-            Tref, _, _ = oracle.register_problem(probs[done])
+            Tref, _, _ = oracle.register_problem(probs[done], oracle.default_params(**front))
             e = []
             for res in (results, results_sp):
                 if res is not None:
@@ -323,6 +327,8 @@ def main():
         "data": "synthetic (seeded room sequence; no dataset)",
         "config": {"workload": f"Kinect-scale room sequence, {n} frame-to-model registrations of 640x480, "
                                "3 levels {10,5,4}, lambda 5, median filter",
+                   "front_end": ("bilateral filter + box-gradient normals" if front else
+                                 "raw depth, forward-difference normals"),
                    "registrations_per_step": n, "px_iterations_per_registration": px_it,
                    "path": "batched (all frames per launch)"},
         "latency_ms": None if lat.size == 0 else {
@@ -332,6 +338,8 @@ def main():
         "batch_latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                              "p99": round(float(np.percentile(step_ms, 99)), 3)},
         "pose_err_vs_oracle": pose_err,
+        "mean_pairs_kept": {f"level{l}": round(float(np.mean([r[1]["levels"][l]["n_kept"] for r in results])), 1)
+                            for l in range(params.levels)},
         "split_precision": split,
         "roofline": roofline,
         "iteration_roofline": {"achieved": round(iteration_gbs, 1), "unit": "GB/s",

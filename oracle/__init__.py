@@ -80,6 +80,8 @@ def lib():
         L.or_depth_down.argtypes = [P, i, i, P]
         L.or_live_vn.argtypes = [P, i, i, P, P, P]
         L.or_bilateral.argtypes = [P, i, i, i, d, d, P]
+        L.or_tsdf_integrate.argtypes = [P, P, i, d, P, d, d, P, i, i, P, P]
+        L.or_tsdf_raycast.argtypes = [P, P, i, d, P, d, d, i, i, P, P, P, P]
         L.or_live_vn_box.argtypes = [P, i, i, P, i, P, P]
         L.or_model_l0.argtypes = [P, P, i, i, P, P]
         L.or_model_down.argtypes = [P, P, i, i, P, P]
@@ -174,6 +176,33 @@ def live_vn_box(D, K, r=2):
     N = np.empty((3, H, W), np.float32)
     lib().or_live_vn_box(_p(D), W, H, _p(_f64(K)), int(r), _p(V), _p(N))
     return V, N
+
+
+class Tsdf:
+    """TSDF volume held as host arrays (test infrastructure)."""
+
+    def __init__(self, dim=64, size=3.0, origin=(-1.5, -1.5, 0.5), mu=None, max_weight=128.0):
+        self.dim, self.size = int(dim), float(size)
+        self.origin = np.ascontiguousarray(origin, dtype=np.float64)
+        self.mu = float(mu) if mu is not None else 4.0 * self.size / self.dim
+        self.max_weight = float(max_weight)
+        self.tsdf = np.zeros(self.dim ** 3, np.float32)
+        self.weight = np.zeros(self.dim ** 3, np.float32)
+
+    def integrate(self, depth, K, T_wc):
+        depth = _f32(depth)
+        H, W = depth.shape
+        lib().or_tsdf_integrate(_p(self.tsdf), _p(self.weight), self.dim, C.c_double(self.size), _p(self.origin),
+                                C.c_double(self.mu), C.c_double(self.max_weight), _p(depth), W, H,
+                                _p(_f64(K)), _p(_f64(np.asarray(T_wc, dtype=np.float64).reshape(16))))
+
+    def raycast(self, W, H, K, T_wc, tmin=0.4, tmax=8.0):
+        vtx = np.empty((H, W, 3), np.float32)
+        nrm = np.empty((H, W, 3), np.float32)
+        lib().or_tsdf_raycast(_p(self.tsdf), _p(self.weight), self.dim, C.c_double(self.size), _p(self.origin),
+                              C.c_double(tmin), C.c_double(tmax), W, H, _p(_f64(K)),
+                              _p(_f64(np.asarray(T_wc, dtype=np.float64).reshape(16))), _p(vtx), _p(nrm))
+        return vtx, nrm
 
 
 def model_l0(vtx, nrm):

@@ -284,6 +284,155 @@ void or_live_vn_box(const float* D, int W, int H, const double K[4], int r, floa
 }
 
 /* ---------------------------------------------------------------------------
+ * TSDF volume (KinectFusion's model; Sec. 5.2 sizes it 512^3 over at most
+ * 6 m).  Readings taken (the paper defers to KinectFusion):
+ *  - integration, per voxel centre x_w: x_c = R^T (x_w - t) in the camera of
+ *    T_wc = [R | t]; skip unless x_c.z > 0 and the projection (rounded as in
+ *    the association) lands on a valid depth z; sdf = z - x_c.z (projective,
+ *    along z); skip if sdf < -mu; f = min(1, sdf / mu); running average
+ *    tsdf = (tsdf w + f) / (w + 1), w = min(w + 1, max_weight); FP64 math,
+ *    FP32 storage;
+ *  - ray casting, per pixel: the ray z (x_u, y_v, 1) in the camera, sampled at
+ *    z = tmin + s * side / 2 (s = 0, 1, ...) up to tmax; a sample is the
+ *    trilinear interpolation of the 8 voxels around the point (all observed,
+ *    weight > 0, else the sample is missing); the first change from > 0 to
+ *    <= 0 between consecutive samples is the surface, at the linearly
+ *    interpolated depth; a change from < 0 to >= 0 (a back face) ends the ray
+ *    without a surface; vertex = z* (x_u, y_v, 1); normal = the normalised
+ *    central-difference gradient (one voxel on each side, six samples) turned
+ *    into the camera frame and facing the camera.
+ * ------------------------------------------------------------------------- */
+void or_tsdf_integrate(float* tsdf, float* weight, int dim, double size, const double origin[3], double mu,
+                       double max_weight, const float* depth, int W, int H, const double K[4],
+                       const double T_wc[16]) {
+    double side = size / dim;
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < dim; ++k) {
+        for (int j = 0; j < dim; ++j) {
+            for (int i = 0; i < dim; ++i) {
+                double xw[3] = {origin[0] + ((double)i + 0.5) * side, origin[1] + ((double)j + 0.5) * side,
+                                origin[2] + ((double)k + 0.5) * side};
+                double dx[3] = {xw[0] - T_wc[3], xw[1] - T_wc[7], xw[2] - T_wc[11]};
+                double xc[3];
+                for (int a = 0; a < 3; ++a)
+                    xc[a] = (T_wc[a] * dx[0] + T_wc[4 + a] * dx[1]) + T_wc[8 + a] * dx[2];
+                if (!(xc[2] > 0.0)) continue;
+                double uu = floor(K[0] * (xc[0] / xc[2]) + K[2] + 0.5);
+                double vv = floor(K[1] * (xc[1] / xc[2]) + K[3] + 0.5);
+                if (!(uu >= 0.0 && uu <= (double)(W - 1) && vv >= 0.0 && vv <= (double)(H - 1))) continue;
+                float z = depth[(size_t)vv * W + (size_t)uu];
+                if (!depth_ok(z)) continue;
+                double sdf = (double)z - xc[2];
+                if (sdf < -mu) continue;
+                double f = sdf / mu;
+                if (f > 1.0) f = 1.0;
+                size_t idx = ((size_t)k * dim + j) * dim + i;
+                double w = (double)weight[idx];
+                tsdf[idx] = (float)(((double)tsdf[idx] * w + f) / (w + 1.0));
+                double wn = w + 1.0;
+                weight[idx] = (float)(wn < max_weight ? wn : max_weight);
+            }
+        }
+    }
+}
+
+/* trilinear TSDF at world point p; returns 0 when a corner voxel is unobserved */
+static int tsdf_sample(const float* tsdf, const float* weight, int dim, double side, const double origin[3],
+                       const double p[3], double* out) {
+    double g[3], fr[3];
+    int i0[3];
+    for (int a = 0; a < 3; ++a) {
+        g[a] = (p[a] - origin[a]) / side - 0.5;
+        double fl = floor(g[a]);
+        if (!(fl >= 0.0 && fl < (double)(dim - 1))) return 0;
+        i0[a] = (int)fl;
+        fr[a] = g[a] - fl;
+    }
+    double c[8];
+    for (int n = 0; n < 8; ++n) {
+        int ii = i0[0] + (n & 1), jj = i0[1] + ((n >> 1) & 1), kk = i0[2] + ((n >> 2) & 1);
+        size_t idx = ((size_t)kk * dim + jj) * dim + ii;
+        if (!(weight[idx] > 0.0f)) return 0;
+        c[n] = (double)tsdf[idx];
+    }
+    double c00 = c[0] * (1.0 - fr[0]) + c[1] * fr[0];
+    double c10 = c[2] * (1.0 - fr[0]) + c[3] * fr[0];
+    double c01 = c[4] * (1.0 - fr[0]) + c[5] * fr[0];
+    double c11 = c[6] * (1.0 - fr[0]) + c[7] * fr[0];
+    double c0 = c00 * (1.0 - fr[1]) + c10 * fr[1];
+    double c1 = c01 * (1.0 - fr[1]) + c11 * fr[1];
+    *out = c0 * (1.0 - fr[2]) + c1 * fr[2];
+    return 1;
+}
+
+void or_tsdf_raycast(const float* tsdf, const float* weight, int dim, double size, const double origin[3],
+                     double tmin, double tmax, int W, int H, const double K[4], const double T_wc[16], float* vtx,
+                     float* nrm) {
+    double side = size / dim;
+    double dz = 0.5 * side;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int v = 0; v < H; ++v) {
+        for (int u = 0; u < W; ++u) {
+            size_t i = (size_t)v * W + u;
+            for (int a = 0; a < 3; ++a) vtx[3 * i + a] = nrm[3 * i + a] = f_nan();
+            double dc[3] = {((double)u - K[2]) / K[0], ((double)v - K[3]) / K[1], 1.0};
+            double dw[3];
+            for (int a = 0; a < 3; ++a) dw[a] = (T_wc[4 * a] * dc[0] + T_wc[4 * a + 1] * dc[1]) + T_wc[4 * a + 2];
+            int have_prev = 0;
+            double t_prev = 0.0, f_prev = 0.0, t_hit = -1.0;
+            for (int s_ = 0;; ++s_) {
+                double t = tmin + (double)s_ * dz;
+                if (t > tmax) break;
+                double p[3] = {T_wc[3] + t * dw[0], T_wc[7] + t * dw[1], T_wc[11] + t * dw[2]};
+                double f;
+                if (!tsdf_sample(tsdf, weight, dim, side, origin, p, &f)) {
+                    have_prev = 0;
+                    continue;
+                }
+                if (have_prev && f_prev > 0.0 && f <= 0.0) {
+                    t_hit = t_prev + (t - t_prev) * (f_prev / (f_prev - f));
+                    break;
+                }
+                if (have_prev && f_prev < 0.0 && f >= 0.0) break;
+                have_prev = 1;
+                t_prev = t;
+                f_prev = f;
+            }
+            if (!(t_hit > 0.0)) continue;
+            double ph[3] = {T_wc[3] + t_hit * dw[0], T_wc[7] + t_hit * dw[1], T_wc[11] + t_hit * dw[2]};
+            double gw[3];
+            int ok = 1;
+            for (int a = 0; a < 3 && ok; ++a) {
+                double q1[3] = {ph[0], ph[1], ph[2]}, q0[3] = {ph[0], ph[1], ph[2]};
+                q1[a] += side;
+                q0[a] -= side;
+                double f1, f0;
+                ok = tsdf_sample(tsdf, weight, dim, side, origin, q1, &f1) &&
+                     tsdf_sample(tsdf, weight, dim, side, origin, q0, &f0);
+                gw[a] = f1 - f0;
+            }
+            if (!ok) continue;
+            double len2 = (gw[0] * gw[0] + gw[1] * gw[1]) + gw[2] * gw[2];
+            if (!(len2 > 0.0)) continue;
+            double len = sqrt(len2);
+            double nw[3] = {gw[0] / len, gw[1] / len, gw[2] / len};
+            double nc[3], pc[3];
+            for (int a = 0; a < 3; ++a) {
+                nc[a] = (T_wc[a] * nw[0] + T_wc[4 + a] * nw[1]) + T_wc[8 + a] * nw[2];
+                pc[a] = t_hit * dc[a];
+            }
+            double sd = (nc[0] * pc[0] + nc[1] * pc[1]) + nc[2] * pc[2];
+            if (sd > 0.0)
+                for (int a = 0; a < 3; ++a) nc[a] = -nc[a];
+            for (int a = 0; a < 3; ++a) {
+                vtx[3 * i + a] = (float)pc[a];
+                nrm[3 * i + a] = (float)nc[a];
+            }
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------
  * Model maps (the raycast prediction of Sec. 3's frame-to-model alignment;
  * an input here).  A pixel is valid iff all six components are finite.
  * ------------------------------------------------------------------------- */

@@ -119,6 +119,18 @@ int or_solve_update(const double M[28], int64_t n, const double T_in[12], int la
                     double lambda_c, int min_corr, double eps, double T_out[12], double x[6]);
 void or_se3_exp(const double w[3], const double tau[3], double R[9], double t[3]);
 
+/* TSDF volume (the model the tracking aligns to, Sec. 5.2: a 512^3 cube of at
+   most 6 m).  dim^3 voxels of side size/dim, voxel (i, j, k) (i fastest) centred
+   at origin + (i + 1/2, j + 1/2, k + 1/2) * side; tsdf and weight arrays of
+   dim^3 floats.  T_wc: camera-to-world pose, 4x4 row-major. */
+void or_tsdf_integrate(float* tsdf, float* weight, int dim, double size, const double origin[3], double mu,
+                       double max_weight, const float* depth, int W, int H, const double K[4],
+                       const double T_wc[16]);
+/* model maps (H*W*3, camera frame of T_wc, NaN where no surface) by ray casting */
+void or_tsdf_raycast(const float* tsdf, const float* weight, int dim, double size, const double origin[3],
+                     double tmin, double tmax, int W, int H, const double K[4], const double T_wc[16], float* vtx,
+                     float* nrm);
+
 /* whole registration; pose_out is 4x4 row-major; trace may be NULL.
    Returns the number of trace records written (or would have written). */
 int or_icp_register(const float* depth, int W, int H, const float* model_vtx, const float* model_nrm,

@@ -447,6 +447,19 @@ class RoomSequence:
             self._cache[i] = hit
         return hit
 
+    def frame(self, k):
+        """Frame k for tracking against a reconstruction: (noisy depth float32,
+        IMU orientation in the world, true camera-to-world pose).  For k >= 1
+        the depth and IMU equal those of problem(k - 1)."""
+        if not 0 <= k < self.n_frames:
+            raise IndexError(k)
+        rng = _rng(2, self.seed, k) if k > 0 else _rng(2, self.seed, 0, 1)
+        P = self.poses[k]
+        d, _, _, _ = self._render(k)
+        d = add_sensor_noise(d, rng)
+        R_imu_world = rot_from_rotvec(random_unit(rng) * rng.normal() * self.imu_sigma) @ P[:3, :3]
+        return d.astype(np.float32), R_imu_world, P
+
     def problem(self, k):
         """Registration of frame k+1 against model maps of frame k (0-based k)."""
         if not 0 <= k < self.n_frames - 1:

@@ -490,3 +490,78 @@ def test_failure_cases():
     _, mv, mn, _ = render([Plane(n=np.array([0, 0, -1.0]), c=-2.0)], W, H, K, np.eye(4))
     pose, st, _ = oracle.register(d, mv, mn, K, np.eye(3), np.eye(4), oracle.default_params(levels=1))
     assert st[0]["status"] == oracle.ILL_COND
+
+
+# --------------------------------------------------------------- TSDF model
+
+def test_tsdf_plane_integration_and_raycast():
+    """P17: one view of a fronto-parallel plane at 2 m: the observed voxels in
+    front of it hold min(1, (2 - z)/mu) (the projective signed distance), those
+    more than mu behind it stay unobserved; integrating the same view again
+    keeps the values and doubles the weights; ray casting from the same camera
+    finds the plane at 2 m with normal (0, 0, -1)."""
+    W, H = 80, 60
+    K = centred_intrinsics(W, H, 70.0)
+    d = np.full((H, W), 2.0, np.float32)
+    vol = oracle.Tsdf(dim=64, size=3.2, origin=(-1.6, -1.6, 0.4))
+    vol.integrate(d, K, np.eye(4))
+    side = vol.size / vol.dim
+    t = vol.tsdf.reshape(vol.dim, vol.dim, vol.dim)  # [k][j][i]
+    w = vol.weight.reshape(vol.dim, vol.dim, vol.dim)
+    zc = vol.origin[2] + (np.arange(vol.dim) + 0.5) * side
+    ic = jc = vol.dim // 2  # the central column projects inside the image
+    for k in range(vol.dim):
+        if 2.0 - zc[k] < -vol.mu:
+            assert w[k, jc, ic] == 0
+        else:
+            assert w[k, jc, ic] == 1
+            assert abs(t[k, jc, ic] - min(1.0, (2.0 - zc[k]) / vol.mu)) < 1e-6
+    before = vol.tsdf.copy()
+    vol.integrate(d, K, np.eye(4))
+    assert np.array_equal(vol.tsdf, before) and np.max(vol.weight) == 2
+    vtx, nrm = vol.raycast(W, H, K, np.eye(4), tmin=0.5, tmax=3.0)
+    hit = ~np.isnan(vtx[..., 2])
+    assert hit[4:-4, 4:-4].all()
+    # a third view of the plane at 2.1 m: the weighted running average
+    vol2 = oracle.Tsdf(dim=64, size=3.2, origin=(-1.6, -1.6, 0.4))
+    vol2.tsdf[:], vol2.weight[:] = vol.tsdf, vol.weight
+    vol2.integrate(np.full((H, W), 2.1, np.float32), K, np.eye(4))
+    t2 = vol2.tsdf.reshape(vol.dim, vol.dim, vol.dim)
+    for k in range(vol.dim):
+        f_new = min(1.0, (np.float32(2.1) - zc[k]) / vol.mu)
+        if f_new < -1.0:
+            continue
+        want = (f_new if w[k, jc, ic] == 0 else (2 * min(1.0, (2.0 - zc[k]) / vol.mu) + f_new) / 3)
+        assert abs(t2[k, jc, ic] - want) < 1e-6, k  # only rays along the frustum's edge meet unobserved voxels
+    assert np.max(np.abs(vtx[hit][:, 2] - 2.0)) < 1e-6
+    assert np.max(np.abs(nrm[hit] - np.array([0, 0, -1.0]))) < 1e-6
+
+
+def test_tsdf_sphere_raycast_lies_on_the_sphere():
+    """P18: a sphere seen from one camera (pixels finer than the voxels),
+    integrated and ray cast back from a slightly moved camera: where the
+    surface faces the camera (within 45 deg; towards the silhouette the
+    projective distance of a single view grows with the grazing angle) the
+    points lie on the sphere to a small fraction of a voxel and the normals
+    are radial within a few degrees."""
+    K = centred_intrinsics(320, 240, 266.0)
+    c, rad = np.array([0.05, -0.03, 2.0]), 0.5
+    sph = synth.scene.Sphere(centre=c, radius=rad)
+    d, _, _, _ = render([sph], 320, 240, K, np.eye(4), zmin=0.5, zmax=4.0)
+    vol = oracle.Tsdf(dim=96, size=1.6, origin=(-0.75, -0.83, 1.2))
+    vol.integrate(d.astype(np.float32), K, np.eye(4))
+    W, H = 96, 72
+    T = synth.pose_matrix(synth.rot_from_rotvec([0.0, 0.01, 0.0]), [0.01, 0.0, 0.0])
+    vtx, nrm = vol.raycast(W, H, centred_intrinsics(W, H, 80.0), T, tmin=0.5, tmax=3.0)
+    hit = ~np.isnan(vtx[..., 2])
+    assert hit.sum() > 500
+    pw = vtx[hit].astype(np.float64) @ T[:3, :3].T + T[:3, 3]
+    r_err = np.linalg.norm(pw - c, axis=1) - rad
+    side = vol.size / vol.dim
+    radial = (pw - c) / np.linalg.norm(pw - c, axis=1)[:, None]
+    view = pw / np.linalg.norm(pw, axis=1)[:, None]
+    facing = -np.sum(radial * view, axis=1) > math.cos(math.radians(45))
+    assert facing.sum() > 300
+    assert np.max(np.abs(r_err[facing])) < 0.15 * side
+    nw = nrm[hit].astype(np.float64) @ T[:3, :3].T
+    assert np.min(np.sum(nw * radial, axis=1)[facing]) > math.cos(math.radians(5))
