@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define ICP_ABI_VERSION 2
+#define ICP_ABI_VERSION 3
 #define ICP_MAX_LEVELS 4
 #define ICP_MAX_DIM 8192
 #define ICP_HIST_BINS 1024 /* distance histogram: bins of 2^-13 m over [0, 0.125) m */
@@ -317,6 +317,64 @@ int icp_stage_solve(icp_ctx* ctx, const double* moments, int64_t n, const double
    depth: H*W float32 on the device.  Asynchronous on `stream`. */
 int icp_live_maps(icp_ctx* ctx, const float* depth, int W, int H, const icp_intrinsics* K, float* vtx,
                   float* nrm, void* stream);
+
+/* ---------------------------------------------------------------- TSDF model */
+
+/* KinectFusion's reconstruction: a truncated signed distance volume, fused
+   from the tracked depth frames and ray-cast into the model maps that the next
+   frame registers against (the frame-to-model loop whose tracking the paper
+   improves; Sec. 4.3 shows its weights overwritten after a failed alignment,
+   Sec. 5.2 sizes it at 512^3 voxels over at most 6 m).  The caller owns the
+   voxel memory: icp_tsdf_bytes(dim) bytes on the device, 8 per voxel, a pair
+   (tsdf, weight) of float32 for voxel (i, j, k) at pair index
+   (k * dim + j) * dim + i (x fastest).  Voxel (i, j, k) is the cube of edge
+   side = size / dim whose centre is origin + (i + 1/2, j + 1/2, k + 1/2) side
+   in world coordinates.  weight 0 = never observed.  All arithmetic is FP64
+   and rounds as written, so results are reproducible bit for bit.
+   T_wc: 16 doubles, row-major 4x4 camera-to-world pose, host memory (only
+   the top 3x4 is read; the rotation must be orthonormal for the geometry to
+   mean anything, which is not checked).  Calls are asynchronous on `stream`
+   and return ICP_EINVAL for NULL pointers, dim outside [2, 1024], size, mu
+   or max_weight not finite and positive (max_weight >= 1), W, H outside
+   [1, ICP_MAX_DIM], or bad intrinsics. */
+typedef struct {
+    float* voxels;        /* device, icp_tsdf_bytes(dim) bytes, 256-byte aligned */
+    int32_t dim;          /* voxels per edge */
+    int32_t pad_;
+    double size;          /* edge of the cube, metres */
+    double origin[3];     /* world position of the cube's minimum corner */
+    double mu;            /* truncation distance, metres */
+    double max_weight;    /* cap of the running-average weight */
+} icp_tsdf;
+
+size_t icp_tsdf_bytes(int dim);
+
+/* Every voxel to (0, 0): nothing observed. */
+int icp_tsdf_reset(icp_ctx* ctx, const icp_tsdf* vol, void* stream);
+
+/* Fuse one depth image (H*W float32 metres, device) taken from T_wc.  Each
+   voxel centre is moved into the camera; if it is in front (z > 0) and its
+   nearest pixel (floor(f x/z + c + 1/2), as in the association) has valid
+   depth D, the projective distance sdf = D - z counts unless sdf < -mu:
+   f = min(1, sdf / mu), tsdf <- (tsdf w + f) / (w + 1), w <- min(w + 1,
+   max_weight).  Voxels not seen keep their values. */
+int icp_tsdf_integrate(icp_ctx* ctx, const icp_tsdf* vol, const float* depth, int W, int H,
+                       const icp_intrinsics* K, const double* T_wc, void* stream);
+
+/* Predicted maps of a W x H camera with intrinsics K at T_wc, written as
+   model maps for icp_register (H*W*3 float32 each, interleaved, camera frame
+   of T_wc, NaN where no surface).  The ray of pixel (u, v) is z (x_u, y_v, 1),
+   x_u = (u - cx) / fx, sampled at z = tmin + s side / 2 (s = 0, 1, ...) while
+   z <= tmax; a sample interpolates the 8 surrounding voxels trilinearly and
+   is missing if any of them has weight 0.  The first step from a positive to
+   a non-positive sample marks the surface (depth interpolated linearly
+   between them); a step from negative to non-negative ends the ray with no
+   surface.  The normal is the normalised central difference of samples one
+   voxel away along each axis (no normal, and no vertex, if one is missing),
+   turned to face the camera.  Requires 0 < tmin < tmax and at most 2^24
+   steps. */
+int icp_tsdf_raycast(icp_ctx* ctx, const icp_tsdf* vol, int W, int H, const icp_intrinsics* K, const double* T_wc,
+                     double tmin, double tmax, float* vtx, float* nrm, void* stream);
 
 /* ---------------------------------------------------------------- serving */
 

@@ -18,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libicp_mi355x.so")
 
-ICP_ABI_VERSION = 2
+ICP_ABI_VERSION = 3
 MAX_LEVELS = 4
 HIST_BINS = 1024
 OK, EINVAL, ENOMEM, EDEVICE, ETIMEOUT = 0, -1, -2, -3, -4
@@ -35,7 +35,8 @@ EXPORTS = (
     "icp_stage_associate", "icp_stage_moments", "icp_stage_solve", "icp_live_maps", "icp_autotune_tiles",
     "icp_server_config_default", "icp_server_clock", "icp_server_create", "icp_server_destroy",
     "icp_server_last_error", "icp_server_open_stream", "icp_server_close_stream", "icp_server_submit",
-    "icp_server_poll", "icp_server_get_counters",
+    "icp_server_poll", "icp_server_get_counters", "icp_tsdf_bytes", "icp_tsdf_reset", "icp_tsdf_integrate",
+    "icp_tsdf_raycast",
 )
 
 
@@ -47,6 +48,11 @@ class IcpError(RuntimeError):
 
 class icp_intrinsics(C.Structure):
     _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double)]
+
+
+class icp_tsdf(C.Structure):
+    _fields_ = [("voxels", C.c_void_p), ("dim", C.c_int32), ("pad_", C.c_int32), ("size", C.c_double),
+                ("origin", C.c_double * 3), ("mu", C.c_double), ("max_weight", C.c_double)]
 
 
 class icp_params(C.Structure):
@@ -144,6 +150,10 @@ def lib():
             "icp_stage_solve": (I, [P, P, C.c_int64, P, C.POINTER(icp_params), P, P, P, P]),
             "icp_live_maps": (I, [P, P, I, I, C.POINTER(icp_intrinsics), P, P, P]),
             "icp_autotune_tiles": (I, [P, I, P, C.POINTER(icp_params), I, P, C.POINTER(D), P]),
+            "icp_tsdf_bytes": (Z, [I]),
+            "icp_tsdf_reset": (I, [P, C.POINTER(icp_tsdf), P]),
+            "icp_tsdf_integrate": (I, [P, C.POINTER(icp_tsdf), P, I, I, C.POINTER(icp_intrinsics), P, P]),
+            "icp_tsdf_raycast": (I, [P, C.POINTER(icp_tsdf), I, I, C.POINTER(icp_intrinsics), P, D, D, P, P, P]),
             "icp_server_config_default": (None, [C.POINTER(icp_server_config)]),
             "icp_server_clock": (D, []),
             "icp_server_create": (I, [C.POINTER(icp_server_config), C.POINTER(P)]),
@@ -460,6 +470,58 @@ def icp_live_maps(ctx, depth, K, stream=None):
                              C.c_void_p(vtx.data_ptr()), C.c_void_p(nrm.data_ptr()), _stream(stream))
     _check(ctx, rc)
     return vtx, nrm
+
+
+# ---------------------------------------------------------------- TSDF model
+
+class TsdfVolume:
+    """A TSDF volume in a device tensor of (dim, dim, dim, 2) float32 pairs
+    (tsdf, weight), indexed [k][j][i] (x fastest).  mu defaults to 4 voxels."""
+
+    def __init__(self, ctx, dim=512, size=6.0, origin=(-3.0, -3.0, -3.0), mu=None, max_weight=128.0):
+        import torch
+        self.ctx = ctx
+        self.dim, self.size = int(dim), float(size)
+        self.origin = tuple(float(o) for o in origin)
+        self.mu = float(mu) if mu is not None else 4.0 * self.size / self.dim
+        self.max_weight = float(max_weight)
+        if lib().icp_tsdf_bytes(self.dim) == 0:
+            raise IcpError(EINVAL, "TSDF dim must be in 2..1024")
+        self.voxels = torch.empty((self.dim, self.dim, self.dim, 2), dtype=torch.float32,
+                                  device=torch.device("cuda", ctx.device))
+        self.desc = icp_tsdf(voxels=self.voxels.data_ptr(), dim=self.dim, pad_=0, size=self.size,
+                             origin=(C.c_double * 3)(*self.origin), mu=self.mu, max_weight=self.max_weight)
+        self.reset()
+
+    def reset(self, stream=None):
+        _check(self.ctx, lib().icp_tsdf_reset(self.ctx.handle, C.byref(self.desc), _stream(stream)))
+
+    def integrate(self, depth, K, T_wc, stream=None):
+        H, W = depth.shape
+        T = _f64(T_wc, 16, "T_wc")
+        Kc = make_intrinsics(K)
+        _check(self.ctx, lib().icp_tsdf_integrate(self.ctx.handle, C.byref(self.desc), _dev_ptr(depth, "float32", "depth"),
+                                                  W, H, C.byref(Kc), _np_ptr(T), _stream(stream)))
+
+    def raycast(self, W, H, K, T_wc, tmin=0.4, tmax=8.0, out=None, stream=None):
+        """Interleaved (H, W, 3) vertex and normal maps in the camera of T_wc."""
+        import torch
+        if out is None:
+            dev = torch.device("cuda", self.ctx.device)
+            out = (torch.empty((H, W, 3), dtype=torch.float32, device=dev),
+                   torch.empty((H, W, 3), dtype=torch.float32, device=dev))
+        vtx, nrm = out
+        T = _f64(T_wc, 16, "T_wc")
+        Kc = make_intrinsics(K)
+        _check(self.ctx, lib().icp_tsdf_raycast(self.ctx.handle, C.byref(self.desc), W, H, C.byref(Kc), _np_ptr(T),
+                                                float(tmin), float(tmax), _dev_ptr(vtx, "float32", "vtx"),
+                                                _dev_ptr(nrm, "float32", "nrm"), _stream(stream)))
+        return vtx, nrm
+
+    def host_arrays(self):
+        """(tsdf, weight) as flat float32 host arrays in voxel order."""
+        v = self.voxels.cpu().numpy().reshape(-1, 2)
+        return np.ascontiguousarray(v[:, 0]), np.ascontiguousarray(v[:, 1])
 
 
 # ---------------------------------------------------------------- serving

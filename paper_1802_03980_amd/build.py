@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libicp_mi355x.so")
-SOURCES = [os.path.join(CSRC, "icp_kernels.hip"), os.path.join(CSRC, "icp_api.cpp"), os.path.join(CSRC, "icp_server.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("icp_kernels.hip", "icp_tsdf.hip", "icp_api.cpp", "icp_server.cpp")]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -761,6 +761,86 @@ int icp_live_maps(icp_ctx* ctx, const float* depth, int W, int H, const icp_intr
     return ICP_OK;
 }
 
+namespace {
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int check_tsdf(icp_ctx* ctx, const icp_tsdf* vol, TsdfDesc* out) {
+    if (!vol || !vol->voxels) return fail(ctx, ICP_EINVAL, "TSDF volume or its voxels is NULL");
+    if (vol->dim < 2 || vol->dim > 1024) return fail(ctx, ICP_EINVAL, "TSDF dim must be in 2..1024");
+    if (!finite_pos(vol->size) || !finite_pos(vol->mu) || !(std::isfinite(vol->max_weight) && vol->max_weight >= 1.0))
+        return fail(ctx, ICP_EINVAL, "TSDF size and mu must be finite and > 0, max_weight finite and >= 1");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(vol->origin[a])) return fail(ctx, ICP_EINVAL, "TSDF origin must be finite");
+    *out = TsdfDesc{vol->voxels, vol->dim, vol->size, {vol->origin[0], vol->origin[1], vol->origin[2]}, vol->mu,
+                          vol->max_weight};
+    return ICP_OK;
+}
+
+int check_camera(icp_ctx* ctx, int W, int H, const icp_intrinsics* K, const double* T_wc, icpk::PoseArg* T) {
+    if (!K || !T_wc) return fail(ctx, ICP_EINVAL, "NULL argument");
+    if (W < 1 || H < 1 || W > ICP_MAX_DIM || H > ICP_MAX_DIM) return fail(ctx, ICP_EINVAL, "W and H must be in 1..8192");
+    if (!(finite_pos(K->fx) && finite_pos(K->fy) && std::isfinite(K->cx) && std::isfinite(K->cy)))
+        return fail(ctx, ICP_EINVAL, "intrinsics must be finite with fx, fy > 0");
+    for (int i = 0; i < 12; ++i) {
+        if (!std::isfinite(T_wc[i])) return fail(ctx, ICP_EINVAL, "T_wc must be finite");
+        T->v[i] = T_wc[i];
+    }
+    return ICP_OK;
+}
+
+}  // namespace
+
+size_t icp_tsdf_bytes(int dim) {
+    if (dim < 2 || dim > 1024) return 0;
+    return (size_t)dim * dim * dim * 8;
+}
+
+int icp_tsdf_reset(icp_ctx* ctx, const icp_tsdf* vol, void* stream) {
+    if (!ctx) return ICP_EINVAL;
+    TsdfDesc d;
+    int rc = check_tsdf(ctx, vol, &d);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, icpk::launch_tsdf_fill(d, static_cast<hipStream_t>(stream)));
+    return ICP_OK;
+}
+
+int icp_tsdf_integrate(icp_ctx* ctx, const icp_tsdf* vol, const float* depth, int W, int H, const icp_intrinsics* K,
+                       const double* T_wc, void* stream) {
+    if (!ctx) return ICP_EINVAL;
+    TsdfDesc d;
+    icpk::PoseArg T;
+    int rc = check_tsdf(ctx, vol, &d);
+    if (rc) return rc;
+    if (!depth) return fail(ctx, ICP_EINVAL, "depth is NULL");
+    rc = check_camera(ctx, W, H, K, T_wc, &T);
+    if (rc) return rc;
+    const double Kv[4] = {K->fx, K->fy, K->cx, K->cy};
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, icpk::launch_tsdf_integrate(d, depth, W, H, Kv, T, static_cast<hipStream_t>(stream)));
+    return ICP_OK;
+}
+
+int icp_tsdf_raycast(icp_ctx* ctx, const icp_tsdf* vol, int W, int H, const icp_intrinsics* K, const double* T_wc,
+                     double tmin, double tmax, float* vtx, float* nrm, void* stream) {
+    if (!ctx) return ICP_EINVAL;
+    TsdfDesc d;
+    icpk::PoseArg T;
+    int rc = check_tsdf(ctx, vol, &d);
+    if (rc) return rc;
+    if (!vtx || !nrm) return fail(ctx, ICP_EINVAL, "output map is NULL");
+    rc = check_camera(ctx, W, H, K, T_wc, &T);
+    if (rc) return rc;
+    const double side = vol->size / (double)vol->dim;
+    if (!(finite_pos(tmin) && std::isfinite(tmax) && tmax > tmin && (tmax - tmin) / (0.5 * side) <= 16777216.0))
+        return fail(ctx, ICP_EINVAL, "need 0 < tmin < tmax and at most 2^24 ray steps");
+    const double Kv[4] = {K->fx, K->fy, K->cx, K->cy};
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, icpk::launch_tsdf_raycast(d, tmin, tmax, W, H, Kv, T, vtx, nrm, static_cast<hipStream_t>(stream)));
+    return ICP_OK;
+}
+
 int icp_register_async(icp_ctx* ctx, const float* live_depth, int W, int H, const float* model_vtx,
                        const float* model_nrm, const icp_intrinsics* K, const double* imu_R, const double* init_pose,
                        const icp_params* params, icp_result* result_dev, void* stream) {

@@ -22,7 +22,7 @@
 #define ICP_PART_STRIDE 32      // floats per tile partial: 28 moments, count, pad
 #define ICP_NMOM 28
 #define ICP_PX_PER_THREAD 4
-#define ICP_PASS1_PX 1          // pixels per thread and round in the single-pass kernel     // consecutive pixels per thread and round in the passes
+#define ICP_PASS1_PX 1          // pixels per thread and round in the single-pass kernel
 #define ICP_TILE_QUANTUM (ICP_WG * ICP_PX_PER_THREAD)
 #define ICP_PLANE_ALIGN 64      // floats
 #define ICP_WIN 48              // bins of the predicted band-edge window (single-pass mode)
@@ -66,6 +66,13 @@ struct MapsDesc {
     float* mn;
     int32_t W, H;
     double fx, fy, cx, cy;
+};
+
+// A TSDF volume as the kernels see it (the caller's icp_tsdf).
+struct TsdfDesc {
+    float* voxels;              // dim^3 (tsdf, weight) pairs, x fastest
+    int32_t dim;
+    double size, origin[3], mu, max_weight;
 };
 
 struct ProbState {

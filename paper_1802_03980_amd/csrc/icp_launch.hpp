@@ -56,4 +56,13 @@ hipError_t launch_stage_pass2(const ProbDesc* probs, const int* owner, int tiles
                               hipStream_t s);
 hipError_t launch_stage_solve(MomArg M, int64_t n, PoseArg pose, const KParams& kp, double* out, hipStream_t s);
 
+// TSDF volume (icp_tsdf.hip): clear every voxel to (0, 0); fuse one depth image
+// taken from camera-to-world pose T (3x4); ray-cast interleaved vertex / normal
+// maps in the camera of T.  K = fx, fy, cx, cy.
+hipError_t launch_tsdf_fill(const TsdfDesc& d, hipStream_t s);
+hipError_t launch_tsdf_integrate(const TsdfDesc& d, const float* depth, int W, int H, const double* K, PoseArg T,
+                                 hipStream_t s);
+hipError_t launch_tsdf_raycast(const TsdfDesc& d, double tmin, double tmax, int W, int H, const double* K, PoseArg T,
+                               float* vtx, float* nrm, hipStream_t s);
+
 }  // namespace icpk

@@ -68,7 +68,7 @@ def test_workspace_bytes_scales_with_pixels():
 def test_public_struct_sizes_match_the_c_compiler(tmp_path):
     """Every struct the binding mirrors has the size the C compiler gives it."""
     names = ["icp_intrinsics", "icp_params", "icp_level_stats", "icp_stats", "icp_problem", "icp_result",
-             "icp_kernel_time", "icp_server_config", "icp_server_result", "icp_server_counters"]
+             "icp_kernel_time", "icp_server_config", "icp_server_result", "icp_server_counters", "icp_tsdf"]
     src = tmp_path / "sz.c"
     src.write_text("#include <stdio.h>\n#include \"icp.h\"\nint main(void) {\n" +
                    "".join(f'  printf("%zu\\n", sizeof({n}));\n' for n in names) + "  return 0;\n}\n")

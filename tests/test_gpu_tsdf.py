@@ -1,0 +1,211 @@
+"""TSDF model on the GPU against the oracle's volume.
+
+  - Integration: every voxel (tsdf, weight) equal to the oracle's bit for bit
+    after several frames (running averages), at ragged volume sizes and at the
+    full 512^3 size over the room.
+  - Ray casting: vertex and normal maps equal to the oracle's bit for bit
+    (NaN where the oracle finds no surface), at ragged image sizes, from a
+    camera outside the volume, along rays parallel to a volume face, and on a
+    crop of a VGA camera over the full-size volume.
+  - The frame-to-model loop (ray cast at the last pose, register, integrate at
+    the new pose) tracks the room like the oracle's loop: poses within
+    1e-5 rad / 1e-5 m per frame.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1802_03980_amd as icp
+from synth.scene import Plane, RoomSequence, Sphere, centred_intrinsics, pose_matrix, render, rot_from_rotvec
+from tests.poseutil import pose_err
+
+pytestmark = pytest.mark.gpu
+
+ROOM_VOL = dict(size=6.4, origin=(-3.2, -3.2, -3.2))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return icp.icp_ctx_create(0)
+
+
+def _bits_equal(a, b):
+    a, b = np.asarray(a, np.float32), np.asarray(b, np.float32)
+    if a.shape != b.shape:
+        return False
+    na, nb = np.isnan(a), np.isnan(b)
+    return np.array_equal(na, nb) and np.array_equal(a[~na].view(np.uint32), b[~nb].view(np.uint32))
+
+
+def _volumes(ctx, dim, **kw):
+    g = icp.TsdfVolume(ctx, dim=dim, **kw)
+    o = oracle.Tsdf(dim=dim, size=g.size, origin=g.origin, mu=g.mu, max_weight=g.max_weight)
+    return g, o
+
+
+def _integrate_both(g, o, depth, K, T):
+    g.integrate(torch.from_numpy(depth).cuda(), K, T)
+    o.integrate(depth, K, T)
+
+
+def _assert_volume_equal(g, o):
+    torch.cuda.synchronize()
+    t, w = g.host_arrays()
+    assert _bits_equal(w, o.weight), "weights differ"
+    assert _bits_equal(t, o.tsdf), "tsdf values differ"
+
+
+def _assert_raycast_equal(g, o, W, H, K, T, tmin=0.4, tmax=8.0):
+    vg, ng = g.raycast(W, H, K, T, tmin, tmax)
+    torch.cuda.synchronize()
+    vo, no = o.raycast(W, H, K, T, tmin, tmax)
+    assert _bits_equal(vg.cpu().numpy(), vo), "vertex maps differ"
+    assert _bits_equal(ng.cpu().numpy(), no), "normal maps differ"
+    return vo
+
+
+@pytest.mark.parametrize("dim", [70, 96])
+def test_integrate_and_raycast_bitwise(ctx, dim):
+    seq = RoomSequence(seed=1, n_frames=5, W=160, H=120, f=131.25)
+    g, o = _volumes(ctx, dim, **ROOM_VOL)
+    for k in range(3):
+        d, _, P = seq.frame(k)
+        _integrate_both(g, o, d, seq.K, P)
+    _assert_volume_equal(g, o)
+    assert o.weight.max() == 3 and (o.weight > 0).mean() > 0.02
+    # ragged image (not a multiple of the 16 x 16 ray tile) from a later pose
+    W, H = 90, 70
+    K = centred_intrinsics(W, H, 131.25 * 90 / 160)
+    vo = _assert_raycast_equal(g, o, W, H, K, seq.poses[4])
+    assert (~np.isnan(vo[..., 2])).mean() > 0.5
+
+
+def test_weight_cap_and_reset(ctx):
+    seq = RoomSequence(seed=2, n_frames=2, W=160, H=120, f=131.25)
+    g, o = _volumes(ctx, 64, max_weight=3.0, **ROOM_VOL)
+    d, _, P = seq.frame(0)
+    for _ in range(5):
+        _integrate_both(g, o, d, seq.K, P)
+    _assert_volume_equal(g, o)
+    assert o.weight.max() == 3.0
+    g.reset()
+    t, w = g.host_arrays()
+    assert not t.any() and not w.any()
+    vg, ng = g.raycast(40, 30, centred_intrinsics(40, 30, 33.0), P)
+    torch.cuda.synchronize()
+    assert torch.isnan(vg).all() and torch.isnan(ng).all()
+
+
+def test_raycast_from_outside_and_parallel_rays(ctx):
+    """A plane and a sphere in a volume that starts 1 m in front of the
+    camera: ray casts from cameras outside the volume (the identity camera
+    with odd W, H, whose central column and row of rays run exactly parallel
+    to volume faces, and a moved one) and from one inside it with short rays."""
+    W, H = 81, 61
+    K = centred_intrinsics(W, H, 70.0)
+    prims = [Plane(n=np.array([0.0, 0.0, -1.0]), c=-2.5), Sphere(centre=np.array([0.1, -0.05, 1.9]), radius=0.35)]
+    d, _, _, _ = render(prims, 161, 121, centred_intrinsics(161, 121, 140.0), np.eye(4), zmin=0.5, zmax=4.0)
+    g, o = _volumes(ctx, 80, size=2.0, origin=(-1.2, -1.0, 1.0))
+    _integrate_both(g, o, d.astype(np.float32), centred_intrinsics(161, 121, 140.0), np.eye(4))
+    _assert_volume_equal(g, o)
+    vo = _assert_raycast_equal(g, o, W, H, K, np.eye(4))
+    assert (~np.isnan(vo[..., 2])).mean() > 0.3 and not np.isnan(vo[H // 2, W // 2, 2])
+    moved = pose_matrix(rot_from_rotvec([0.02, 0.1, 0.0]), [0.2, 0.1, -0.3])
+    vo = _assert_raycast_equal(g, o, W, H, K, moved)
+    assert (~np.isnan(vo[..., 2])).mean() > 0.2
+    inside = pose_matrix(np.eye(3), [0.0, 0.0, 1.2])
+    vo = _assert_raycast_equal(g, o, W, H, K, inside, tmin=0.2, tmax=0.9)
+    assert (~np.isnan(vo[..., 2])).mean() > 0.3
+
+
+def test_full_size_volume_and_vga_crop(ctx):
+    """512^3 over the room (1.25 cm voxels): the whole volume after one VGA
+    frame, and a 64 x 48 crop of the VGA ray cast from the next pose (the
+    crop shifts the principal point by whole pixels, which keeps every ray
+    bit for bit)."""
+    seq = RoomSequence(seed=0, n_frames=3)
+    g, o = _volumes(ctx, 512, **ROOM_VOL)
+    d, _, P = seq.frame(0)
+    _integrate_both(g, o, d, seq.K, P)
+    _assert_volume_equal(g, o)
+    fx, fy, cx, cy = seq.K
+    T = seq.poses[1]
+    vg, ng = g.raycast(640, 480, seq.K, T)
+    torch.cuda.synchronize()
+    vg, ng = vg.cpu().numpy(), ng.cpu().numpy()
+    for (u0, v0) in [(288, 216), (0, 0), (576, 432)]:
+        Kc = (fx, fy, cx - u0, cy - v0)
+        vo, no = o.raycast(64, 48, Kc, T)
+        assert _bits_equal(vg[v0:v0 + 48, u0:u0 + 64], vo), (u0, v0)
+        assert _bits_equal(ng[v0:v0 + 48, u0:u0 + 64], no), (u0, v0)
+    assert (~np.isnan(vg[..., 2])).mean() > 0.4  # one frame seen: depth beyond 4 m is dropped
+
+
+def _track(seq, n, step):
+    """Frame-to-model loop: returns the camera-to-world poses of frames
+    0..n-1 (frame 0 at its true pose).  step(k, T_prev, depth, imu) -> T_k."""
+    d0, _, P0 = seq.frame(0)
+    poses = [P0]
+    for k in range(1, n):
+        d, Rw, _ = seq.frame(k)
+        poses.append(step(k, poses[-1], d, Rw))
+    return poses
+
+
+def test_frame_to_model_loop_matches_oracle(ctx):
+    seq = RoomSequence(seed=4, n_frames=7, W=160, H=120, f=131.25)
+    W, H, K = seq.W, seq.H, seq.K
+    params = icp.icp_params_default()
+    oparams = oracle.default_params()
+    g, o = _volumes(ctx, 128, **ROOM_VOL)
+    d0, _, P0 = seq.frame(0)
+    g.integrate(torch.from_numpy(d0).cuda(), K, P0)
+    o.integrate(d0, K, P0)
+
+    def gpu_step(k, Tp, d, Rw):
+        mv, mn = g.raycast(W, H, K, Tp)
+        dd = torch.from_numpy(d).cuda()
+        T, _ = icp.icp_register(ctx, dd, mv, mn, K, Tp[:3, :3].T @ Rw, np.eye(4), params)
+        Tk = Tp @ T
+        g.integrate(dd, K, Tk)
+        return Tk
+
+    def oracle_step(k, Tp, d, Rw):
+        mv, mn = o.raycast(W, H, K, Tp)
+        T, _, _ = oracle.register(d, mv, mn, K, Tp[:3, :3].T @ Rw, np.eye(4), oparams)
+        Tk = Tp @ T
+        o.integrate(d, K, Tk)
+        return Tk
+
+    pg = _track(seq, seq.n_frames, gpu_step)
+    po = _track(seq, seq.n_frames, oracle_step)
+    for k in range(1, seq.n_frames):
+        ang, dt = pose_err(pg[k], po[k])
+        assert ang < 1e-5 and dt < 1e-5, (k, ang, dt)
+        ang_t, dt_t = pose_err(po[k], seq.poses[k])
+        assert ang_t < np.radians(2.0) and dt_t < 0.05, (k, ang_t, dt_t)  # 5 cm voxels, 160 x 120
+
+
+def test_bad_arguments(ctx):
+    g = icp.TsdfVolume(ctx, dim=16, size=1.0, origin=(0, 0, 0))
+    K = centred_intrinsics(32, 24, 30.0)
+    d = torch.ones((24, 32), dtype=torch.float32, device="cuda")
+    with pytest.raises(icp.IcpError) as e:
+        icp.TsdfVolume(ctx, dim=1)
+    assert e.value.code == icp.EINVAL
+    bad = np.eye(4)
+    bad[0, 3] = np.nan
+    with pytest.raises(icp.IcpError) as e:
+        g.integrate(d, K, bad)
+    assert e.value.code == icp.EINVAL
+    with pytest.raises(icp.IcpError) as e:
+        g.raycast(32, 24, K, np.eye(4), tmin=1.0, tmax=0.5)
+    assert e.value.code == icp.EINVAL
+    g.desc.mu = 0.0
+    with pytest.raises(icp.IcpError) as e:
+        g.integrate(d, K, np.eye(4))
+    assert e.value.code == icp.EINVAL
+    g.desc.mu = g.mu
+    g.integrate(d, K, pose_matrix(rot_from_rotvec([0, 0.1, 0]), [0.5, 0.5, -0.5]))
+    torch.cuda.synchronize()
