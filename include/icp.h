@@ -19,6 +19,9 @@
  *     unit length and face the camera.
  *   - Poses are row-major doubles: 4x4 (16 values) in the public calls, 3x4
  *     [R | t] (12 values) in the stage calls.  imu_R is 3x3 row-major.
+ *     Rotations are used as given (orthonormality is not checked): a caller
+ *     that chains poses should project them back onto SO(3), or rounding
+ *     errors in a prior built from an estimated pose grow from frame to frame.
  *   - W and H must be divisible by 2^(levels-1); 1 <= levels <= ICP_MAX_LEVELS;
  *     W, H <= ICP_MAX_DIM.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).

@@ -9,12 +9,14 @@
 // voxels of 4 rows, and the 8 corners of a trilinear sample are 4 pairs of
 // adjacent voxels.
 //
-// Integration: one thread per voxel.  The voxel centre goes into the camera,
+// Integration: one thread per 16 voxels along z.  The voxel centre goes into the camera,
 // is projected with the pixel rounding of the association (nearest pixel),
 // and the projective signed distance sdf = z(pixel) - z(voxel) is truncated
 // at mu: voxels more than mu behind the surface stay untouched, the others
 // take f = min(1, sdf / mu) into a running average whose weight saturates at
-// max_weight.  Only voxels that are updated are read or written.
+// max_weight.  Only voxels that are updated are read or written, and an FP32
+// frustum pre-test (conservative by a wide margin) spares the FP64 arithmetic
+// for voxels outside the camera's view.
 //
 // Ray casting: one thread per pixel of a 16 x 16 tile.  The ray z (x_u, y_v, 1)
 // is sampled at z = tmin + s * side / 2; a sample is the trilinear value of the
@@ -49,15 +51,35 @@ __global__ void __launch_bounds__(256) k_tsdf_fill(float2* vox, int64_t n) {
         vox[i] = make_float2(0.0f, 0.0f);
 }
 
-// grid (ceil(dim/64), ceil(dim/4), dim), block 64 x 4
-__global__ void __launch_bounds__(256) k_tsdf_integrate(Geo g, double mu, double maxw, const float* __restrict__ depth,
-                                                        int W, int H, double fx, double fy, double cx, double cy,
-                                                        PoseArg T) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * 4 + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.dim || j >= g.dim) return;
-    const double* P = T.v;
+// FP32 copy of the camera for a conservative pre-test: a voxel whose FP32
+// camera coordinates lie more than `margin` outside the viewing frustum
+// (behind the camera, or beyond the outer edges of the border pixels) fails
+// the exact FP64 test too.  margin is ~100x the FP32 rounding of coordinates
+// of the volume's magnitude, so the pre-test only saves work.
+struct Cull {
+    float o[3], side, t[3], R[9];
+    float a_lo, a_hi, b_lo, b_hi;  // x/z and y/z over the image, half a pixel beyond the border centres
+    float margin;
+};
+
+constexpr int kIntegrateZ = 16;  // voxels along z per thread
+
+// One voxel: pre-test, then the exact FP64 update.
+__device__ __forceinline__ void integrate_voxel(const Geo& g, const Cull& c, double mu, double maxw,
+                                                const float* __restrict__ depth, int W, int H, double fx, double fy,
+                                                double cx, double cy, const double* P, int i, int j, int k) {
+    {
+        const float e0 = c.o[0] + ((float)i + 0.5f) * c.side - c.t[0];
+        const float e1 = c.o[1] + ((float)j + 0.5f) * c.side - c.t[1];
+        const float e2 = c.o[2] + ((float)k + 0.5f) * c.side - c.t[2];
+        const float z = c.R[2] * e0 + c.R[5] * e1 + c.R[8] * e2;
+        const float x = c.R[0] * e0 + c.R[3] * e1 + c.R[6] * e2;
+        const float y = c.R[1] * e0 + c.R[4] * e1 + c.R[7] * e2;
+        const float m = c.margin;
+        if (!(z > -m) || x < c.a_lo * z - m * (1.0f + fabsf(c.a_lo)) || x > c.a_hi * z + m * (1.0f + fabsf(c.a_hi)) ||
+            y < c.b_lo * z - m * (1.0f + fabsf(c.b_lo)) || y > c.b_hi * z + m * (1.0f + fabsf(c.b_hi)))
+            return;
+    }
     const double xw0 = g.o[0] + ((double)i + 0.5) * g.side;
     const double xw1 = g.o[1] + ((double)j + 0.5) * g.side;
     const double xw2 = g.o[2] + ((double)k + 0.5) * g.side;
@@ -81,6 +103,20 @@ __global__ void __launch_bounds__(256) k_tsdf_integrate(Geo g, double mu, double
     const double w = (double)cur.y;
     const double wn = w + 1.0;
     *p = make_float2((float)(((double)cur.x * w + f) / wn), (float)(wn < maxw ? wn : maxw));
+}
+
+// grid (ceil(dim/64), ceil(dim/4), ceil(dim/kIntegrateZ)), block 64 x 4; a
+// thread takes kIntegrateZ voxels along z (fewer, longer work-groups: one
+// voxel per thread left the launch rate, not the arithmetic, as the limit)
+__global__ void __launch_bounds__(256) k_tsdf_integrate(Geo g, Cull c, double mu, double maxw,
+                                                        const float* __restrict__ depth, int W, int H, double fx,
+                                                        double fy, double cx, double cy, PoseArg T) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int j = blockIdx.y * 4 + threadIdx.y;
+    if (i >= g.dim || j >= g.dim) return;
+    const int k0 = blockIdx.z * kIntegrateZ;
+    const int k1 = min(k0 + kIntegrateZ, g.dim);
+    for (int k = k0; k < k1; ++k) integrate_voxel(g, c, mu, maxw, depth, W, H, fx, fy, cx, cy, T.v, i, j, k);
 }
 
 // Trilinear TSDF at world point (p0, p1, p2); false when a corner is unobserved
@@ -186,10 +222,26 @@ __global__ void __launch_bounds__(256) k_tsdf_raycast(Geo g, double tmin, double
     }
     if (t_hit > 0.0) {
         const double h0 = P[3] + t_hit * dw0, h1 = P[7] + t_hit * dw1, h2 = P[11] + t_hit * dw2;
-        double gx0, gx1, gy0, gy1, gz0, gz1;
-        const bool ok = sample(g, h0 + g.side, h1, h2, gx1) && sample(g, h0 - g.side, h1, h2, gx0) &&
-                        sample(g, h0, h1 + g.side, h2, gy1) && sample(g, h0, h1 - g.side, h2, gy0) &&
-                        sample(g, h0, h1, h2 + g.side, gz1) && sample(g, h0, h1, h2 - g.side, gz0);
+        // six samples one voxel away along +x, -x, +y, -y, +z, -z, taken one
+        // at a time (unrolled, their loads would all be live at once)
+        double gx0 = 0.0, gx1 = 0.0, gy0 = 0.0, gy1 = 0.0, gz0 = 0.0, gz1 = 0.0;
+        bool ok = true;
+#pragma unroll 1
+        for (int q = 0; q < 6; ++q) {
+            const double sg = (q & 1) ? -g.side : g.side;  // h - side == h + (-side) exactly
+            const int a = q >> 1;
+            double v;
+            if (!sample(g, a == 0 ? h0 + sg : h0, a == 1 ? h1 + sg : h1, a == 2 ? h2 + sg : h2, v)) {
+                ok = false;
+                break;
+            }
+            gx1 = q == 0 ? v : gx1;
+            gx0 = q == 1 ? v : gx0;
+            gy1 = q == 2 ? v : gy1;
+            gy0 = q == 3 ? v : gy0;
+            gz1 = q == 4 ? v : gz1;
+            gz0 = q == 5 ? v : gz0;
+        }
         if (ok) {
             const double gw0 = gx1 - gx0, gw1 = gy1 - gy0, gw2 = gz1 - gz0;
             const double len2 = (gw0 * gw0 + gw1 * gw1) + gw2 * gw2;
@@ -242,8 +294,23 @@ hipError_t launch_tsdf_fill(const TsdfDesc& d, hipStream_t s) {
 
 hipError_t launch_tsdf_integrate(const TsdfDesc& d, const float* depth, int W, int H, const double* K, PoseArg T,
                                  hipStream_t s) {
-    dim3 grid((unsigned)((d.dim + 63) / 64), (unsigned)((d.dim + 3) / 4), (unsigned)d.dim);
-    hipLaunchKernelGGL(k_tsdf_integrate, grid, dim3(64, 4), 0, s, make_geo(d), d.mu, d.max_weight, depth, W, H,
+    Cull c;
+    double extent = d.size;
+    for (int a = 0; a < 3; ++a) {
+        c.o[a] = (float)d.origin[a];
+        c.t[a] = (float)T.v[4 * a + 3];
+        extent += fabs(d.origin[a]) + fabs(T.v[4 * a + 3]);
+        for (int b = 0; b < 3; ++b) c.R[3 * a + b] = (float)T.v[4 * a + b];
+    }
+    c.side = (float)(d.size / (double)d.dim);
+    c.a_lo = (float)((-0.5 - K[2]) / K[0]);
+    c.a_hi = (float)(((double)W - 0.5 - K[2]) / K[0]);
+    c.b_lo = (float)((-0.5 - K[3]) / K[1]);
+    c.b_hi = (float)(((double)H - 0.5 - K[3]) / K[1]);
+    c.margin = (float)(1e-4 * (1.0 + extent));
+    dim3 grid((unsigned)((d.dim + 63) / 64), (unsigned)((d.dim + 3) / 4),
+              (unsigned)((d.dim + kIntegrateZ - 1) / kIntegrateZ));
+    hipLaunchKernelGGL(k_tsdf_integrate, grid, dim3(64, 4), 0, s, make_geo(d), c, d.mu, d.max_weight, depth, W, H,
                        K[0], K[1], K[2], K[3], T);
     return hipGetLastError();
 }

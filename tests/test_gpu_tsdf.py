@@ -142,6 +142,15 @@ def test_full_size_volume_and_vga_crop(ctx):
     assert (~np.isnan(vg[..., 2])).mean() > 0.4  # one frame seen: depth beyond 4 m is dropped
 
 
+def _compose(T, Tr):
+    """T Tr with its rotation projected onto SO(3) (the next IMU prior is
+    R^T R_imu: an unprojected R would double its rounding error each frame)."""
+    out = T @ Tr
+    U, _, Vt = np.linalg.svd(out[:3, :3])
+    out[:3, :3] = U @ Vt
+    return out
+
+
 def _track(seq, n, step):
     """Frame-to-model loop: returns the camera-to-world poses of frames
     0..n-1 (frame 0 at its true pose).  step(k, T_prev, depth, imu) -> T_k."""
@@ -167,14 +176,14 @@ def test_frame_to_model_loop_matches_oracle(ctx):
         mv, mn = g.raycast(W, H, K, Tp)
         dd = torch.from_numpy(d).cuda()
         T, _ = icp.icp_register(ctx, dd, mv, mn, K, Tp[:3, :3].T @ Rw, np.eye(4), params)
-        Tk = Tp @ T
+        Tk = _compose(Tp, T)
         g.integrate(dd, K, Tk)
         return Tk
 
     def oracle_step(k, Tp, d, Rw):
         mv, mn = o.raycast(W, H, K, Tp)
         T, _, _ = oracle.register(d, mv, mn, K, Tp[:3, :3].T @ Rw, np.eye(4), oparams)
-        Tk = Tp @ T
+        Tk = _compose(Tp, T)
         o.integrate(d, K, Tk)
         return Tk
 
