@@ -628,12 +628,28 @@ __device__ void sum_partials(const float* part, int n_tiles, int tile_stride, in
     if (j <= ICP_NMOM) {
         const int per = (n_tiles + 7) / 8;
         const int t0 = c * per, t1 = min(t0 + per, n_tiles);
+        // Sixteen tiles' loads are issued before their adds (the adds stay in
+        // tile order): one memory latency per sixteen tiles, not per tile.  The
+        // second slot is always loaded (slot 0 again when unused) and selected,
+        // so no branch separates the loads.
+        const bool two = slot2 > 0;
+        const size_t off2 = two ? (size_t)slot2 * ICP_PART_STRIDE : 0;
         double s = 0.0;
-        for (int t = t0; t < t1; ++t) {
+        int t = t0;
+        for (; t + 16 <= t1; t += 16) {
+            float a[16], b[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const float* q = part + (size_t)(t + u) * tile_stride + j;
+                a[u] = q[0];
+                b[u] = q[off2];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) s += two ? (double)a[u] + (double)b[u] : (double)a[u];
+        }
+        for (; t < t1; ++t) {
             const float* q = part + (size_t)t * tile_stride + j;
-            double v = (double)q[0];
-            if (slot2 > 0) v += (double)q[slot2 * ICP_PART_STRIDE];
-            s += v;
+            s += two ? (double)q[0] + (double)q[off2] : (double)q[0];
         }
         sh_sum[j][c] = s;
     }
@@ -661,11 +677,11 @@ __device__ Band median_band(ProbState* st, const KParams& kp, uint32_t* dbg_hist
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint32_t h[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        h[k] = st->hist[4 * tid + k];
-        st->hist[4 * tid + k] = 0u;
-        if (dbg_hist) dbg_hist[4 * tid + k] = h[k];
-    }
+    for (int k = 0; k < 4; ++k) h[k] = st->hist[4 * tid + k];  // all four loads before any store
+#pragma unroll
+    for (int k = 0; k < 4; ++k) st->hist[4 * tid + k] = 0u;
+    if (dbg_hist)
+        for (int k = 0; k < 4; ++k) dbg_hist[4 * tid + k] = h[k];
     const uint32_t own = (h[0] + h[1]) + (h[2] + h[3]);
     uint32_t incl = own;
 #pragma unroll
@@ -733,8 +749,9 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     const ProbDesc& P = probs[blockIdx.x];
     const LevelDesc& L = P.lv[ctl.level];
     ProbState* st = P.st;
-    if (st->level_done) return;
-    const int h0 = fused ? window_start(st->pred_hi) : -1;
+    const int done = st->level_done, pred = st->pred_hi;  // both loads in flight together
+    if (done) return;
+    const int h0 = fused ? window_start(pred) : -1;
     const Band b = median_band(st, kp, dbg_hist);
     const bool hit = h0 >= 0 && b.N > 0 && b.k_lo == 0 && b.k_hi >= h0 - 1 && b.k_hi <= h0 + ICP_WIN - 1;
     if (hit) {
