@@ -348,9 +348,17 @@ typedef struct {
     double origin[3];     /* world position of the cube's minimum corner */
     double mu;            /* truncation distance, metres */
     double max_weight;    /* cap of the running-average weight */
+    void* bricks;         /* optional device buffer of icp_tsdf_brick_bytes(dim) bytes, 256-byte
+                             aligned, or NULL.  Per 8^3 brick it counts the observed voxels with
+                             tsdf <= 0 so that the ray cast can jump over bricks that hold none
+                             (free or unobserved space); results are identical with and without
+                             it.  Its contents are valid only if every change to the voxels went
+                             through icp_tsdf_reset / icp_tsdf_integrate with this same buffer
+                             attached (attach it before the first reset). */
 } icp_tsdf;
 
 size_t icp_tsdf_bytes(int dim);
+size_t icp_tsdf_brick_bytes(int dim);
 
 /* Every voxel to (0, 0): nothing observed. */
 int icp_tsdf_reset(icp_ctx* ctx, const icp_tsdf* vol, void* stream);

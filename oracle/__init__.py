@@ -68,7 +68,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        stale = not os.path.exists(LIB_PATH) or any(
+            os.path.getmtime(src) > os.path.getmtime(LIB_PATH)
+            for src in SOURCES + [os.path.join(HERE, "icp_oracle.h")])
+        if stale:
             build()
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p

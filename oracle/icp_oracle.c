@@ -293,7 +293,8 @@ void or_live_vn_box(const float* D, int W, int H, const double K[4], int r, floa
  *    tsdf = (tsdf w + f) / (w + 1), w = min(w + 1, max_weight); FP64 math,
  *    FP32 storage;
  *  - ray casting, per pixel: the ray z (x_u, y_v, 1) in the camera, sampled at
- *    z = tmin + s * side / 2 (s = 0, 1, ...) up to tmax; a sample is the
+ *    z = tmin + s * side / 2 (s = 0, 1, ...) up to tmax, marched in grid
+ *    coordinates (voxel units, voxel centres at integers); a sample is the
  *    trilinear interpolation of the 8 voxels around the point (all observed,
  *    weight > 0, else the sample is missing); the first change from > 0 to
  *    <= 0 between consecutive samples is the surface, at the linearly
@@ -336,13 +337,13 @@ void or_tsdf_integrate(float* tsdf, float* weight, int dim, double size, const d
     }
 }
 
-/* trilinear TSDF at world point p; returns 0 when a corner voxel is unobserved */
-static int tsdf_sample(const float* tsdf, const float* weight, int dim, double side, const double origin[3],
-                       const double p[3], double* out) {
-    double g[3], fr[3];
+/* trilinear TSDF at grid point g (voxel (i, j, k) has its centre at grid
+   point (i, j, k)); returns 0 when a corner voxel is unobserved or g is out of
+   the interior */
+static int tsdf_sample(const float* tsdf, const float* weight, int dim, const double g[3], double* out) {
+    double fr[3];
     int i0[3];
     for (int a = 0; a < 3; ++a) {
-        g[a] = (p[a] - origin[a]) / side - 0.5;
         double fl = floor(g[a]);
         if (!(fl >= 0.0 && fl < (double)(dim - 1))) return 0;
         i0[a] = (int)fl;
@@ -365,27 +366,34 @@ static int tsdf_sample(const float* tsdf, const float* weight, int dim, double s
     return 1;
 }
 
+/* The ray is marched in grid coordinates: with inv = 1/side (rounded once),
+   the camera centre sits at gc = (t_wc - origin) inv - 1/2 and the ray
+   direction is gd = d_w inv, so the step at depth z is the grid point
+   gc + z gd. */
 void or_tsdf_raycast(const float* tsdf, const float* weight, int dim, double size, const double origin[3],
                      double tmin, double tmax, int W, int H, const double K[4], const double T_wc[16], float* vtx,
                      float* nrm) {
     double side = size / dim;
+    double inv = 1.0 / side;
     double dz = 0.5 * side;
+    double gc[3];
+    for (int a = 0; a < 3; ++a) gc[a] = (T_wc[4 * a + 3] - origin[a]) * inv - 0.5;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int v = 0; v < H; ++v) {
         for (int u = 0; u < W; ++u) {
             size_t i = (size_t)v * W + u;
             for (int a = 0; a < 3; ++a) vtx[3 * i + a] = nrm[3 * i + a] = f_nan();
             double dc[3] = {((double)u - K[2]) / K[0], ((double)v - K[3]) / K[1], 1.0};
-            double dw[3];
-            for (int a = 0; a < 3; ++a) dw[a] = (T_wc[4 * a] * dc[0] + T_wc[4 * a + 1] * dc[1]) + T_wc[4 * a + 2];
+            double gd[3];
+            for (int a = 0; a < 3; ++a) gd[a] = ((T_wc[4 * a] * dc[0] + T_wc[4 * a + 1] * dc[1]) + T_wc[4 * a + 2]) * inv;
             int have_prev = 0;
             double t_prev = 0.0, f_prev = 0.0, t_hit = -1.0;
             for (int s_ = 0;; ++s_) {
                 double t = tmin + (double)s_ * dz;
                 if (t > tmax) break;
-                double p[3] = {T_wc[3] + t * dw[0], T_wc[7] + t * dw[1], T_wc[11] + t * dw[2]};
+                double g[3] = {gc[0] + t * gd[0], gc[1] + t * gd[1], gc[2] + t * gd[2]};
                 double f;
-                if (!tsdf_sample(tsdf, weight, dim, side, origin, p, &f)) {
+                if (!tsdf_sample(tsdf, weight, dim, g, &f)) {
                     have_prev = 0;
                     continue;
                 }
@@ -399,16 +407,15 @@ void or_tsdf_raycast(const float* tsdf, const float* weight, int dim, double siz
                 f_prev = f;
             }
             if (!(t_hit > 0.0)) continue;
-            double ph[3] = {T_wc[3] + t_hit * dw[0], T_wc[7] + t_hit * dw[1], T_wc[11] + t_hit * dw[2]};
+            double gh[3] = {gc[0] + t_hit * gd[0], gc[1] + t_hit * gd[1], gc[2] + t_hit * gd[2]};
             double gw[3];
             int ok = 1;
             for (int a = 0; a < 3 && ok; ++a) {
-                double q1[3] = {ph[0], ph[1], ph[2]}, q0[3] = {ph[0], ph[1], ph[2]};
-                q1[a] += side;
-                q0[a] -= side;
+                double q1[3] = {gh[0], gh[1], gh[2]}, q0[3] = {gh[0], gh[1], gh[2]};
+                q1[a] += 1.0;
+                q0[a] -= 1.0;
                 double f1, f0;
-                ok = tsdf_sample(tsdf, weight, dim, side, origin, q1, &f1) &&
-                     tsdf_sample(tsdf, weight, dim, side, origin, q0, &f0);
+                ok = tsdf_sample(tsdf, weight, dim, q1, &f1) && tsdf_sample(tsdf, weight, dim, q0, &f0);
                 gw[a] = f1 - f0;
             }
             if (!ok) continue;

@@ -35,8 +35,8 @@ EXPORTS = (
     "icp_stage_associate", "icp_stage_moments", "icp_stage_solve", "icp_live_maps", "icp_autotune_tiles",
     "icp_server_config_default", "icp_server_clock", "icp_server_create", "icp_server_destroy",
     "icp_server_last_error", "icp_server_open_stream", "icp_server_close_stream", "icp_server_submit",
-    "icp_server_poll", "icp_server_get_counters", "icp_tsdf_bytes", "icp_tsdf_reset", "icp_tsdf_integrate",
-    "icp_tsdf_raycast",
+    "icp_server_poll", "icp_server_get_counters", "icp_tsdf_bytes", "icp_tsdf_brick_bytes", "icp_tsdf_reset",
+    "icp_tsdf_integrate", "icp_tsdf_raycast",
 )
 
 
@@ -52,7 +52,7 @@ class icp_intrinsics(C.Structure):
 
 class icp_tsdf(C.Structure):
     _fields_ = [("voxels", C.c_void_p), ("dim", C.c_int32), ("pad_", C.c_int32), ("size", C.c_double),
-                ("origin", C.c_double * 3), ("mu", C.c_double), ("max_weight", C.c_double)]
+                ("origin", C.c_double * 3), ("mu", C.c_double), ("max_weight", C.c_double), ("bricks", C.c_void_p)]
 
 
 class icp_params(C.Structure):
@@ -151,6 +151,7 @@ def lib():
             "icp_live_maps": (I, [P, P, I, I, C.POINTER(icp_intrinsics), P, P, P]),
             "icp_autotune_tiles": (I, [P, I, P, C.POINTER(icp_params), I, P, C.POINTER(D), P]),
             "icp_tsdf_bytes": (Z, [I]),
+            "icp_tsdf_brick_bytes": (Z, [I]),
             "icp_tsdf_reset": (I, [P, C.POINTER(icp_tsdf), P]),
             "icp_tsdf_integrate": (I, [P, C.POINTER(icp_tsdf), P, I, I, C.POINTER(icp_intrinsics), P, P]),
             "icp_tsdf_raycast": (I, [P, C.POINTER(icp_tsdf), I, I, C.POINTER(icp_intrinsics), P, D, D, P, P, P]),
@@ -476,9 +477,11 @@ def icp_live_maps(ctx, depth, K, stream=None):
 
 class TsdfVolume:
     """A TSDF volume in a device tensor of (dim, dim, dim, 2) float32 pairs
-    (tsdf, weight), indexed [k][j][i] (x fastest).  mu defaults to 4 voxels."""
+    (tsdf, weight), indexed [k][j][i] (x fastest).  mu defaults to 4 voxels.
+    With bricks=True (the default) it also holds the per-brick buffer that
+    lets the ray cast skip free and unobserved space (same results)."""
 
-    def __init__(self, ctx, dim=512, size=6.0, origin=(-3.0, -3.0, -3.0), mu=None, max_weight=128.0):
+    def __init__(self, ctx, dim=512, size=6.0, origin=(-3.0, -3.0, -3.0), mu=None, max_weight=128.0, bricks=True):
         import torch
         self.ctx = ctx
         self.dim, self.size = int(dim), float(size)
@@ -487,10 +490,13 @@ class TsdfVolume:
         self.max_weight = float(max_weight)
         if lib().icp_tsdf_bytes(self.dim) == 0:
             raise IcpError(EINVAL, "TSDF dim must be in 2..1024")
-        self.voxels = torch.empty((self.dim, self.dim, self.dim, 2), dtype=torch.float32,
-                                  device=torch.device("cuda", ctx.device))
+        dev = torch.device("cuda", ctx.device)
+        self.voxels = torch.empty((self.dim, self.dim, self.dim, 2), dtype=torch.float32, device=dev)
+        self.bricks = (torch.empty(lib().icp_tsdf_brick_bytes(self.dim), dtype=torch.uint8, device=dev)
+                       if bricks else None)
         self.desc = icp_tsdf(voxels=self.voxels.data_ptr(), dim=self.dim, pad_=0, size=self.size,
-                             origin=(C.c_double * 3)(*self.origin), mu=self.mu, max_weight=self.max_weight)
+                             origin=(C.c_double * 3)(*self.origin), mu=self.mu, max_weight=self.max_weight,
+                             bricks=self.bricks.data_ptr() if bricks else None)
         self.reset()
 
     def reset(self, stream=None):
@@ -517,6 +523,17 @@ class TsdfVolume:
                                                 float(tmin), float(tmax), _dev_ptr(vtx, "float32", "vtx"),
                                                 _dev_ptr(nrm, "float32", "nrm"), _stream(stream)))
         return vtx, nrm
+
+    def brick_state(self):
+        """Host copies of the per-brick counts of observed voxels with
+        tsdf <= 0, shape (nb, nb, nb) indexed [bz][by][bx], and the skip flags
+        (1 = skippable), same shape."""
+        nb = (self.dim + 7) // 8
+        raw = self.bricks.cpu().numpy()
+        cnt_bytes = (nb ** 3 * 4 + 255) // 256 * 256
+        cnt = raw[:nb ** 3 * 4].view(np.int32).reshape(nb, nb, nb)
+        flags = raw[cnt_bytes:cnt_bytes + nb ** 3].reshape(nb, nb, nb)
+        return cnt, flags
 
     def host_arrays(self):
         """(tsdf, weight) as flat float32 host arrays in voxel order."""

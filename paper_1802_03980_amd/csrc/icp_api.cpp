@@ -773,7 +773,7 @@ int check_tsdf(icp_ctx* ctx, const icp_tsdf* vol, TsdfDesc* out) {
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(vol->origin[a])) return fail(ctx, ICP_EINVAL, "TSDF origin must be finite");
     *out = TsdfDesc{vol->voxels, vol->dim, vol->size, {vol->origin[0], vol->origin[1], vol->origin[2]}, vol->mu,
-                          vol->max_weight};
+                    vol->max_weight, vol->bricks};
     return ICP_OK;
 }
 
@@ -794,6 +794,11 @@ int check_camera(icp_ctx* ctx, int W, int H, const icp_intrinsics* K, const doub
 size_t icp_tsdf_bytes(int dim) {
     if (dim < 2 || dim > 1024) return 0;
     return (size_t)dim * dim * dim * 8;
+}
+
+size_t icp_tsdf_brick_bytes(int dim) {
+    if (dim < 2 || dim > 1024) return 0;
+    return icpk::tsdf_brick_bytes(dim);
 }
 
 int icp_tsdf_reset(icp_ctx* ctx, const icp_tsdf* vol, void* stream) {

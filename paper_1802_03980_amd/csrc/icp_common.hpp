@@ -73,6 +73,7 @@ struct TsdfDesc {
     float* voxels;              // dim^3 (tsdf, weight) pairs, x fastest
     int32_t dim;
     double size, origin[3], mu, max_weight;
+    void* bricks;               // per-brick counts and flags (NULL: no brick skipping)
 };
 
 struct ProbState {

@@ -58,8 +58,12 @@ hipError_t launch_stage_solve(MomArg M, int64_t n, PoseArg pose, const KParams& 
 
 // TSDF volume (icp_tsdf.hip): clear every voxel to (0, 0); fuse one depth image
 // taken from camera-to-world pose T (3x4); ray-cast interleaved vertex / normal
-// maps in the camera of T.  K = fx, fy, cx, cy.
+// maps in the camera of T.  K = fx, fy, cx, cy.  With a brick buffer the fill
+// and the fusion keep its counts and flags current and the ray cast uses them.
 hipError_t launch_tsdf_fill(const TsdfDesc& d, hipStream_t s);
+// bytes of the brick buffer of a dim^3 volume (counts, then flags), and of its counts part
+size_t tsdf_brick_bytes(int dim);
+size_t tsdf_count_bytes(size_t nb3);
 hipError_t launch_tsdf_integrate(const TsdfDesc& d, const float* depth, int W, int H, const double* K, PoseArg T,
                                  hipStream_t s);
 hipError_t launch_tsdf_raycast(const TsdfDesc& d, double tmin, double tmax, int W, int H, const double* K, PoseArg T,

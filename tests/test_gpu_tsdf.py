@@ -7,6 +7,9 @@
     (NaN where the oracle finds no surface), at ragged image sizes, from a
     camera outside the volume, along rays parallel to a volume face, and on a
     crop of a VGA camera over the full-size volume.
+  - The per-brick counts and flags that let the ray cast skip free and
+    unobserved space equal those recomputed from the voxels; ray casts with
+    and without them are the oracle's bit for bit.
   - The frame-to-model loop (ray cast at the last pose, register, integrate at
     the new pose) tracks the room like the oracle's loop: poses within
     1e-5 rad / 1e-5 m per frame.
@@ -38,8 +41,8 @@ def _bits_equal(a, b):
     return np.array_equal(na, nb) and np.array_equal(a[~na].view(np.uint32), b[~nb].view(np.uint32))
 
 
-def _volumes(ctx, dim, **kw):
-    g = icp.TsdfVolume(ctx, dim=dim, **kw)
+def _volumes(ctx, dim, bricks=True, **kw):
+    g = icp.TsdfVolume(ctx, dim=dim, bricks=bricks, **kw)
     o = oracle.Tsdf(dim=dim, size=g.size, origin=g.origin, mu=g.mu, max_weight=g.max_weight)
     return g, o
 
@@ -65,10 +68,10 @@ def _assert_raycast_equal(g, o, W, H, K, T, tmin=0.4, tmax=8.0):
     return vo
 
 
-@pytest.mark.parametrize("dim", [70, 96])
-def test_integrate_and_raycast_bitwise(ctx, dim):
+@pytest.mark.parametrize("dim,bricks", [(70, True), (96, True), (96, False)])
+def test_integrate_and_raycast_bitwise(ctx, dim, bricks):
     seq = RoomSequence(seed=1, n_frames=5, W=160, H=120, f=131.25)
-    g, o = _volumes(ctx, dim, **ROOM_VOL)
+    g, o = _volumes(ctx, dim, bricks=bricks, **ROOM_VOL)
     for k in range(3):
         d, _, P = seq.frame(k)
         _integrate_both(g, o, d, seq.K, P)
@@ -79,6 +82,48 @@ def test_integrate_and_raycast_bitwise(ctx, dim):
     K = centred_intrinsics(W, H, 131.25 * 90 / 160)
     vo = _assert_raycast_equal(g, o, W, H, K, seq.poses[4])
     assert (~np.isnan(vo[..., 2])).mean() > 0.5
+
+
+def _host_brick_state(tsdf, weight, dim):
+    """Per-brick counts of observed voxels with tsdf <= 0, and the skip flags:
+    1 when the brick and its +1 neighbours along x, y, z (inside the volume)
+    count none."""
+    nb = (dim + 7) // 8
+    t = tsdf.reshape(dim, dim, dim)
+    w = weight.reshape(dim, dim, dim)
+    pad = nb * 8 - dim
+    neg = np.pad((w > 0) & (t <= 0), ((0, pad),) * 3).reshape(nb, 8, nb, 8, nb, 8)
+    cnt = neg.sum(axis=(1, 3, 5)).astype(np.int32)
+    flags = np.zeros((nb, nb, nb), np.uint8)
+    for bz in range(nb):
+        for by in range(nb):
+            for bx in range(nb):
+                flags[bz, by, bx] = all(cnt[bz + dz, by + dy, bx + dx] == 0 for dz in (0, 1) for dy in (0, 1)
+                                        for dx in (0, 1) if bz + dz < nb and by + dy < nb and bx + dx < nb)
+    return cnt, flags
+
+
+@pytest.mark.parametrize("dim", [128, 132])
+def test_brick_counts_and_flags(ctx, dim):
+    """The per-brick counts kept by integration (and the skip flags from them)
+    equal those recomputed from the voxels, over frames that flip voxels'
+    signs (the camera slides 5 cm per frame against the true pose) and after a
+    reset."""
+    seq = RoomSequence(seed=5, n_frames=4, W=160, H=120, f=131.25)
+    g = icp.TsdfVolume(ctx, dim=dim, size=6.4, origin=(-3.2, -3.2, -3.2), mu=0.5)
+    for k in range(4):
+        d, _, P = seq.frame(k)
+        g.integrate(torch.from_numpy(d).cuda(), seq.K, P @ pose_matrix(np.eye(3), [0.05 * k, 0, 0]))
+        torch.cuda.synchronize()
+        t, w = g.host_arrays()
+        cnt, flags = g.brick_state()
+        want_cnt, want_flags = _host_brick_state(t, w, dim)
+        assert np.array_equal(cnt, want_cnt), k
+        assert np.array_equal(flags, want_flags), k
+    assert flags.mean() > 0.3 and not flags.all()
+    g.reset()
+    cnt, flags = g.brick_state()
+    assert not cnt.any() and flags.all()
 
 
 def test_weight_cap_and_reset(ctx):
