@@ -138,7 +138,7 @@ int pick_tile(int npx, int nprob, int req) {
 
 // Workspace layout of a batch; offsets are relative to the workspace base.
 struct Plan {
-    size_t off_desc = 0, off_state = 0, off_res = 0, off_scratch = 0, off_owner[ICP_MAX_LEVELS] = {};
+    size_t off_desc = 0, off_state = 0, off_res = 0, off_scratch = 0, off_flags = 0, off_owner[ICP_MAX_LEVELS] = {};
     int tiles[ICP_MAX_LEVELS] = {};
     int max_npx[ICP_MAX_LEVELS] = {};
     int max_vn[ICP_MAX_LEVELS] = {};  // live-map work-groups of the largest level
@@ -161,6 +161,7 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
     P.off_state = take(sizeof(ProbState) * n);
     P.off_res = take(sizeof(icp_result) * n);
     P.off_scratch = take(kScratchBytes);
+    P.off_flags = take(sizeof(int32_t));
     for (int l = 0; l < levels; ++l) {
         P.tiles[l] = 0;
         P.max_npx[l] = 0;
@@ -440,10 +441,11 @@ int resolve_timing(icp_ctx* ctx) {
 int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* res_dev, hipStream_t s) {
     char* base = static_cast<char*>(ctx->ws);
     const ProbDesc* d_desc = reinterpret_cast<const ProbDesc*>(base + P.off_desc);
-    const KParams kp = kparams(prm);
+    KParams kp = kparams(prm);
+    kp.need2 = reinterpret_cast<int32_t*>(base + P.off_flags);
     int rc;
     icp_ctx::EvRec r;
-    HIP_TRY(ctx, icpk::launch_init(d_desc, n, prm->use_imu_seed, s));
+    HIP_TRY(ctx, icpk::launch_init(d_desc, n, prm->use_imu_seed, kp.need2, s));
     int64_t px0 = 0;
     for (int p = 0; p < n; ++p) px0 += P.desc[p].lv[0].npx;
     if ((rc = time_begin(ctx, s, r, ICP_TIME_FRONT_END, px0))) return rc;
@@ -895,7 +897,7 @@ int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const
     ctx->d_scratch = reinterpret_cast<double*>(base + P.off_scratch);
     ctx->stage_desc = P.desc[0];
     ctx->stage_levels = levels;
-    HIP_TRY(ctx, icpk::launch_init(ctx->d_desc, 1, 0, s));
+    HIP_TRY(ctx, icpk::launch_init(ctx->d_desc, 1, 0, nullptr, s));
     HIP_TRY(ctx, icpk::launch_prepare(ctx->d_desc, 1, levels, P.max_npx, P.max_vn, P.max_mp, P.max_q, true,
                                       front_end(prm), s));
     HIP_TRY(ctx, icpk::launch_centroid(ctx->d_desc, 1, levels, s));

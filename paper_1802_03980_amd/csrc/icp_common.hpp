@@ -123,4 +123,5 @@ struct KParams {
     int32_t min_corr;
     int32_t converge_window;
     int32_t reduce_mode;        // 0: FP32 rows; 1: FP16 hi+lo split MFMA on centred rows
+    int32_t* need2;             // batch flag: some problem needs pass 2 this iteration (NULL: always run it)
 };

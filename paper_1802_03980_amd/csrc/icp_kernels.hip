@@ -21,9 +21,11 @@ namespace icpk {
 
 // ------------------------------------------------------------------ init
 
-__global__ __launch_bounds__(ICP_WG) void k_init(const ProbDesc* __restrict__ probs, int use_imu_seed) {
+__global__ __launch_bounds__(ICP_WG) void k_init(const ProbDesc* __restrict__ probs, int use_imu_seed,
+                                                 int32_t* need2) {
     const ProbDesc& P = probs[blockIdx.x];
     ProbState* st = P.st;
+    if (need2 && blockIdx.x == 0 && threadIdx.x == 0) *need2 = 0;
     for (int b = threadIdx.x; b < ICP_HIST_BINS; b += ICP_WG) st->hist[b] = 0u;
     if (threadIdx.x == 0) {
         // Sec. 3: the live points are pre-oriented by the IMU rotation
@@ -760,6 +762,7 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     }
     if (threadIdx.x == 0) {
         st->fused_done = hit ? 1 : 0;
+        if (!hit && kp.need2) atomicExch(kp.need2, 1);  // pass 2 has work this iteration
         if (b.N > 0) st->pred_hi = b.k_hi;
         if (kp.reduce_mode == 1) set_centre(st, ctl.level);
     }
@@ -771,6 +774,8 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
 
 __global__ __launch_bounds__(ICP_WG) void k_pass2(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
                                                   IterCtl ctl, KParams kp) {
+    // every problem of the batch finished its iteration in the band kernel
+    if (kp.need2 && __builtin_amdgcn_readfirstlane(*kp.need2) == 0) return;
     __shared__ float sh_red[ICP_WAVES][ICP_PART_STRIDE];
     const int g = blockIdx.x;
     const ProbDesc& P = probs[owner[g]];
@@ -820,6 +825,7 @@ constexpr float kScaleB = 1024.0f;    // |b| < dist_max <= 0.125 m; lifts b's lo
 
 __global__ __launch_bounds__(ICP_WG) void k_pass2_mfma(const ProbDesc* __restrict__ probs,
                                                        const int* __restrict__ owner, IterCtl ctl, KParams kp) {
+    if (kp.need2 && __builtin_amdgcn_readfirstlane(*kp.need2) == 0) return;  // nothing to do (see k_pass2)
     __shared__ _Float16 sh_x[ICP_WAVES][8][16][32];  // [wave][group][column][row in group]
     __shared__ float sh_d[ICP_WAVES][16][17];
     __shared__ float sh_red[ICP_WAVES][ICP_PART_STRIDE];
@@ -953,6 +959,7 @@ __global__ __launch_bounds__(ICP_WG) void k_solve(const ProbDesc* __restrict__ p
     }
     if (threadIdx.x == 0) {
         st->fused_done = 0;
+        if (kp.need2 && blockIdx.x == 0) *kp.need2 = 0;  // pass 2 of this iteration has run
         if (ctl.last_of_level) {
             st->level_done = 0;
             st->settled = 0;
@@ -1017,8 +1024,8 @@ __global__ void k_stage_solve(MomArg M, int64_t n, PoseArg pose, KParams kp, dou
 
 static inline unsigned blocks_for(int n) { return (unsigned)((n + ICP_WG - 1) / ICP_WG); }
 
-hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, hipStream_t s) {
-    hipLaunchKernelGGL(k_init, dim3(n), dim3(ICP_WG), 0, s, probs, use_imu_seed);
+hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, int32_t* need2, hipStream_t s) {
+    hipLaunchKernelGGL(k_init, dim3(n), dim3(ICP_WG), 0, s, probs, use_imu_seed, need2);
     return hipGetLastError();
 }
 

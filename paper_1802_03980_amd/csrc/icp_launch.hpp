@@ -16,8 +16,8 @@ struct MomArg {
 };
 
 // per problem: seed the pose (IMU rotation or the initial pose), clear the
-// histogram, tickets, flags and statistics
-hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, hipStream_t s);
+// histogram, tickets, flags and statistics; clear the batch's pass-2 flag
+hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, int32_t* need2, hipStream_t s);
 // centroid of every level's valid live vertices (split-precision reduction)
 hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, hipStream_t s);
 // live depth pyramid, live vertex/normal maps, model maps for every level;
