@@ -16,12 +16,14 @@
 // untouched, the others take f = min(1, sdf / mu) into a running average whose
 // weight saturates at max_weight.  Only voxels that are updated are read or
 // written, and an FP32 frustum pre-test (conservative by a wide margin) spares
-// the FP64 arithmetic for voxels outside the camera's view.
+// the FP64 arithmetic for voxels outside the camera's view, first for a
+// thread's whole run of 16 voxels (from its two ends), then voxel by voxel.
 //
-// Ray casting: eight lanes per pixel, each taking every eighth step (the walk
-// is latency-bound: one dependent gather per step).  The ray z (x_u, y_v, 1)
-// is sampled at z = tmin + s * side / 2; a sample is the trilinear value of
-// the 8 voxels around the point and is missing when any of them is
+// Ray casting: kRayLanes (4) lanes per pixel, each taking every fourth step
+// of the walk (four lanes per ray measured faster than one, two or eight).
+// The ray z (x_u, y_v, 1) is sampled at z = tmin + s * side / 2, in grid
+// coordinates (voxel centres at integers); a sample is the trilinear value
+// of the 8 voxels around the point and is missing when any of them is
 // unobserved.  The first step from a positive to a non-positive sample is the
 // surface (depth interpolated linearly between the two samples), a step from
 // negative to non-negative (the back of a surface) ends the ray.  The normal
@@ -84,22 +86,36 @@ struct Cull {
 
 constexpr int kIntegrateZ = 16;  // voxels along z per thread
 
+// The pre-test's five constraints at voxel (i, j, k), each >= 0 (the first
+// > 0) where the voxel may lie in the frustum: in front of the camera, right
+// of the left edge, left of the right edge, below the top, above the bottom.
+// Each is, up to FP32 rounding far below the margin, a linear function of the
+// voxel centre, so a constraint negative at both ends of a run of voxels
+// along z is negative (the exact test fails) all along it.
+__device__ __forceinline__ void frustum_terms(const Cull& c, int i, int j, int k, float (&q)[5]) {
+    const float e0 = c.o[0] + ((float)i + 0.5f) * c.side - c.t[0];
+    const float e1 = c.o[1] + ((float)j + 0.5f) * c.side - c.t[1];
+    const float e2 = c.o[2] + ((float)k + 0.5f) * c.side - c.t[2];
+    const float z = c.R[2] * e0 + c.R[5] * e1 + c.R[8] * e2;
+    const float x = c.R[0] * e0 + c.R[3] * e1 + c.R[6] * e2;
+    const float y = c.R[1] * e0 + c.R[4] * e1 + c.R[7] * e2;
+    const float m = c.margin;
+    q[0] = z + m;
+    q[1] = x - (c.a_lo * z - m * (1.0f + fabsf(c.a_lo)));
+    q[2] = (c.a_hi * z + m * (1.0f + fabsf(c.a_hi))) - x;
+    q[3] = y - (c.b_lo * z - m * (1.0f + fabsf(c.b_lo)));
+    q[4] = (c.b_hi * z + m * (1.0f + fabsf(c.b_hi))) - y;
+}
+
 // One voxel: pre-test, then the exact FP64 update.
 __device__ __forceinline__ void integrate_voxel(const Geo& g, const Cull& c, double mu, double maxw,
                                                 const float* __restrict__ depth, int W, int H, double fx, double fy,
                                                 double cx, double cy, const double* P, int i, int j, int k,
                                                 int& d_neg) {
     {
-        const float e0 = c.o[0] + ((float)i + 0.5f) * c.side - c.t[0];
-        const float e1 = c.o[1] + ((float)j + 0.5f) * c.side - c.t[1];
-        const float e2 = c.o[2] + ((float)k + 0.5f) * c.side - c.t[2];
-        const float z = c.R[2] * e0 + c.R[5] * e1 + c.R[8] * e2;
-        const float x = c.R[0] * e0 + c.R[3] * e1 + c.R[6] * e2;
-        const float y = c.R[1] * e0 + c.R[4] * e1 + c.R[7] * e2;
-        const float m = c.margin;
-        if (!(z > -m) || x < c.a_lo * z - m * (1.0f + fabsf(c.a_lo)) || x > c.a_hi * z + m * (1.0f + fabsf(c.a_hi)) ||
-            y < c.b_lo * z - m * (1.0f + fabsf(c.b_lo)) || y > c.b_hi * z + m * (1.0f + fabsf(c.b_hi)))
-            return;
+        float q[5];
+        frustum_terms(c, i, j, k, q);
+        if (!(q[0] > 0.0f) || q[1] < 0.0f || q[2] < 0.0f || q[3] < 0.0f || q[4] < 0.0f) return;
     }
     const double xw0 = g.o[0] + ((double)i + 0.5) * g.side;
     const double xw1 = g.o[1] + ((double)j + 0.5) * g.side;
@@ -137,9 +153,20 @@ __global__ void __launch_bounds__(256) k_tsdf_integrate(Geo g, Cull c, double mu
     const int i = blockIdx.x * 64 + threadIdx.x;
     const int j = blockIdx.y * 4 + threadIdx.y;  // the same for the whole wave
     if (j >= g.dim) return;
-    const bool active = i < g.dim;
     const int k0 = blockIdx.z * kIntegrateZ;
     const int k1 = min(k0 + kIntegrateZ, g.dim);
+    const bool inside = i < g.dim;
+    bool active = inside;
+    if (active) {  // the whole run outside one side of the frustum?
+        float qa[5], qb[5];
+        frustum_terms(c, i, j, k0, qa);
+        frustum_terms(c, i, j, k1 - 1, qb);
+        const bool out = (!(qa[0] > 0.0f) && !(qb[0] > 0.0f)) || (qa[1] < 0.0f && qb[1] < 0.0f) ||
+                         (qa[2] < 0.0f && qb[2] < 0.0f) || (qa[3] < 0.0f && qb[3] < 0.0f) ||
+                         (qa[4] < 0.0f && qb[4] < 0.0f);
+        active = !out;
+    }
+    if (__ballot(active) == 0) return;  // nothing to update or count in this wave
     int a_neg = 0;
     for (int k = k0; k < k1; ++k) {
         if (active) integrate_voxel(g, c, mu, maxw, depth, W, H, fx, fy, cx, cy, T.v, i, j, k, a_neg);
@@ -147,7 +174,7 @@ __global__ void __launch_bounds__(256) k_tsdf_integrate(Geo g, Cull c, double mu
             // the 8 lanes sharing i >> 3 cover one brick row: one atomic per brick and row
 #pragma unroll
             for (int off = 1; off < 8; off <<= 1) a_neg += __shfl_xor(a_neg, off, 64);
-            if (active && (threadIdx.x & 7) == 0 && a_neg != 0)
+            if (inside && (threadIdx.x & 7) == 0 && a_neg != 0)  // the group's first lane, culled or not
                 atomicAdd(g.cnt + (((size_t)(k >> 3) * g.nb) + (j >> 3)) * g.nb + (i >> 3), a_neg);
             a_neg = 0;
         }
@@ -366,8 +393,8 @@ __global__ void __launch_bounds__(256) k_tsdf_raycast(Geo g, double gc0, double 
     const float fnan = __builtin_nanf("");
     for (int a = 0; a < 3; ++a) pv3[a] = pn3[a] = fnan;
     if (t_hit > 0.0) {
-        // the six samples one voxel away along +x, -x, +y, -y, +z, -z (one per
-        // lane with eight or more lanes, in turn otherwise)
+        // the six samples one voxel away along +x, -x, +y, -y, +z, -z, spread
+        // over the ray's lanes (two rounds with four lanes)
         const double h0 = gc0 + t_hit * gd0, h1 = gc1 + t_hit * gd1, h2 = gc2 + t_hit * gd2;
         double gq[6];
         bool ok = true;
