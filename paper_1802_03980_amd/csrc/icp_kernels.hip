@@ -575,14 +575,33 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
         float* part = L.part1 + (size_t)tile * ICP_WIN_SLOTS * ICP_PART_STRIDE;
         block_reduce_row(acc, cnt, sh_red, part);
         // slot b+1 holds the prefix sum over window bins 0..b, so the band
-        // kernel needs two slots per tile whatever the band edge
+        // kernel needs two slots per tile whatever the band edge.  The 48 bins
+        // are scanned as 8 chunks of 6 by 8 x 29 threads: each sums its chunk
+        // (waves, then bins in order), the chunk totals go through LDS, and
+        // each thread adds the totals of the chunks before its own.
+        constexpr int kChunks = 8, kPer = ICP_WIN / kChunks;
+        static_assert(kChunks * kPer == ICP_WIN && kChunks * (ICP_NMOM + 1) <= ICP_WAVES * ICP_STAGE * 8,
+                      "window scan layout");
+        float* sh_tot = &sh_stage[0][0][0];  // reused: [chunk][moment]
         __syncthreads();
-        if (tid <= ICP_NMOM) {
+        const int cj = tid / (ICP_NMOM + 1), mj = tid - cj * (ICP_NMOM + 1);
+        float pre[kPer];
+        if (cj < kChunks) {
             float run = 0.0f;
-            for (int b = 0; b < ICP_WIN; ++b) {
-                run += (sh_win[0][b][tid] + sh_win[1][b][tid]) + (sh_win[2][b][tid] + sh_win[3][b][tid]);
-                part[(b + 1) * ICP_PART_STRIDE + tid] = run;
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int b = cj * kPer + q;
+                run += (sh_win[0][b][mj] + sh_win[1][b][mj]) + (sh_win[2][b][mj] + sh_win[3][b][mj]);
+                pre[q] = run;
             }
+            sh_tot[cj * (ICP_NMOM + 1) + mj] = run;
+        }
+        __syncthreads();
+        if (cj < kChunks) {
+            float off = 0.0f;
+            for (int c2 = 0; c2 < cj; ++c2) off += sh_tot[c2 * (ICP_NMOM + 1) + mj];
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) part[(cj * kPer + q + 1) * ICP_PART_STRIDE + mj] = off + pre[q];
         }
     }
 }
@@ -637,21 +656,18 @@ __device__ void sum_partials(const float* part, int n_tiles, int tile_stride, in
         const bool two = slot2 > 0;
         const size_t off2 = two ? (size_t)slot2 * ICP_PART_STRIDE : 0;
         double s = 0.0;
-        int t = t0;
-        for (; t + 16 <= t1; t += 16) {
+        for (int t = t0; t < t1; t += 16) {
             float a[16], b[16];
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
-                const float* q = part + (size_t)(t + u) * tile_stride + j;
+                const int tt = min(t + u, t1 - 1);  // past the end: a valid tile, not added
+                const float* q = part + (size_t)tt * tile_stride + j;
                 a[u] = q[0];
                 b[u] = q[off2];
             }
 #pragma unroll
-            for (int u = 0; u < 16; ++u) s += two ? (double)a[u] + (double)b[u] : (double)a[u];
-        }
-        for (; t < t1; ++t) {
-            const float* q = part + (size_t)t * tile_stride + j;
-            s += two ? (double)q[0] + (double)q[off2] : (double)q[0];
+            for (int u = 0; u < 16; ++u)
+                if (t + u < t1) s += two ? (double)a[u] + (double)b[u] : (double)a[u];
         }
         sh_sum[j][c] = s;
     }
