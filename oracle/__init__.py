@@ -79,6 +79,7 @@ def lib():
         i = C.c_int
         L.or_params_default.argtypes = [C.POINTER(Params)]
         L.or_num_threads.restype = C.c_int
+        L.or_set_num_threads.argtypes = [C.c_int]
         L.or_level_intrinsics.argtypes = [P, i, P]
         L.or_depth_down.argtypes = [P, i, i, P]
         L.or_live_vn.argtypes = [P, i, i, P, P, P]
@@ -129,6 +130,11 @@ def default_params(**over):
 
 def num_threads():
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n):
+    """Threads of the oracle's later calls (for timing; results do not depend on it)."""
+    lib().or_set_num_threads(int(n))
 
 
 def level_intrinsics(K, level):

@@ -47,6 +47,14 @@ int or_num_threads(void) {
 #endif
 }
 
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 void or_params_default(or_params* p) {
     memset(p, 0, sizeof(*p));
     p->levels = 3;

@@ -84,6 +84,7 @@ typedef struct {
 void or_params_default(or_params* p);
 /* threads the per-pixel loops use (OpenMP) */
 int or_num_threads(void);
+void or_set_num_threads(int n); /* OpenMP threads of later calls (timing only) */
 void or_level_intrinsics(const double K0[4], int level, double Kl[4]);
 
 /* live front end */
