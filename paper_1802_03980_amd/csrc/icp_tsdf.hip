@@ -217,9 +217,12 @@ __device__ __forceinline__ bool sample_cell(const Geo& g, double g0, double g1, 
     const pair2_t x10 = *reinterpret_cast<const pair2_t*>(b + dim);            // j + 1
     const pair2_t x01 = *reinterpret_cast<const pair2_t*>(b + dim * dim);      // k + 1
     const pair2_t x11 = *reinterpret_cast<const pair2_t*>(b + dim * dim + dim);
-    const float wmin = fminf(fminf(fminf(x00.y, x00.w), fminf(x10.y, x10.w)),
-                             fminf(fminf(x01.y, x01.w), fminf(x11.y, x11.w)));
-    if (!(wmin > 0.0f)) return false;
+    // weights are +0 or >= 1, so their bit patterns order like their values
+    const uint32_t wmin = min(min(min(__float_as_uint(x00.y), __float_as_uint(x00.w)),
+                                  min(__float_as_uint(x10.y), __float_as_uint(x10.w))),
+                              min(min(__float_as_uint(x01.y), __float_as_uint(x01.w)),
+                                  min(__float_as_uint(x11.y), __float_as_uint(x11.w))));
+    if (wmin == 0u) return false;
     const double q0 = 1.0 - r0, q1 = 1.0 - r1, q2 = 1.0 - r2;
     const double a00 = (double)x00.x * q0 + (double)x00.z * r0;
     const double a10 = (double)x10.x * q0 + (double)x10.z * r0;
@@ -344,7 +347,8 @@ __global__ void __launch_bounds__(256) k_tsdf_raycast(Geo g, double gc0, double 
             // brick of the round's last step (-1: beyond the walk or outside the range)
             const int bq = __shfl(inr ? pack_brick(f0, f1, f2) : -1, kRayLanes - 1, kRayLanes);
             const bool hop = g.flags && bq >= 0 &&
-                             g.flags[((size_t)(bq >> 20) * g.nb + ((bq >> 10) & 1023)) * g.nb + (bq & 1023)] != 0;
+                             g.flags[(((uint32_t)bq >> 20) * (uint32_t)g.nb + (((uint32_t)bq >> 10) & 1023u)) *
+                                         (uint32_t)g.nb + ((uint32_t)bq & 1023u)] != 0;
             // the walk's rule in step order
             double pf = __shfl_up(fj, 1, kRayLanes);
             if (j == 0) pf = c_f;
