@@ -314,6 +314,25 @@ def main():
         cpu["single_thread"] = {"value": round(done1 / cpu1_s, 3), "unit": "registrations/s", "cores": 1,
                                 "sample": f"first {done1} registrations, {cpu1_s:.1f} s"}
         log(f"oracle on one thread: {done1 / cpu1_s:.3f} reg/s")
+        # the single-pair 160x120 problem: the oracle 20 times on all threads and on one, beside one GPU call
+        p1 = synth.config1_problem(0)
+        cfg1 = {}
+        for nth in (threads, 1):
+            oracle.set_num_threads(nth)
+            ts1 = time.perf_counter()
+            for _ in range(20):
+                oracle.register_problem(p1, oracle.default_params(**front))
+            cfg1[f"oracle_ms_{nth}_threads"] = round((time.perf_counter() - ts1) / 20 * 1e3, 3)
+        oracle.set_num_threads(threads)
+        d1 = [torch.from_numpy(a).to(dev) for a in (p1.live_depth, p1.model_vtx, p1.model_nrm)]
+        for _ in range(3):
+            icp.icp_register(ctx, d1[0], d1[1], d1[2], p1.K, p1.imu_R, p1.init_pose, params)
+        ts1 = time.perf_counter()
+        for _ in range(20):
+            icp.icp_register(ctx, d1[0], d1[1], d1[2], p1.K, p1.imu_R, p1.init_pose, params)
+        cfg1["gpu_ms_one_call"] = round((time.perf_counter() - ts1) / 20 * 1e3, 3)
+        cpu["single_pair_160x120"] = cfg1
+        log(f"160x120 single pair: {cfg1}")
         errs = np.array(errs)
         pose_err = {"frames_checked": done, "max_rad": float(errs[:, 0].max()), "max_m": float(errs[:, 1].max()),
                     "p50_rad": float(np.median(errs[:, 0])), "p50_m": float(np.median(errs[:, 1]))}
