@@ -315,14 +315,14 @@ def main():
                                 "sample": f"first {done1} registrations, {cpu1_s:.1f} s"}
         log(f"oracle on one thread: {done1 / cpu1_s:.3f} reg/s")
         # the single-pair 160x120 problem: the oracle 20 times on all threads and on one, beside one GPU call
-        p1 = synth.config1_problem(0)
-        cfg1 = {}
+        p1 = synth.pair_problem(0)
+        pair = {}
         for nth in (threads, 1):
             oracle.set_num_threads(nth)
             ts1 = time.perf_counter()
             for _ in range(20):
                 oracle.register_problem(p1, oracle.default_params(**front))
-            cfg1[f"oracle_ms_{nth}_threads"] = round((time.perf_counter() - ts1) / 20 * 1e3, 3)
+            pair[f"oracle_ms_{nth}_threads"] = round((time.perf_counter() - ts1) / 20 * 1e3, 3)
         oracle.set_num_threads(threads)
         d1 = [torch.from_numpy(a).to(dev) for a in (p1.live_depth, p1.model_vtx, p1.model_nrm)]
         for _ in range(3):
@@ -330,9 +330,9 @@ def main():
         ts1 = time.perf_counter()
         for _ in range(20):
             icp.icp_register(ctx, d1[0], d1[1], d1[2], p1.K, p1.imu_R, p1.init_pose, params)
-        cfg1["gpu_ms_one_call"] = round((time.perf_counter() - ts1) / 20 * 1e3, 3)
-        cpu["single_pair_160x120"] = cfg1
-        log(f"160x120 single pair: {cfg1}")
+        pair["gpu_ms_one_call"] = round((time.perf_counter() - ts1) / 20 * 1e3, 3)
+        cpu["single_pair_160x120"] = pair
+        log(f"160x120 single pair: {pair}")
         errs = np.array(errs)
         pose_err = {"frames_checked": done, "max_rad": float(errs[:, 0].max()), "max_m": float(errs[:, 1].max()),
                     "p50_rad": float(np.median(errs[:, 0])), "p50_m": float(np.median(errs[:, 1]))}
@@ -398,9 +398,9 @@ def main():
 BYTES_PER_L0_PX_FRONT = 67  # per frame: depth and level-0 model read, live maps of all levels and model pyramid written
 
 
-def _make_cfg4(i):
+def _make_uneven(i):
     import synth
-    return synth.config4_problem(i)
+    return synth.uneven_problem(i)
 
 
 def _alg_bytes(W, H, iters, levels):
@@ -415,7 +415,7 @@ def batch64_main(args):
     log("generating 64 uneven problems")
     t0 = time.time()
     with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        probs = pool.map(_make_cfg4, range(64))
+        probs = pool.map(_make_uneven, range(64))
     log(f"  done in {time.time() - t0:.1f} s")
 
     import torch
@@ -524,7 +524,7 @@ SWEEP_ANGLES = (5, 10, 15, 20, 30, 45, 60)
 def _make_sweep_problem(job):
     import synth
     ang, k = job
-    return synth.config1_problem(seed=1000 * ang + k, W=320, H=240, f=260.0, rot_deg=float(ang), trans_m=0.02)
+    return synth.pair_problem(seed=1000 * ang + k, W=320, H=240, f=260.0, rot_deg=float(ang), trans_m=0.02)
 
 
 def sweep_main(args):
@@ -900,7 +900,7 @@ def cadence_main(args):
     import multiprocessing as mp
     log("generating 64 uneven problems")
     with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        p64 = pool.map(_make_cfg4, range(64))
+        p64 = pool.map(_make_uneven, range(64))
 
     import torch
 

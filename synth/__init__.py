@@ -1,5 +1,5 @@
 """Seeded synthetic inputs (depth frames, model maps, motions, IMU priors)."""
 from .scene import (  # noqa: F401
-    DEG, Problem, RoomSequence, config1_problem, config4_problem, three_plane_problem,
+    DEG, Problem, RoomSequence, pair_problem, uneven_problem, three_plane_problem,
     centred_intrinsics, rot_from_rotvec, pose_matrix, random_unit, render,
 )

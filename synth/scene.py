@@ -307,7 +307,7 @@ def make_pair_problem(prims, W, H, K, T_gt, imu_R, rng, noise=True, dropout=0.02
                    T_gt=T_gt, name=name)
 
 
-def config1_problem(seed=0, W=160, H=120, f=130.0, rot_deg=2.0, trans_m=0.02,
+def pair_problem(seed=0, W=160, H=120, f=130.0, rot_deg=2.0, trans_m=0.02,
                     imu_deg=0.5, noise=True, spheres=True):
     """Single frame pair, plain method: 3 random planes plus 4 spheres, 2 deg /
     2 cm ground-truth motion, IMU prior perturbed by 0.5 deg."""
@@ -321,7 +321,7 @@ def config1_problem(seed=0, W=160, H=120, f=130.0, rot_deg=2.0, trans_m=0.02,
     T_gt = pose_matrix(R_gt, t_gt)
     imu_R = rot_from_rotvec(random_unit(rng) * imu_deg * DEG) @ R_gt
     return make_pair_problem(prims, W, H, K, T_gt, imu_R, rng, noise=noise,
-                             dropout=0.02 if noise else 0.0, name=f"cfg1/seed{seed}")
+                             dropout=0.02 if noise else 0.0, name=f"pair/seed{seed}")
 
 
 def three_plane_problem(seed=0, W=160, H=120, f=130.0, rot_deg=2.0, trans_m=0.02):
@@ -341,9 +341,9 @@ def three_plane_problem(seed=0, W=160, H=120, f=130.0, rot_deg=2.0, trans_m=0.02
 BATCH_RESOLUTIONS = ((320, 240), (640, 480), (848, 480), (1280, 720))
 
 
-def config4_problem(index, seed=0):
+def uneven_problem(index, seed=0):
     """One of the 64 uneven batched problems: resolution uniform over
-    320x240 / 640x480 / 848x480 / 1280x720, f = 525 H / 480, config-1 scene
+    320x240 / 640x480 / 848x480 / 1280x720, f = 525 H / 480, single-pair scene
     type, motion up to 5 deg / 5 cm, IMU prior noise U(0.3, 1.0) deg."""
     rng = _rng(4, seed, index)
     W, H = BATCH_RESOLUTIONS[int(rng.integers(0, len(BATCH_RESOLUTIONS)))]
@@ -353,7 +353,7 @@ def config4_problem(index, seed=0):
     t_gt = random_unit(rng) * rng.uniform(0.0, 0.05)
     T_gt = pose_matrix(R_gt, t_gt)
     imu_R = rot_from_rotvec(random_unit(rng) * rng.uniform(0.3, 1.0) * DEG) @ R_gt
-    return make_pair_problem(prims, W, H, K, T_gt, imu_R, rng, name=f"cfg4/{index}")
+    return make_pair_problem(prims, W, H, K, T_gt, imu_R, rng, name=f"uneven/{index}")
 
 
 # ----------------------------------------------------------------------------

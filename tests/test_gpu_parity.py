@@ -64,10 +64,10 @@ def _gpu_levels(ctx, prob, levels=3):
 
 
 PROBLEMS = {
-    "cfg1_s0": lambda: synth.config1_problem(0),
-    "cfg1_s1": lambda: synth.config1_problem(1),
-    "cfg4_0": lambda: synth.config4_problem(0),
-    "odd_41x31_at_l2": lambda: synth.config1_problem(7, W=164, H=124, f=133.0),
+    "pair_s0": lambda: synth.pair_problem(0),
+    "pair_s1": lambda: synth.pair_problem(1),
+    "uneven_0": lambda: synth.uneven_problem(0),
+    "odd_41x31_at_l2": lambda: synth.pair_problem(7, W=164, H=124, f=133.0),
 }
 
 
@@ -93,7 +93,7 @@ FRONT_ENDS = {"filter": dict(depth_filter=1), "box_normals": dict(normal_mode=1)
 def test_s1_front_end_modes_bitwise(ctx, mode):
     """The bilateral filter and the box-gradient normals give the oracle's maps
     bit for bit at every level."""
-    prob = synth.config1_problem(4)
+    prob = synth.pair_problem(4)
     params = icp.icp_params_default(**FRONT_ENDS[mode])
     d, mv, mn = upload(prob)
     _ALIVE[:] = [d, mv, mn]
@@ -117,7 +117,7 @@ def test_s1_front_end_modes_bitwise(ctx, mode):
 @pytest.mark.parametrize("mode", list(FRONT_ENDS))
 def test_end_to_end_front_end_modes(ctx, mode):
     params = icp.icp_params_default(**FRONT_ENDS[mode])
-    for prob in [synth.config1_problem(1), synth.RoomSequence(0, n_frames=2).problem(0)]:
+    for prob in [synth.pair_problem(1), synth.RoomSequence(0, n_frames=2).problem(0)]:
         Tg, sg, To, so = _register_both(ctx, prob, params)
         ang, dt = pose_err(Tg, To)
         assert ang < POSE_TOL and dt < POSE_TOL, (mode, prob.name, ang, dt)
@@ -191,7 +191,7 @@ def test_s3_moments(ctx, name, reduce_mode):
 
 
 def test_s4_solve_update(ctx):
-    prob = synth.config1_problem(0)
+    prob = synth.pair_problem(0)
     lvl = oracle.pyramids(prob.live_depth, prob.model_vtx, prob.model_nrm, prob.K, 1)[0]
     rng = np.random.default_rng(3)
     for mode, c in [(icp.LAMBDA_CONST, 0.0), (icp.LAMBDA_CONST, 5.0), (icp.LAMBDA_C_OVER_SQRT_N, 2.0),
@@ -232,8 +232,8 @@ def _register_both(ctx, prob, params):
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("lam", [5.0, 0.0])
-def test_end_to_end_config1(ctx, seed, lam):
-    prob = synth.config1_problem(seed)
+def test_end_to_end_pair(ctx, seed, lam):
+    prob = synth.pair_problem(seed)
     params = icp.icp_params_default(lambda_c=lam)
     Tg, sg, To, so = _register_both(ctx, prob, params)
     ang, dt = pose_err(Tg, To)
@@ -261,7 +261,7 @@ def test_end_to_end_split_precision(ctx, lam):
     scenes and on VGA room frames."""
     params = icp.icp_params_default(reduce_mode=1, lambda_c=lam)
     seq = synth.RoomSequence(0, n_frames=3)
-    for prob in [synth.config1_problem(0), synth.config1_problem(1), seq.problem(0), seq.problem(1)]:
+    for prob in [synth.pair_problem(0), synth.pair_problem(1), seq.problem(0), seq.problem(1)]:
         Tg, sg, To, so = _register_both(ctx, prob, params)
         ang, dt = pose_err(Tg, To)
         assert ang < POSE_TOL and dt < POSE_TOL, (prob.name, ang, dt)
@@ -276,7 +276,7 @@ def test_pass_modes_match_oracle(ctx, over):
     """Single-pass (predicted band window) and two-pass reductions give the
     oracle's pose; beta < 1 takes the two-pass route automatically."""
     params = icp.icp_params_default(**over)
-    probs = [synth.config1_problem(3), synth.RoomSequence(1, n_frames=3).problem(1)]
+    probs = [synth.pair_problem(3), synth.RoomSequence(1, n_frames=3).problem(1)]
     for prob in probs:
         Tg, sg, To, so = _register_both(ctx, prob, params)
         ang, dt = pose_err(Tg, To)
@@ -288,7 +288,7 @@ def test_pass_modes_match_oracle(ctx, over):
 
 
 def test_convergence_control_matches(ctx):
-    prob = synth.config1_problem(0)
+    prob = synth.pair_problem(0)
     params = icp.icp_params_default(converge_window=3, iters=(30, 30, 30), lambda_c=0.0)
     Tg, sg, To, so = _register_both(ctx, prob, params)
     ang, dt = pose_err(Tg, To)
@@ -297,8 +297,8 @@ def test_convergence_control_matches(ctx):
 
 
 def test_batch_matches_single(ctx):
-    probs = [synth.config1_problem(0), synth.config4_problem(1), synth.config1_problem(2),
-             synth.config4_problem(3)]
+    probs = [synth.pair_problem(0), synth.uneven_problem(1), synth.pair_problem(2),
+             synth.uneven_problem(3)]
     params = icp.icp_params_default()
     items = []
     keep = []
@@ -322,7 +322,7 @@ def test_graph_replays_match_eager(ctx, reduce_mode):
     launched ones bit for bit, replay after replay, with unrelated eager GPU
     work and synchronisations in between."""
     seq = synth.RoomSequence(2, n_frames=4)
-    probs = [seq.problem(k) for k in range(3)] + [synth.config1_problem(4)]
+    probs = [seq.problem(k) for k in range(3)] + [synth.pair_problem(4)]
     data = [upload(p) for p in probs]
     params = icp.icp_params_default(reduce_mode=reduce_mode)
     icp.icp_ctx_set_graphs(ctx, False)
@@ -342,7 +342,7 @@ def test_graph_replays_match_eager(ctx, reduce_mode):
 
 
 def test_edge_cases(ctx):
-    prob = synth.config1_problem(0)
+    prob = synth.pair_problem(0)
     params = icp.icp_params_default()
     # all depth invalid: every level reports too few correspondences, pose = seed
     z = prob.live_depth * 0
@@ -373,7 +373,7 @@ def test_edge_cases(ctx):
     # the coarse levels (pixel pairs of the model pyramid, row/column lookup of
     # the rebuilt vertices), 1 / 2 / 4 levels
     for levels, W, H in [(1, 100, 70), (3, 168, 124), (4, 176, 136), (2, 162, 122), (3, 164, 124)]:
-        p = synth.config1_problem(5, W=W, H=H, f=130.0 * W / 160)
+        p = synth.pair_problem(5, W=W, H=H, f=130.0 * W / 160)
         prm = icp.icp_params_default(levels=levels, iters=[10, 5, 4, 3][:levels])
         Tg, sg, To, so = _register_both(ctx, p, prm)
         ang, dt = pose_err(Tg, To)
@@ -397,7 +397,7 @@ def test_edge_cases(ctx):
 
 
 def test_invalid_arguments(ctx):
-    prob = synth.config1_problem(0)
+    prob = synth.pair_problem(0)
     d, mv, mn = upload(prob)
     with pytest.raises(icp.IcpError) as e:
         icp.icp_register(ctx, d[:, :155].contiguous(), mv, mn, prob.K, prob.imu_R, prob.init_pose)
@@ -417,7 +417,7 @@ def test_invalid_arguments(ctx):
 def test_autotuned_tiles_match_oracle(ctx):
     """The autotuner returns candidate tile sizes, and the batch registered
     with them reaches the oracle's poses."""
-    probs = [synth.config1_problem(5), synth.config4_problem(2), synth.config1_problem(6)]
+    probs = [synth.pair_problem(5), synth.uneven_problem(2), synth.pair_problem(6)]
     keep = [upload(p) for p in probs]
     items = [dict(live_depth=d, model_vtx=mv, model_nrm=mn, K=p.K, imu_R=p.imu_R, init_pose=p.init_pose)
              for p, (d, mv, mn) in zip(probs, keep)]

@@ -51,10 +51,10 @@ def _interleave(V, N):
     return np.ascontiguousarray(np.moveaxis(V, 0, -1)), np.ascontiguousarray(np.moveaxis(N, 0, -1))
 
 
-@pytest.mark.parametrize("case", ["cfg1", "stream_qvga"])
+@pytest.mark.parametrize("case", ["pair", "stream_qvga"])
 def test_live_maps_match_oracle(ctx, case):
-    if case == "cfg1":
-        p = synth.config1_problem(2)
+    if case == "pair":
+        p = synth.pair_problem(2)
         depth, K = p.live_depth, p.K
     else:
         s = CameraStream(3, 320, 240, period=4)

@@ -184,7 +184,7 @@ def test_paper_front_end_registration():
     T, st, _ = oracle.register_problem(prob, p)
     ang, dt = pose_err(T, prob.T_gt)
     assert ang < 5e-4 and dt < 1e-3, (ang, dt)
-    noisy = synth.config1_problem(3)
+    noisy = synth.pair_problem(3)
     _, s0, _ = oracle.register_problem(noisy, oracle.default_params())
     _, s1, _ = oracle.register_problem(noisy, oracle.default_params(depth_filter=1, normal_mode=1))
     assert s1[0]["n_gated"] > s0[0]["n_gated"]
@@ -428,7 +428,7 @@ def test_truth_recovery_three_planes(seed):
 def test_large_lambda_pins_rotation_to_imu():
     """P9: lambda -> infinity keeps the rotation at the IMU seed; the loop then
     solves for the translation alone (its last increment vanishes)."""
-    prob = synth.config1_problem(0)
+    prob = synth.pair_problem(0)
     p = oracle.default_params(lambda_c=1e12, iters=(30, 5, 4))
     pose, st, tr = oracle.register_problem(prob, p)
     assert rot_angle(pose[:3, :3] @ prob.imu_R.T) < 1e-9
@@ -439,7 +439,7 @@ def test_large_lambda_pins_rotation_to_imu():
 def test_lambda_zero_corrects_imu_error():
     """Sec. 4.1: without regularisation the IMU error is corrected; with a large
     lambda the IMU rotation is kept."""
-    prob = synth.config1_problem(0)
+    prob = synth.pair_problem(0)
     imu_err = rot_angle(prob.imu_R @ prob.T_gt[:3, :3].T)
     pose0, _, _ = oracle.register_problem(prob, oracle.default_params(lambda_c=0.0))
     pose5, _, _ = oracle.register_problem(prob, oracle.default_params(lambda_c=5.0))
@@ -449,7 +449,7 @@ def test_lambda_zero_corrects_imu_error():
 
 
 def test_imu_seed_sets_initial_rotation():
-    prob = synth.config1_problem(0)
+    prob = synth.pair_problem(0)
     init = synth.pose_matrix(synth.rot_from_rotvec([0.1, 0, 0]), [0.1, 0.2, 0.3])
     p = oracle.default_params(iters=(0, 0, 0))
     pose, st, tr = oracle.register(prob.live_depth, prob.model_vtx, prob.model_nrm, prob.K, prob.imu_R, init, p)
@@ -465,7 +465,7 @@ def test_convergence_rule_stops_on_settled_median():
     p = oracle.default_params(converge_window=3, iters=(30, 30, 30), lambda_c=0.0)
     early = 0
     for seed in range(3):
-        prob = synth.config1_problem(seed)
+        prob = synth.pair_problem(seed)
         _, st, tr = oracle.register_problem(prob, p, trace_cap=128)
         for lvl in range(3):
             ks = [t["k_med"] for t in tr if t["level"] == lvl]
@@ -478,7 +478,7 @@ def test_convergence_rule_stops_on_settled_median():
 
 
 def test_failure_cases():
-    prob = synth.config1_problem(0)
+    prob = synth.pair_problem(0)
     z = np.zeros_like(prob.live_depth)
     pose, st, _ = oracle.register(z, prob.model_vtx, prob.model_nrm, prob.K, prob.imu_R, prob.init_pose)
     assert all(s["status"] == oracle.TOO_FEW_CORR and s["iters_run"] == 1 for s in st)
