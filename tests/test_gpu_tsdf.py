@@ -164,6 +164,24 @@ def test_raycast_from_outside_and_parallel_rays(ctx):
     assert (~np.isnan(vo[..., 2])).mean() > 0.3
 
 
+@pytest.mark.parametrize("dim", [8, 9, 17])
+def test_tiny_volumes_anisotropic_camera(ctx, dim):
+    """Volumes of one or a few bricks (the last one partial), a camera with
+    fx != fy and an off-centre principal point, two integrations from
+    different poses, ray casts from a third."""
+    prims = [Plane(n=np.array([0.0, 0.0, -1.0]), c=-1.6), Sphere(centre=np.array([0.05, 0.0, 1.3]), radius=0.2)]
+    Kd = (95.0, 80.0, 41.3, 28.9)
+    g, o = _volumes(ctx, dim, size=1.2, origin=(-0.6, -0.6, 0.8))
+    for T in (np.eye(4), pose_matrix(rot_from_rotvec([0.0, 0.05, 0.02]), [0.03, -0.02, 0.01])):
+        d, _, _, _ = render(prims, 83, 61, Kd, T, zmin=0.5, zmax=4.0)
+        _integrate_both(g, o, d.astype(np.float32), Kd, T)
+    _assert_volume_equal(g, o)
+    W, H = 37, 29
+    K = (50.0, 44.0, 17.2, 15.7)
+    T = pose_matrix(rot_from_rotvec([0.01, -0.03, 0.0]), [-0.02, 0.01, 0.05])
+    _assert_raycast_equal(g, o, W, H, K, T, tmin=0.3, tmax=3.0)
+
+
 def test_full_size_volume_and_vga_crop(ctx):
     """512^3 over the room (1.25 cm voxels): the whole volume after one VGA
     frame, and a 64 x 48 crop of the VGA ray cast from the next pose (the
