@@ -644,8 +644,10 @@ void or_pairs(const float* LV, const float* LN, const float* MV, const float* MN
 
 /* Median from the CDF (Sec. 3.3) at bin resolution: the lower median bin
    k_med = min{k : C_k >= ceil(N/2)}.  Band kept around it (reading taken; the
-   paper keeps "pairs that gather around the median"):
-   [max(0, floor((1-beta) k_med)), ceil((1+beta)(k_med+1)) - 1]. */
+   paper keeps the pairs that gather around the median and gives no formula):
+   [max(0, floor((1-beta) k_med)), ceil((1+beta)(k_med+1)) - 1].  Parity
+   unpinned for the band's width beyond the paper's one illustration (about
+   75% of the pairs kept, which beta = 1 reproduces on the room frames). */
 void or_band(const uint32_t* hist, int use_filter, double beta, int64_t out[4]) {
     int64_t N = 0;
     for (int k = 0; k < OR_BINS; ++k) N += hist[k];

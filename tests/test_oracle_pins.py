@@ -565,3 +565,17 @@ def test_tsdf_sphere_raycast_lies_on_the_sphere():
     assert np.max(np.abs(r_err[facing])) < 0.15 * side
     nw = nrm[hit].astype(np.float64) @ T[:3, :3].T
     assert np.min(np.sum(nw * radial, axis=1)[facing]) > math.cos(math.radians(5))
+
+def test_band_keeps_about_three_quarters_of_the_pairs():
+    """P19: the band rule against the paper's one quantitative statement about
+    the filter (Sec. 3.3, the caption of its median-filtering figure: about 75%
+    of the pairs kept in the example shown).  On room registrations the finest
+    level keeps between 60% and 90% of the gated pairs; a band a few bins wide
+    around the median, no band at all, or one that never reaches above the
+    median would fall outside."""
+    seq = synth.RoomSequence(0, n_frames=6)
+    fracs = []
+    for k in (0, 2, 4):
+        _, st, _ = oracle.register_problem(seq.problem(k))
+        fracs.append(st[0]["n_kept"] / st[0]["n_gated"])
+    assert all(0.6 < f < 0.9 for f in fracs), fracs
