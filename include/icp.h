@@ -55,7 +55,7 @@ extern "C" {
 #define ICP_EINVAL (-1)   /* null pointer, bad size or bad parameter */
 #define ICP_ENOMEM (-2)   /* workspace would exceed the context's HBM budget, or allocation failed */
 #define ICP_EDEVICE (-3)  /* a HIP runtime error; icp_last_error() has its text */
-#define ICP_ETIMEOUT (-4) /* a device-side wait gave up (persistent batch kernel) */
+#define ICP_ETIMEOUT (-4) /* reserved for a device-side wait that gives up; no call returns it at present */
 
 /* per-level numerical status (icp_level_stats.status) */
 #define ICP_LEVEL_OK 0
