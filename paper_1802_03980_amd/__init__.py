@@ -195,6 +195,18 @@ def _dev_ptr(t, dtype_name, name):
     return C.c_void_p(t.data_ptr())
 
 
+def _maps_match(live_depth, model_vtx, model_nrm):
+    """(H, W) of a problem after checking that the model maps are (H, W, 3)
+    like the depth (the library reads H*W*3 floats from each)."""
+    if live_depth.dim() != 2:
+        raise ValueError(f"live_depth must be (H, W), got {tuple(live_depth.shape)}")
+    H, W = live_depth.shape
+    for name, t in (("model_vtx", model_vtx), ("model_nrm", model_nrm)):
+        if tuple(t.shape) != (H, W, 3):
+            raise ValueError(f"{name} must have shape ({H}, {W}, 3), got {tuple(t.shape)}")
+    return H, W
+
+
 def _f64(a, n, name):
     a = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
     if a.size != n:
@@ -271,7 +283,7 @@ def icp_workspace_bytes(sizes, levels=3):
 
 def icp_register(ctx, live_depth, model_vtx, model_nrm, K, imu_R, init_pose, params=None, stream=None):
     """Register one frame; returns (4x4 pose ndarray, stats dict)."""
-    H, W = live_depth.shape
+    H, W = _maps_match(live_depth, model_vtx, model_nrm)
     p = params if params is not None else icp_params_default()
     Kc = make_intrinsics(K)
     R = _f64(imu_R, 9, "imu_R")
@@ -290,7 +302,7 @@ def icp_register_async(ctx, live_depth, model_vtx, model_nrm, K, imu_R, init_pos
                        stream=None):
     """Asynchronous register; result_dev is a uint8 device tensor of at least
     sizeof(icp_result) bytes that receives the icp_result."""
-    H, W = live_depth.shape
+    H, W = _maps_match(live_depth, model_vtx, model_nrm)
     p = params if params is not None else icp_params_default()
     if result_dev.numel() * result_dev.element_size() < C.sizeof(icp_result):
         raise ValueError("result_dev too small")
@@ -325,7 +337,7 @@ def _problem_array(problems):
     arr = (icp_problem * n)()
     for i, q in enumerate(problems):
         d = q["live_depth"]
-        H, W = d.shape
+        H, W = _maps_match(d, q["model_vtx"], q["model_nrm"])
         a = arr[i]
         a.live_depth = _dev_ptr(d, "float32", "live_depth").value
         a.model_vtx = _dev_ptr(q["model_vtx"], "float32", "model_vtx").value
@@ -389,7 +401,7 @@ def icp_ctx_get_timing(ctx):
 # ---------------------------------------------------------------- stage access
 
 def icp_stage_prepare(ctx, live_depth, model_vtx, model_nrm, K, levels=3, params=None, stream=None):
-    H, W = live_depth.shape
+    H, W = _maps_match(live_depth, model_vtx, model_nrm)
     Kc = make_intrinsics(K)
     prm = C.byref(params) if params is not None else None
     rc = lib().icp_stage_prepare(ctx.handle, _dev_ptr(live_depth, "float32", "live_depth"), W, H,
@@ -517,6 +529,9 @@ class TsdfVolume:
             out = (torch.empty((H, W, 3), dtype=torch.float32, device=dev),
                    torch.empty((H, W, 3), dtype=torch.float32, device=dev))
         vtx, nrm = out
+        for name, t in (("vtx", vtx), ("nrm", nrm)):
+            if tuple(t.shape) != (H, W, 3):
+                raise ValueError(f"{name} must have shape ({H}, {W}, 3), got {tuple(t.shape)}")
         T = _f64(T_wc, 16, "T_wc")
         Kc = make_intrinsics(K)
         _check(self.ctx, lib().icp_tsdf_raycast(self.ctx.handle, C.byref(self.desc), W, H, C.byref(Kc), _np_ptr(T),
@@ -577,6 +592,7 @@ class Server:
             raise IcpError(rc, "icp_server_create failed")
         self.handle = h
         self.config = cfg
+        self.sizes = {}  # open stream id -> (H, W): a submitted frame must have that shape
 
     def _check(self, rc):
         if rc < 0:
@@ -588,13 +604,17 @@ class Server:
         sid = C.c_int(-1)
         Kc = make_intrinsics(K)
         self._check(lib().icp_server_open_stream(self.handle, W, H, C.byref(Kc), C.byref(sid)))
+        self.sizes[sid.value] = (H, W)
         return sid.value
 
     def close_stream(self, sid):
         self._check(lib().icp_server_close_stream(self.handle, sid))
+        self.sizes.pop(sid, None)
 
     def submit(self, sid, depth, imu_rel_R, tag=0, t_submit=0.0):
         d = np.ascontiguousarray(depth, dtype=np.float32)
+        if sid in self.sizes and d.shape != self.sizes[sid]:  # the library copies H*W floats from it
+            raise ValueError(f"depth must have shape {self.sizes[sid]}, got {d.shape}")
         R = np.ascontiguousarray(imu_rel_R, dtype=np.float64).reshape(9)
         self._check(lib().icp_server_submit(self.handle, sid, d.ctypes.data_as(C.c_void_p),
                                             R.ctypes.data_as(C.c_void_p), int(tag), float(t_submit)))

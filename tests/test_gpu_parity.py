@@ -399,9 +399,12 @@ def test_edge_cases(ctx):
 def test_invalid_arguments(ctx):
     prob = synth.pair_problem(0)
     d, mv, mn = upload(prob)
-    with pytest.raises(icp.IcpError) as e:
-        icp.icp_register(ctx, d[:, :155].contiguous(), mv, mn, prob.K, prob.imu_R, prob.init_pose)
+    with pytest.raises(icp.IcpError) as e:  # W = 155 is not divisible by 2^(levels-1)
+        icp.icp_register(ctx, d[:, :155].contiguous(), mv[:, :155].contiguous(), mn[:, :155].contiguous(), prob.K,
+                         prob.imu_R, prob.init_pose)
     assert e.value.code == icp.EINVAL
+    with pytest.raises(ValueError):  # model maps smaller than the frame never reach the library
+        icp.icp_register(ctx, d, mv[:, :156].contiguous(), mn, prob.K, prob.imu_R, prob.init_pose)
     for bad in [dict(levels=0), dict(levels=5), dict(dist_max=0.2), dict(lambda_mode=9), dict(lambda_c=-1.0),
                 dict(tile_px=(100, 0, 0)), dict(reduce_mode=2), dict(depth_filter=1, filter_radius=8),
                 dict(normal_mode=2), dict(normal_mode=1, normal_radius=0)]:

@@ -198,6 +198,8 @@ def test_server_rejects_bad_arguments():
         with pytest.raises(icp.IcpError) as e:
             srv.submit(sid, np.zeros((120, 160), np.float32), np.full((3, 3), np.nan))
         assert e.value.code == icp.EINVAL
+        with pytest.raises(ValueError):  # a frame of another size never reaches the library
+            srv.submit(sid, np.zeros((120, 150), np.float32), np.eye(3))
         assert srv.poll(8, timeout_ms=0) == []
     finally:
         srv.close()

@@ -274,6 +274,9 @@ def test_bad_arguments(ctx):
     with pytest.raises(icp.IcpError) as e:
         g.raycast(32, 24, K, np.eye(4), tmin=1.0, tmax=0.5)
     assert e.value.code == icp.EINVAL
+    with pytest.raises(ValueError):  # an output map of the wrong size never reaches the kernel
+        g.raycast(32, 24, K, np.eye(4), out=(torch.empty((24, 31, 3), device="cuda"),
+                                             torch.empty((24, 32, 3), device="cuda")))
     g.desc.mu = 0.0
     with pytest.raises(icp.IcpError) as e:
         g.integrate(d, K, np.eye(4))
