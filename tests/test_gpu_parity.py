@@ -297,8 +297,10 @@ def test_convergence_control_matches(ctx):
 
 
 def test_batch_matches_single(ctx):
+    # 160x120 pairs and the four batch resolutions (848x480, 640x480, 1280x720,
+    # 320x240) in one batch
     probs = [synth.pair_problem(0), synth.uneven_problem(1), synth.pair_problem(2),
-             synth.uneven_problem(3)]
+             synth.uneven_problem(3), synth.uneven_problem(5), synth.uneven_problem(6)]
     params = icp.icp_params_default()
     items = []
     keep = []
