@@ -34,6 +34,11 @@
  *     last good value.  No C++ exception crosses this interface.
  *   - A context is used by one host thread at a time.  It owns all device
  *     workspace (pyramids, histograms, partial sums, per-problem state).
+ *     Its calls may name different streams: since they share that workspace,
+ *     each call's stream first waits for the work the context's previous call
+ *     queued, so calls on one context never overlap on the device (concurrent
+ *     work takes one context per stream).  The TSDF calls use no context
+ *     memory and are ordered by their streams alone.
  */
 #ifndef ICP_MI355X_H
 #define ICP_MI355X_H

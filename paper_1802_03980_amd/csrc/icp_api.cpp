@@ -23,6 +23,9 @@ struct icp_ctx {
     size_t hstage_cap = 0;
     hipEvent_t ev_upload = nullptr;  // upload of the staging buffer finished
     bool ev_pending = false;
+    hipEvent_t ev_done = nullptr;       // end of the work the last call queued
+    hipStream_t done_stream = nullptr;  // the stream it was queued on
+    bool done_valid = false;
     std::string err;
     // stage-access problem (problem 0 of the last icp_stage_prepare)
     bool stage_ready = false;
@@ -261,6 +264,33 @@ int ensure_workspace(icp_ctx* ctx, size_t bytes) {
     ctx->ws_cap = want;
     return ICP_OK;
 }
+
+// Calls may come on different streams, while the workspace, descriptors and
+// staging memory of a context are shared: a call first orders its stream
+// after the work the previous call queued, and on its way out (on every path,
+// errors included) records where its own work ends.
+class StreamTurn {
+  public:
+    int enter(icp_ctx* ctx, hipStream_t s) {
+        if (ctx->done_valid && s != ctx->done_stream) HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->ev_done, 0));
+        ctx_ = ctx;
+        s_ = s;
+        return ICP_OK;
+    }
+    ~StreamTurn() {
+        if (!ctx_) return;
+        if (hipEventRecord(ctx_->ev_done, s_) == hipSuccess) {
+            ctx_->done_stream = s_;
+            ctx_->done_valid = true;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+
+  private:
+    icp_ctx* ctx_ = nullptr;
+    hipStream_t s_ = nullptr;
+};
 
 int ensure_stage(icp_ctx* ctx, size_t bytes) {
     if (ctx->ev_pending) {
@@ -584,7 +614,9 @@ int icp_ctx_create(int device, size_t hbm_budget_bytes, icp_ctx** out) {
     icp_ctx* ctx = new icp_ctx();
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;
-    if (hipEventCreateWithFlags(&ctx->ev_upload, hipEventDisableTiming) != hipSuccess) {
+    if (hipEventCreateWithFlags(&ctx->ev_upload, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_done, hipEventDisableTiming) != hipSuccess) {
+        if (ctx->ev_upload) (void)hipEventDestroy(ctx->ev_upload);
         delete ctx;
         return ICP_EDEVICE;
     }
@@ -599,6 +631,7 @@ void icp_ctx_destroy(icp_ctx* ctx) {
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->hstage) (void)hipHostFree(ctx->hstage);
     if (ctx->ev_upload) (void)hipEventDestroy(ctx->ev_upload);
+    if (ctx->ev_done) (void)hipEventDestroy(ctx->ev_done);
     for (auto& r : ctx->pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -656,6 +689,8 @@ int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_
         if ((rc = check_problem(ctx, probs[p], params->levels))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamTurn turn;
+    if (const int trc = turn.enter(ctx, s)) return trc;
     Plan& P = ctx_plan(ctx);
     if ((rc = stage_batch(ctx, n, probs, params->levels, params->tile_px, params->depth_filter, P, s))) return rc;
     ctx->stage_ready = false;
@@ -675,6 +710,8 @@ int icp_autotune_tiles(icp_ctx* ctx, int n, const icp_problem* probs, const icp_
     if (rc) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamTurn turn;
+    if (const int trc = turn.enter(ctx, s)) return trc;
     std::vector<icp_result> res(n);
     icp_params p = *params;
     for (int l = 0; l < ICP_MAX_LEVELS; ++l)
@@ -751,6 +788,8 @@ int icp_live_maps(icp_ctx* ctx, const float* depth, int W, int H, const icp_intr
         return fail(ctx, ICP_EINVAL, "intrinsics must be finite with fx, fy > 0");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamTurn turn;
+    if (const int trc = turn.enter(ctx, s)) return trc;
     if (!ctx->d_jobs) HIP_TRY(ctx, hipMalloc(&ctx->d_jobs, sizeof(MapsDesc)));
     int rc = ensure_stage(ctx, sizeof(MapsDesc));
     if (rc) return rc;
@@ -859,6 +898,8 @@ int icp_register_async(icp_ctx* ctx, const float* live_depth, int W, int H, cons
     if ((rc = check_problem(ctx, q, params->levels))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamTurn turn;
+    if (const int trc = turn.enter(ctx, s)) return trc;
     Plan& P = ctx_plan(ctx);
     if ((rc = stage_batch(ctx, 1, &q, params->levels, params->tile_px, params->depth_filter, P, s))) return rc;
     ctx->stage_ready = false;
@@ -885,6 +926,8 @@ int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const
     if ((rc = check_problem(ctx, q, levels))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamTurn turn;
+    if (const int trc = turn.enter(ctx, s)) return trc;
     Plan& P = ctx_plan(ctx);
     if ((rc = stage_batch(ctx, 1, &q, levels, nullptr, prm->depth_filter, P, s))) return rc;
     char* base = static_cast<char*>(ctx->ws);
@@ -919,6 +962,8 @@ int icp_stage_level(icp_ctx* ctx, int level, float* depth, float* live_vtx, floa
     if (rc) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamTurn turn;
+    if (const int trc = turn.enter(ctx, s)) return trc;
     const LevelDesc& L = ctx->stage_desc.lv[level];
     const size_t S = (size_t)L.npx * sizeof(float);
     if (depth) HIP_TRY(ctx, hipMemcpyAsync(depth, L.D, S, hipMemcpyDeviceToDevice, s));
@@ -950,6 +995,8 @@ int icp_stage_associate(icp_ctx* ctx, int level, const double* pose12, const icp
     if ((rc = check_params(ctx, params))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamTurn turn;
+    if (const int trc = turn.enter(ctx, s)) return trc;
     const KParams kp = kparams(params);
     uint32_t* d_hist = reinterpret_cast<uint32_t*>(ctx->d_scratch);
     HIP_TRY(ctx, icpk::launch_stage_set(ctx->d_desc, pose_arg(pose12), 0, -1, level, s));
@@ -979,6 +1026,8 @@ int icp_stage_moments(icp_ctx* ctx, int level, const double* pose12, const icp_p
     if ((rc = check_params(ctx, params))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamTurn turn;
+    if (const int trc = turn.enter(ctx, s)) return trc;
     const KParams kp = kparams(params);
     HIP_TRY(ctx, icpk::launch_stage_set(ctx->d_desc, pose_arg(pose12), k_lo, k_hi, level, s));
     IterCtl ctl{level, 0, 0, 1};
@@ -997,6 +1046,8 @@ int icp_stage_solve(icp_ctx* ctx, const double* moments, int64_t n, const double
     if (rc) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamTurn turn;
+    if (const int trc = turn.enter(ctx, s)) return trc;
     if (!ctx->ws || ctx->ws_cap < kScratchBytes) {
         if ((rc = ensure_workspace(ctx, kScratchBytes))) return rc;
         ctx->stage_ready = false;

@@ -1,0 +1,110 @@
+"""GPU (HIP C-ABI): the asynchronous registration call, the kernel-timing
+calls and the context's workspace accounting.
+
+  * icp_register_async on a side stream writes the same icp_result, bit for
+    bit, as the synchronous call on the same inputs, also when consecutive
+    calls alternate between two streams.
+  * With timing on, one registration records one front-end bracket and one
+    launch of each iteration kind per iteration, covering the level pixels of
+    every iteration; switching timing on or off clears the totals; the traced
+    (eager) launches give the same pose as the untraced ones.
+  * The context holds at least the workspace icp_workspace_bytes names for
+    the batch it ran.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1802_03980_amd as icp
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return icp.icp_ctx_create(0)
+
+
+def upload(p):
+    return tuple(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (p.live_depth, p.model_vtx, p.model_nrm))
+
+
+def test_async_matches_sync(ctx):
+    probs = [synth.pair_problem(3), synth.RoomSequence(1, n_frames=2).problem(0)]
+    data = [upload(p) for p in probs]
+    params = icp.icp_params_default()
+    sync = [icp.icp_register(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, params)
+            for p, (d, mv, mn) in zip(probs, data)]
+    side = torch.cuda.Stream()
+    nbytes = C.sizeof(icp.icp_result)
+    outs = [torch.zeros(nbytes, dtype=torch.uint8, device="cuda") for _ in probs]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        for p, (d, mv, mn), out in zip(probs, data, outs):
+            icp.icp_register_async(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, out, params)
+    side.synchronize()
+    for (Ts, ss), out in zip(sync, outs):
+        Ta, sa = icp.result_from_bytes(out.cpu().numpy().tobytes())
+        assert np.array_equal(Ta, Ts)
+        assert sa["status"] == ss["status"] and sa["iters_total"] == ss["iters_total"]
+        for la, ls in zip(sa["levels"], ss["levels"]):
+            assert la == ls
+    # calls on two streams in turn, with nothing synchronised in between: each
+    # call's stream waits for the work the previous call queued, since all
+    # calls share the context's workspace
+    pairs = [synth.pair_problem(k) for k in (4, 5, 6)]
+    pdata = [upload(p) for p in pairs]
+    ref = [icp.icp_register(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, params)[0]
+           for p, (d, mv, mn) in zip(pairs, pdata)]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs2 = [torch.zeros(nbytes, dtype=torch.uint8, device="cuda") for _ in pairs]
+    torch.cuda.synchronize()
+    for k, (p, (d, mv, mn), out) in enumerate(zip(pairs, pdata, outs2)):
+        with torch.cuda.stream(s1 if k % 2 == 0 else s2):
+            icp.icp_register_async(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, out, params)
+    torch.cuda.synchronize()
+    for T, out in zip(ref, outs2):
+        assert np.array_equal(icp.result_from_bytes(out.cpu().numpy().tobytes())[0], T)
+    with pytest.raises(ValueError):  # a result buffer smaller than one icp_result never reaches the library
+        icp.icp_register_async(ctx, *data[0], probs[0].K, probs[0].imu_R, probs[0].init_pose, outs[0][:8], params)
+
+
+def test_kernel_timing_counts_launches(ctx):
+    p = synth.RoomSequence(1, n_frames=3).problem(1)
+    d, mv, mn = upload(p)
+    params = icp.icp_params_default()
+    T_graph, _ = icp.icp_register(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, params)
+    icp.icp_ctx_set_timing(ctx, True)
+    try:
+        T_traced, _ = icp.icp_register(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, params)
+        t = icp.icp_ctx_get_timing(ctx)
+    finally:
+        icp.icp_ctx_set_timing(ctx, False)
+    assert np.array_equal(T_traced, T_graph)
+    H, W = p.live_depth.shape
+    iters = list(params.iters)[:params.levels]
+    level_px = [(W >> l) * (H >> l) for l in range(params.levels)]
+    n_it = sum(iters)
+    assert t["front_end"]["launches"] == 1 and t["front_end"]["pixels"] == W * H
+    for kind in ("pass1", "band", "pass2", "solve"):
+        assert t[kind]["launches"] == n_it, (kind, t[kind])
+        assert t[kind]["total_ms"] > 0.0, kind
+    px_it = sum(i * n for i, n in zip(iters, level_px))
+    assert t["pass1"]["pixels"] == px_it and t["pass2"]["pixels"] == px_it
+    assert all(v["total_ms"] > 0.0 for v in t.values())
+    # switching off cleared the totals, and untraced calls add nothing
+    icp.icp_register(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, params)
+    assert all(v["launches"] == 0 and v["total_ms"] == 0.0 for v in icp.icp_ctx_get_timing(ctx).values())
+
+
+def test_context_workspace_covers_the_batch(ctx):
+    probs = [synth.uneven_problem(6), synth.uneven_problem(2)]
+    data = [upload(p) for p in probs]
+    items = [dict(live_depth=d, model_vtx=mv, model_nrm=mn, K=p.K, imu_R=p.imu_R, init_pose=p.init_pose)
+             for p, (d, mv, mn) in zip(probs, data)]
+    icp.icp_register_batch(ctx, items, icp.icp_params_default())
+    need = icp.icp_workspace_bytes([(p.live_depth.shape[1], p.live_depth.shape[0]) for p in probs])
+    assert need > 0 and ctx.workspace_bytes() >= need
