@@ -23,6 +23,9 @@
  *   Sec. 4.4         coarse-to-fine cadence (4,5,10) iterations
  * Where the paper is silent (A and b of Eq. (3), bins, the band, gates,
  * pyramid, normals) the reading taken is stated beside the code.
+ *
+ * Parity unpinned: the median band's width (or_band), which the paper does
+ * not define beyond one illustration; see icp_oracle.h.
  */
 #include "icp_oracle.h"
 

@@ -8,6 +8,12 @@
  * CPU-baseline leg load this library; the GPU library never links, loads or
  * calls it and the two share no code, header, table or constant.
  *
+ * Parity unpinned: the width of the median band (or_band).  The paper gives
+ * no formula or printed values for it; the band is pinned only to its own
+ * definition (hand-worked fixtures) and to the paper's one illustration of
+ * the filter (about three quarters of the pairs kept).  Every other function
+ * is pinned by the tests to closed forms, worked fixtures or invariants.
+ *
  * Every array is a host pointer.  Maps are row-major, pixel (u, v) at index
  * v*W + u.  "SoA" maps hold three planes of W*H floats (x plane, y plane,
  * z plane).  Poses are 3x4 row-major [R | t] (12 doubles) unless stated.
