@@ -86,6 +86,7 @@ struct ProbState {
     uint32_t N;                 // gated pairs of the current iteration
     int32_t k_med, k_lo, k_hi;  // median bin and kept band of the current iteration
     int32_t pred_hi;            // band upper edge predicted for the next iteration (-1: none)
+    int32_t pred_hw;            // half-width of the window around it, in bins (at most ICP_WIN / 2)
     int32_t fused_done;         // this iteration was completed from the single-pass partials
     int32_t level_done;         // the current level has ended (status or convergence)
     int32_t settled;            // successive iterations with an unchanged median

@@ -41,6 +41,7 @@ __global__ __launch_bounds__(ICP_WG) void k_init(const ProbDesc* __restrict__ pr
         st->k_lo = 0;
         st->k_hi = -1;
         st->pred_hi = -1;
+        st->pred_hw = ICP_WIN / 2;
         st->fused_done = 0;
         st->level_done = 0;
         st->settled = 0;
@@ -418,10 +419,29 @@ __global__ __launch_bounds__(ICP_WG) void k_centroid(const ProbDesc* __restrict_
 // accumulators, rows inside the window to per-bin LDS sums, so that once the
 // band is known the kept rows' moments are a prefix of the tile partials.
 
-__device__ __forceinline__ int window_start(int pred_hi) {
-    if (pred_hi < 0) return -1;
-    const int h0 = pred_hi - ICP_WIN / 2;
-    return h0 < 0 ? 0 : (h0 > ICP_HIST_BINS - ICP_WIN ? ICP_HIST_BINS - ICP_WIN : h0);
+// The window of an iteration: bins [h0, h0 + w), 2 hw of them around the
+// predicted edge.  The first iteration of a level, whose prediction comes
+// from the coarser level, takes the full ICP_WIN bins; later iterations take
+// the half-width the band kernel derived from how far the edge last moved.
+// h0 = -1: no prediction, no window.
+struct Win {
+    int h0, w;
+};
+
+__device__ __forceinline__ Win band_window(int pred_hi, int pred_hw, int iter) {
+    if (pred_hi < 0) return Win{-1, 0};
+    const int hw = iter == 0 ? ICP_WIN / 2 : pred_hw;
+    const int h0 = pred_hi - hw, hmax = ICP_HIST_BINS - 2 * hw;
+    return Win{h0 < 0 ? 0 : (h0 > hmax ? hmax : h0), 2 * hw};
+}
+
+// Half-width of the next iteration's window: twice the edge's last move plus
+// four bins, at least six and at most ICP_WIN / 2 (the full window when the
+// move is unknown: the first iteration of a level, or no prediction).
+__device__ __forceinline__ int next_half_width(int k_hi, int pred_hi, int iter) {
+    if (iter == 0 || pred_hi < 0) return ICP_WIN / 2;
+    const int hw = 2 * abs(k_hi - pred_hi) + 4;
+    return hw < 6 ? 6 : (hw > ICP_WIN / 2 ? ICP_WIN / 2 : hw);
 }
 
 // Sum the 28 accumulators and the count over the work-group into `out`
@@ -515,7 +535,8 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
     const int tid = threadIdx.x;
     const int tile = g - L.tile_base;
     if (st->level_done) return;  // uniform: the level has ended for this problem
-    const int h0 = kFused ? window_start(st->pred_hi) : -1;
+    const Win win = kFused ? band_window(st->pred_hi, st->pred_hw, ctl.iter) : Win{-1, 0};
+    const int h0 = win.h0;
     for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) sh_hist[b] = 0u;
     if (kFused && h0 >= 0)
         for (int b = tid; b < ICP_WAVES * ICP_WIN * (ICP_NMOM + 1); b += ICP_WG) (&sh_win[0][0][0])[b] = 0.0f;
@@ -558,7 +579,7 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
                         accumulate_row(q.p, q.d, q.n, acc);
                         cnt += 1.0f;
                     }
-                    const bool inwin = gated && q.bin >= h0 && q.bin < h0 + ICP_WIN;
+                    const bool inwin = gated && q.bin >= h0 && q.bin < h0 + win.w;
                     window_add(inwin, q.bin - h0, q.p, q.d, q.n, sh_win[wave], sh_stage[wave]);
                 }
             });
@@ -574,8 +595,8 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
     if (kFused && h0 >= 0) {
         float* part = L.part1 + (size_t)tile * ICP_WIN_SLOTS * ICP_PART_STRIDE;
         block_reduce_row(acc, cnt, sh_red, part);
-        // slot b+1 holds the prefix sum over window bins 0..b, so the band
-        // kernel needs two slots per tile whatever the band edge.  The 48 bins
+        // slot b+1 holds the prefix sum over window bins 0..b (b < w), so the
+        // band kernel needs two slots per tile whatever the band edge.  The 48 bins
         // are scanned as 8 chunks of 6 by 8 x 29 threads: each sums its chunk
         // (waves, then bins in order), the chunk totals go through LDS, and
         // each thread adds the totals of the chunks before its own.
@@ -601,7 +622,8 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
             float off = 0.0f;
             for (int c2 = 0; c2 < cj; ++c2) off += sh_tot[c2 * (ICP_NMOM + 1) + mj];
 #pragma unroll
-            for (int q = 0; q < kPer; ++q) part[(cj * kPer + q + 1) * ICP_PART_STRIDE + mj] = off + pre[q];
+            for (int q = 0; q < kPer; ++q)
+                if (cj * kPer + q < win.w) part[(cj * kPer + q + 1) * ICP_PART_STRIDE + mj] = off + pre[q];
         }
     }
 }
@@ -767,11 +789,12 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     const ProbDesc& P = probs[blockIdx.x];
     const LevelDesc& L = P.lv[ctl.level];
     ProbState* st = P.st;
-    const int done = st->level_done, pred = st->pred_hi;  // both loads in flight together
+    const int done = st->level_done, pred = st->pred_hi, pred_hw = st->pred_hw;  // loads in flight together
     if (done) return;
-    const int h0 = fused ? window_start(pred) : -1;
+    const Win win = fused ? band_window(pred, pred_hw, ctl.iter) : Win{-1, 0};
+    const int h0 = win.h0;
     const Band b = median_band(st, kp, dbg_hist);
-    const bool hit = h0 >= 0 && b.N > 0 && b.k_lo == 0 && b.k_hi >= h0 - 1 && b.k_hi <= h0 + ICP_WIN - 1;
+    const bool hit = h0 >= 0 && b.N > 0 && b.k_lo == 0 && b.k_hi >= h0 - 1 && b.k_hi <= h0 + win.w - 1;
     if (hit) {
         sum_partials(L.part1, L.n_tiles, ICP_WIN_SLOTS * ICP_PART_STRIDE, b.k_hi - h0 + 1, sh_M);
         if (threadIdx.x == 0) solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp);
@@ -779,7 +802,10 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     if (threadIdx.x == 0) {
         st->fused_done = hit ? 1 : 0;
         if (!hit && kp.need2) atomicExch(kp.need2, 1);  // pass 2 has work this iteration
-        if (b.N > 0) st->pred_hi = b.k_hi;
+        if (b.N > 0) {
+            st->pred_hw = next_half_width(b.k_hi, pred, ctl.iter);
+            st->pred_hi = b.k_hi;
+        }
         if (kp.reduce_mode == 1) set_centre(st, ctl.level);
     }
 }
@@ -1013,6 +1039,7 @@ __global__ void k_stage_set(const ProbDesc* __restrict__ probs, PoseArg pose, in
         st->k_lo = k_lo;
         st->k_hi = k_hi;
         st->pred_hi = -1;
+        st->pred_hw = ICP_WIN / 2;
         st->fused_done = 0;
         st->level_done = 0;
         set_centre(st, level);
