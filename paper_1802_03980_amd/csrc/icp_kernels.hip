@@ -113,37 +113,57 @@ __device__ __forceinline__ void live_px(const ICP_GLOBAL float* D, int W, int H,
 // over the (2r+1)^2 window in row-major order, valid neighbours within the
 // range cut-off add ws * (1 - (dz/c)^2)^2 to the weight sum and that times z
 // to the weighted sum (FP64); out = sum(w z) / sum(w); invalid pixels stay 0.
+// A work-group takes an FE_TX x FE_TY tile whose depth and R-pixel halo are
+// staged in LDS (0, an invalid depth, outside the image).
+constexpr int kBoxW = FE_TX + 2 * ICP_FILTER_MAX_R, kBoxH = FE_TY + 2 * ICP_FILTER_MAX_R;
+
+template <int R>
 __global__ __launch_bounds__(ICP_WG) void k_bilateral(const ProbDesc* __restrict__ probs, FrontEnd fe) {
+    static_assert(R >= 1 && R <= ICP_FILTER_MAX_R, "filter radius");
+    constexpr int HW = FE_TX + 2 * R, HH = FE_TY + 2 * R, N = 2 * R + 1;
+    __shared__ float sz[kBoxH][kBoxW];
     const ProbDesc& P = probs[blockIdx.y];
     const LevelDesc& L = P.lv[0];
-    const int i = blockIdx.x * ICP_WG + threadIdx.x;
-    if (i >= L.npx) return;
+    const int tiles_x = (L.W + FE_TX - 1) / FE_TX;
+    const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+    const int u0 = bx * FE_TX, v0 = by * FE_TY;
+    if (v0 >= L.H) return;  // uniform: grids cover the largest frame of the batch
     const ICP_GLOBAL float* D = gconst(P.depth_in);
-    const int u = i % L.W, v = i / L.W, r = fe.filter_radius, n = 2 * r + 1;
-    const float z = D[i];
-    float out = 0.0f;
-    if (depth_ok(z)) {
-        double sw = 0.0, swz = 0.0;
-        for (int dv = -r; dv <= r; ++dv) {
-            const int y = v + dv;
-            if (y < 0 || y >= L.H) continue;
-            for (int du = -r; du <= r; ++du) {
-                const int x = u + du;
-                if (x < 0 || x >= L.W) continue;
-                const float zq = D[y * L.W + x];
-                if (!depth_ok(zq)) continue;
-                const double dz = (double)zq - (double)z;
-                if (!(fabs(dz) < fe.sigma_m)) continue;
-                const double t = dz / fe.sigma_m;
-                const double a = 1.0 - t * t;
-                const double w = fe.ws[(dv + r) * n + (du + r)] * (a * a);
-                sw += w;
-                swz += w * (double)zq;
-            }
-        }
-        out = (float)(swz / sw);
+    for (int t = threadIdx.x; t < HW * HH; t += ICP_WG) {
+        const int ly = t / HW, lx = t - ly * HW;
+        const int x = u0 - R + lx, y = v0 - R + ly;
+        sz[ly][lx] = (x >= 0 && x < L.W && y >= 0 && y < L.H) ? D[y * L.W + x] : 0.0f;
     }
-    gmut(L.Dw)[i] = out;
+    __syncthreads();
+    const int tx = threadIdx.x % FE_TX;
+    const int u = u0 + tx;
+    if (u >= L.W) return;
+    ICP_GLOBAL float* out_plane = gmut(L.Dw);
+    for (int ty = threadIdx.x / FE_TX; ty < FE_TY; ty += ICP_WG / FE_TX) {
+        const int v = v0 + ty;
+        if (v >= L.H) break;
+        const float z = sz[ty + R][tx + R];
+        float out = 0.0f;
+        if (depth_ok(z)) {
+            double sw = 0.0, swz = 0.0;
+#pragma unroll
+            for (int dv = -R; dv <= R; ++dv)
+#pragma unroll
+                for (int du = -R; du <= R; ++du) {
+                    const float zq = sz[ty + R + dv][tx + R + du];
+                    if (!depth_ok(zq)) continue;
+                    const double dz = (double)zq - (double)z;
+                    if (!(fabs(dz) < fe.sigma_m)) continue;
+                    const double t = dz / fe.sigma_m;
+                    const double a = 1.0 - t * t;
+                    const double w = fe.ws[(dv + R) * N + (du + R)] * (a * a);
+                    sw += w;
+                    swz += w * (double)zq;
+                }
+            out = (float)(swz / sw);
+        }
+        out_plane[v * L.W + u] = out;
+    }
 }
 
 // Box-average 3D-gradient normals (normal_mode 1): for the (2r+1)^2 box around
@@ -152,68 +172,97 @@ __global__ __launch_bounds__(ICP_WG) void k_bilateral(const ProbDesc* __restrict
 // FP64 sum of the FP32 vertices; n = normalise(h x g), flipped to face the
 // camera; the pixel needs a valid vertex, a box inside the image and at least
 // half of each half box valid.
-__global__ __launch_bounds__(ICP_WG) void k_live_n_box(const ProbDesc* __restrict__ probs, int level, int r) {
+//
+// A work-group takes an FE_TX x FE_TY tile: the live vertices of the tile and
+// an R-pixel halo are formed once into LDS (the same live_vertex of the same
+// depth and quotients, NaN outside the image), then every pixel sums its box
+// from LDS in row-major order.
+template <int R>
+__global__ __launch_bounds__(ICP_WG) void k_live_n_box(const ProbDesc* __restrict__ probs, int level) {
+    static_assert(R >= 1 && R <= ICP_FILTER_MAX_R, "box radius");
+    constexpr int HW = FE_TX + 2 * R, HH = FE_TY + 2 * R;
+    __shared__ float sv[3][kBoxH][kBoxW];
     const LevelDesc& L = probs[blockIdx.y].lv[level];
-    const int i = blockIdx.x * ICP_WG + threadIdx.x;
-    if (i >= L.npx) return;
-    const int u = i % L.W, v = i / L.W;
+    const int tiles_x = (L.W + FE_TX - 1) / FE_TX;
+    const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+    const int u0 = bx * FE_TX, v0 = by * FE_TY;
+    if (v0 >= L.H) return;  // uniform: grids cover the largest level of the batch
     const ICP_GLOBAL float* D = gconst(L.D);
     const ICP_GLOBAL double* XQ = gconst(L.XQ);
     const ICP_GLOBAL double* YQ = gconst(L.YQ);
     const float qnan = __builtin_nanf("");
-    float n[3] = {qnan, qnan, qnan};
-    float p[3];
-    live_vertex(D[i], XQ[u], YQ[v], p);
-    if (u - r >= 0 && u + r < L.W && v - r >= 0 && v + r < L.H && fin(p[2])) {
-        double sr[3] = {0, 0, 0}, sl[3] = {0, 0, 0}, sd[3] = {0, 0, 0}, su[3] = {0, 0, 0};
-        int nr = 0, nl = 0, nd = 0, nu = 0;
-        for (int dv = -r; dv <= r; ++dv)
-            for (int du = -r; du <= r; ++du) {
-                float q[3];
-                live_vertex(D[(v + dv) * L.W + (u + du)], XQ[u + du], YQ[v + dv], q);
-                if (!fin(q[2])) continue;
+    for (int t = threadIdx.x; t < HW * HH; t += ICP_WG) {
+        const int ly = t / HW, lx = t - ly * HW;
+        const int x = u0 - R + lx, y = v0 - R + ly;
+        float p[3] = {qnan, qnan, qnan};
+        if (x >= 0 && x < L.W && y >= 0 && y < L.H) live_vertex(D[y * L.W + x], XQ[x], YQ[y], p);
+        sv[0][ly][lx] = p[0];
+        sv[1][ly][lx] = p[1];
+        sv[2][ly][lx] = p[2];
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % FE_TX;
+    const int u = u0 + tx;
+    if (u >= L.W) return;
+    ICP_GLOBAL float* LN = gmut(L.LN);
+    constexpr int need = (R * (2 * R + 1) + 1) / 2;
+    for (int ty = threadIdx.x / FE_TX; ty < FE_TY; ty += ICP_WG / FE_TX) {
+        const int v = v0 + ty;
+        if (v >= L.H) break;
+        float n[3] = {qnan, qnan, qnan};
+        const float p[3] = {sv[0][ty + R][tx + R], sv[1][ty + R][tx + R], sv[2][ty + R][tx + R]};
+        if (u - R >= 0 && u + R < L.W && v - R >= 0 && v + R < L.H && fin(p[2])) {
+            double sr[3] = {0, 0, 0}, sl[3] = {0, 0, 0}, sd[3] = {0, 0, 0}, su[3] = {0, 0, 0};
+            int nr = 0, nl = 0, nd = 0, nu = 0;
+#pragma unroll
+            for (int dv = -R; dv <= R; ++dv)
+#pragma unroll
+                for (int du = -R; du <= R; ++du) {
+                    const int yy = ty + R + dv, xx = tx + R + du;
+                    const float q[3] = {sv[0][yy][xx], sv[1][yy][xx], sv[2][yy][xx]};
+                    if (!fin(q[2])) continue;
+                    for (int k = 0; k < 3; ++k) {
+                        const double x = (double)q[k];
+                        if (du > 0) sr[k] += x;
+                        if (du < 0) sl[k] += x;
+                        if (dv > 0) sd[k] += x;
+                        if (dv < 0) su[k] += x;
+                    }
+                    nr += du > 0;
+                    nl += du < 0;
+                    nd += dv > 0;
+                    nu += dv < 0;
+                }
+            if (nr >= need && nl >= need && nd >= need && nu >= need) {
+                double h[3], g[3];
                 for (int k = 0; k < 3; ++k) {
-                    const double x = (double)q[k];
-                    if (du > 0) sr[k] += x;
-                    if (du < 0) sl[k] += x;
-                    if (dv > 0) sd[k] += x;
-                    if (dv < 0) su[k] += x;
+                    h[k] = sr[k] / nr - sl[k] / nl;
+                    g[k] = sd[k] / nd - su[k] / nu;
                 }
-                nr += du > 0;
-                nl += du < 0;
-                nd += dv > 0;
-                nu += dv < 0;
-            }
-        const int need = (r * (2 * r + 1) + 1) / 2;
-        if (nr >= need && nl >= need && nd >= need && nu >= need) {
-            double h[3], g[3];
-            for (int k = 0; k < 3; ++k) {
-                h[k] = sr[k] / nr - sl[k] / nl;
-                g[k] = sd[k] / nd - su[k] / nu;
-            }
-            const double c0 = h[1] * g[2] - h[2] * g[1];
-            const double c1 = h[2] * g[0] - h[0] * g[2];
-            const double c2 = h[0] * g[1] - h[1] * g[0];
-            const double len2 = (c0 * c0 + c1 * c1) + c2 * c2;
-            if (len2 > 0.0 && __builtin_isfinite(len2)) {
-                const double len = sqrt(len2);
-                double m0 = c0 / len, m1 = c1 / len, m2 = c2 / len;
-                const double side = (m0 * (double)p[0] + m1 * (double)p[1]) + m2 * (double)p[2];
-                if (side > 0.0) {
-                    m0 = -m0;
-                    m1 = -m1;
-                    m2 = -m2;
+                const double c0 = h[1] * g[2] - h[2] * g[1];
+                const double c1 = h[2] * g[0] - h[0] * g[2];
+                const double c2 = h[0] * g[1] - h[1] * g[0];
+                const double len2 = (c0 * c0 + c1 * c1) + c2 * c2;
+                if (len2 > 0.0 && __builtin_isfinite(len2)) {
+                    const double len = sqrt(len2);
+                    double m0 = c0 / len, m1 = c1 / len, m2 = c2 / len;
+                    const double side = (m0 * (double)p[0] + m1 * (double)p[1]) + m2 * (double)p[2];
+                    if (side > 0.0) {
+                        m0 = -m0;
+                        m1 = -m1;
+                        m2 = -m2;
+                    }
+                    n[0] = (float)m0;
+                    n[1] = (float)m1;
+                    n[2] = (float)m2;
                 }
-                n[0] = (float)m0;
-                n[1] = (float)m1;
-                n[2] = (float)m2;
             }
         }
+        const int i = v * L.W + u;
+        LN[i] = n[0];
+        LN[L.ps + i] = n[1];
+        LN[2 * L.ps + i] = n[2];
     }
-    ICP_GLOBAL float* LN = gmut(L.LN);
-    LN[i] = n[0];
-    LN[L.ps + i] = n[1];
-    LN[2 * L.ps + i] = n[2];
 }
 
 // Back-projection quotient tables of a level: XQ[u] = (u - cx)/fx for
@@ -1084,8 +1133,19 @@ int model_pairs(int W, int H) { return ((W + 1) / 2) * H; }
 hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, const int* max_vn_blocks,
                           const int* max_model_pairs, const int* max_quot, bool with_live_maps, const FrontEnd& fe,
                           hipStream_t s) {
-    if (fe.depth_filter)
-        hipLaunchKernelGGL(k_bilateral, dim3(blocks_for(max_npx[0]), n), dim3(ICP_WG), 0, s, probs, fe);
+    if (fe.depth_filter) {
+        const dim3 grid(max_vn_blocks[0], n);
+        switch (fe.filter_radius) {
+            case 1: hipLaunchKernelGGL(k_bilateral<1>, grid, dim3(ICP_WG), 0, s, probs, fe); break;
+            case 2: hipLaunchKernelGGL(k_bilateral<2>, grid, dim3(ICP_WG), 0, s, probs, fe); break;
+            case 3: hipLaunchKernelGGL(k_bilateral<3>, grid, dim3(ICP_WG), 0, s, probs, fe); break;
+            case 4: hipLaunchKernelGGL(k_bilateral<4>, grid, dim3(ICP_WG), 0, s, probs, fe); break;
+            case 5: hipLaunchKernelGGL(k_bilateral<5>, grid, dim3(ICP_WG), 0, s, probs, fe); break;
+            case 6: hipLaunchKernelGGL(k_bilateral<6>, grid, dim3(ICP_WG), 0, s, probs, fe); break;
+            case 7: hipLaunchKernelGGL(k_bilateral<7>, grid, dim3(ICP_WG), 0, s, probs, fe); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
     for (int l = 1; l < levels; ++l)
         hipLaunchKernelGGL(k_depth_down, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
     for (int l = 0; l < levels; ++l)
@@ -1095,9 +1155,19 @@ hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* m
         if (with_live_maps || fe.normal_mode == 0)
             hipLaunchKernelGGL(k_live_vn, dim3(max_vn_blocks[l], n), dim3(ICP_WG), 0, s, probs, l,
                                with_live_maps ? 1 : 0);
-        if (fe.normal_mode == 1)
-            hipLaunchKernelGGL(k_live_n_box, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l,
-                               fe.normal_radius);
+        if (fe.normal_mode == 1) {
+            const dim3 grid(max_vn_blocks[l], n);
+            switch (fe.normal_radius) {
+                case 1: hipLaunchKernelGGL(k_live_n_box<1>, grid, dim3(ICP_WG), 0, s, probs, l); break;
+                case 2: hipLaunchKernelGGL(k_live_n_box<2>, grid, dim3(ICP_WG), 0, s, probs, l); break;
+                case 3: hipLaunchKernelGGL(k_live_n_box<3>, grid, dim3(ICP_WG), 0, s, probs, l); break;
+                case 4: hipLaunchKernelGGL(k_live_n_box<4>, grid, dim3(ICP_WG), 0, s, probs, l); break;
+                case 5: hipLaunchKernelGGL(k_live_n_box<5>, grid, dim3(ICP_WG), 0, s, probs, l); break;
+                case 6: hipLaunchKernelGGL(k_live_n_box<6>, grid, dim3(ICP_WG), 0, s, probs, l); break;
+                case 7: hipLaunchKernelGGL(k_live_n_box<7>, grid, dim3(ICP_WG), 0, s, probs, l); break;
+                default: return hipErrorInvalidValue;
+            }
+        }
     }
     for (int l = 1; l < levels; ++l)
         hipLaunchKernelGGL(k_model_down, dim3(blocks_for(max_model_pairs[l]), n), dim3(ICP_WG), 0, s, probs, l);

@@ -89,12 +89,7 @@ FRONT_ENDS = {"filter": dict(depth_filter=1), "box_normals": dict(normal_mode=1)
               "both": dict(depth_filter=1, normal_mode=1, normal_radius=3)}
 
 
-@pytest.mark.parametrize("mode", list(FRONT_ENDS))
-def test_s1_front_end_modes_bitwise(ctx, mode):
-    """The bilateral filter and the box-gradient normals give the oracle's maps
-    bit for bit at every level."""
-    prob = synth.pair_problem(4)
-    params = icp.icp_params_default(**FRONT_ENDS[mode])
+def _check_front_end_maps(ctx, prob, params, tag):
     d, mv, mn = upload(prob)
     _ALIVE[:] = [d, mv, mn]
     icp.icp_stage_prepare(ctx, d, mv, mn, prob.K, 3, params)
@@ -111,7 +106,28 @@ def test_s1_front_end_modes_bitwise(ctx, mode):
             V, N = oracle.live_vn(D, Kl)
         Dg, LV, LN, _, _ = (host(t) for t in icp.icp_stage_level(ctx, l, prob.H, prob.W))
         for key, g, o in (("D", Dg, D), ("LV", LV, V), ("LN", LN, N)):
-            assert _same_nan(g, o), f"{mode} level {l} {key}"
+            assert _same_nan(g, o), f"{tag} level {l} {key}"
+        if params.normal_mode:
+            assert np.isfinite(N).any(), f"{tag} level {l}: no box normal at all"
+
+
+@pytest.mark.parametrize("mode", list(FRONT_ENDS))
+def test_s1_front_end_modes_bitwise(ctx, mode):
+    """The bilateral filter and the box-gradient normals give the oracle's maps
+    bit for bit at every level."""
+    _check_front_end_maps(ctx, synth.pair_problem(4), icp.icp_params_default(**FRONT_ENDS[mode]), mode)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 6, 7])
+def test_s1_front_end_radii_bitwise(ctx, r):
+    """Every filter and box radius (each its own kernel instance, staging an
+    r-pixel halo in LDS) gives the oracle's maps bit for bit, on frames whose
+    64 x 16 tiles are ragged at every level (160 x 120, and 168 x 124 whose
+    coarse levels have odd sizes)."""
+    params = icp.icp_params_default(depth_filter=1, filter_radius=r, filter_sigma_px=1.5 * r,
+                                    normal_mode=1, normal_radius=r)
+    _check_front_end_maps(ctx, synth.pair_problem(4), params, f"r={r}")
+    _check_front_end_maps(ctx, synth.pair_problem(5, W=168, H=124, f=130.0 * 168 / 160), params, f"r={r} 168x124")
 
 
 @pytest.mark.parametrize("mode", list(FRONT_ENDS))
