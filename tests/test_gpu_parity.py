@@ -414,6 +414,35 @@ def test_edge_cases(ctx):
     assert np.array_equal(Tg[:3, :3], prob.imu_R) and sg["iters_total"] == 0
 
 
+def test_band_edge_at_either_end_of_the_histogram(ctx):
+    """Model maps 9 cm behind the live frame (dist_max 12.5 cm): the first band
+    edge clamps at the last bin, the next iteration's window sits at the top of
+    the histogram and misses, and later windows narrow as the edge settles.
+    Noise-free identical frames: the edge stays at bin 1 and the window starts
+    at bin 0.  The poses follow the oracle's."""
+    same = synth.pair_problem(8, trans_m=0.0, rot_deg=0.0, imu_deg=0.0, noise=False)
+    params = icp.icp_params_default()
+    Tg, sg, To, so = _register_both(ctx, same, params)
+    _, _, trace = oracle.register_problem(same, _oracle_params(params))
+    assert max(t["k_hi"] for t in trace) <= 3  # the case this part is for
+    ang, dt = pose_err(Tg, To)
+    assert ang < POSE_TOL and dt < POSE_TOL, ("identical frames", ang, dt)
+    p = synth.pair_problem(7, trans_m=0.0, rot_deg=0.0)
+    mv = p.model_vtx.copy()
+    mv[..., 2] += 0.09
+    q = synth.Problem(live_depth=p.live_depth, model_vtx=mv, model_nrm=p.model_nrm, K=p.K, imu_R=p.imu_R,
+                      init_pose=p.init_pose, T_gt=p.T_gt, name="shifted-9cm")
+    params = icp.icp_params_default(dist_max=0.125)
+    Tg, sg, To, so = _register_both(ctx, q, params)
+    _, _, trace = oracle.register_problem(q, _oracle_params(params))
+    assert trace[0]["k_hi"] == 1023  # the case this test is for
+    ang, dt = pose_err(Tg, To)
+    assert ang < POSE_TOL and dt < POSE_TOL, (ang, dt)
+    for l in range(3):
+        assert sg["levels"][l]["iters_run"] == so[l]["iters_run"]
+        assert sg["levels"][l]["status"] == so[l]["status"]
+
+
 def test_invalid_arguments(ctx):
     prob = synth.pair_problem(0)
     d, mv, mn = upload(prob)
