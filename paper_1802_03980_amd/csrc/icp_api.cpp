@@ -488,6 +488,10 @@ int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* r
                               (!prm->use_median_filter || prm->band_beta >= 1.0)
                           ? 1
                           : 0;
+    // one problem in single-pass mode: most iterations end in the band kernel,
+    // so the solve launch is folded into pass 2 (whose last work-group solves
+    // the iterations the window missed) and one launch per iteration goes
+    kp.fold_solve = fused && n == 1 ? 1 : 0;
     for (int l = prm->levels - 1; l >= 0; --l) {
         const int* owner = reinterpret_cast<const int*>(base + P.off_owner[l]);
         int64_t px = 0;
@@ -503,6 +507,7 @@ int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* r
             if ((rc = time_begin(ctx, s, r, ICP_TIME_PASS2, px))) return rc;
             HIP_TRY(ctx, icpk::launch_pass2(d_desc, owner, P.tiles[l], ctl, kp, s));
             if ((rc = time_end(ctx, s, r))) return rc;
+            if (kp.fold_solve) continue;
             if ((rc = time_begin(ctx, s, r, ICP_TIME_SOLVE, 0))) return rc;
             HIP_TRY(ctx, icpk::launch_solve(d_desc, n, ctl, kp, s));
             if ((rc = time_end(ctx, s, r))) return rc;

@@ -92,6 +92,7 @@ struct ProbState {
     int32_t settled;            // successive iterations with an unchanged median
     int32_t last_kmed;
     int32_t last_status;        // status of the last solve
+    int32_t ticket;             // pass-2 tiles finished this iteration (solve folded into pass 2)
     icp_stats stats;
     double cen[ICP_MAX_LEVELS][3];  // centroid of each level's valid live vertices
     double cur_c[3];            // centring point of the current iteration (model frame)
@@ -125,4 +126,6 @@ struct KParams {
     int32_t converge_window;
     int32_t reduce_mode;        // 0: FP32 rows; 1: FP16 hi+lo split MFMA on centred rows
     int32_t* need2;             // batch flag: some problem needs pass 2 this iteration (NULL: always run it)
+    int32_t fold_solve;         // one problem, single pass: no solve launch; the band kernel keeps the level's
+                                //   books and pass 2's last work-group solves an iteration the window missed
 };

@@ -43,6 +43,7 @@ __global__ __launch_bounds__(ICP_WG) void k_init(const ProbDesc* __restrict__ pr
         st->pred_hi = -1;
         st->pred_hw = ICP_WIN / 2;
         st->fused_done = 0;
+        st->ticket = 0;
         st->level_done = 0;
         st->settled = 0;
         st->last_kmed = -2;
@@ -679,6 +680,13 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
 
 // ------------------------------------------------------------------ epilogues
 
+// After a level's last scheduled iteration: the next level starts afresh.
+__device__ __forceinline__ void level_reset(ProbState* st) {
+    st->level_done = 0;
+    st->settled = 0;
+    st->last_kmed = -2;
+}
+
 // Regularised solve (Eq. (5)), pose update and per-level bookkeeping of one
 // problem; thread 0 only.
 __device__ void solve_epilogue(ProbState* st, const double* M, int64_t n, const IterCtl& ctl, const KParams& kp) {
@@ -839,7 +847,10 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     const LevelDesc& L = P.lv[ctl.level];
     ProbState* st = P.st;
     const int done = st->level_done, pred = st->pred_hi, pred_hw = st->pred_hw;  // loads in flight together
-    if (done) return;
+    if (done) {
+        if (kp.fold_solve && ctl.last_of_level && threadIdx.x == 0) level_reset(st);
+        return;
+    }
     const Win win = fused ? band_window(pred, pred_hw, ctl.iter) : Win{-1, 0};
     const int h0 = win.h0;
     const Band b = median_band(st, kp, dbg_hist);
@@ -855,6 +866,9 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
             st->pred_hw = next_half_width(b.k_hi, pred, ctl.iter);
             st->pred_hi = b.k_hi;
         }
+        // with the solve folded into pass 2, an iteration finished here also
+        // closes the level (pass 2 skips this problem: fused_done is set)
+        if (kp.fold_solve && hit && ctl.last_of_level) level_reset(st);
         if (kp.reduce_mode == 1) set_centre(st, ctl.level);
     }
 }
@@ -896,6 +910,28 @@ __global__ __launch_bounds__(ICP_WG) void k_pass2(const ProbDesc* __restrict__ p
         }
     }
     block_reduce_row(acc, cnt, sh_red, L.part + (size_t)tile * ICP_PART_STRIDE);
+    if (!kp.fold_solve) return;
+    // The solve folded into pass 2 (one problem): every thread's stores are
+    // made visible device-wide before the barrier, thread 0 takes a ticket,
+    // and the work-group that finishes last sums the partials in tile order,
+    // solves and keeps the level's books, as the solve kernel would.
+    __shared__ int sh_last;
+    __shared__ double sh_M[ICP_NMOM + 1];
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) sh_last = atomicAdd(&P.st->ticket, 1) == L.n_tiles - 1;
+    __syncthreads();
+    if (!sh_last) return;
+    __threadfence();
+    sum_partials(L.part, L.n_tiles, ICP_PART_STRIDE, 0, sh_M);
+    if (tid == 0) {
+        ProbState* sw = P.st;
+        solve_epilogue(sw, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp);
+        sw->ticket = 0;
+        sw->fused_done = 0;
+        *kp.need2 = 0;
+        if (ctl.last_of_level) level_reset(sw);
+    }
 }
 
 // Split-precision variant of pass 2 (reduce_mode 1): each kept row
@@ -1051,11 +1087,7 @@ __global__ __launch_bounds__(ICP_WG) void k_solve(const ProbDesc* __restrict__ p
     if (threadIdx.x == 0) {
         st->fused_done = 0;
         if (kp.need2 && blockIdx.x == 0) *kp.need2 = 0;  // pass 2 of this iteration has run
-        if (ctl.last_of_level) {
-            st->level_done = 0;
-            st->settled = 0;
-            st->last_kmed = -2;
-        }
+        if (ctl.last_of_level) level_reset(st);
     }
 }
 

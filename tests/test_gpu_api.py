@@ -6,8 +6,10 @@ calls and the context's workspace accounting.
     calls alternate between two streams.
   * With timing on, one registration records one front-end bracket and one
     launch of each iteration kind per iteration, covering the level pixels of
-    every iteration; switching timing on or off clears the totals; the traced
-    (eager) launches give the same pose as the untraced ones.
+    every iteration (a single problem in single-pass mode folds the solve
+    into pass 2: no solve launches, and the same pose bit for bit as in a
+    batch); switching timing on or off clears the totals; the traced (eager)
+    launches give the same pose as the untraced ones.
   * The context holds at least the workspace icp_workspace_bytes names for
     the batch it ran.
 """
@@ -89,12 +91,28 @@ def test_kernel_timing_counts_launches(ctx):
     level_px = [(W >> l) * (H >> l) for l in range(params.levels)]
     n_it = sum(iters)
     assert t["front_end"]["launches"] == 1 and t["front_end"]["pixels"] == W * H
-    for kind in ("pass1", "band", "pass2", "solve"):
+    for kind in ("pass1", "band", "pass2"):
         assert t[kind]["launches"] == n_it, (kind, t[kind])
         assert t[kind]["total_ms"] > 0.0, kind
+    # one problem in single-pass mode: the solve is folded into pass 2
+    assert t["solve"]["launches"] == 0
     px_it = sum(i * n for i, n in zip(iters, level_px))
     assert t["pass1"]["pixels"] == px_it and t["pass2"]["pixels"] == px_it
-    assert all(v["total_ms"] > 0.0 for v in t.values())
+    # a batch of two (and two-pass mode) launches the solve kernel every iteration
+    q = synth.RoomSequence(1, n_frames=3).problem(0)
+    dq = upload(q)
+    items = [dict(live_depth=a, model_vtx=b, model_nrm=c, K=pp.K, imu_R=pp.imu_R, init_pose=pp.init_pose)
+             for pp, (a, b, c) in ((p, (d, mv, mn)), (q, dq))]
+    icp.icp_ctx_set_timing(ctx, True)
+    try:
+        batch = icp.icp_register_batch(ctx, items, params)
+        icp.icp_register(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, icp.icp_params_default(pass_mode=1))
+        t2 = icp.icp_ctx_get_timing(ctx)
+    finally:
+        icp.icp_ctx_set_timing(ctx, False)
+    assert t2["solve"]["launches"] == 2 * n_it and t2["pass1"]["launches"] == 2 * n_it
+    # the batch's solve kernel and the folded solve give the same pose, bit for bit
+    assert np.array_equal(batch[0][0], T_graph)
     # switching off cleared the totals, and untraced calls add nothing
     icp.icp_register(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, params)
     assert all(v["launches"] == 0 and v["total_ms"] == 0.0 for v in icp.icp_ctx_get_timing(ctx).values())
