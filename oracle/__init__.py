@@ -47,7 +47,7 @@ class Params(C.Structure):
         ("lambda_c", C.c_double), ("min_corr", C.c_int), ("ill_cond_eps", C.c_double),
         ("converge_window", C.c_int), ("depth_filter", C.c_int), ("filter_radius", C.c_int),
         ("filter_sigma_px", C.c_double), ("filter_sigma_m", C.c_double), ("normal_mode", C.c_int),
-        ("normal_radius", C.c_int),
+        ("normal_radius", C.c_int), ("anchor_to_imu", C.c_int),
     ]
 
 
@@ -98,6 +98,9 @@ def lib():
         L.or_solve_update.argtypes = [P, C.c_int64, P, i, d, i, d, P, P]
         L.or_solve_update.restype = i
         L.or_se3_exp.argtypes = [P, P, P, P]
+        L.or_so3_log.argtypes = [P, P]
+        L.or_solve_update_anchor.argtypes = [P, C.c_int64, P, i, d, i, d, P, P, P]
+        L.or_solve_update_anchor.restype = i
         L.or_icp_register.argtypes = [P, i, i, P, P, P, P, P, C.POINTER(Params), P, P, P, i]
         L.or_icp_register.restype = i
         _lib = L
@@ -300,14 +303,25 @@ def moments(lvl, T, k_lo, k_hi, dist_max=0.10, cos_max=None):
     return M, int(n[0])
 
 
-def solve_update(M, n, T, lambda_mode=LAMBDA_CONST, lambda_c=5.0, min_corr=6, eps=1e-12):
+def solve_update(M, n, T, lambda_mode=LAMBDA_CONST, lambda_c=5.0, min_corr=6, eps=1e-12, imu_R=None):
+    """Regularised solve and update; with imu_R the damping is anchored to it."""
     Tout = np.zeros(12)
     x = np.zeros(6)
-    st = lib().or_solve_update(_p(_f64(M)), int(n), _p(pose12(T)), lambda_mode, lambda_c, min_corr, eps,
-                               _p(Tout), _p(x))
+    if imu_R is None:
+        st = lib().or_solve_update(_p(_f64(M)), int(n), _p(pose12(T)), lambda_mode, lambda_c, min_corr, eps,
+                                   _p(Tout), _p(x))
+    else:
+        st = lib().or_solve_update_anchor(_p(_f64(M)), int(n), _p(pose12(T)), lambda_mode, lambda_c, min_corr,
+                                          eps, _p(_f64(imu_R)), _p(Tout), _p(x))
     P = np.eye(4)
     P[:3, :4] = Tout.reshape(3, 4)
     return st, P, x
+
+
+def so3_log(R):
+    w = np.zeros(3)
+    lib().or_so3_log(_p(_f64(R)), _p(w))
+    return w
 
 
 def se3_exp(w, tau):

@@ -80,6 +80,7 @@ void or_params_default(or_params* p) {
     p->filter_sigma_m = 0.05;
     p->normal_mode = 0;
     p->normal_radius = 2;
+    p->anchor_to_imu = 0;
 }
 
 /* Level l pixel (u, v) averages level-(l-1) pixels 2u..2u+1, 2v..2v+1; its
@@ -755,6 +756,21 @@ void or_se3_exp(const double w[3], const double tau[3], double R[9], double t[3]
     for (int i = 0; i < 3; ++i) t[i] = (V[3 * i] * tau[0] + V[3 * i + 1] * tau[1]) + V[3 * i + 2] * tau[2];
 }
 
+/* Rotation vector w of R (|w| in [0, pi)): with v = (R32 - R23, R13 - R31,
+   R21 - R12) = 2 sin(th) u and trace(R) = 1 + 2 cos(th), th = atan2(|v| / 2,
+   (trace - 1) / 2) and w = th u; below |v| = 1e-12 the first-order w = v / 2. */
+void or_so3_log(const double R[9], double w[3]) {
+    double v[3] = {R[7] - R[5], R[2] - R[6], R[3] - R[1]};
+    double s = 0.5 * sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    double c = 0.5 * (((R[0] + R[4]) + R[8]) - 1.0);
+    if (s < 0.5e-12) {
+        for (int i = 0; i < 3; ++i) w[i] = 0.5 * v[i];
+        return;
+    }
+    double th = atan2(s, c);
+    for (int i = 0; i < 3; ++i) w[i] = v[i] * (th / (2.0 * s));
+}
+
 static double lambda_of(int mode, double c, int64_t n) {
     double nd = (double)n;
     switch (mode) {
@@ -769,9 +785,29 @@ static double lambda_of(int mode, double c, int64_t n) {
    i.e. solve (A^T A + 2 lambda n P^T P) x = A^T b.  The paper solves the 6x6
    system by SVD on the host; for this symmetric positive definite system an
    LDL^T factorisation gives the same x and flags a singular system by its
-   pivots.  The increment is then composed on the left of the pose. */
+   pivots.  The increment is then composed on the left of the pose.
+   Anchored to the IMU (imu_R not NULL): the damped quantity is the rotation's
+   deviation after the update, w + d with d = Log(R_in imu_R^T) (first order in
+   w, since R_new = Exp(w) R_in), so the right-hand side becomes
+   A^T b - 2 lambda n P^T d; lambda = 0 leaves plain ICP in both forms. */
+static int solve_update_core(const double M[28], int64_t n, const double T_in[12], int lambda_mode,
+                             double lambda_c, int min_corr, double eps, const double* imu_R, double T_out[12],
+                             double x[6]);
+
 int or_solve_update(const double M[28], int64_t n, const double T_in[12], int lambda_mode, double lambda_c,
                     int min_corr, double eps, double T_out[12], double x[6]) {
+    return solve_update_core(M, n, T_in, lambda_mode, lambda_c, min_corr, eps, NULL, T_out, x);
+}
+
+int or_solve_update_anchor(const double M[28], int64_t n, const double T_in[12], int lambda_mode,
+                           double lambda_c, int min_corr, double eps, const double imu_R[9], double T_out[12],
+                           double x[6]) {
+    return solve_update_core(M, n, T_in, lambda_mode, lambda_c, min_corr, eps, imu_R, T_out, x);
+}
+
+static int solve_update_core(const double M[28], int64_t n, const double T_in[12], int lambda_mode,
+                             double lambda_c, int min_corr, double eps, const double* imu_R, double T_out[12],
+                             double x[6]) {
     memcpy(T_out, T_in, 12 * sizeof(double));
     for (int k = 0; k < 6; ++k) x[k] = 0.0;
     if (n < min_corr) return OR_TOO_FEW_CORR;
@@ -782,6 +818,15 @@ int or_solve_update(const double M[28], int64_t n, const double T_in[12], int la
     }
     double lam = lambda_of(lambda_mode, lambda_c, n);
     for (int i = 0; i < 3; ++i) Hm[i][i] += 2.0 * lam * (double)n;
+    if (imu_R) {
+        double Dv[9], dw[3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) /* R_in imu_R^T */
+                Dv[3 * i + j] = (T_in[4 * i] * imu_R[3 * j] + T_in[4 * i + 1] * imu_R[3 * j + 1]) +
+                                T_in[4 * i + 2] * imu_R[3 * j + 2];
+        or_so3_log(Dv, dw);
+        for (int i = 0; i < 3; ++i) g[i] -= 2.0 * lam * (double)n * dw[i];
+    }
     double maxdiag = 0.0;
     for (int i = 0; i < 6; ++i) maxdiag = Hm[i][i] > maxdiag ? Hm[i][i] : maxdiag;
     double L[6][6] = {{0}}, d[6];
@@ -887,7 +932,8 @@ int or_icp_register(const float* depth, int W, int H, const float* model_vtx, co
                            (int)band[2], (int)band[3], M, &n);
             else
                 memset(M, 0, sizeof(M));
-            int status = or_solve_update(M, n, T, p->lambda_mode, p->lambda_c, p->min_corr, p->ill_cond_eps, Tn, x);
+            int status = solve_update_core(M, n, T, p->lambda_mode, p->lambda_c, p->min_corr, p->ill_cond_eps,
+                                           p->anchor_to_imu ? imu_R : NULL, Tn, x);
             st->iters_run = it + 1;
             st->status = status;
             st->n_gated = band[0];

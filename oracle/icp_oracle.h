@@ -68,6 +68,8 @@ typedef struct {
     double filter_sigma_m;      /* range kernel cut-off, metres */
     int normal_mode;            /* 0: forward differences; 1: box-average 3D gradients */
     int normal_radius;          /* the boxes of normal_mode 1 span (2r+1) pixels */
+    int anchor_to_imu;          /* 0: Eq. (5) damps each increment's angles (literal);
+                                   1: it damps the deviation from the IMU rotation */
 } or_params;
 
 typedef struct {
@@ -125,6 +127,12 @@ void or_moments(const float* LV, const float* LN, const float* MV, const float* 
 int or_solve_update(const double M[28], int64_t n, const double T_in[12], int lambda_mode,
                     double lambda_c, int min_corr, double eps, double T_out[12], double x[6]);
 void or_se3_exp(const double w[3], const double tau[3], double R[9], double t[3]);
+/* rotation vector of a rotation matrix (angle in [0, pi)) */
+void or_so3_log(const double R[9], double w[3]);
+/* or_solve_update with the damping anchored to the IMU rotation imu_R */
+int or_solve_update_anchor(const double M[28], int64_t n, const double T_in[12], int lambda_mode,
+                           double lambda_c, int min_corr, double eps, const double imu_R[9],
+                           double T_out[12], double x[6]);
 
 /* TSDF volume (the model the tracking aligns to, Sec. 5.2: a 512^3 cube of at
    most 6 m).  dim^3 voxels of side size/dim, voxel (i, j, k) (i fastest) centred

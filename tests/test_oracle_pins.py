@@ -436,6 +436,70 @@ def test_large_lambda_pins_rotation_to_imu():
     assert np.linalg.norm(tr[-1]["x"][:3]) < 1e-12
 
 
+def test_so3_log_inverts_the_exponential():
+    """P20: the rotation vector of Exp(w) is w again, from 1e-13 rad to nearly
+    pi, and agrees with scipy's rotation vector of the same matrix."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(20)
+    for ang in [0.0, 1e-13, 1e-9, 1e-5, 0.01, 0.3, 1.0, 2.0, 3.1]:
+        ax = rng.normal(size=3)
+        w = ax / np.linalg.norm(ax) * ang
+        R, _ = oracle.se3_exp(w, np.zeros(3))
+        v = oracle.so3_log(R)
+        assert np.abs(v - w).max() <= 1e-14 * max(1.0, ang) + 1e-300, (ang, v, w)
+        assert np.abs(v - Rotation.from_matrix(R).as_rotvec()).max() <= 1e-14, ang
+
+
+def test_anchored_regulariser_stationarity():
+    """P21: with the damping anchored to the IMU rotation (the reading that
+    penalises the deviation w + Log(R imu_R^T) instead of each increment w),
+    the iteration converges to the point where the moments' rotation rows
+    equal 2 lambda n Log(R imu_R^T) and the translation rows vanish: the
+    stationarity condition of (1/2n)|Ax - b|^2 + lambda |w + d|^2 at x = 0.
+    Lambda = 0 leaves plain ICP, identical to the literal form."""
+    prob = synth.pair_problem(3, noise=False)
+    lam = 50.0
+    p = oracle.default_params(levels=1, iters=[60], lambda_c=lam, anchor_to_imu=1)
+    pose, st, tr = oracle.register_problem(prob, p)
+    assert st[0]["status"] == oracle.LEVEL_OK and np.abs(tr[-1]["x"]).max() < 1e-12
+    lv = oracle.pyramids(prob.live_depth, prob.model_vtx, prob.model_nrm, prob.K, 1)[0]
+    _, _, _, hist = oracle.associate(lv, pose)
+    _, _, klo, khi = oracle.band(hist)
+    M, n = oracle.moments(lv, pose, klo, khi)
+    g = np.array([M[oracle.tri_index(i, 6)] for i in range(6)])
+    d = oracle.so3_log(pose[:3, :3] @ prob.imu_R.T)
+    assert np.linalg.norm(g[:3]) > 1.0  # a real balance between the data and the prior
+    assert np.abs(g[:3] - 2.0 * lam * n * d).max() < 1e-9 * np.abs(g[:3]).max()
+    assert np.abs(g[3:]).max() < 1e-9 * np.abs(g[:3]).max()
+    # the literal form with the same lambda ends farther from the IMU rotation
+    pl, _, _ = oracle.register_problem(prob, oracle.default_params(levels=1, iters=[60], lambda_c=lam))
+    assert rot_angle(pose[:3, :3] @ prob.imu_R.T) < 0.2 * rot_angle(pl[:3, :3] @ prob.imu_R.T)
+    # lambda = 0: the anchor has no weight
+    a0, _, _ = oracle.register_problem(prob, oracle.default_params(lambda_c=0.0, anchor_to_imu=1))
+    l0, _, _ = oracle.register_problem(prob, oracle.default_params(lambda_c=0.0))
+    assert np.array_equal(a0, l0)
+    # the one-step solve: anchored right-hand side against lstsq of the stacked system
+    T0 = np.eye(4)
+    T0[:3, :3] = prob.imu_R @ synth.rot_from_rotvec([0.01, -0.02, 0.015])
+    code, bins, pp, q, nq = oracle.pairs(lv, T0)
+    keep = code.reshape(-1) == 6
+    A = np.hstack([np.cross(pp[keep], nq[keep]), nq[keep]])
+    b = np.einsum("ij,ij->i", nq[keep], q[keep] - pp[keep])
+    nk = int(keep.sum())
+    Mk = np.zeros(28)
+    Ab = np.hstack([A, b[:, None]])
+    for i in range(7):
+        for j in range(i, 7):
+            Mk[oracle.tri_index(i, j)] = Ab[:, i] @ Ab[:, j]
+    _, _, x = oracle.solve_update(Mk, nk, T0, lambda_c=lam, imu_R=prob.imu_R)
+    d0 = oracle.so3_log(T0[:3, :3] @ prob.imu_R.T)
+    s = np.sqrt(2.0 * lam * nk)
+    A_st = np.vstack([A, np.hstack([s * np.eye(3), np.zeros((3, 3))])])
+    b_st = np.concatenate([b, -s * d0])
+    x_ls = np.linalg.lstsq(A_st, b_st, rcond=None)[0]
+    assert np.abs(x - x_ls).max() < 1e-9 * np.abs(x_ls).max()
+
+
 def test_lambda_zero_corrects_imu_error():
     """Sec. 4.1: without regularisation the IMU error is corrected; with a large
     lambda the IMU rotation is kept."""
