@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define ICP_ABI_VERSION 3
+#define ICP_ABI_VERSION 4
 #define ICP_MAX_LEVELS 4
 #define ICP_MAX_DIM 8192
 #define ICP_HIST_BINS 1024 /* distance histogram: bins of 2^-13 m over [0, 0.125) m */
@@ -130,6 +130,13 @@ typedef struct {
                                        lower minus upper); needs a valid pixel, the box inside the
                                        image and half of each half box valid */
     int32_t normal_radius;          /* 1..7 (default 2) */
+    /* regulariser (Eq. (5)) */
+    int32_t anchor_to_imu;          /* 0 (default): damp the angles w of each increment, as Eq. (5)
+                                       reads; 1: damp the rotation's deviation from the IMU prior
+                                       after the update, w + Log(R imu_R^T): the right-hand side
+                                       becomes A^T b - 2 lambda n [Log(R imu_R^T); 0] (not for
+                                       icp_stage_solve, which has no IMU prior) */
+    int32_t reserved;               /* 0 */
 } icp_params;
 
 typedef struct {

@@ -18,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libicp_mi355x.so")
 
-ICP_ABI_VERSION = 3
+ICP_ABI_VERSION = 4
 MAX_LEVELS = 4
 HIST_BINS = 1024
 OK, EINVAL, ENOMEM, EDEVICE, ETIMEOUT = 0, -1, -2, -3, -4
@@ -64,6 +64,7 @@ class icp_params(C.Structure):
         ("reduce_mode", C.c_int32), ("pass_mode", C.c_int32), ("tile_px", C.c_int32 * MAX_LEVELS),
         ("depth_filter", C.c_int32), ("filter_radius", C.c_int32), ("filter_sigma_px", C.c_double),
         ("filter_sigma_m", C.c_double), ("normal_mode", C.c_int32), ("normal_radius", C.c_int32),
+        ("anchor_to_imu", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

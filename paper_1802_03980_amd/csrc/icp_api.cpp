@@ -110,6 +110,7 @@ int check_params(icp_ctx* ctx, const icp_params* p) {
     if (p->normal_mode != 0 && p->normal_mode != 1) return fail(ctx, ICP_EINVAL, "normal_mode must be 0 or 1");
     if (p->normal_mode == 1 && (p->normal_radius < 1 || p->normal_radius > ICP_FILTER_MAX_R))
         return fail(ctx, ICP_EINVAL, "normal_radius must be in 1..7");
+    if (p->anchor_to_imu != 0 && p->anchor_to_imu != 1) return fail(ctx, ICP_EINVAL, "anchor_to_imu must be 0 or 1");
     return ICP_OK;
 }
 
@@ -337,6 +338,7 @@ KParams kparams(const icp_params* p) {
     k.min_corr = p->min_corr;
     k.converge_window = p->converge_window;
     k.reduce_mode = p->reduce_mode;
+    k.anchor_to_imu = p->anchor_to_imu;
     return k;
 }
 
@@ -605,6 +607,8 @@ void icp_params_default(icp_params* p) {
     p->filter_sigma_m = 0.05;
     p->normal_mode = 0;
     p->normal_radius = 2;
+    p->anchor_to_imu = 0;
+    p->reserved = 0;
 }
 
 int icp_ctx_create(int device, size_t hbm_budget_bytes, icp_ctx** out) {
@@ -1049,6 +1053,7 @@ int icp_stage_solve(icp_ctx* ctx, const double* moments, int64_t n, const double
     if (!moments || !pose12_in || !pose12_out) return fail(ctx, ICP_EINVAL, "NULL argument");
     int rc = check_params(ctx, params);
     if (rc) return rc;
+    if (params->anchor_to_imu) return fail(ctx, ICP_EINVAL, "the stage solve has no IMU prior: anchor_to_imu must be 0");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     StreamTurn turn;

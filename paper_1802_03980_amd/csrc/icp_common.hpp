@@ -126,6 +126,7 @@ struct KParams {
     int32_t converge_window;
     int32_t reduce_mode;        // 0: FP32 rows; 1: FP16 hi+lo split MFMA on centred rows
     int32_t* need2;             // batch flag: some problem needs pass 2 this iteration (NULL: always run it)
+    int32_t anchor_to_imu;      // the damping acts on the deviation from the IMU rotation
     int32_t fold_solve;         // one problem, single pass: no solve launch; the band kernel keeps the level's
                                 //   books and pass 2's last work-group solves an iteration the window missed
 };

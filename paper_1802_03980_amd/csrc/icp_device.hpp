@@ -377,7 +377,27 @@ __device__ __forceinline__ int tri7(int i, int j) { return i * 7 - i * (i - 1) /
 // Regularised normal equations of Eq. (5): (A^T A + 2 lambda n P^T P) x = A^T b,
 // P = [I3 | 0], solved by LDL^T (the system is symmetric positive definite
 // whenever it is solvable).  Returns an ICP_LEVEL_* status.
-__device__ inline int solve_regularised(const double* M, int64_t n, const KParams& kp, double* x) {
+// Rotation vector of a rotation matrix (angle in [0, pi)): v = (R32 - R23,
+// R13 - R31, R21 - R12) has length 2 sin(th) and trace(R) = 1 + 2 cos(th),
+// so th = atan2(|v| / 2, (trace - 1) / 2) and the vector is v th / (2 sin th)
+// (v / 2 when |v| is below 1e-12).
+__device__ inline void rotation_vector(const double* R, double* w) {
+    const double v0 = R[7] - R[5], v1 = R[2] - R[6], v2 = R[3] - R[1];
+    const double s = 0.5 * sqrt((v0 * v0 + v1 * v1) + v2 * v2);
+    const double c = 0.5 * (((R[0] + R[4]) + R[8]) - 1.0);
+    const double f = s < 0.5e-12 ? 0.5 : atan2(s, c) / (2.0 * s);
+    w[0] = v0 * f;
+    w[1] = v1 * f;
+    w[2] = v2 * f;
+}
+
+// Eq. (4)/(5): (A^T A + 2 lambda n P^T P) x = A^T b, LDL^T in FP64.  With the
+// damping anchored to the IMU prior (kp.anchor_to_imu, imu_R given), the
+// damped angles are those of the deviation after the update, w + d with
+// d = Log(R imu_R^T), R the rotation before it: the right-hand side loses
+// 2 lambda n d in its rotation rows.
+__device__ inline int solve_regularised(const double* M, int64_t n, const KParams& kp, const double* R,
+                                        const double* imu_R, double* x) {
     for (int k = 0; k < 6; ++k) x[k] = 0.0;
     if (n < kp.min_corr) return ICP_TOO_FEW_CORR;
     double A[6][6], g[6];
@@ -391,6 +411,14 @@ __device__ inline int solve_regularised(const double* M, int64_t n, const KParam
     else if (kp.lambda_mode == ICP_LAMBDA_C_OVER_N) lam = kp.lambda_c / nd;
     else if (kp.lambda_mode == ICP_LAMBDA_C_OVER_N2) lam = kp.lambda_c / (nd * nd);
     for (int i = 0; i < 3; ++i) A[i][i] += 2.0 * lam * nd;
+    if (kp.anchor_to_imu && imu_R) {
+        double Dv[9], d[3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)  // R imu_R^T
+                Dv[3 * i + j] = (R[3 * i] * imu_R[3 * j] + R[3 * i + 1] * imu_R[3 * j + 1]) + R[3 * i + 2] * imu_R[3 * j + 2];
+        rotation_vector(Dv, d);
+        for (int i = 0; i < 3; ++i) g[i] -= 2.0 * lam * nd * d[i];
+    }
     double dmax = 0.0;
     for (int i = 0; i < 6; ++i) dmax = A[i][i] > dmax ? A[i][i] : dmax;
     // A = L D L^T, L unit lower triangular (stored below the diagonal of A)

@@ -689,13 +689,14 @@ __device__ __forceinline__ void level_reset(ProbState* st) {
 
 // Regularised solve (Eq. (5)), pose update and per-level bookkeeping of one
 // problem; thread 0 only.
-__device__ void solve_epilogue(ProbState* st, const double* M, int64_t n, const IterCtl& ctl, const KParams& kp) {
+__device__ void solve_epilogue(ProbState* st, const double* M, int64_t n, const IterCtl& ctl, const KParams& kp,
+                               const double* imu_R) {
     if (st->level_done) return;
     for (int k = 0; k < ICP_NMOM; ++k) st->M[k] = M[k];
     st->n_last = n;
     if (ctl.no_update) return;
     double x[6];
-    const int status = solve_regularised(M, n, kp, x);
+    const int status = solve_regularised(M, n, kp, st->R, imu_R, x);
     if (status == ICP_LEVEL_OK) compose_exp(x, st->R, st->t);
     for (int k = 0; k < 6; ++k) st->x[k] = x[k];
     st->last_status = status;
@@ -857,7 +858,7 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     const bool hit = h0 >= 0 && b.N > 0 && b.k_lo == 0 && b.k_hi >= h0 - 1 && b.k_hi <= h0 + win.w - 1;
     if (hit) {
         sum_partials(L.part1, L.n_tiles, ICP_WIN_SLOTS * ICP_PART_STRIDE, b.k_hi - h0 + 1, sh_M);
-        if (threadIdx.x == 0) solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp);
+        if (threadIdx.x == 0) solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
     }
     if (threadIdx.x == 0) {
         st->fused_done = hit ? 1 : 0;
@@ -877,7 +878,8 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
 // Filter (kept iff gated and its bin lies in the band) and the 28-moment
 // reduction of the kept rows into one partial per tile.
 
-__global__ __launch_bounds__(ICP_WG) void k_pass2(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
+__global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(4))) void k_pass2(
+    const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
                                                   IterCtl ctl, KParams kp) {
     // every problem of the batch finished its iteration in the band kernel
     if (kp.need2 && __builtin_amdgcn_readfirstlane(*kp.need2) == 0) return;
@@ -926,7 +928,7 @@ __global__ __launch_bounds__(ICP_WG) void k_pass2(const ProbDesc* __restrict__ p
     sum_partials(L.part, L.n_tiles, ICP_PART_STRIDE, 0, sh_M);
     if (tid == 0) {
         ProbState* sw = P.st;
-        solve_epilogue(sw, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp);
+        solve_epilogue(sw, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
         sw->ticket = 0;
         sw->fused_done = 0;
         *kp.need2 = 0;
@@ -1081,7 +1083,7 @@ __global__ __launch_bounds__(ICP_WG) void k_solve(const ProbDesc* __restrict__ p
         sum_partials(L.part, L.n_tiles, ICP_PART_STRIDE, 0, sh_M);
         if (threadIdx.x == 0) {
             if (kp.reduce_mode == 1) uncentre(sh_M, st->cur_c);
-            solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp);
+            solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
         }
     }
     if (threadIdx.x == 0) {
@@ -1134,7 +1136,7 @@ __global__ void k_stage_solve(MomArg M, int64_t n, PoseArg pose, KParams kp, dou
         for (int j = 0; j < 3; ++j) R[3 * i + j] = pose.v[4 * i + j];
         t[i] = pose.v[4 * i + 3];
     }
-    const int status = solve_regularised(M.m, n, kp, x);
+    const int status = solve_regularised(M.m, n, kp, R, nullptr, x);
     if (status == ICP_LEVEL_OK) compose_exp(x, R, t);
     for (int i = 0; i < 3; ++i) {
         for (int j = 0; j < 3; ++j) out[4 * i + j] = R[3 * i + j];

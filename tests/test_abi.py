@@ -42,7 +42,7 @@ def test_library_loads_and_host_calls():
     assert L.icp_strerror(icp.EINVAL) == b"invalid argument"
     p = icp.icp_params_default()
     assert p.levels == 3 and list(p.iters[:3]) == [10, 5, 4]
-    assert p.lambda_c == 5.0 and p.use_imu_seed == 1 and p.use_median_filter == 1
+    assert p.lambda_c == 5.0 and p.use_imu_seed == 1 and p.use_median_filter == 1 and p.anchor_to_imu == 0
     assert abs(p.cos_angle_max - np.cos(np.radians(20))) < 1e-15
 
 

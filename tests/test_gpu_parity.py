@@ -236,7 +236,8 @@ def _oracle_params(p):
                                  ill_cond_eps=p.ill_cond_eps, converge_window=p.converge_window,
                                  depth_filter=p.depth_filter, filter_radius=p.filter_radius,
                                  filter_sigma_px=p.filter_sigma_px, filter_sigma_m=p.filter_sigma_m,
-                                 normal_mode=p.normal_mode, normal_radius=p.normal_radius)
+                                 normal_mode=p.normal_mode, normal_radius=p.normal_radius,
+                                 anchor_to_imu=p.anchor_to_imu)
 
 
 def _register_both(ctx, prob, params):
@@ -414,6 +415,31 @@ def test_edge_cases(ctx):
     assert np.array_equal(Tg[:3, :3], prob.imu_R) and sg["iters_total"] == 0
 
 
+@pytest.mark.parametrize("lam", [5.0, 50.0])
+def test_end_to_end_anchored_regulariser(ctx, lam):
+    """The regulariser anchored to the IMU rotation (the damped angles are
+    those of w + Log(R imu_R^T)) reaches the oracle's pose one problem per
+    call (the solve folded into pass 2) and in a batch (the solve kernel),
+    and it differs from the literal form."""
+    params = icp.icp_params_default(anchor_to_imu=1, lambda_c=lam)
+    seq = synth.RoomSequence(0, n_frames=3)
+    probs = [synth.pair_problem(1), synth.pair_problem(2), seq.problem(0)]
+    data = [upload(p) for p in probs]
+    items = []
+    for p, (d, mv, mn) in zip(probs, data):
+        Tg, sg = icp.icp_register(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, params)
+        To, so, _ = oracle.register_problem(p, _oracle_params(params))
+        ang, dt = pose_err(Tg, To)
+        assert ang < POSE_TOL and dt < POSE_TOL, (p.name, ang, dt)
+        Tl, _ = icp.icp_register(ctx, d, mv, mn, p.K, p.imu_R, p.init_pose, icp.icp_params_default(lambda_c=lam))
+        assert pose_err(Tg, Tl)[0] > 1e-7, p.name
+        items.append(dict(live_depth=d, model_vtx=mv, model_nrm=mn, K=p.K, imu_R=p.imu_R, init_pose=p.init_pose))
+    for p, (Tb, sb) in zip(probs, icp.icp_register_batch(ctx, items, params)):
+        To, so, _ = oracle.register_problem(p, _oracle_params(params))
+        ang, dt = pose_err(Tb, To)
+        assert ang < POSE_TOL and dt < POSE_TOL, ("batch", p.name, ang, dt)
+
+
 def test_band_edge_at_either_end_of_the_histogram(ctx):
     """Model maps 9 cm behind the live frame (dist_max 12.5 cm): the first band
     edge clamps at the last bin, the next iteration's window sits at the top of
@@ -453,11 +479,15 @@ def test_invalid_arguments(ctx):
     with pytest.raises(ValueError):  # model maps smaller than the frame never reach the library
         icp.icp_register(ctx, d, mv[:, :156].contiguous(), mn, prob.K, prob.imu_R, prob.init_pose)
     for bad in [dict(levels=0), dict(levels=5), dict(dist_max=0.2), dict(lambda_mode=9), dict(lambda_c=-1.0),
+                dict(anchor_to_imu=2),
                 dict(tile_px=(100, 0, 0)), dict(reduce_mode=2), dict(depth_filter=1, filter_radius=8),
                 dict(normal_mode=2), dict(normal_mode=1, normal_radius=0)]:
         with pytest.raises(icp.IcpError) as e:
             icp.icp_register(ctx, d, mv, mn, prob.K, prob.imu_R, prob.init_pose, icp.icp_params_default(**bad))
         assert e.value.code == icp.EINVAL, bad
+    with pytest.raises(icp.IcpError) as e:  # the stage solve has no IMU prior to anchor to
+        icp.icp_stage_solve(ctx, np.zeros(28), 100, np.eye(4), icp.icp_params_default(anchor_to_imu=1))
+    assert e.value.code == icp.EINVAL
     small = icp.icp_ctx_create(0, hbm_budget_bytes=1 << 16)
     with pytest.raises(icp.IcpError) as e:
         icp.icp_register(small, d, mv, mn, prob.K, prob.imu_R, prob.init_pose)

@@ -44,7 +44,8 @@ def _oracle_params(p):
                                  ill_cond_eps=p.ill_cond_eps, converge_window=p.converge_window,
                                  depth_filter=p.depth_filter, filter_radius=p.filter_radius,
                                  filter_sigma_px=p.filter_sigma_px, filter_sigma_m=p.filter_sigma_m,
-                                 normal_mode=p.normal_mode, normal_radius=p.normal_radius)
+                                 normal_mode=p.normal_mode, normal_radius=p.normal_radius,
+                                 anchor_to_imu=p.anchor_to_imu)
 
 
 def _interleave(V, N):
