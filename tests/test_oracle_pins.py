@@ -237,6 +237,36 @@ def test_band_median_matches_partition():
     assert (klo, khi) == (0, oracle.BINS - 1)
 
 
+def test_band_properties_over_beta():
+    """For any histogram and any band factor beta >= 0 the band contains the
+    median bin, beta = 0 keeps exactly the median bin, beta >= 1 starts at bin
+    0, and the kept count never shrinks as beta grows (hypothesis-generated
+    histograms)."""
+    from hypothesis import given, settings, strategies as st
+
+    @settings(max_examples=150, deadline=None)
+    @given(st.lists(st.integers(0, oracle.BINS - 1), min_size=1, max_size=400),
+           st.lists(st.floats(0.0, 3.0, allow_nan=False), min_size=2, max_size=6))
+    def check(samples, betas):
+        hist = np.bincount(samples, minlength=oracle.BINS).astype(np.uint32)
+        cdf = np.cumsum(hist)
+        kept_prev = -1
+        for beta in sorted(betas):
+            N, kmed, klo, khi = oracle.band(hist, 1, beta)
+            assert N == len(samples) and klo <= kmed <= khi <= oracle.BINS - 1
+            if beta == 0.0:
+                assert klo == kmed == khi
+            if beta >= 1.0:
+                assert klo == 0
+            kept = int(cdf[khi] - (cdf[klo - 1] if klo > 0 else 0))
+            assert kept >= kept_prev and kept >= int(hist[kmed]) > 0
+            kept_prev = kept
+        N, kmed, klo, khi = oracle.band(hist, 1, 0.0)
+        assert cdf[kmed] >= (N + 1) // 2 and (kmed == 0 or cdf[kmed - 1] < (N + 1) // 2)
+
+    check()
+
+
 # --------------------------------------------------------------- association
 
 def _tiny_level(W=24, H=18, f=20.0, seed=3, T=None):
