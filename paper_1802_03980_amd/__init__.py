@@ -123,8 +123,13 @@ def lib():
     if _lib is None:
         import torch  # noqa: F401  (loads torch's HIP runtime first)
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
-                              "python paper_1802_03980_amd/build.py")
+            # nothing built yet: compile it in-tree (hipcc for gfx950); a failed
+            # build is an error, there is no other implementation to fall back on
+            from . import build as _build
+            try:
+                _build.build()
+            except Exception as e:
+                raise ImportError(f"{LIB_PATH} is not built and building it failed: {e}") from e
         L = C.CDLL(LIB_PATH)
         P, I, D, Z = C.c_void_p, C.c_int, C.c_double, C.c_size_t
         sig = {
