@@ -586,10 +586,16 @@ def sweep_main(args):
     forms = [("c", icp.LAMBDA_CONST, c) for c in (0.0, 1.0, 5.0, 25.0, 100.0)]
     forms += [("c/sqrt(n)", icp.LAMBDA_C_OVER_SQRT_N, 500.0), ("c/n", icp.LAMBDA_C_OVER_N, 5.0e4),
               ("c/n^2", icp.LAMBDA_C_OVER_N2, 5.0e8)]
+    forms = [(name, mode, c, 0) for name, mode, c in forms]
+    # the reading that anchors the damping to the IMU rotation (Eq. (5) damps
+    # each increment; anchored, it damps the deviation from the IMU prior)
+    forms += [("c", icp.LAMBDA_CONST, c, 1) for c in (1.0, 5.0, 25.0, 100.0)]
     lam = []
-    for name, mode, c in forms:
-        e = errors(icp.icp_register_batch(ctx, items, icp.icp_params_default(lambda_mode=mode, lambda_c=c)), rps)
-        r = {"form": name, "c": c, "rmse_rot_deg": round(float(np.sqrt(np.mean(e[:, 0] ** 2))), 5),
+    for name, mode, c, anchor in forms:
+        e = errors(icp.icp_register_batch(ctx, items, icp.icp_params_default(lambda_mode=mode, lambda_c=c,
+                                                                            anchor_to_imu=anchor)), rps)
+        r = {"form": name, "c": c, "anchor_to_imu": anchor,
+             "rmse_rot_deg": round(float(np.sqrt(np.mean(e[:, 0] ** 2))), 5),
              "rmse_trans_m": round(float(np.sqrt(np.mean(e[:, 1] ** 2))), 6),
              "max_rot_deg": round(float(e[:, 0].max()), 4), "max_trans_m": round(float(e[:, 1].max()), 5)}
         log(f"  {r}")
@@ -597,7 +603,9 @@ def sweep_main(args):
     print(json.dumps({"workload": "robustness sweeps", "angular": angular, "lambda_forms": lam,
                       "notes": "failure = rotation error > 5 deg or translation error > 5 cm against the true "
                                "motion; IMU prior 0.5 deg off the truth; lambda errors are per-frame "
-                               f"frame-to-model errors against the true motion over {len(rps)} room registrations"}),
+                               f"frame-to-model errors against the true motion over {len(rps)} room registrations; "
+                               "anchor_to_imu = 1 damps the deviation from the IMU rotation instead of each "
+                               "increment"}),
           flush=True)
 
 
