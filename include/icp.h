@@ -242,6 +242,15 @@ int icp_register_async(icp_ctx* ctx, const float* live_depth, int W, int H, cons
 int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params,
                        icp_result* results, void* stream);
 
+/* Same as icp_register_batch but asynchronous: results_dev is a device array
+   of n icp_result written by the stream; nothing is synchronised.  The call
+   returns once the batch's launches are queued (it waits only until the
+   previous call's descriptors have left the context's staging memory), so a
+   caller can prepare the next batch while this one runs; calls on one context
+   still run one after another on the device. */
+int icp_register_batch_async(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params,
+                             icp_result* results_dev, void* stream);
+
 /* Tile-size autotuner for a batch: for each level, coarsest first, time the
    whole batched registration (HIP events on `stream`, `reps` runs each, the
    median) for every tile size in {1024, 2048, 4096, 8192, 16384} with the

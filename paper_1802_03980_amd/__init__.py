@@ -30,7 +30,7 @@ PX_INVALID_LIVE, PX_BEHIND, PX_OUTSIDE, PX_INVALID_MODEL, PX_FAR, PX_ANGLE, PX_G
 EXPORTS = (
     "icp_abi_version", "icp_strerror", "icp_last_error", "icp_ctx_create", "icp_ctx_destroy",
     "icp_ctx_workspace_bytes", "icp_workspace_bytes", "icp_params_default", "icp_register",
-    "icp_register_async", "icp_register_batch", "icp_ctx_set_timing", "icp_ctx_get_timing", "icp_ctx_set_graphs",
+    "icp_register_async", "icp_register_batch", "icp_register_batch_async", "icp_ctx_set_timing", "icp_ctx_get_timing", "icp_ctx_set_graphs",
     "icp_stage_prepare", "icp_stage_level",
     "icp_stage_associate", "icp_stage_moments", "icp_stage_solve", "icp_live_maps", "icp_autotune_tiles",
     "icp_server_config_default", "icp_server_clock", "icp_server_create", "icp_server_destroy",
@@ -146,6 +146,7 @@ def lib():
             "icp_register_async": (I, [P, P, I, I, P, P, C.POINTER(icp_intrinsics), P, P,
                                        C.POINTER(icp_params), P, P]),
             "icp_register_batch": (I, [P, I, P, C.POINTER(icp_params), P, P]),
+            "icp_register_batch_async": (I, [P, I, P, C.POINTER(icp_params), P, P]),
             "icp_ctx_set_timing": (I, [P, I]),
             "icp_ctx_set_graphs": (I, [P, I]),
             "icp_ctx_get_timing": (I, [P, P]),
@@ -369,6 +370,29 @@ def icp_register_batch(ctx, problems, params=None, stream=None):
                                   _stream(stream))
     _check(ctx, rc)
     return [(np.array(r.pose[:]).reshape(4, 4), stats_to_dict(r.stats, p.levels)) for r in res]
+
+
+def icp_register_batch_async(ctx, problems, results_dev, params=None, stream=None):
+    """Queue a batched registration on the stream and return: results_dev is
+    a uint8 device tensor of at least n * sizeof(icp_result) bytes that the
+    stream fills (decode with results_from_bytes once it has finished).  The
+    problems' tensors and results_dev must stay alive until then."""
+    p = params if params is not None else icp_params_default()
+    if isinstance(problems, ProblemArray):
+        n, arr = problems.n, problems.arr
+    else:
+        n, arr = len(problems), _problem_array(problems)
+    if results_dev.numel() * results_dev.element_size() < n * C.sizeof(icp_result):
+        raise ValueError("results_dev too small")
+    rc = lib().icp_register_batch_async(ctx.handle, n, C.cast(arr, C.c_void_p), C.byref(p),
+                                        C.c_void_p(results_dev.data_ptr()), _stream(stream))
+    _check(ctx, rc)
+
+
+def results_from_bytes(buf, n, levels=MAX_LEVELS):
+    """Decode n consecutive icp_result records from host bytes: [(pose, stats)]."""
+    arr = (icp_result * n).from_buffer_copy(bytes(buf)[:n * C.sizeof(icp_result)])
+    return [(np.array(r.pose[:]).reshape(4, 4), stats_to_dict(r.stats, levels)) for r in arr]
 
 
 def icp_autotune_tiles(ctx, problems, params=None, reps=3, stream=None):

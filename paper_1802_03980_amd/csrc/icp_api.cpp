@@ -531,6 +531,9 @@ int execute(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, hipStream_t s) 
     const int64_t* pw = reinterpret_cast<const int64_t*>(prm);
     for (size_t k = 0; k < sizeof(icp_params) / sizeof(int64_t); ++k) key.push_back(pw[k]);
     if (key != ctx->graph_key) {
+        // an asynchronous call may still be running the old graph: it is
+        // destroyed only after the previous call's work has finished
+        if (ctx->graph_exec && ctx->done_valid) HIP_TRY(ctx, hipEventSynchronize(ctx->ev_done));
         drop_graph(ctx);
         if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
         HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -687,9 +690,12 @@ size_t icp_workspace_bytes(int n, const int32_t* W, const int32_t* H, int levels
     return P.total;
 }
 
-int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params, icp_result* results,
-                       void* stream) {
-    if (!ctx) return ICP_EINVAL;
+namespace {
+
+// A batched registration queued on s, its n results copied to `results`
+// (host memory when to_host, else device memory) by the stream; nothing waits.
+int batch_submit(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params, icp_result* results,
+                 bool to_host, hipStream_t s) {
     if (n < 1 || !probs || !results) return fail(ctx, ICP_EINVAL, "empty batch or NULL array");
     if (n > 65535) return fail(ctx, ICP_EINVAL, "at most 65535 problems per batch");
     int rc = check_params(ctx, params);
@@ -697,7 +703,6 @@ int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_
     for (int p = 0; p < n; ++p)
         if ((rc = check_problem(ctx, probs[p], params->levels))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    hipStream_t s = static_cast<hipStream_t>(stream);
     StreamTurn turn;
     if (const int trc = turn.enter(ctx, s)) return trc;
     Plan& P = ctx_plan(ctx);
@@ -705,9 +710,27 @@ int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_
     ctx->stage_ready = false;
     if ((rc = execute(ctx, n, params, P, s))) return rc;
     icp_result* d_res = reinterpret_cast<icp_result*>(static_cast<char*>(ctx->ws) + P.off_res);
-    HIP_TRY(ctx, hipMemcpyAsync(results, d_res, sizeof(icp_result) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(results, d_res, sizeof(icp_result) * n,
+                                to_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+    return ICP_OK;
+}
+
+}  // namespace
+
+int icp_register_batch(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params, icp_result* results,
+                       void* stream) {
+    if (!ctx) return ICP_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = batch_submit(ctx, n, probs, params, results, true, s);
+    if (rc) return rc;
     HIP_TRY(ctx, hipStreamSynchronize(s));
     return resolve_timing(ctx);
+}
+
+int icp_register_batch_async(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params,
+                             icp_result* results_dev, void* stream) {
+    if (!ctx) return ICP_EINVAL;
+    return batch_submit(ctx, n, probs, params, results_dev, false, static_cast<hipStream_t>(stream));
 }
 
 int icp_autotune_tiles(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params* params, int reps,

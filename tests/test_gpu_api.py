@@ -74,6 +74,33 @@ def test_async_matches_sync(ctx):
         icp.icp_register_async(ctx, *data[0], probs[0].K, probs[0].imu_R, probs[0].init_pose, outs[0][:8], params)
 
 
+def test_batch_async_matches_sync(ctx):
+    """icp_register_batch_async queues the batch and returns; two batches
+    queued back to back (the second in the reverse order, so a new plan and
+    graph are built while the first may still run) give the synchronous
+    batch's results bit for bit."""
+    probs = [synth.pair_problem(3), synth.pair_problem(4), synth.uneven_problem(6)]
+    data = [upload(p) for p in probs]
+    items = [dict(live_depth=d, model_vtx=mv, model_nrm=mn, K=p.K, imu_R=p.imu_R, init_pose=p.init_pose)
+             for p, (d, mv, mn) in zip(probs, data)]
+    params = icp.icp_params_default()
+    sync = icp.icp_register_batch(ctx, items, params)
+    nbytes = C.sizeof(icp.icp_result) * len(items)
+    out1 = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    out2 = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    icp.icp_register_batch_async(ctx, icp.ProblemArray(items), out1, params)
+    icp.icp_register_batch_async(ctx, list(reversed(items)), out2, params)
+    torch.cuda.synchronize()
+    r1 = icp.results_from_bytes(out1.cpu().numpy().tobytes(), len(items), params.levels)
+    r2 = icp.results_from_bytes(out2.cpu().numpy().tobytes(), len(items), params.levels)
+    for (Ts, ss), (T1, s1), (T2, s2) in zip(sync, r1, reversed(r2)):
+        assert np.array_equal(T1, Ts) and s1 == ss
+        assert np.array_equal(T2, Ts) and s2 == ss
+    with pytest.raises(ValueError):  # a result buffer smaller than the batch never reaches the library
+        icp.icp_register_batch_async(ctx, items, out1[:nbytes - 1], params)
+
+
 def test_kernel_timing_counts_launches(ctx):
     p = synth.RoomSequence(1, n_frames=3).problem(1)
     d, mv, mn = upload(p)
