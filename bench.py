@@ -7,8 +7,11 @@ independent frame-to-model registrations, each a 3-level pyramid with
 {10,5,4} ICP iterations (finest first), FP32 maps with FP64 decisions.
 
 One step registers all 299 frames in one batched call (every kernel launch
-covers the tiles of all frames).  `value` is registrations per second over
-the timed steps with every input already resident in HBM.  Also reported:
+covers the tiles of all frames); the timed steps are queued with the
+asynchronous batched call, so the host stages a step while the previous one
+runs.  `value` is registrations per second over the timed steps with every
+input already resident in HBM (the synchronous call's rate is reported
+beside it).  Also reported:
 per-registration latency percentiles of the one-frame-per-call path, the
 roofline of the dominant kernel from HIP events recorded live on its stream,
 the pose error against the FP64 oracle on a sample of frames (for the FP32
@@ -19,6 +22,7 @@ a CPU baseline.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import math
@@ -189,19 +193,29 @@ def main():
     for _ in range(args.warmup):
         icp.icp_register_batch(ctx, batch, params)
     torch.cuda.synchronize()
+    # timed: the steps are queued with the asynchronous batched call (the
+    # host stages step k+1 while step k runs), results into device memory
     log(f"timed: {args.steps} batched steps")
+    res_dev = torch.zeros(ctypes.sizeof(icp.icp_result) * n, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    step_ms = []
-    results = None
     for _ in range(args.steps):
-        ts = time.perf_counter()
-        results = icp.icp_register_batch(ctx, batch, params)
-        step_ms.append((time.perf_counter() - ts) * 1e3)
+        icp.icp_register_batch_async(ctx, batch, res_dev, params)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     value = n * args.steps / t_total
+    results = icp.results_from_bytes(res_dev.cpu().numpy().tobytes(), n, params.levels)
     log(f"batched: {value:.1f} registrations/s, {t_total / args.steps * 1e3:.2f} ms per step")
+    # the same steps through the synchronous call (results on the host when it
+    # returns): its per-step wall times are the batch latencies
+    step_ms = []
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        res_sync = icp.icp_register_batch(ctx, batch, params)
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+    sync_value = n * len(step_ms) / (sum(step_ms) * 1e-3)
+    assert all(np.array_equal(a[0], b[0]) for a, b in zip(results, res_sync))
+    log(f"synchronous call per step: {sync_value:.1f} registrations/s")
     # per-kernel times: the same steps again, launched eagerly with HIP events
     # recorded on the launch stream around every kernel (not part of `value`)
     icp.icp_ctx_set_timing(ctx, True)
@@ -370,7 +384,8 @@ def main():
                    "front_end": ("bilateral filter + box-gradient normals" if front else
                                  "raw depth, forward-difference normals"),
                    "registrations_per_step": n, "px_iterations_per_registration": px_it,
-                   "path": "batched (all frames per launch)"},
+                   "path": "batched (all frames per launch), steps queued with icp_register_batch_async"},
+        "synchronous_call_registrations_per_s": round(sync_value, 1),
         "latency_ms": None if lat.size == 0 else {
             "path": "one frame per call (icp_register, synchronous)",
             "p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
