@@ -97,7 +97,7 @@ def rot_err(A, B):
     return math.atan2(s, 0.5 * (np.trace(R) - 1.0))
 
 
-def main():
+def build_parser():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -125,10 +125,14 @@ def main():
     ap.add_argument("--serve-frames", type=int, default=600, help="frames per stream (serve)")
     ap.add_argument("--serve-period", type=int, default=30, help="distinct frames per stream (serve)")
     ap.add_argument("--serve-sweep", default="1,4,16,64", help="arrival-rate multipliers of the saturation sweep")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = build_parser().parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU; the registrations shard by frame with no "
+        print("bench.py measures one GPU: the registrations shard by frame with no "
               "communication, so runs on more than one GPU are not provided.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "serve":
