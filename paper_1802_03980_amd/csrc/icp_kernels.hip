@@ -293,11 +293,29 @@ __global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__
     const int S = L.ps;
     ICP_GLOBAL float* LV = gmut(L.LV);
     ICP_GLOBAL float* LN = gmut(L.LN);
-    for (int dv = threadIdx.x / FE_TX; dv < FE_TY; dv += ICP_WG / FE_TX) {
+    // every row's depth, right and lower neighbour are loaded before any row
+    // is computed and stored (rows past the image read row v0 and are unused)
+    constexpr int kStep = ICP_WG / FE_TX, kRows = FE_TY / kStep;
+    const ICP_GLOBAL float* D = gconst(L.D);
+    const int r0 = threadIdx.x / FE_TX;
+    const bool has_r = u + 1 < L.W;
+    float zc[kRows], zr[kRows], zb[kRows];
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+        const int v = v0 + r0 + q * kStep;
+        const bool in = v < L.H;
+        const int i = (in ? v : v0) * L.W + u;
+        zc[q] = D[i];
+        zr[q] = has_r ? D[i + 1] : 0.0f;
+        zb[q] = in && v + 1 < L.H ? D[i + L.W] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+        const int dv = r0 + q * kStep;
         const int v = v0 + dv;
         if (v >= L.H) break;
         float p[3], n[3];
-        live_px(gconst(L.D), L.W, L.H, sx, sy, du, dv, u, v, p, n);
+        live_from_depth(zc[q], zr[q], zb[q], has_r, v + 1 < L.H, sx[du], sx[du + 1], sy[dv], sy[dv + 1], p, n);
         const int i = v * L.W + u;
         if (with_vertex) {
             LV[i] = p[0];
