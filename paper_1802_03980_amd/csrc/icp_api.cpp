@@ -189,7 +189,7 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
             P.tiles[l] += L.n_tiles;
             P.max_npx[l] = std::max(P.max_npx[l], L.npx);
             P.max_vn[l] = std::max(P.max_vn[l], icpk::live_vn_blocks(L.W, L.H));
-            P.max_mp[l] = std::max(P.max_mp[l], icpk::model_pairs(L.W, L.H));
+            P.max_mp[l] = std::max(P.max_mp[l], icpk::model_blocks(L.W, L.H));
             P.max_q[l] = std::max(P.max_q[l], L.W + L.H + 2);
             for (int t = 0; t < L.n_tiles; ++t) P.owner[l].push_back(p);
             const size_t S = (size_t)L.ps * sizeof(float);

@@ -383,63 +383,88 @@ __device__ __forceinline__ void model_px(const float (&cv)[4][3], const float (&
     }
 }
 
-// One thread per pair of output pixels (u, u+1), u even: each child row of
-// the pair is 12 consecutive floats per map, read as three 16-byte loads when
-// the maps are 16-byte aligned (any caller buffer at level 0 is accepted: an
-// unaligned one takes the scalar loads).
-__global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restrict__ probs, int level) {
+// Model level l from l - 1 and, with also_next, level l + 1 in the same
+// launch: one thread per 2 x 2 block of level-l pixels.  For each of the
+// block's rows it reads the two child rows below it as 12 consecutive floats
+// per map (three 16-byte loads when the maps are 16-byte aligned; any caller
+// buffer at level 0 is accepted: an unaligned one takes the scalar loads),
+// writes the level-l pixels and keeps them, and forms the level-(l+1) pixel
+// from the four it kept, so level l is never read back.  A block is partial
+// only at the right or bottom edge of an odd-sized level, and then it has no
+// level-(l+1) pixel (each level halves the size, rounding down).
+__global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restrict__ probs, int level,
+                                                       int also_next) {
     const ProbDesc& P = probs[blockIdx.y];
     const LevelDesc& F = P.lv[level - 1];
     const LevelDesc& C = P.lv[level];
-    const int half = (C.W + 1) >> 1;  // pairs per row
+    const int qw = (C.W + 1) >> 1;  // blocks per row
     const int t = blockIdx.x * ICP_WG + threadIdx.x;
-    if (t >= half * C.H) return;
-    const int v = t / half, u = 2 * (t % half);
+    if (t >= qw * ((C.H + 1) >> 1)) return;
+    const int vb = t / qw, u = 2 * (t % qw);
     const bool two = u + 1 < C.W;
+    const int rows = 2 * vb + 1 < C.H ? 2 : 1;
     const ICP_GLOBAL float* MV = gconst(F.MV);
     const ICP_GLOBAL float* MN = gconst(F.MN);
     const bool vec = two && ((reinterpret_cast<uintptr_t>(F.MV) | reinterpret_cast<uintptr_t>(F.MN)) & 15) == 0;
-    float rv[2][12], rn[2][12];  // [child row][4 children x 3 components]
-    for (int r = 0; r < 2; ++r) {
-        const int base = 3 * ((2 * v + r) * F.W + 2 * u);
-        if (vec) {
-            for (int q = 0; q < 3; ++q) {
-                const vf4 a = *(const ICP_GLOBAL vf4*)(MV + base + 4 * q);
-                const vf4 b = *(const ICP_GLOBAL vf4*)(MN + base + 4 * q);
-                for (int c = 0; c < 4; ++c) {
-                    rv[r][4 * q + c] = a[c];
-                    rn[r][4 * q + c] = b[c];
+    ICP_GLOBAL float* MVo = gmut(C.MVw);
+    ICP_GLOBAL float* MNo = gmut(C.MNw);
+    float kv[4][3], kn[4][3];  // the block's level-l values, row-major
+    for (int b = 0; b < rows; ++b) {
+        const int v = 2 * vb + b;
+        float rv[2][12], rn[2][12];  // [child row][4 children x 3 components]
+        for (int r = 0; r < 2; ++r) {
+            const int base = 3 * ((2 * v + r) * F.W + 2 * u);
+            if (vec) {
+                for (int q = 0; q < 3; ++q) {
+                    const vf4 a = *(const ICP_GLOBAL vf4*)(MV + base + 4 * q);
+                    const vf4 c = *(const ICP_GLOBAL vf4*)(MN + base + 4 * q);
+                    for (int k = 0; k < 4; ++k) {
+                        rv[r][4 * q + k] = a[k];
+                        rn[r][4 * q + k] = c[k];
+                    }
+                }
+            } else {
+                const int cnt = two ? 12 : 6;
+                for (int k = 0; k < 12; ++k) {
+                    rv[r][k] = k < cnt ? MV[base + k] : 0.0f;
+                    rn[r][k] = k < cnt ? MN[base + k] : 0.0f;
                 }
             }
-        } else {
-            const int cnt = two ? 12 : 6;
-            for (int c = 0; c < 12; ++c) {
-                rv[r][c] = c < cnt ? MV[base + c] : 0.0f;
-                rn[r][c] = c < cnt ? MN[base + c] : 0.0f;
+        }
+        for (int o = 0; o < (two ? 2 : 1); ++o) {
+            float cv[4][3], cn[4][3];
+            for (int k = 0; k < 3; ++k) {
+                cv[0][k] = rv[0][6 * o + k];
+                cv[1][k] = rv[0][6 * o + 3 + k];
+                cv[2][k] = rv[1][6 * o + k];
+                cv[3][k] = rv[1][6 * o + 3 + k];
+                cn[0][k] = rn[0][6 * o + k];
+                cn[1][k] = rn[0][6 * o + 3 + k];
+                cn[2][k] = rn[1][6 * o + k];
+                cn[3][k] = rn[1][6 * o + 3 + k];
+            }
+            float vo[3], no[3];
+            model_px(cv, cn, vo, no);
+            const int i = v * C.W + u + o;
+            for (int k = 0; k < 3; ++k) {
+                MVo[3 * i + k] = vo[k];
+                MNo[3 * i + k] = no[k];
+                kv[2 * b + o][k] = vo[k];
+                kn[2 * b + o][k] = no[k];
             }
         }
     }
-    ICP_GLOBAL float* MVo = gmut(C.MVw);
-    ICP_GLOBAL float* MNo = gmut(C.MNw);
-    for (int o = 0; o < (two ? 2 : 1); ++o) {
-        float cv[4][3], cn[4][3];
-        for (int k = 0; k < 3; ++k) {
-            cv[0][k] = rv[0][6 * o + k];
-            cv[1][k] = rv[0][6 * o + 3 + k];
-            cv[2][k] = rv[1][6 * o + k];
-            cv[3][k] = rv[1][6 * o + 3 + k];
-            cn[0][k] = rn[0][6 * o + k];
-            cn[1][k] = rn[0][6 * o + 3 + k];
-            cn[2][k] = rn[1][6 * o + k];
-            cn[3][k] = rn[1][6 * o + 3 + k];
-        }
-        float vo[3], no[3];
-        model_px(cv, cn, vo, no);
-        const int i = v * C.W + u + o;
-        for (int k = 0; k < 3; ++k) {
-            MVo[3 * i + k] = vo[k];
-            MNo[3 * i + k] = no[k];
-        }
+    if (!also_next || !two || rows != 2) return;
+    // a whole block: level l+1 (C.W >> 1 by C.H >> 1) has its pixel (u / 2, vb)
+    const LevelDesc& N = P.lv[level + 1];
+    float vo[3], no[3];
+    model_px(kv, kn, vo, no);
+    const int i = vb * N.W + (u >> 1);
+    ICP_GLOBAL float* NVo = gmut(N.MVw);
+    ICP_GLOBAL float* NNo = gmut(N.MNw);
+    for (int k = 0; k < 3; ++k) {
+        NVo[3 * i + k] = vo[k];
+        NNo[3 * i + k] = no[k];
     }
 }
 
@@ -1180,10 +1205,10 @@ hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, hipStream_t
 
 int live_vn_blocks(int W, int H) { return ((W + FE_TX - 1) / FE_TX) * ((H + FE_TY - 1) / FE_TY); }
 
-int model_pairs(int W, int H) { return ((W + 1) / 2) * H; }
+int model_blocks(int W, int H) { return ((W + 1) / 2) * ((H + 1) / 2); }
 
 hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, const int* max_vn_blocks,
-                          const int* max_model_pairs, const int* max_quot, bool with_live_maps, const FrontEnd& fe,
+                          const int* max_model_blocks, const int* max_quot, bool with_live_maps, const FrontEnd& fe,
                           hipStream_t s) {
     if (fe.depth_filter) {
         const dim3 grid(max_vn_blocks[0], n);
@@ -1221,8 +1246,9 @@ hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* m
             }
         }
     }
-    for (int l = 1; l < levels; ++l)
-        hipLaunchKernelGGL(k_model_down, dim3(blocks_for(max_model_pairs[l]), n), dim3(ICP_WG), 0, s, probs, l);
+    for (int l = 1; l < levels; l += 2)
+        hipLaunchKernelGGL(k_model_down, dim3(blocks_for(max_model_blocks[l]), n), dim3(ICP_WG), 0, s, probs, l,
+                           l + 1 < levels ? 1 : 0);
     return hipGetLastError();
 }
 

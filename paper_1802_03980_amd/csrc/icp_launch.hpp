@@ -26,16 +26,16 @@ hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, hipStream_t
 hipError_t launch_depth_to_maps(const MapsDesc* jobs, int n, int max_blocks, hipStream_t s);
 // live-map work-groups of a W x H level (one per 64 x 4 pixels)
 int live_vn_blocks(int W, int H);
-// model-pyramid threads of a W x H level (one per pair of pixels in a row)
-int model_pairs(int W, int H);
+// model-pyramid threads of a W x H level (one per 2 x 2 block of pixels)
+int model_blocks(int W, int H);
 // Front end of every problem: optional bilateral filter of the caller's depth
-// into the level-0 workspace plane, depth pyramid,
-// back-projection quotient tables, live normal planes (forward differences or
-// box gradients), model pyramid, and (with_live_maps) the live vertex planes,
-// which only the stage-access calls read (the pixel passes rebuild the
-// vertices from depth).
+// into the level-0 workspace plane, depth pyramid, back-projection quotient
+// tables, live normal planes (forward differences or box gradients), model
+// pyramid (two levels per launch), and (with_live_maps) the live vertex
+// planes, which only the stage-access calls read (the pixel passes rebuild
+// the vertices from depth).
 hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, const int* max_vn_blocks,
-                          const int* max_model_pairs, const int* max_quot, bool with_live_maps, const FrontEnd& fe,
+                          const int* max_model_blocks, const int* max_quot, bool with_live_maps, const FrontEnd& fe,
                           hipStream_t s);
 // one ICP iteration at ctl.level: pass 1 over `tiles` flat tiles of all
 // problems, the per-problem band, pass 2 over the tiles, the per-problem solve

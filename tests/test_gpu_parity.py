@@ -85,6 +85,21 @@ def test_s1_pyramid_maps_bitwise(ctx, name):
                 pytest.fail(f"{name} level {l} {key}: {bad.sum()} of {bad.size} entries differ")
 
 
+def test_s1_four_level_pyramid_bitwise(ctx):
+    """Four levels of a 168 x 120 pair: levels 1 and 2 come from one launch,
+    level 3 (21 x 15, odd both ways, so its right and bottom blocks are
+    partial) from a second."""
+    prob = synth.pair_problem(8, W=168, H=120, f=136.0)
+    gpu = _gpu_levels(ctx, prob, levels=4)
+    ref = oracle.pyramids(prob.live_depth, prob.model_vtx, prob.model_nrm, prob.K, 4)
+    assert gpu[3]["MV"].shape == (3, 15, 21)
+    for l in range(4):
+        for key in ("D", "LV", "LN", "MV", "MN"):
+            g, o = gpu[l][key], ref[l][key]
+            assert g.shape == o.shape and _same_nan(g, o), (l, key)
+        assert np.isfinite(gpu[l]["MV"]).mean() > 0.5, l
+
+
 FRONT_ENDS = {"filter": dict(depth_filter=1), "box_normals": dict(normal_mode=1),
               "both": dict(depth_filter=1, normal_mode=1, normal_radius=3)}
 
