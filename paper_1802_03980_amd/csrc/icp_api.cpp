@@ -144,9 +144,8 @@ int pick_tile(int npx, int nprob, int req) {
 struct Plan {
     size_t off_desc = 0, off_state = 0, off_res = 0, off_scratch = 0, off_flags = 0, off_owner[ICP_MAX_LEVELS] = {};
     int tiles[ICP_MAX_LEVELS] = {};
-    int max_npx[ICP_MAX_LEVELS] = {};
     int max_vn[ICP_MAX_LEVELS] = {};  // live-map work-groups of the largest level
-    int max_mp[ICP_MAX_LEVELS] = {};  // model-pyramid threads of the largest level
+    int max_mp[ICP_MAX_LEVELS] = {};  // pyramid threads (2 x 2 blocks) of the largest level
     int max_q[ICP_MAX_LEVELS] = {};   // quotient-table entries (W + H + 2) of the largest level
     std::vector<ProbDesc> desc;  // pointers hold offsets until rebased
     std::vector<int> owner[ICP_MAX_LEVELS];
@@ -168,7 +167,6 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
     P.off_flags = take(sizeof(int32_t));
     for (int l = 0; l < levels; ++l) {
         P.tiles[l] = 0;
-        P.max_npx[l] = 0;
         P.max_vn[l] = 0;
         P.max_mp[l] = 0;
         P.max_q[l] = 0;
@@ -187,7 +185,6 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
             L.n_tiles = (L.npx + L.tile_px - 1) / L.tile_px;
             L.tile_base = P.tiles[l];
             P.tiles[l] += L.n_tiles;
-            P.max_npx[l] = std::max(P.max_npx[l], L.npx);
             P.max_vn[l] = std::max(P.max_vn[l], icpk::live_vn_blocks(L.W, L.H));
             P.max_mp[l] = std::max(P.max_mp[l], icpk::model_blocks(L.W, L.H));
             P.max_q[l] = std::max(P.max_q[l], L.W + L.H + 2);
@@ -481,7 +478,7 @@ int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* r
     int64_t px0 = 0;
     for (int p = 0; p < n; ++p) px0 += P.desc[p].lv[0].npx;
     if ((rc = time_begin(ctx, s, r, ICP_TIME_FRONT_END, px0))) return rc;
-    HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, P.max_npx, P.max_vn, P.max_mp, P.max_q, false,
+    HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, P.max_vn, P.max_mp, P.max_q, false,
                                       front_end(prm), s));
     if (prm->reduce_mode == 1) HIP_TRY(ctx, icpk::launch_centroid(d_desc, n, prm->levels, s));
     if ((rc = time_end(ctx, s, r))) return rc;
@@ -973,7 +970,7 @@ int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const
     ctx->stage_desc = P.desc[0];
     ctx->stage_levels = levels;
     HIP_TRY(ctx, icpk::launch_init(ctx->d_desc, 1, 0, nullptr, s));
-    HIP_TRY(ctx, icpk::launch_prepare(ctx->d_desc, 1, levels, P.max_npx, P.max_vn, P.max_mp, P.max_q, true,
+    HIP_TRY(ctx, icpk::launch_prepare(ctx->d_desc, 1, levels, P.max_vn, P.max_mp, P.max_q, true,
                                       front_end(prm), s));
     HIP_TRY(ctx, icpk::launch_centroid(ctx->d_desc, 1, levels, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));

@@ -65,21 +65,53 @@ __global__ __launch_bounds__(ICP_WG) void k_init(const ProbDesc* __restrict__ pr
 
 // ------------------------------------------------------------------ front end
 // Depth pyramid: 2x2 mean of the four children when all four are valid.
+// Level l and, with also_next, level l + 1 in one launch: one thread per
+// 2 x 2 block of level-l pixels reads the 4 x 2 children of each of the
+// block's rows (one 16-byte load when the rows allow it), writes the level-l
+// depths and forms the level-(l+1) depth from the four it kept.  Only a block
+// at the right or bottom edge of an odd-sized level is partial, and such a
+// block has no level-(l+1) pixel.
+__device__ __forceinline__ float depth_px(float a, float b, float c, float d) {
+    if (!(depth_ok(a) && depth_ok(b) && depth_ok(c) && depth_ok(d))) return 0.0f;
+    return (float)(((((double)a + (double)b) + (double)c) + (double)d) * 0.25);
+}
 
-__global__ __launch_bounds__(ICP_WG) void k_depth_down(const ProbDesc* __restrict__ probs, int level) {
+__global__ __launch_bounds__(ICP_WG) void k_depth_down(const ProbDesc* __restrict__ probs, int level,
+                                                       int also_next) {
     const ProbDesc& P = probs[blockIdx.y];
     const LevelDesc& F = P.lv[level - 1];
     const LevelDesc& C = P.lv[level];
-    const int i = blockIdx.x * ICP_WG + threadIdx.x;
-    if (i >= C.npx) return;
-    const int u = i % C.W, v = i / C.W;
+    const int qw = (C.W + 1) >> 1;  // blocks per row
+    const int t = blockIdx.x * ICP_WG + threadIdx.x;
+    if (t >= qw * ((C.H + 1) >> 1)) return;
+    const int vb = t / qw, u = 2 * (t % qw);
+    const bool two = u + 1 < C.W;
+    const int rows = 2 * vb + 1 < C.H ? 2 : 1;
     const ICP_GLOBAL float* D = gconst(F.D);
-    const float a = D[(2 * v) * F.W + 2 * u], b = D[(2 * v) * F.W + 2 * u + 1];
-    const float c = D[(2 * v + 1) * F.W + 2 * u], d = D[(2 * v + 1) * F.W + 2 * u + 1];
-    float out = 0.0f;
-    if (depth_ok(a) && depth_ok(b) && depth_ok(c) && depth_ok(d))
-        out = (float)(((((double)a + (double)b) + (double)c) + (double)d) * 0.25);
-    gmut(C.Dw)[i] = out;
+    const bool vec = two && (F.W & 3) == 0 && (reinterpret_cast<uintptr_t>(F.D) & 15) == 0;
+    ICP_GLOBAL float* Do = gmut(C.Dw);
+    float kept[4];
+    for (int b = 0; b < rows; ++b) {
+        const int v = 2 * vb + b;
+        float r[2][4];
+        for (int q = 0; q < 2; ++q) {
+            const int base = (2 * v + q) * F.W + 2 * u;
+            if (vec) {
+                const vf4 x = *(const ICP_GLOBAL vf4*)(D + base);
+                for (int c = 0; c < 4; ++c) r[q][c] = x[c];
+            } else {
+                for (int c = 0; c < 4; ++c) r[q][c] = c < (two ? 4 : 2) ? D[base + c] : 0.0f;
+            }
+        }
+        for (int o = 0; o < (two ? 2 : 1); ++o) {
+            const float z = depth_px(r[0][2 * o], r[0][2 * o + 1], r[1][2 * o], r[1][2 * o + 1]);
+            Do[v * C.W + u + o] = z;
+            kept[2 * b + o] = z;
+        }
+    }
+    if (!also_next || !two || rows != 2) return;
+    const LevelDesc& N = P.lv[level + 1];  // C.W >> 1 by C.H >> 1
+    gmut(N.Dw)[vb * N.W + (u >> 1)] = depth_px(kept[0], kept[1], kept[2], kept[3]);
 }
 
 // Live vertex map and forward-difference normal map (flipped to face the
@@ -1207,7 +1239,7 @@ int live_vn_blocks(int W, int H) { return ((W + FE_TX - 1) / FE_TX) * ((H + FE_T
 
 int model_blocks(int W, int H) { return ((W + 1) / 2) * ((H + 1) / 2); }
 
-hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, const int* max_vn_blocks,
+hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_vn_blocks,
                           const int* max_model_blocks, const int* max_quot, bool with_live_maps, const FrontEnd& fe,
                           hipStream_t s) {
     if (fe.depth_filter) {
@@ -1223,8 +1255,9 @@ hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* m
             default: return hipErrorInvalidValue;
         }
     }
-    for (int l = 1; l < levels; ++l)
-        hipLaunchKernelGGL(k_depth_down, dim3(blocks_for(max_npx[l]), n), dim3(ICP_WG), 0, s, probs, l);
+    for (int l = 1; l < levels; l += 2)  // two levels per launch, as for the model maps
+        hipLaunchKernelGGL(k_depth_down, dim3(blocks_for(max_model_blocks[l]), n), dim3(ICP_WG), 0, s, probs, l,
+                           l + 1 < levels ? 1 : 0);
     for (int l = 0; l < levels; ++l)
         hipLaunchKernelGGL(k_quotients, dim3(blocks_for(max_quot[l]), n), dim3(ICP_WG), 0, s, probs, l);
     for (int l = 0; l < levels; ++l) {

@@ -20,13 +20,11 @@ struct MomArg {
 hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, int32_t* need2, hipStream_t s);
 // centroid of every level's valid live vertices (split-precision reduction)
 hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, hipStream_t s);
-// live depth pyramid, live vertex/normal maps, model maps for every level;
-// max_npx[l] is the largest level-l pixel count over the problems
 // interleaved vertex / normal maps of n depth images (grid: max_blocks x n)
 hipError_t launch_depth_to_maps(const MapsDesc* jobs, int n, int max_blocks, hipStream_t s);
 // live-map work-groups of a W x H level (one per 64 x 4 pixels)
 int live_vn_blocks(int W, int H);
-// model-pyramid threads of a W x H level (one per 2 x 2 block of pixels)
+// depth- and model-pyramid threads of a W x H level (one per 2 x 2 block)
 int model_blocks(int W, int H);
 // Front end of every problem: optional bilateral filter of the caller's depth
 // into the level-0 workspace plane, depth pyramid, back-projection quotient
@@ -34,7 +32,7 @@ int model_blocks(int W, int H);
 // pyramid (two levels per launch), and (with_live_maps) the live vertex
 // planes, which only the stage-access calls read (the pixel passes rebuild
 // the vertices from depth).
-hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_npx, const int* max_vn_blocks,
+hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_vn_blocks,
                           const int* max_model_blocks, const int* max_quot, bool with_live_maps, const FrontEnd& fe,
                           hipStream_t s);
 // one ICP iteration at ctl.level: pass 1 over `tiles` flat tiles of all
