@@ -19,9 +19,13 @@
  *     unit length and face the camera.
  *   - Poses are row-major doubles: 4x4 (16 values) in the public calls, 3x4
  *     [R | t] (12 values) in the stage calls.  imu_R is 3x3 row-major.
- *     Rotations are used as given (orthonormality is not checked): a caller
- *     that chains poses should project them back onto SO(3), or rounding
- *     errors in a prior built from an estimated pose grow from frame to frame.
+ *     Every rotation the library takes (imu_R; the rotation of init_pose when
+ *     the IMU seed is off; the rotation of a TSDF camera pose T_wc; the server's
+ *     imu_rel_R) must be a rotation: finite, |(R^T R - I)_ij| <= 1e-6 for every
+ *     entry and det R > 0, else the call returns ICP_EINVAL (the pose is an
+ *     element of SE(3), paper Sec. 3).  A caller that chains estimated poses
+ *     should project them back onto SO(3): rounding errors in a prior built
+ *     from an estimated pose otherwise grow from frame to frame.
  *   - W and H must be divisible by 2^(levels-1); 1 <= levels <= ICP_MAX_LEVELS;
  *     W, H <= ICP_MAX_DIM.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
@@ -50,7 +54,7 @@
 extern "C" {
 #endif
 
-#define ICP_ABI_VERSION 4
+#define ICP_ABI_VERSION 5
 #define ICP_MAX_LEVELS 4
 #define ICP_MAX_DIM 8192
 #define ICP_HIST_BINS 1024 /* distance histogram: bins of 2^-13 m over [0, 0.125) m */
@@ -211,6 +215,12 @@ size_t icp_workspace_bytes(int n, const int32_t* W, const int32_t* H, int levels
    single-pass mode, tiles chosen by the library. */
 void icp_params_default(icp_params* p);
 
+/* Check one problem and the parameters the way icp_register_batch checks
+   them, on the host only (no context, no device: the problem's pointers are
+   compared with NULL, never read): ICP_OK or ICP_EINVAL, with the reason in
+   msg (msg_len bytes, may be NULL/0). */
+int icp_validate_problem(const icp_problem* problem, const icp_params* params, char* msg, size_t msg_len);
+
 /* -------------------------------------------------------------- hot path */
 
 /* Register one live depth frame against the model maps (Sec. 3): build the
@@ -323,6 +333,27 @@ int icp_stage_associate(icp_ctx* ctx, int level, const double* pose12, const icp
 int icp_stage_moments(icp_ctx* ctx, int level, const double* pose12, const icp_params* params,
                       int k_lo, int k_hi, double* moments, int64_t* n, void* stream);
 
+/* One iteration of the single-pass reduction that icp_register runs by
+   default (reduce_mode 0, pass_mode 0; paper Eq. (3) over the pairs the median
+   band of Sec. 3.3 keeps), at `level` for pose12 (host): pass 1 associates,
+   histograms and reduces the rows into per-tile partials -- rows whose bin lies
+   below a window of bins around the predicted band edge pred_hi into one sum,
+   rows inside the window per bin -- then the band kernel finds the band and,
+   when its lower edge is bin 0 and its upper edge lies in the window or just
+   below it, sums the partials up to the edge into the moments.  iter = 0 takes
+   the full 48-bin window (a level's first iteration); iter > 0 a window of
+   2 pred_hw bins (pred_hw 1..24).  pred_hi = -1: no prediction, no window.
+   The window is [pred_hi - hw, pred_hi + hw) clamped into 0..1023.
+   Outputs (host): band {N, k_med, k_lo, k_hi}; window {h0, width} (h0 = -1:
+   none); *hit = 1 when the moments came from the partials, else 0 (the
+   registration would then run pass 2), with moments and *n zeroed; moments
+   (28 doubles, as icp_stage_moments) and *n otherwise.  Needs a prepared stage
+   problem, reduce_mode 0 and band_beta >= 1 or no median filter (else
+   ICP_EINVAL).  Synchronises. */
+int icp_stage_single_pass(icp_ctx* ctx, int level, const double* pose12, const icp_params* params, int iter,
+                          int pred_hi, int pred_hw, int64_t* band, int32_t* window, int* hit, double* moments,
+                          int64_t* n, void* stream);
+
 /* The device solve and update on given moments: pose12_out = Exp(x) pose12_in
    with x solving Eq. (5).  All pointers host.  *status receives ICP_LEVEL_*.
    Synchronises. */
@@ -356,11 +387,11 @@ int icp_live_maps(icp_ctx* ctx, const float* depth, int W, int H, const icp_intr
    in world coordinates.  weight 0 = never observed.  All arithmetic is FP64
    and rounds as written, so results are reproducible bit for bit.
    T_wc: 16 doubles, row-major 4x4 camera-to-world pose, host memory (only
-   the top 3x4 is read; the rotation must be orthonormal for the geometry to
-   mean anything, which is not checked).  Calls are asynchronous on `stream`
-   and return ICP_EINVAL for NULL pointers, dim outside [2, 1024], size, mu
-   or max_weight not finite and positive (max_weight >= 1), W, H outside
-   [1, ICP_MAX_DIM], or bad intrinsics. */
+   the top 3x4 is read; its rotation must pass the rotation check of the
+   conventions above).  Calls are asynchronous on `stream` and return
+   ICP_EINVAL for NULL pointers, dim outside [2, 1024], size, mu or max_weight
+   not finite and positive (max_weight >= 1), W, H outside [1, ICP_MAX_DIM],
+   bad intrinsics or a T_wc that is not a rigid motion. */
 typedef struct {
     float* voxels;        /* device, icp_tsdf_bytes(dim) bytes, 256-byte aligned */
     int32_t dim;          /* voxels per edge */
@@ -424,10 +455,12 @@ int icp_tsdf_raycast(icp_ctx* ctx, const icp_tsdf* vol, int W, int H, const icp_
    stream only builds its model maps (pose = identity).
 
    Admission: icp_server_open_stream fails with ICP_ENOMEM when the resident
-   state of every open stream plus, per slot, the workspace of the largest
-   batch the open streams can form would exceed hbm_budget_bytes (0: no
-   limit); a stream's resident state is (frames_in_flight + 1) x 28 bytes per
-   pixel.  The server uses the default front end (params.depth_filter and
+   state of every open stream plus, per slot, a workspace that any batch the
+   open streams can form fits in would exceed hbm_budget_bytes (0: no limit).
+   A stream's resident state is (frames_in_flight + 1) x 28 bytes per pixel;
+   the workspace bound counts frames_in_flight frames of every stream (largest
+   first, at most max_batch) at the smallest tile size (or params.tile_px),
+   and a slot reserves exactly that bound before launching a batch.  The server uses the default front end (params.depth_filter and
    params.normal_mode 0; other values are rejected at creation).  All calls may come from any host thread; results are taken with
    icp_server_poll.  A HIP failure inside the scheduler makes every later call
    return it. */
@@ -469,6 +502,7 @@ typedef struct {
     size_t workspace_bytes;     /* per-slot batch workspace accounted by admission, all slots */
     int32_t streams_open;
     int32_t pad;
+    size_t workspace_held_bytes; /* device workspace the slots hold now (<= workspace_bytes) */
 } icp_server_counters;
 
 void icp_server_config_default(icp_server_config* cfg);

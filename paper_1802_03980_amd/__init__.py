@@ -18,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libicp_mi355x.so")
 
-ICP_ABI_VERSION = 4
+ICP_ABI_VERSION = 5
 MAX_LEVELS = 4
 HIST_BINS = 1024
 OK, EINVAL, ENOMEM, EDEVICE, ETIMEOUT = 0, -1, -2, -3, -4
@@ -29,10 +29,10 @@ PX_INVALID_LIVE, PX_BEHIND, PX_OUTSIDE, PX_INVALID_MODEL, PX_FAR, PX_ANGLE, PX_G
 # symbols of include/icp.h
 EXPORTS = (
     "icp_abi_version", "icp_strerror", "icp_last_error", "icp_ctx_create", "icp_ctx_destroy",
-    "icp_ctx_workspace_bytes", "icp_workspace_bytes", "icp_params_default", "icp_register",
+    "icp_ctx_workspace_bytes", "icp_workspace_bytes", "icp_params_default", "icp_validate_problem", "icp_register",
     "icp_register_async", "icp_register_batch", "icp_register_batch_async", "icp_ctx_set_timing", "icp_ctx_get_timing", "icp_ctx_set_graphs",
     "icp_stage_prepare", "icp_stage_level",
-    "icp_stage_associate", "icp_stage_moments", "icp_stage_solve", "icp_live_maps", "icp_autotune_tiles",
+    "icp_stage_associate", "icp_stage_moments", "icp_stage_single_pass", "icp_stage_solve", "icp_live_maps", "icp_autotune_tiles",
     "icp_server_config_default", "icp_server_clock", "icp_server_create", "icp_server_destroy",
     "icp_server_last_error", "icp_server_open_stream", "icp_server_close_stream", "icp_server_submit",
     "icp_server_poll", "icp_server_get_counters", "icp_tsdf_bytes", "icp_tsdf_brick_bytes", "icp_tsdf_reset",
@@ -111,7 +111,7 @@ class icp_server_result(C.Structure):
 class icp_server_counters(C.Structure):
     _fields_ = [("batches", C.c_uint64), ("frames", C.c_uint64), ("registrations", C.c_uint64),
                 ("busy_s", C.c_double), ("resident_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t),
-                ("streams_open", C.c_int32), ("pad", C.c_int32)]
+                ("streams_open", C.c_int32), ("pad", C.c_int32), ("workspace_held_bytes", C.c_size_t)]
 
 
 _lib = None
@@ -141,6 +141,7 @@ def lib():
             "icp_ctx_workspace_bytes": (Z, [P]),
             "icp_workspace_bytes": (Z, [I, P, P, I]),
             "icp_params_default": (None, [C.POINTER(icp_params)]),
+            "icp_validate_problem": (I, [C.POINTER(icp_problem), C.POINTER(icp_params), C.c_char_p, Z]),
             "icp_register": (I, [P, P, I, I, P, P, C.POINTER(icp_intrinsics), P, P, C.POINTER(icp_params), P,
                                  C.POINTER(icp_stats), P]),
             "icp_register_async": (I, [P, P, I, I, P, P, C.POINTER(icp_intrinsics), P, P,
@@ -155,6 +156,7 @@ def lib():
             "icp_stage_associate": (I, [P, I, P, C.POINTER(icp_params), P, P, P, P, P]),
             "icp_stage_moments": (I, [P, I, P, C.POINTER(icp_params), I, I, P, P, P]),
             "icp_stage_solve": (I, [P, P, C.c_int64, P, C.POINTER(icp_params), P, P, P, P]),
+            "icp_stage_single_pass": (I, [P, I, P, C.POINTER(icp_params), I, I, I, P, P, C.POINTER(I), P, P, P]),
             "icp_live_maps": (I, [P, P, I, I, C.POINTER(icp_intrinsics), P, P, P]),
             "icp_autotune_tiles": (I, [P, I, P, C.POINTER(icp_params), I, P, C.POINTER(D), P]),
             "icp_tsdf_bytes": (Z, [I]),
@@ -253,6 +255,22 @@ def icp_params_default(**over):
     return p
 
 
+def icp_validate_problem(W, H, K, imu_R, init_pose, params=None):
+    """Host-only check of a problem's sizes, intrinsics and rotations and of
+    the parameters (the checks icp_register makes); returns (code, message).
+    The map pointers are placeholders: they are compared with NULL only."""
+    p = params if params is not None else icp_params_default()
+    q = icp_problem()
+    q.live_depth = q.model_vtx = q.model_nrm = 256
+    q.W, q.H = int(W), int(H)
+    q.K = make_intrinsics(K)
+    q.imu_R[:] = [float(v) for v in _f64(imu_R, 9, "imu_R")]
+    q.init_pose[:] = [float(v) for v in _f64(init_pose, 16, "init_pose")]
+    buf = C.create_string_buffer(256)
+    rc = lib().icp_validate_problem(C.byref(q), C.byref(p), buf, 256)
+    return rc, buf.value.decode()
+
+
 def make_intrinsics(K):
     fx, fy, cx, cy = (float(v) for v in K)
     return icp_intrinsics(fx, fy, cx, cy)
@@ -309,6 +327,7 @@ def icp_register_async(ctx, live_depth, model_vtx, model_nrm, K, imu_R, init_pos
                        stream=None):
     """Asynchronous register; result_dev is a uint8 device tensor of at least
     sizeof(icp_result) bytes that receives the icp_result."""
+    res_ptr = _dev_ptr(result_dev, "uint8", "result_dev")
     H, W = _maps_match(live_depth, model_vtx, model_nrm)
     p = params if params is not None else icp_params_default()
     if result_dev.numel() * result_dev.element_size() < C.sizeof(icp_result):
@@ -319,7 +338,7 @@ def icp_register_async(ctx, live_depth, model_vtx, model_nrm, K, imu_R, init_pos
     rc = lib().icp_register_async(ctx.handle, _dev_ptr(live_depth, "float32", "live_depth"), W, H,
                                   _dev_ptr(model_vtx, "float32", "model_vtx"),
                                   _dev_ptr(model_nrm, "float32", "model_nrm"), C.byref(Kc), _np_ptr(R),
-                                  _np_ptr(T0), C.byref(p), C.c_void_p(result_dev.data_ptr()), _stream(stream))
+                                  _np_ptr(T0), C.byref(p), res_ptr, _stream(stream))
     _check(ctx, rc)
 
 
@@ -377,6 +396,7 @@ def icp_register_batch_async(ctx, problems, results_dev, params=None, stream=Non
     a uint8 device tensor of at least n * sizeof(icp_result) bytes that the
     stream fills (decode with results_from_bytes once it has finished).  The
     problems' tensors and results_dev must stay alive until then."""
+    res_ptr = _dev_ptr(results_dev, "uint8", "results_dev")
     p = params if params is not None else icp_params_default()
     if isinstance(problems, ProblemArray):
         n, arr = problems.n, problems.arr
@@ -385,7 +405,7 @@ def icp_register_batch_async(ctx, problems, results_dev, params=None, stream=Non
     if results_dev.numel() * results_dev.element_size() < n * C.sizeof(icp_result):
         raise ValueError("results_dev too small")
     rc = lib().icp_register_batch_async(ctx.handle, n, C.cast(arr, C.c_void_p), C.byref(p),
-                                        C.c_void_p(results_dev.data_ptr()), _stream(stream))
+                                        res_ptr, _stream(stream))
     _check(ctx, rc)
 
 
@@ -482,6 +502,22 @@ def icp_stage_moments(ctx, level, pose, k_lo, k_hi, params=None, stream=None):
                                  _np_ptr(n), _stream(stream))
     _check(ctx, rc)
     return M, int(n[0])
+
+
+def icp_stage_single_pass(ctx, level, pose, iter=0, pred_hi=-1, pred_hw=24, params=None, stream=None):
+    """Single-pass iteration at `level`: returns (hit, band[4], window(h0, width), moments[28], n)."""
+    p = params if params is not None else icp_params_default()
+    P12 = _f64(np.asarray(pose, dtype=np.float64)[:3, :4], 12, "pose")
+    band = np.zeros(4, np.int64)
+    win = np.zeros(2, np.int32)
+    hit = C.c_int(0)
+    M = np.zeros(28)
+    n = np.zeros(1, np.int64)
+    rc = lib().icp_stage_single_pass(ctx.handle, level, _np_ptr(P12), C.byref(p), int(iter), int(pred_hi),
+                                     int(pred_hw), _np_ptr(band), _np_ptr(win), C.byref(hit), _np_ptr(M), _np_ptr(n),
+                                     _stream(stream))
+    _check(ctx, rc)
+    return bool(hit.value), band, (int(win[0]), int(win[1])), M, int(n[0])
 
 
 def icp_stage_solve(ctx, moments, n, pose, params=None, stream=None):

@@ -114,7 +114,7 @@ int check_params(icp_ctx* ctx, const icp_params* p) {
     return ICP_OK;
 }
 
-int check_problem(icp_ctx* ctx, const icp_problem& q, int levels) {
+int check_problem(icp_ctx* ctx, const icp_problem& q, int levels, int use_imu_seed) {
     if (!q.live_depth || !q.model_vtx || !q.model_nrm) return fail(ctx, ICP_EINVAL, "input pointer is NULL");
     const int div = 1 << (levels - 1);
     if (q.W < 1 || q.H < 1 || q.W > ICP_MAX_DIM || q.H > ICP_MAX_DIM)
@@ -128,6 +128,11 @@ int check_problem(icp_ctx* ctx, const icp_problem& q, int levels) {
         if (!std::isfinite(q.imu_R[k])) return fail(ctx, ICP_EINVAL, "imu_R not finite");
     for (int k = 0; k < 12; ++k)
         if (!std::isfinite(q.init_pose[k])) return fail(ctx, ICP_EINVAL, "init_pose not finite");
+    // the pose lives in SE(3): the rotation the registration starts from must be one
+    if (!icpi::is_rotation(q.imu_R, 3))
+        return fail(ctx, ICP_EINVAL, "imu_R is not a rotation (|R^T R - I| > 1e-6 or det R <= 0)");
+    if (!use_imu_seed && !icpi::is_rotation(q.init_pose, 4))
+        return fail(ctx, ICP_EINVAL, "init_pose's rotation is not a rotation (|R^T R - I| > 1e-6 or det R <= 0)");
     return ICP_OK;
 }
 
@@ -152,6 +157,39 @@ struct Plan {
     size_t total = 0;
 };
 
+// Level sizes, tiles and level buffers of one problem of an n-problem batch:
+// the buffers' offsets come from take(bytes), its tiles are appended to the
+// flat tile ranges tiles[l], and the largest launch sizes are kept.
+template <class Take>
+void lay_out_problem(ProbDesc& d, int32_t W, int32_t H, int levels, const int32_t* tile_req, int nprob, int* tiles,
+                     int* max_vn, int* max_mp, int* max_q, Take&& take) {
+    for (int l = 0; l < levels; ++l) {
+        LevelDesc& L = d.lv[l];
+        L.W = W >> l;
+        L.H = H >> l;
+        L.npx = L.W * L.H;
+        L.ps = (L.npx + ICP_PLANE_ALIGN - 1) / ICP_PLANE_ALIGN * ICP_PLANE_ALIGN;
+        L.tile_px = pick_tile(L.npx, nprob, tile_req ? tile_req[l] : 0);
+        L.n_tiles = (L.npx + L.tile_px - 1) / L.tile_px;
+        L.tile_base = tiles[l];
+        tiles[l] += L.n_tiles;
+        max_vn[l] = std::max(max_vn[l], icpk::live_vn_blocks(L.W, L.H));
+        max_mp[l] = std::max(max_mp[l], icpk::model_blocks(L.W, L.H));
+        max_q[l] = std::max(max_q[l], L.W + L.H + 2);
+        const size_t S = (size_t)L.ps * sizeof(float);
+        L.Dw = reinterpret_cast<float*>(take(S));  // level 0: the filtered depth, when filtering
+        L.LV = reinterpret_cast<float*>(take(3 * S));
+        L.LN = reinterpret_cast<float*>(take(3 * S));
+        const size_t A = (size_t)L.npx * 3 * sizeof(float);
+        L.MVw = l > 0 ? reinterpret_cast<float*>(take(A)) : nullptr;
+        L.MNw = l > 0 ? reinterpret_cast<float*>(take(A)) : nullptr;
+        L.XQ = reinterpret_cast<double*>(take((size_t)(L.W + 1) * sizeof(double)));
+        L.YQ = reinterpret_cast<double*>(take((size_t)(L.H + 1) * sizeof(double)));
+        L.part = reinterpret_cast<float*>(take((size_t)L.n_tiles * ICP_PART_STRIDE * sizeof(float)));
+        L.part1 = reinterpret_cast<float*>(take((size_t)L.n_tiles * ICP_WIN_SLOTS * ICP_PART_STRIDE * sizeof(float)));
+    }
+}
+
 void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int32_t* tile_req, Plan& P) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -175,33 +213,9 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
     for (int p = 0; p < n; ++p) {
         ProbDesc& d = P.desc[p];
         d.st = reinterpret_cast<ProbState*>(P.off_state + sizeof(ProbState) * p);
-        for (int l = 0; l < levels; ++l) {
-            LevelDesc& L = d.lv[l];
-            L.W = W[p] >> l;
-            L.H = H[p] >> l;
-            L.npx = L.W * L.H;
-            L.ps = (L.npx + ICP_PLANE_ALIGN - 1) / ICP_PLANE_ALIGN * ICP_PLANE_ALIGN;
-            L.tile_px = pick_tile(L.npx, n, tile_req ? tile_req[l] : 0);
-            L.n_tiles = (L.npx + L.tile_px - 1) / L.tile_px;
-            L.tile_base = P.tiles[l];
-            P.tiles[l] += L.n_tiles;
-            P.max_vn[l] = std::max(P.max_vn[l], icpk::live_vn_blocks(L.W, L.H));
-            P.max_mp[l] = std::max(P.max_mp[l], icpk::model_blocks(L.W, L.H));
-            P.max_q[l] = std::max(P.max_q[l], L.W + L.H + 2);
-            for (int t = 0; t < L.n_tiles; ++t) P.owner[l].push_back(p);
-            const size_t S = (size_t)L.ps * sizeof(float);
-            L.Dw = reinterpret_cast<float*>(take(S));  // level 0: the filtered depth, when filtering
-            L.LV = reinterpret_cast<float*>(take(3 * S));
-            L.LN = reinterpret_cast<float*>(take(3 * S));
-            const size_t A = (size_t)L.npx * 3 * sizeof(float);
-            L.MVw = l > 0 ? reinterpret_cast<float*>(take(A)) : nullptr;
-            L.MNw = l > 0 ? reinterpret_cast<float*>(take(A)) : nullptr;
-            L.XQ = reinterpret_cast<double*>(take((size_t)(L.W + 1) * sizeof(double)));
-            L.YQ = reinterpret_cast<double*>(take((size_t)(L.H + 1) * sizeof(double)));
-            L.part = reinterpret_cast<float*>(take((size_t)L.n_tiles * ICP_PART_STRIDE * sizeof(float)));
-            L.part1 = reinterpret_cast<float*>(
-                take((size_t)L.n_tiles * ICP_WIN_SLOTS * ICP_PART_STRIDE * sizeof(float)));
-        }
+        lay_out_problem(d, W[p], H[p], levels, tile_req, n, P.tiles, P.max_vn, P.max_mp, P.max_q, take);
+        for (int l = 0; l < levels; ++l)
+            for (int t = 0; t < d.lv[l].n_tiles; ++t) P.owner[l].push_back(p);
     }
     for (int l = 0; l < levels; ++l) P.off_owner[l] = take(sizeof(int) * std::max(1, P.tiles[l]));
     P.total = off;
@@ -238,7 +252,7 @@ T* rebase(T* off, char* base) {
     return reinterpret_cast<T*>(base + reinterpret_cast<size_t>(off));
 }
 
-int ensure_workspace(icp_ctx* ctx, size_t bytes) {
+int ensure_workspace(icp_ctx* ctx, size_t bytes, bool exact = false) {
     if (ctx->budget && bytes > ctx->budget)
         return fail(ctx, ICP_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes exceeds the HBM budget");
     if (bytes <= ctx->ws_cap) return ICP_OK;
@@ -251,7 +265,9 @@ int ensure_workspace(icp_ctx* ctx, size_t bytes) {
     }
     ctx->owners_key.clear();
     drop_graph(ctx);
-    size_t want = bytes + bytes / 4;
+    // growth margin so that slightly larger batches reuse the allocation; none
+    // when the caller sized the request itself
+    size_t want = exact ? bytes : bytes + bytes / 4;
     if (ctx->budget) want = std::min(want, ctx->budget);
     hipError_t e = hipMalloc(&ctx->ws, want);
     if (e != hipSuccess) {
@@ -339,6 +355,38 @@ KParams kparams(const icp_params* p) {
     return k;
 }
 
+// A laid-out descriptor (pointers holding workspace offsets) made absolute
+// against the workspace base, with the problem's inputs, level intrinsics
+// (the pixel centre of a level-(l+1) pixel is the mean of its children's:
+// f / 2^l, (c + 1/2) / 2^l - 1/2), IMU prior and initial pose.
+void bind_problem(ProbDesc& d, const icp_problem& q, int levels, int depth_filter, char* base) {
+    d.st = rebase(d.st, base);
+    for (int l = 0; l < levels; ++l) {
+        LevelDesc& L = d.lv[l];
+        const double s2 = std::ldexp(1.0, -l);
+        L.fx = q.K.fx * s2;
+        L.fy = q.K.fy * s2;
+        L.cx = (q.K.cx + 0.5) * s2 - 0.5;
+        L.cy = (q.K.cy + 0.5) * s2 - 0.5;
+        L.Dw = rebase(L.Dw, base);
+        L.D = (l > 0 || depth_filter) ? L.Dw : q.live_depth;
+        L.LV = rebase(L.LV, base);
+        L.LN = rebase(L.LN, base);
+        L.MVw = l > 0 ? rebase(L.MVw, base) : nullptr;
+        L.MNw = l > 0 ? rebase(L.MNw, base) : nullptr;
+        L.MV = l > 0 ? L.MVw : q.model_vtx;
+        L.MN = l > 0 ? L.MNw : q.model_nrm;
+        L.XQ = rebase(L.XQ, base);
+        L.YQ = rebase(L.YQ, base);
+        L.part = rebase(L.part, base);
+        L.part1 = rebase(L.part1, base);
+    }
+    d.depth_in = q.live_depth;
+    std::memcpy(d.imu_R, q.imu_R, sizeof(d.imu_R));
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 4; ++j) d.init[4 * i + j] = q.init_pose[4 * i + j];
+}
+
 // Plan, place and upload a batch; leaves device descriptors ready.
 int stage_batch(icp_ctx* ctx, int n, const icp_problem* probs, int levels, const int32_t* tile_req,
                 int depth_filter, Plan& P, hipStream_t s) {
@@ -365,35 +413,7 @@ int stage_batch(icp_ctx* ctx, int n, const icp_problem* probs, int levels, const
     int rc = ensure_workspace(ctx, P.total);
     if (rc) return rc;
     char* base = static_cast<char*>(ctx->ws);
-    for (int p = 0; p < n; ++p) {
-        ProbDesc& d = P.desc[p];
-        const icp_problem& q = probs[p];
-        d.st = rebase(d.st, base);
-        for (int l = 0; l < levels; ++l) {
-            LevelDesc& L = d.lv[l];
-            const double s2 = std::ldexp(1.0, -l);
-            L.fx = q.K.fx * s2;
-            L.fy = q.K.fy * s2;
-            L.cx = (q.K.cx + 0.5) * s2 - 0.5;
-            L.cy = (q.K.cy + 0.5) * s2 - 0.5;
-            L.Dw = rebase(L.Dw, base);
-            L.D = (l > 0 || depth_filter) ? L.Dw : q.live_depth;
-            L.LV = rebase(L.LV, base);
-            L.LN = rebase(L.LN, base);
-            L.MVw = l > 0 ? rebase(L.MVw, base) : nullptr;
-            L.MNw = l > 0 ? rebase(L.MNw, base) : nullptr;
-            L.MV = l > 0 ? L.MVw : q.model_vtx;
-            L.MN = l > 0 ? L.MNw : q.model_nrm;
-            L.XQ = rebase(L.XQ, base);
-            L.YQ = rebase(L.YQ, base);
-            L.part = rebase(L.part, base);
-            L.part1 = rebase(L.part1, base);
-        }
-        d.depth_in = q.live_depth;
-        std::memcpy(d.imu_R, q.imu_R, sizeof(d.imu_R));
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 4; ++j) d.init[4 * i + j] = q.init_pose[4 * i + j];
-    }
+    for (int p = 0; p < n; ++p) bind_problem(P.desc[p], probs[p], levels, depth_filter, base);
     const size_t up = sizeof(ProbDesc) * n;
     const bool owners = ctx->owners_key != key;
     size_t owner_bytes = 0;
@@ -466,22 +486,35 @@ int resolve_timing(icp_ctx* ctx) {
     return ICP_OK;
 }
 
-// Whole registration of a staged batch; results into `res_dev` (device).
-int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* res_dev, hipStream_t s) {
-    char* base = static_cast<char*>(ctx->ws);
-    const ProbDesc* d_desc = reinterpret_cast<const ProbDesc*>(base + P.off_desc);
+// Where the launches of a registration find their device data.
+struct Launches {
+    const ProbDesc* d_desc;
+    int32_t* need2;                        // batch flag: some problem needs pass 2
+    const int* owner[ICP_MAX_LEVELS];      // problem of every flat tile, per level
+    int tiles[ICP_MAX_LEVELS];
+    const int* max_vn;                     // largest launch sizes per level
+    const int* max_mp;
+    const int* max_q;
+    int64_t px[ICP_MAX_LEVELS];            // pixels of all problems per level (kernel timing)
+};
+
+// Every launch of a registration of n problems on s, results into `res_dev`
+// (device).  ctx may be NULL (no kernel timing, no error message).
+int launch_registration(icp_ctx* ctx, int n, const icp_params* prm, const Launches& G, icp_result* res_dev,
+                        hipStream_t s) {
+    const ProbDesc* d_desc = G.d_desc;
     KParams kp = kparams(prm);
-    kp.need2 = reinterpret_cast<int32_t*>(base + P.off_flags);
+    kp.need2 = G.need2;
     int rc;
     icp_ctx::EvRec r;
+    const bool timed = ctx && ctx->timing;
+    auto begin = [&](int kind, int64_t px) { return timed ? time_begin(ctx, s, r, kind, px) : ICP_OK; };
+    auto end = [&]() { return timed ? time_end(ctx, s, r) : ICP_OK; };
     HIP_TRY(ctx, icpk::launch_init(d_desc, n, prm->use_imu_seed, kp.need2, s));
-    int64_t px0 = 0;
-    for (int p = 0; p < n; ++p) px0 += P.desc[p].lv[0].npx;
-    if ((rc = time_begin(ctx, s, r, ICP_TIME_FRONT_END, px0))) return rc;
-    HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, P.max_vn, P.max_mp, P.max_q, false,
-                                      front_end(prm), s));
+    if ((rc = begin(ICP_TIME_FRONT_END, G.px[0]))) return rc;
+    HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, G.max_vn, G.max_mp, G.max_q, false, front_end(prm), s));
     if (prm->reduce_mode == 1) HIP_TRY(ctx, icpk::launch_centroid(d_desc, n, prm->levels, s));
-    if ((rc = time_end(ctx, s, r))) return rc;
+    if ((rc = end())) return rc;
     // single pass needs the band's lower edge at bin 0 and the FP32 reduction
     const int fused = prm->pass_mode == 0 && prm->reduce_mode == 0 &&
                               (!prm->use_median_filter || prm->band_beta >= 1.0)
@@ -492,28 +525,44 @@ int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* r
     // the iterations the window missed) and one launch per iteration goes
     kp.fold_solve = fused && n == 1 ? 1 : 0;
     for (int l = prm->levels - 1; l >= 0; --l) {
-        const int* owner = reinterpret_cast<const int*>(base + P.off_owner[l]);
-        int64_t px = 0;
-        for (int p = 0; p < n; ++p) px += P.desc[p].lv[l].npx;
+        const int* owner = G.owner[l];
+        const int64_t px = G.px[l];
         for (int it = 0; it < prm->iters[l]; ++it) {
             IterCtl ctl{l, it, it == prm->iters[l] - 1 ? 1 : 0, 0};
-            if ((rc = time_begin(ctx, s, r, ICP_TIME_PASS1, px))) return rc;
-            HIP_TRY(ctx, icpk::launch_pass1(d_desc, owner, P.tiles[l], ctl, kp, fused, s));
-            if ((rc = time_end(ctx, s, r))) return rc;
-            if ((rc = time_begin(ctx, s, r, ICP_TIME_BAND, 0))) return rc;
+            if ((rc = begin(ICP_TIME_PASS1, px))) return rc;
+            HIP_TRY(ctx, icpk::launch_pass1(d_desc, owner, G.tiles[l], ctl, kp, fused, s));
+            if ((rc = end())) return rc;
+            if ((rc = begin(ICP_TIME_BAND, 0))) return rc;
             HIP_TRY(ctx, icpk::launch_band(d_desc, n, ctl, kp, fused, s));
-            if ((rc = time_end(ctx, s, r))) return rc;
-            if ((rc = time_begin(ctx, s, r, ICP_TIME_PASS2, px))) return rc;
-            HIP_TRY(ctx, icpk::launch_pass2(d_desc, owner, P.tiles[l], ctl, kp, s));
-            if ((rc = time_end(ctx, s, r))) return rc;
+            if ((rc = end())) return rc;
+            if ((rc = begin(ICP_TIME_PASS2, px))) return rc;
+            HIP_TRY(ctx, icpk::launch_pass2(d_desc, owner, G.tiles[l], ctl, kp, s));
+            if ((rc = end())) return rc;
             if (kp.fold_solve) continue;
-            if ((rc = time_begin(ctx, s, r, ICP_TIME_SOLVE, 0))) return rc;
+            if ((rc = begin(ICP_TIME_SOLVE, 0))) return rc;
             HIP_TRY(ctx, icpk::launch_solve(d_desc, n, ctl, kp, s));
-            if ((rc = time_end(ctx, s, r))) return rc;
+            if ((rc = end())) return rc;
         }
     }
     HIP_TRY(ctx, icpk::launch_finalize(d_desc, n, res_dev, s));
     return ICP_OK;
+}
+
+// Whole registration of a staged batch; results into `res_dev` (device).
+int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* res_dev, hipStream_t s) {
+    char* base = static_cast<char*>(ctx->ws);
+    Launches G{};
+    G.d_desc = reinterpret_cast<const ProbDesc*>(base + P.off_desc);
+    G.need2 = reinterpret_cast<int32_t*>(base + P.off_flags);
+    for (int l = 0; l < prm->levels; ++l) {
+        G.owner[l] = reinterpret_cast<const int*>(base + P.off_owner[l]);
+        G.tiles[l] = P.tiles[l];
+        for (int p = 0; p < n; ++p) G.px[l] += P.desc[p].lv[l].npx;
+    }
+    G.max_vn = P.max_vn;
+    G.max_mp = P.max_mp;
+    G.max_q = P.max_q;
+    return launch_registration(ctx, n, prm, G, res_dev, s);
 }
 
 // Launch the whole registration of a staged batch on s, results into the
@@ -611,6 +660,18 @@ void icp_params_default(icp_params* p) {
     p->reserved = 0;
 }
 
+int icp_validate_problem(const icp_problem* problem, const icp_params* params, char* msg, size_t msg_len) {
+    icp_ctx tmp;  // holds the message only: no device state is touched
+    int rc = problem ? check_params(&tmp, params) : fail(&tmp, ICP_EINVAL, "problem is NULL");
+    if (rc == ICP_OK) rc = check_problem(&tmp, *problem, params->levels, params->use_imu_seed);
+    if (msg && msg_len > 0) {
+        const size_t n = std::min(msg_len - 1, tmp.err.size());
+        std::memcpy(msg, tmp.err.data(), n);
+        msg[n] = '\0';
+    }
+    return rc;
+}
+
 int icp_ctx_create(int device, size_t hbm_budget_bytes, icp_ctx** out) {
     if (!out) return ICP_EINVAL;
     *out = nullptr;
@@ -698,7 +759,7 @@ int batch_submit(icp_ctx* ctx, int n, const icp_problem* probs, const icp_params
     int rc = check_params(ctx, params);
     if (rc) return rc;
     for (int p = 0; p < n; ++p)
-        if ((rc = check_problem(ctx, probs[p], params->levels))) return rc;
+        if ((rc = check_problem(ctx, probs[p], params->levels, params->use_imu_seed))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     StreamTurn turn;
     if (const int trc = turn.enter(ctx, s)) return trc;
@@ -856,6 +917,8 @@ int check_camera(icp_ctx* ctx, int W, int H, const icp_intrinsics* K, const doub
         if (!std::isfinite(T_wc[i])) return fail(ctx, ICP_EINVAL, "T_wc must be finite");
         T->v[i] = T_wc[i];
     }
+    if (!icpi::is_rotation(T_wc, 4))
+        return fail(ctx, ICP_EINVAL, "T_wc's rotation is not a rotation (|R^T R - I| > 1e-6 or det R <= 0)");
     return ICP_OK;
 }
 
@@ -924,7 +987,7 @@ int icp_register_async(icp_ctx* ctx, const float* live_depth, int W, int H, cons
     int rc = check_params(ctx, params);
     if (rc) return rc;
     icp_problem q = one_problem(live_depth, W, H, model_vtx, model_nrm, K, imu_R, init_pose);
-    if ((rc = check_problem(ctx, q, params->levels))) return rc;
+    if ((rc = check_problem(ctx, q, params->levels, params->use_imu_seed))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     StreamTurn turn;
@@ -952,7 +1015,7 @@ int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const
     int rc = check_params(ctx, prm);
     if (rc) return rc;
     icp_problem q = one_problem(live_depth, W, H, model_vtx, model_nrm, K, nullptr, nullptr);
-    if ((rc = check_problem(ctx, q, levels))) return rc;
+    if ((rc = check_problem(ctx, q, levels, 1))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     StreamTurn turn;
@@ -1028,7 +1091,7 @@ int icp_stage_associate(icp_ctx* ctx, int level, const double* pose12, const icp
     if (const int trc = turn.enter(ctx, s)) return trc;
     const KParams kp = kparams(params);
     uint32_t* d_hist = reinterpret_cast<uint32_t*>(ctx->d_scratch);
-    HIP_TRY(ctx, icpk::launch_stage_set(ctx->d_desc, pose_arg(pose12), 0, -1, level, s));
+    HIP_TRY(ctx, icpk::launch_stage_set(ctx->d_desc, pose_arg(pose12), 0, -1, level, -1, ICP_WIN / 2, s));
     IterCtl ctl{level, 0, 0, 0};
     HIP_TRY(ctx, icpk::launch_stage_pass1(ctx->d_desc, ctx->d_owner[level], ctx->tiles[level], ctl, kp, code, bin,
                                           d_hist, s));
@@ -1058,12 +1121,54 @@ int icp_stage_moments(icp_ctx* ctx, int level, const double* pose12, const icp_p
     StreamTurn turn;
     if (const int trc = turn.enter(ctx, s)) return trc;
     const KParams kp = kparams(params);
-    HIP_TRY(ctx, icpk::launch_stage_set(ctx->d_desc, pose_arg(pose12), k_lo, k_hi, level, s));
+    HIP_TRY(ctx, icpk::launch_stage_set(ctx->d_desc, pose_arg(pose12), k_lo, k_hi, level, -1, ICP_WIN / 2, s));
     IterCtl ctl{level, 0, 0, 1};
     HIP_TRY(ctx, icpk::launch_stage_pass2(ctx->d_desc, ctx->d_owner[level], ctx->tiles[level], ctl, kp, s));
     HIP_TRY(ctx, hipMemcpyAsync(moments, ctx->d_state->M, sizeof(double) * ICP_NMOM, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipMemcpyAsync(n, &ctx->d_state->n_last, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
+    return ICP_OK;
+}
+
+int icp_stage_single_pass(icp_ctx* ctx, int level, const double* pose12, const icp_params* params, int iter,
+                          int pred_hi, int pred_hw, int64_t* band, int32_t* window, int* hit, double* moments,
+                          int64_t* n, void* stream) {
+    int rc = stage_check(ctx, level);
+    if (rc) return rc;
+    if (!pose12 || !band || !window || !hit || !moments || !n) return fail(ctx, ICP_EINVAL, "NULL argument");
+    if ((rc = check_params(ctx, params))) return rc;
+    if (params->reduce_mode != 0 || (params->use_median_filter && params->band_beta < 1.0))
+        return fail(ctx, ICP_EINVAL, "the single pass needs reduce_mode 0 and band_beta >= 1 (or no median filter)");
+    if (iter < 0 || pred_hi < -1 || pred_hi >= ICP_HIST_BINS || (iter > 0 && (pred_hw < 1 || pred_hw > ICP_WIN / 2)))
+        return fail(ctx, ICP_EINVAL, "iter >= 0, pred_hi in -1..1023 and (iter > 0) pred_hw in 1..24");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamTurn turn;
+    if (const int trc = turn.enter(ctx, s)) return trc;
+    const KParams kp = kparams(params);
+    int32_t* d_win = reinterpret_cast<int32_t*>(ctx->d_scratch);
+    HIP_TRY(ctx, icpk::launch_stage_set(ctx->d_desc, pose_arg(pose12), 0, -1, level, pred_hi,
+                                        iter > 0 ? pred_hw : ICP_WIN / 2, s));
+    IterCtl ctl{level, iter, 0, 1};
+    HIP_TRY(ctx, icpk::launch_stage_single(ctx->d_desc, ctx->d_owner[level], ctx->tiles[level], ctl, kp, d_win, s));
+    int32_t bandv[4], win[2], fused = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(bandv, &ctx->d_state->N, sizeof(bandv), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(win, d_win, sizeof(win), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(&fused, &ctx->d_state->fused_done, sizeof(fused), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(moments, ctx->d_state->M, sizeof(double) * ICP_NMOM, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(n, &ctx->d_state->n_last, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    band[0] = (int64_t)(uint32_t)bandv[0];
+    band[1] = bandv[1];
+    band[2] = bandv[2];
+    band[3] = bandv[3];
+    window[0] = win[0];
+    window[1] = win[1];
+    *hit = fused;
+    if (!fused) {
+        for (int k = 0; k < ICP_NMOM; ++k) moments[k] = 0.0;
+        *n = 0;
+    }
     return ICP_OK;
 }
 
@@ -1109,7 +1214,7 @@ int register_batch_async(icp_ctx* ctx, int n, const icp_problem* probs, const ic
     int rc = check_params(ctx, params);
     if (rc) return rc;
     for (int p = 0; p < n; ++p)
-        if ((rc = check_problem(ctx, probs[p], params->levels))) return rc;
+        if ((rc = check_problem(ctx, probs[p], params->levels, params->use_imu_seed))) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     Plan& P = ctx_plan(ctx);
     if ((rc = stage_batch(ctx, n, probs, params->levels, params->tile_px, params->depth_filter, P, s))) return rc;
@@ -1123,7 +1228,16 @@ int register_batch_async(icp_ctx* ctx, int n, const icp_problem* probs, const ic
 int reserve_workspace(icp_ctx* ctx, size_t bytes) {
     if (!ctx) return ICP_EINVAL;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    return ensure_workspace(ctx, bytes);
+    return ensure_workspace(ctx, bytes, true);
+}
+
+size_t workspace_bound(int n, const int32_t* W, const int32_t* H, int levels, const int32_t* tile_px) {
+    if (n < 1 || !W || !H || levels < 1 || levels > ICP_MAX_LEVELS) return 0;
+    int32_t req[ICP_MAX_LEVELS];
+    for (int l = 0; l < ICP_MAX_LEVELS; ++l) req[l] = (tile_px && tile_px[l] > 0) ? tile_px[l] : ICP_TILE_QUANTUM;
+    Plan P;
+    make_plan(n, W, H, levels, req, P);
+    return P.total;
 }
 
 int validate_params(icp_ctx* ctx, const icp_params* params) { return check_params(ctx, params); }

@@ -437,7 +437,10 @@ __global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restric
     const int rows = 2 * vb + 1 < C.H ? 2 : 1;
     const ICP_GLOBAL float* MV = gconst(F.MV);
     const ICP_GLOBAL float* MN = gconst(F.MN);
-    const bool vec = two && ((reinterpret_cast<uintptr_t>(F.MV) | reinterpret_cast<uintptr_t>(F.MN)) & 15) == 0;
+    // 16-byte row loads need every row start aligned too: row r starts 3 r W
+    // floats in, a multiple of four for any r only when W is
+    const bool vec = two && (F.W & 3) == 0 &&
+                     ((reinterpret_cast<uintptr_t>(F.MV) | reinterpret_cast<uintptr_t>(F.MN)) & 15) == 0;
     ICP_GLOBAL float* MVo = gmut(C.MVw);
     ICP_GLOBAL float* MNo = gmut(C.MNw);
     float kv[4][3], kn[4][3];  // the block's level-l values, row-major
@@ -1186,7 +1189,8 @@ __global__ void k_finalize(const ProbDesc* __restrict__ probs, int n, icp_result
 
 // ------------------------------------------------------------------ stage access
 
-__global__ void k_stage_set(const ProbDesc* __restrict__ probs, PoseArg pose, int k_lo, int k_hi, int level) {
+__global__ void k_stage_set(const ProbDesc* __restrict__ probs, PoseArg pose, int k_lo, int k_hi, int level,
+                            int pred_hi, int pred_hw) {
     ProbState* st = probs[0].st;
     for (int b = threadIdx.x; b < ICP_HIST_BINS; b += blockDim.x) st->hist[b] = 0u;
     if (threadIdx.x == 0) {
@@ -1196,12 +1200,22 @@ __global__ void k_stage_set(const ProbDesc* __restrict__ probs, PoseArg pose, in
         }
         st->k_lo = k_lo;
         st->k_hi = k_hi;
-        st->pred_hi = -1;
-        st->pred_hw = ICP_WIN / 2;
+        st->pred_hi = pred_hi;
+        st->pred_hw = pred_hw;
         st->fused_done = 0;
         st->level_done = 0;
         set_centre(st, level);
     }
+}
+
+// The band-edge window that pass 1 used for problem 0 (h0, width), read before
+// the band kernel replaces the prediction.
+__global__ void k_stage_window(const ProbDesc* __restrict__ probs, IterCtl ctl, int32_t* out) {
+    if (threadIdx.x != 0) return;
+    const ProbState* st = probs[0].st;
+    const Win w = band_window(st->pred_hi, st->pred_hw, ctl.iter);
+    out[0] = w.h0;
+    out[1] = w.w;
 }
 
 __global__ void k_stage_solve(MomArg M, int64_t n, PoseArg pose, KParams kp, double* out) {
@@ -1325,8 +1339,18 @@ hipError_t launch_finalize(const ProbDesc* probs, int n, icp_result* results, hi
     return hipGetLastError();
 }
 
-hipError_t launch_stage_set(const ProbDesc* probs, PoseArg pose, int k_lo, int k_hi, int level, hipStream_t s) {
-    hipLaunchKernelGGL(k_stage_set, dim3(1), dim3(ICP_WG), 0, s, probs, pose, k_lo, k_hi, level);
+hipError_t launch_stage_set(const ProbDesc* probs, PoseArg pose, int k_lo, int k_hi, int level, int pred_hi,
+                            int pred_hw, hipStream_t s) {
+    hipLaunchKernelGGL(k_stage_set, dim3(1), dim3(ICP_WG), 0, s, probs, pose, k_lo, k_hi, level, pred_hi, pred_hw);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_single(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
+                               int32_t* window, hipStream_t s) {
+    hipLaunchKernelGGL((k_pass1<false, true>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp, nullptr,
+                       nullptr);
+    hipLaunchKernelGGL(k_stage_window, dim3(1), dim3(64), 0, s, probs, ctl, window);
+    hipLaunchKernelGGL(k_band, dim3(1), dim3(ICP_WG), 0, s, probs, ctl, kp, 1, nullptr);
     return hipGetLastError();
 }
 

@@ -47,7 +47,13 @@ hipError_t launch_solve(const ProbDesc* probs, int n, IterCtl ctl, const KParams
 hipError_t launch_finalize(const ProbDesc* probs, int n, icp_result* results, hipStream_t s);
 
 // stage access (problem 0 of `probs`)
-hipError_t launch_stage_set(const ProbDesc* probs, PoseArg pose, int k_lo, int k_hi, int level, hipStream_t s);
+hipError_t launch_stage_set(const ProbDesc* probs, PoseArg pose, int k_lo, int k_hi, int level, int pred_hi,
+                            int pred_hw, hipStream_t s);
+// the single-pass iteration's pass 1 (band-edge window partials) and band
+// kernel (moments from the partials when the edge fell in the window), with
+// the window's (h0, width) written to window[2] (device)
+hipError_t launch_stage_single(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
+                               int32_t* window, hipStream_t s);
 hipError_t launch_stage_pass1(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
                               uint8_t* code, int32_t* bin, uint32_t* hist, hipStream_t s);
 hipError_t launch_stage_pass2(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,

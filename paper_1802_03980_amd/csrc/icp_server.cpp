@@ -126,22 +126,25 @@ int srv_fail(icp_server* s, int code, const std::string& m) {
     return code;
 }
 
-// Workspace of the largest batch the given streams can form (at most
-// max_batch of them, the largest first), with the context's growth margin.
-size_t batch_workspace(const std::vector<Stream*>& ss, int max_batch, int levels) {
+// Workspace that any batch the given streams can form fits in: a batch holds
+// up to frames_in_flight frames of each stream and at most max_batch frames,
+// so the largest frames_in_flight copies of every stream, largest first, cut
+// at max_batch, planned with the parameters' tiles or the smallest tile
+// (a batch of fewer problems picks smaller tiles and so needs more partials).
+size_t batch_workspace(const std::vector<Stream*>& ss, const icp_server_config& cfg) {
     std::vector<std::pair<int, int>> wh;
     for (Stream* st : ss)
-        if (st && !st->closing) wh.push_back({st->W, st->H});
+        if (st && !st->closing)
+            for (int f = 0; f < cfg.frames_in_flight; ++f) wh.push_back({st->W, st->H});
     if (wh.empty()) return 0;
     std::sort(wh.begin(), wh.end(), [](auto a, auto b) { return (long)a.first * a.second > (long)b.first * b.second; });
-    if ((int)wh.size() > max_batch) wh.resize(max_batch);
+    if ((int)wh.size() > cfg.max_batch) wh.resize(cfg.max_batch);
     std::vector<int32_t> W, H;
     for (auto& p : wh) {
         W.push_back(p.first);
         H.push_back(p.second);
     }
-    const size_t b = icp_workspace_bytes((int)W.size(), W.data(), H.data(), levels);
-    return b + b / 4;
+    return icpi::workspace_bound((int)W.size(), W.data(), H.data(), cfg.params.levels, cfg.params.tile_px);
 }
 
 size_t stream_bytes(int W, int H, int ring) {
@@ -480,7 +483,7 @@ int icp_server_open_stream(icp_server* S, int W, int H, const icp_intrinsics* K,
     // admission: resident state of all streams + per-slot workspace of the largest batch
     std::vector<Stream*> with = S->streams;
     with.push_back(st);
-    const size_t ws = batch_workspace(with, S->cfg.max_batch, S->cfg.params.levels);
+    const size_t ws = batch_workspace(with, S->cfg);
     const size_t need = S->resident + st->bytes + ws * S->slots.size();
     if (S->cfg.hbm_budget_bytes && need > S->cfg.hbm_budget_bytes) {
         delete st;
@@ -517,7 +520,7 @@ int icp_server_close_stream(icp_server* S, int id) {
         free_stream(st);
     }
     // the per-slot workspace already reserved stays; admission counts the streams left
-    S->ws_need = batch_workspace(S->streams, S->cfg.max_batch, S->cfg.params.levels);
+    S->ws_need = batch_workspace(S->streams, S->cfg);
     return ICP_OK;
 }
 
@@ -526,6 +529,8 @@ int icp_server_submit(icp_server* S, int id, const float* depth_host, const doub
     if (!S || !depth_host || !imu_rel_R) return ICP_EINVAL;
     for (int k = 0; k < 9; ++k)
         if (!std::isfinite(imu_rel_R[k])) return srv_fail(S, ICP_EINVAL, "imu_rel_R not finite");
+    if (!icpi::is_rotation(imu_rel_R, 3))
+        return srv_fail(S, ICP_EINVAL, "imu_rel_R is not a rotation (|R^T R - I| > 1e-6 or det R <= 0)");
     float* buf = nullptr;
     size_t bytes = 0;
     {
@@ -587,6 +592,8 @@ int icp_server_get_counters(icp_server* S, icp_server_counters* out) {
     *out = S->ctr;
     out->resident_bytes = S->resident;
     out->workspace_bytes = S->ws_need * S->slots.size();
+    out->workspace_held_bytes = 0;
+    for (const Slot& sl : S->slots) out->workspace_held_bytes += icp_ctx_workspace_bytes(sl.ctx);
     int open = 0;
     for (Stream* st : S->streams)
         if (st) ++open;

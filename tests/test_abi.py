@@ -77,3 +77,42 @@ def test_public_struct_sizes_match_the_c_compiler(tmp_path):
     sizes = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     for n, sz in zip(names, sizes):
         assert C.sizeof(getattr(icp, n)) == sz, n
+
+
+def test_rotations_are_checked_at_the_boundary():
+    """The pose is an element of SE(3) (Sec. 3): imu_R, and the initial
+    rotation when the IMU seed is off, must be rotations (|R^T R - I| <= 1e-6
+    entry by entry, det R > 0); the host-only validation makes the same checks
+    as a registration call, so no GPU is needed here."""
+    K = (525.0, 525.0, 319.5, 239.5)
+    R = np.array([[0.36, 0.48, -0.8], [-0.8, 0.6, 0.0], [0.48, 0.64, 0.6]])  # a rotation
+    T = np.eye(4)
+    assert icp.icp_validate_problem(640, 480, K, R, T)[0] == icp.OK
+    # first-order rounding well inside the tolerance still passes
+    assert icp.icp_validate_problem(640, 480, K, R * (1 + 1e-9), T)[0] == icp.OK
+    for bad in (R * 1.001, -R, R[[1, 0, 2]], R + np.diag([2e-6, 0, 0]), np.full((3, 3), np.nan)):
+        rc, msg = icp.icp_validate_problem(640, 480, K, bad, T)
+        assert rc == icp.EINVAL and ("rotation" in msg or "finite" in msg), msg
+    # the initial rotation counts only when the IMU seed is off
+    Tbad = np.eye(4)
+    Tbad[:3, :3] = R * 1.01
+    assert icp.icp_validate_problem(640, 480, K, R, Tbad)[0] == icp.OK
+    rc, msg = icp.icp_validate_problem(640, 480, K, R, Tbad, icp.icp_params_default(use_imu_seed=0))
+    assert rc == icp.EINVAL and "init_pose" in msg
+    # the other host checks of a problem
+    assert icp.icp_validate_problem(642, 480, K, R, T)[0] == icp.EINVAL  # not divisible by 4
+    assert icp.icp_validate_problem(640, 480, (0.0, 525.0, 319.5, 239.5), R, T)[0] == icp.EINVAL
+    assert icp.icp_validate_problem(640, 480, K, R, T, icp.icp_params_default(levels=5))[0] == icp.EINVAL
+
+
+def test_async_results_must_be_device_tensors():
+    """The asynchronous calls copy their results device to device: a host
+    tensor (or one of another dtype) is refused before the library is called."""
+    import torch
+    host = torch.zeros(4096, dtype=torch.uint8)
+    d = torch.zeros((8, 8), dtype=torch.float32)
+    m = torch.zeros((8, 8, 3), dtype=torch.float32)
+    with pytest.raises(TypeError, match="result_dev"):
+        icp.icp_register_async(None, d, m, m, (1, 1, 1, 1), np.eye(3), np.eye(4), host)
+    with pytest.raises(TypeError, match="results_dev"):
+        icp.icp_register_batch_async(None, [], host)

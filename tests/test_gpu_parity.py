@@ -18,6 +18,7 @@ import torch
 import oracle
 import paper_1802_03980_amd as icp
 import synth
+from tests.parity_util import assert_registration_matches, oracle_params
 from tests.poseutil import pose_err
 
 pytestmark = pytest.mark.gpu
@@ -100,6 +101,19 @@ def test_s1_four_level_pyramid_bitwise(ctx):
         assert np.isfinite(gpu[l]["MV"]).mean() > 0.5, l
 
 
+def test_s1_pyramid_width_two_mod_four(ctx):
+    """Level-0 width 162 (2 mod 4): every second row of the model maps starts
+    8 bytes off a 16-byte boundary, so the model pyramid must read them with
+    scalar loads; two levels, bitwise."""
+    prob = synth.pair_problem(9, W=162, H=122, f=131.6)
+    gpu = _gpu_levels(ctx, prob, levels=2)
+    ref = oracle.pyramids(prob.live_depth, prob.model_vtx, prob.model_nrm, prob.K, 2)
+    for l in range(2):
+        for key in ("D", "LV", "LN", "MV", "MN"):
+            assert _same_nan(gpu[l][key], ref[l][key]), (l, key)
+    assert np.isfinite(gpu[1]["MV"]).mean() > 0.5
+
+
 FRONT_ENDS = {"filter": dict(depth_filter=1), "box_normals": dict(normal_mode=1),
               "both": dict(depth_filter=1, normal_mode=1, normal_radius=3)}
 
@@ -149,12 +163,8 @@ def test_s1_front_end_radii_bitwise(ctx, r):
 def test_end_to_end_front_end_modes(ctx, mode):
     params = icp.icp_params_default(**FRONT_ENDS[mode])
     for prob in [synth.pair_problem(1), synth.RoomSequence(0, n_frames=2).problem(0)]:
-        Tg, sg, To, so = _register_both(ctx, prob, params)
-        ang, dt = pose_err(Tg, To)
-        assert ang < POSE_TOL and dt < POSE_TOL, (mode, prob.name, ang, dt)
-        for l in range(3):
-            assert sg["levels"][l]["iters_run"] == so[l]["iters_run"]
-            assert abs(sg["levels"][l]["n_kept"] - so[l]["n_kept"]) <= max(2, 1e-3 * so[l]["n_kept"])
+        Tg, sg = _register_gpu(ctx, prob, params)
+        assert_registration_matches(prob, params, Tg, sg, f"{mode} {prob.name}")
 
 
 def _poses_for(prob):
@@ -221,6 +231,88 @@ def test_s3_moments(ctx, name, reduce_mode):
             assert np.all(err <= tol), f"level {level}: worst ratio {np.max(err / tol):.3g}"
 
 
+def _window_cases(k_hi, hw_full=24):
+    """(iter, pred_hi, pred_hw) placing a window so that the band edge k_hi
+    falls just below it (h0 - 1), in its middle, on its last bin, above it and
+    below it (misses), with the full first-iteration window and with a
+    narrowed later one."""
+    cases = [(0, k_hi + 1 + hw_full, hw_full), (0, k_hi, hw_full), (0, k_hi - hw_full + 1, hw_full),
+             (0, k_hi - hw_full - 6, hw_full), (0, k_hi + hw_full + 16, hw_full),
+             (3, k_hi, 6), (3, k_hi + 7, 6), (3, k_hi - 5, 6), (5, k_hi - 7, 6)]
+    return [(it, max(-1, min(1023, ph)), hw) for it, ph, hw in cases]
+
+
+def _check_single_pass(ctx, prob, gpu_lv, level, T, params, cases, tag):
+    _, band = _check_associate(ctx, prob, gpu_lv, level, T, params)
+    N, kmed, klo, khi = (int(v) for v in band)
+    code, bins, pp, q, nq = oracle.pairs(gpu_lv[level], T, params.dist_max, params.cos_angle_max)
+    hits = 0
+    for it, pred_hi, hw in cases:
+        hit, band_g, (h0, w), Mg, ng = icp.icp_stage_single_pass(ctx, level, T, it, pred_hi, hw, params)
+        assert list(band_g) == [N, kmed, klo, khi], (tag, level, it, pred_hi)
+        hw_used = 24 if it == 0 else hw
+        want_h0 = -1 if pred_hi < 0 else min(max(pred_hi - hw_used, 0), 1024 - 2 * hw_used)
+        assert (h0, w) == (want_h0, 0 if pred_hi < 0 else 2 * hw_used), (tag, level, it, pred_hi, h0, w)
+        want_hit = h0 >= 0 and N > 0 and klo == 0 and h0 - 1 <= khi <= h0 + w - 1
+        assert hit == want_hit, (tag, level, it, pred_hi, h0, w, khi)
+        if not hit:
+            continue
+        hits += 1
+        Mo, no = oracle.moments(gpu_lv[level], T, klo, khi, params.dist_max, params.cos_angle_max)
+        assert ng == no, (tag, level, it, pred_hi, ng, no)
+        keep = (code == oracle.GATED) & (bins >= klo) & (bins <= khi)
+        tol = 1e-5 * _abs_terms(pp[keep], q[keep], nq[keep]) + 1e-30
+        err = np.abs(Mg - Mo)
+        assert np.all(err <= tol), f"{tag} level {level} window ({h0}, {w}) edge {khi}: worst {np.max(err / tol):.3g}"
+    return hits
+
+
+def test_s3_single_pass_window_moments(ctx):
+    """The reduction the registration runs by default: rows below the
+    predicted band-edge window summed per tile, rows inside it per bin, and
+    the band kernel's FP64 sum of the partials up to the band edge.  Per entry
+    against the oracle's FP64 moments over the same band, with the edge just
+    below the window, inside it, on its last bin, and missed from above and
+    below (the band kernel must then decline), on VGA room levels."""
+    seq = synth.RoomSequence(0, n_frames=3)
+    prob = seq.problem(1)
+    gpu_lv = _gpu_levels(ctx, prob)
+    params = icp.icp_params_default()
+    hits = 0
+    for T in _poses_for(prob)[:2]:
+        for level in range(3):
+            _, band = _check_associate(ctx, prob, gpu_lv, level, T, params)
+            hits += _check_single_pass(ctx, prob, gpu_lv, level, T, params, _window_cases(int(band[3])), "room")
+    assert hits >= 6 * 6  # six of the nine placements hit when the window is not clamped
+
+
+def test_s3_single_pass_window_clamped_at_either_end(ctx):
+    """Windows clamped into the histogram: noise-free identical frames put the
+    band edge at bin 1 or 2 with the window from bin 0; model maps 9 cm behind
+    the live frame put it at the last bin with the window at 976..1023."""
+    same = synth.pair_problem(8, trans_m=0.0, rot_deg=0.0, imu_deg=0.0, noise=False)
+    params = icp.icp_params_default()
+    gpu_lv = _gpu_levels(ctx, same)
+    T = np.eye(4)
+    for level in range(3):
+        _, band = _check_associate(ctx, same, gpu_lv, level, T, params)
+        assert band[3] <= 3
+        cases = [(0, 0, 24), (0, int(band[3]), 24), (2, 0, 6), (2, 5, 6)]
+        assert _check_single_pass(ctx, same, gpu_lv, level, T, params, cases, "identical") == len(cases)
+    p = synth.pair_problem(7, trans_m=0.0, rot_deg=0.0)
+    mv = p.model_vtx.copy()
+    mv[..., 2] += 0.09
+    q = synth.Problem(live_depth=p.live_depth, model_vtx=mv, model_nrm=p.model_nrm, K=p.K, imu_R=p.imu_R,
+                      init_pose=p.init_pose, T_gt=p.T_gt, name="shifted-9cm")
+    params = icp.icp_params_default(dist_max=0.125)
+    gpu_lv = _gpu_levels(ctx, q)
+    _, band = _check_associate(ctx, q, gpu_lv, 0, T, params)
+    assert band[3] == 1023
+    cases = [(0, 1023, 24), (0, 1000, 24), (4, 1023, 6), (4, 1023, 24), (0, 960, 24)]
+    hits = _check_single_pass(ctx, q, gpu_lv, 0, T, params, cases, "shifted")
+    assert hits == 4
+
+
 def test_s4_solve_update(ctx):
     prob = synth.pair_problem(0)
     lvl = oracle.pyramids(prob.live_depth, prob.model_vtx, prob.model_nrm, prob.K, 1)[0]
@@ -243,16 +335,12 @@ def test_s4_solve_update(ctx):
     assert st_g == icp.TOO_FEW_CORR
 
 
-def _oracle_params(p):
-    return oracle.default_params(levels=p.levels, iters=list(p.iters), dist_max=p.dist_max,
-                                 cos_angle_max=p.cos_angle_max, band_beta=p.band_beta,
-                                 use_median_filter=p.use_median_filter, use_imu_seed=p.use_imu_seed,
-                                 lambda_mode=p.lambda_mode, lambda_c=p.lambda_c, min_corr=p.min_corr,
-                                 ill_cond_eps=p.ill_cond_eps, converge_window=p.converge_window,
-                                 depth_filter=p.depth_filter, filter_radius=p.filter_radius,
-                                 filter_sigma_px=p.filter_sigma_px, filter_sigma_m=p.filter_sigma_m,
-                                 normal_mode=p.normal_mode, normal_radius=p.normal_radius,
-                                 anchor_to_imu=p.anchor_to_imu)
+_oracle_params = oracle_params
+
+
+def _register_gpu(ctx, prob, params):
+    d, mv, mn = upload(prob)
+    return icp.icp_register(ctx, d, mv, mn, prob.K, prob.imu_R, prob.init_pose, params)
 
 
 def _register_both(ctx, prob, params):
@@ -267,13 +355,8 @@ def _register_both(ctx, prob, params):
 def test_end_to_end_pair(ctx, seed, lam):
     prob = synth.pair_problem(seed)
     params = icp.icp_params_default(lambda_c=lam)
-    Tg, sg, To, so = _register_both(ctx, prob, params)
-    ang, dt = pose_err(Tg, To)
-    assert ang < POSE_TOL and dt < POSE_TOL, (ang, dt)
-    for l in range(3):
-        assert sg["levels"][l]["iters_run"] == so[l]["iters_run"]
-        assert sg["levels"][l]["status"] == so[l]["status"]
-        assert abs(sg["levels"][l]["n_kept"] - so[l]["n_kept"]) <= max(2, 1e-3 * so[l]["n_kept"])
+    Tg, sg = _register_gpu(ctx, prob, params)
+    assert_registration_matches(prob, params, Tg, sg, f"seed {seed} lambda {lam}")
 
 
 def test_end_to_end_vga_room(ctx):
@@ -281,9 +364,8 @@ def test_end_to_end_vga_room(ctx):
     params = icp.icp_params_default()
     for k in range(2):
         prob = seq.problem(k)
-        Tg, sg, To, so = _register_both(ctx, prob, params)
-        ang, dt = pose_err(Tg, To)
-        assert ang < POSE_TOL and dt < POSE_TOL, (k, ang, dt)
+        Tg, sg = _register_gpu(ctx, prob, params)
+        assert_registration_matches(prob, params, Tg, sg, f"room frame {k}")
         assert sg["status"] == icp.LEVEL_OK
 
 
@@ -294,12 +376,8 @@ def test_end_to_end_split_precision(ctx, lam):
     params = icp.icp_params_default(reduce_mode=1, lambda_c=lam)
     seq = synth.RoomSequence(0, n_frames=3)
     for prob in [synth.pair_problem(0), synth.pair_problem(1), seq.problem(0), seq.problem(1)]:
-        Tg, sg, To, so = _register_both(ctx, prob, params)
-        ang, dt = pose_err(Tg, To)
-        assert ang < POSE_TOL and dt < POSE_TOL, (prob.name, ang, dt)
-        for l in range(3):
-            assert sg["levels"][l]["iters_run"] == so[l]["iters_run"]
-            assert abs(sg["levels"][l]["n_kept"] - so[l]["n_kept"]) <= max(2, 1e-3 * so[l]["n_kept"])
+        Tg, sg = _register_gpu(ctx, prob, params)
+        assert_registration_matches(prob, params, Tg, sg, f"split {prob.name}")
 
 
 @pytest.mark.parametrize("over", [dict(pass_mode=1), dict(pass_mode=0), dict(band_beta=0.5),
@@ -310,22 +388,15 @@ def test_pass_modes_match_oracle(ctx, over):
     params = icp.icp_params_default(**over)
     probs = [synth.pair_problem(3), synth.RoomSequence(1, n_frames=3).problem(1)]
     for prob in probs:
-        Tg, sg, To, so = _register_both(ctx, prob, params)
-        ang, dt = pose_err(Tg, To)
-        assert ang < POSE_TOL and dt < POSE_TOL, (over, prob.name, ang, dt)
-        for l in range(3):
-            assert sg["levels"][l]["iters_run"] == so[l]["iters_run"]
-            assert sg["levels"][l]["n_kept"] == so[l]["n_kept"] or \
-                abs(sg["levels"][l]["n_kept"] - so[l]["n_kept"]) <= 2
+        Tg, sg = _register_gpu(ctx, prob, params)
+        assert_registration_matches(prob, params, Tg, sg, f"{over} {prob.name}")
 
 
 def test_convergence_control_matches(ctx):
     prob = synth.pair_problem(0)
     params = icp.icp_params_default(converge_window=3, iters=(30, 30, 30), lambda_c=0.0)
-    Tg, sg, To, so = _register_both(ctx, prob, params)
-    ang, dt = pose_err(Tg, To)
-    assert ang < POSE_TOL and dt < POSE_TOL
-    assert [s["iters_run"] for s in sg["levels"]] == [s["iters_run"] for s in so]
+    Tg, sg = _register_gpu(ctx, prob, params)
+    assert_registration_matches(prob, params, Tg, sg, "convergence")
 
 
 def test_batch_matches_single(ctx):
@@ -500,6 +571,23 @@ def test_invalid_arguments(ctx):
         with pytest.raises(icp.IcpError) as e:
             icp.icp_register(ctx, d, mv, mn, prob.K, prob.imu_R, prob.init_pose, icp.icp_params_default(**bad))
         assert e.value.code == icp.EINVAL, bad
+    # rotations must be rotations (SE(3), Sec. 3): scaled, reflected, and the
+    # initial rotation when the seed is off; the batch call checks each problem
+    for R, prm in [(prob.imu_R * 1.001, icp.icp_params_default()), (-prob.imu_R, icp.icp_params_default())]:
+        with pytest.raises(icp.IcpError) as e:
+            icp.icp_register(ctx, d, mv, mn, prob.K, R, prob.init_pose, prm)
+        assert e.value.code == icp.EINVAL and "rotation" in str(e.value)
+    T0 = np.eye(4)
+    T0[:3, :3] *= 1.01
+    icp.icp_register(ctx, d, mv, mn, prob.K, prob.imu_R, T0)  # seed on: init_pose's rotation is not used
+    with pytest.raises(icp.IcpError) as e:
+        icp.icp_register(ctx, d, mv, mn, prob.K, prob.imu_R, T0, icp.icp_params_default(use_imu_seed=0))
+    assert e.value.code == icp.EINVAL
+    items = [dict(live_depth=d, model_vtx=mv, model_nrm=mn, K=prob.K, imu_R=R, init_pose=prob.init_pose)
+             for R in (prob.imu_R, prob.imu_R * 1.001)]
+    with pytest.raises(icp.IcpError) as e:
+        icp.icp_register_batch(ctx, items)
+    assert e.value.code == icp.EINVAL
     with pytest.raises(icp.IcpError) as e:  # the stage solve has no IMU prior to anchor to
         icp.icp_stage_solve(ctx, np.zeros(28), 100, np.eye(4), icp.icp_params_default(anchor_to_imu=1))
     assert e.value.code == icp.EINVAL

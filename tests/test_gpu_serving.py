@@ -161,15 +161,22 @@ def test_server_matches_oracle_sample(ctx):
 
 
 def test_server_admission_by_budget():
-    params = _params()
-    cfg = icp.icp_server_config_default(params=params, max_batch=8, slots=2)
+    """A budget that holds one VGA stream (its frame slots and, per slot, a
+    workspace bound for any batch it can form) admits one stream and not a
+    second; frames_in_flight = 2 frames of the stream in one batch fit in the
+    workspace admission counted, so the slots never hold more than it."""
+    params = icp.icp_params_default()  # tiles picked per batch: the bound must cover any of them
     K = synth.centred_intrinsics(640, 480, 525.0)
-    # the budget of one VGA stream (its frame slots) and its two batch
-    # workspaces, not of two streams
-    ring = cfg.frames_in_flight + 1
-    ws1 = icp.icp_workspace_bytes([(640, 480)])
-    ws2 = icp.icp_workspace_bytes([(640, 480), (640, 480)])
-    cfg.hbm_budget_bytes = int(ring * 640 * 480 * 28 + 4096 + 2 * 1.25 * ws1 + 0.5 * (2 * 1.25 * (ws2 - ws1)))
+    probe = icp.Server(icp.icp_server_config_default(params=params, max_batch=8, slots=2))
+    try:
+        probe.open_stream(640, 480, K)
+        c = probe.counters()
+        one = c["resident_bytes"] + c["workspace_bytes"]
+        assert c["workspace_held_bytes"] == 0
+    finally:
+        probe.close()
+    cfg = icp.icp_server_config_default(params=params, max_batch=8, slots=2)
+    cfg.hbm_budget_bytes = one + 4096
     srv = icp.Server(cfg)
     try:
         a = srv.open_stream(640, 480, K)
@@ -177,7 +184,19 @@ def test_server_admission_by_budget():
             srv.open_stream(640, 480, K)
         assert e.value.code == icp.ENOMEM
         c0 = srv.counters()
-        assert c0["streams_open"] == 1 and c0["resident_bytes"] > 0
+        assert c0["streams_open"] == 1 and c0["resident_bytes"] + c0["workspace_bytes"] <= cfg.hbm_budget_bytes
+        # five frames of the stream queued at once: the scheduler takes two per batch
+        seq = synth.RoomSequence(0, n_frames=6)
+        for k in range(5):
+            srv.submit(a, seq.problem(k).live_depth, np.eye(3))
+        got = []
+        while len(got) < 5:
+            got += srv.poll(8, timeout_ms=20000)
+        assert all(r["status"] == icp.OK for r in got)
+        assert max(r["batch_size"] for r in got) <= 2
+        c1 = srv.counters()
+        assert 0 < c1["workspace_held_bytes"] <= c1["workspace_bytes"]
+        assert c1["resident_bytes"] + c1["workspace_held_bytes"] <= cfg.hbm_budget_bytes
         srv.close_stream(a)
         b = srv.open_stream(640, 480, K)  # admitted once the first left
         assert b != a
@@ -199,6 +218,10 @@ def test_server_rejects_bad_arguments():
         with pytest.raises(icp.IcpError) as e:
             srv.submit(sid, np.zeros((120, 160), np.float32), np.full((3, 3), np.nan))
         assert e.value.code == icp.EINVAL
+        for R in (np.eye(3) * 1.001, np.diag([1.0, -1.0, 1.0])):  # not a rotation
+            with pytest.raises(icp.IcpError) as e:
+                srv.submit(sid, np.zeros((120, 160), np.float32), R)
+            assert e.value.code == icp.EINVAL
         with pytest.raises(ValueError):  # a frame of another size never reaches the library
             srv.submit(sid, np.zeros((120, 150), np.float32), np.eye(3))
         assert srv.poll(8, timeout_ms=0) == []

@@ -274,6 +274,16 @@ def test_bad_arguments(ctx):
     with pytest.raises(icp.IcpError) as e:
         g.raycast(32, 24, K, np.eye(4), tmin=1.0, tmax=0.5)
     assert e.value.code == icp.EINVAL
+    # camera poses must be rigid motions
+    for R in (np.diag([1.0, 1.0, 1.01]), np.diag([1.0, 1.0, -1.0])):
+        nonrigid = np.eye(4)
+        nonrigid[:3, :3] = R
+        with pytest.raises(icp.IcpError) as e:
+            g.integrate(d, K, nonrigid)
+        assert e.value.code == icp.EINVAL
+        with pytest.raises(icp.IcpError) as e:
+            g.raycast(32, 24, K, nonrigid)
+        assert e.value.code == icp.EINVAL
     with pytest.raises(ValueError):  # an output map of the wrong size never reaches the kernel
         g.raycast(32, 24, K, np.eye(4), out=(torch.empty((24, 31, 3), device="cuda"),
                                              torch.empty((24, 32, 3), device="cuda")))
