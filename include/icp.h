@@ -245,6 +245,27 @@ int icp_register_async(icp_ctx* ctx, const float* live_depth, int W, int H, cons
                        const double* init_pose, const icp_params* params, icp_result* result_dev,
                        void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the
+   registration of icp_register_async with no context and no allocation.  Its
+   workspace is one static device array of 32 MiB (ICP_NOALLOC_BYTES) that
+   every GPU the library runs on holds from the first call until the process
+   ends.  A problem fits when icp_workspace_bytes(1, &W, &H, levels) is at
+   most that with tile_px 0 (640x480 and 848x480 do at 3 or 4 levels,
+   1280x720 does not); a larger one returns ICP_ENOMEM before anything is
+   queued.  Arguments are checked as icp_register checks them (ICP_EINVAL).
+   The launches are queued on `stream` (the current device's) and the call
+   returns; result_dev, a device pointer to one icp_result, is written by the
+   stream.  Every call on one GPU uses that GPU's array and leaves its
+   contents behind: calls that overlap on one GPU (different streams, several
+   threads) race, so the caller orders them (one stream, or events).  The
+   problem descriptor is written by a kernel from its launch arguments, so the
+   launches read no host memory. */
+#define ICP_NOALLOC_BYTES ((size_t)32 << 20)
+int icp_register_noalloc(const float* live_depth, int W, int H, const float* model_vtx, const float* model_nrm,
+                         const icp_intrinsics* K, const double* imu_R, const double* init_pose,
+                         const icp_params* params, icp_result* result_dev, void* stream);
+
 /* Register n independent problems (possibly of different sizes) with shared
    params in one set of launches: every kernel covers the tiles of all
    problems.  probs: host array of n problems; results: host array of n,

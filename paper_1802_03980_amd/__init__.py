@@ -30,7 +30,7 @@ PX_INVALID_LIVE, PX_BEHIND, PX_OUTSIDE, PX_INVALID_MODEL, PX_FAR, PX_ANGLE, PX_G
 EXPORTS = (
     "icp_abi_version", "icp_strerror", "icp_last_error", "icp_ctx_create", "icp_ctx_destroy",
     "icp_ctx_workspace_bytes", "icp_workspace_bytes", "icp_params_default", "icp_validate_problem", "icp_register",
-    "icp_register_async", "icp_register_batch", "icp_register_batch_async", "icp_ctx_set_timing", "icp_ctx_get_timing", "icp_ctx_set_graphs",
+    "icp_register_async", "icp_register_noalloc", "icp_register_batch", "icp_register_batch_async", "icp_ctx_set_timing", "icp_ctx_get_timing", "icp_ctx_set_graphs",
     "icp_stage_prepare", "icp_stage_level",
     "icp_stage_associate", "icp_stage_moments", "icp_stage_single_pass", "icp_stage_solve", "icp_live_maps", "icp_autotune_tiles",
     "icp_server_config_default", "icp_server_clock", "icp_server_create", "icp_server_destroy",
@@ -146,6 +146,8 @@ def lib():
                                  C.POINTER(icp_stats), P]),
             "icp_register_async": (I, [P, P, I, I, P, P, C.POINTER(icp_intrinsics), P, P,
                                        C.POINTER(icp_params), P, P]),
+            "icp_register_noalloc": (I, [P, I, I, P, P, C.POINTER(icp_intrinsics), P, P, C.POINTER(icp_params), P,
+                                         P]),
             "icp_register_batch": (I, [P, I, P, C.POINTER(icp_params), P, P]),
             "icp_register_batch_async": (I, [P, I, P, C.POINTER(icp_params), P, P]),
             "icp_ctx_set_timing": (I, [P, I]),
@@ -340,6 +342,28 @@ def icp_register_async(ctx, live_depth, model_vtx, model_nrm, K, imu_R, init_pos
                                   _dev_ptr(model_nrm, "float32", "model_nrm"), C.byref(Kc), _np_ptr(R),
                                   _np_ptr(T0), C.byref(p), res_ptr, _stream(stream))
     _check(ctx, rc)
+
+
+def icp_register_noalloc(live_depth, model_vtx, model_nrm, K, imu_R, init_pose, result_dev, params=None,
+                         stream=None):
+    """icp_register_noalloc: the registration of icp_register_async with no
+    context and no device allocation (a static 32 MiB device array per GPU);
+    result_dev is a uint8 device tensor of at least sizeof(icp_result) bytes.
+    Raises IcpError (no context, so the message is the code's)."""
+    res_ptr = _dev_ptr(result_dev, "uint8", "result_dev")
+    H, W = _maps_match(live_depth, model_vtx, model_nrm)
+    p = params if params is not None else icp_params_default()
+    if result_dev.numel() * result_dev.element_size() < C.sizeof(icp_result):
+        raise ValueError("result_dev too small")
+    Kc = make_intrinsics(K)
+    R = _f64(imu_R, 9, "imu_R")
+    T0 = _f64(init_pose, 16, "init_pose")
+    rc = lib().icp_register_noalloc(_dev_ptr(live_depth, "float32", "live_depth"), W, H,
+                                    _dev_ptr(model_vtx, "float32", "model_vtx"),
+                                    _dev_ptr(model_nrm, "float32", "model_nrm"), C.byref(Kc), _np_ptr(R),
+                                    _np_ptr(T0), C.byref(p), res_ptr, _stream(stream))
+    if rc != OK:
+        raise IcpError(rc, lib().icp_strerror(rc).decode())
 
 
 def result_from_bytes(buf):

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -57,6 +58,12 @@ struct icp_ctx {
     void* plan_mem = nullptr;  // the cached Plan (see ctx_plan)
     MapsDesc* d_jobs = nullptr;  // icp_live_maps job descriptor (device)
 };
+
+// Device memory of icp_register_noalloc: one file-scope array.  Every GPU the
+// library runs on holds its own copy, at its own address, until the process
+// ends; the host-side name is only a handle (see static_scratch).
+constexpr size_t kStaticScratchBytes = ICP_NOALLOC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -613,6 +620,29 @@ icp_problem one_problem(const float* depth, int W, int H, const float* mv, const
     return q;
 }
 
+// The device address of `scratch` on device `dev` (the current device): looked
+// up with hipGetSymbolAddress once per device, with that device current, and
+// kept.  Kernels take this address, never the array's host-side name.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(int dev, char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return ICP_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return ICP_EDEVICE;
+        }
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return ICP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -999,6 +1029,60 @@ int icp_register_async(icp_ctx* ctx, const float* live_depth, int W, int H, cons
     icp_result* d_res = reinterpret_cast<icp_result*>(static_cast<char*>(ctx->ws) + P.off_res);
     HIP_TRY(ctx, hipMemcpyAsync(result_dev, d_res, sizeof(icp_result), hipMemcpyDeviceToDevice, s));
     return ICP_OK;
+}
+
+int icp_register_noalloc(const float* live_depth, int W, int H, const float* model_vtx, const float* model_nrm,
+                         const icp_intrinsics* K, const double* imu_R, const double* init_pose,
+                         const icp_params* params, icp_result* result_dev, void* stream) {
+    if (!K || !imu_R || !init_pose || !result_dev) return ICP_EINVAL;
+    int rc = check_params(nullptr, params);
+    if (rc) return rc;
+    const icp_problem q = one_problem(live_depth, W, H, model_vtx, model_nrm, K, imu_R, init_pose);
+    if ((rc = check_problem(nullptr, q, params->levels, params->use_imu_seed))) return rc;
+    // layout in the static array (as a one-problem batch in a context's
+    // workspace): descriptor, state, batch flag, level buffers, tile owners
+    const int levels = params->levels;
+    ProbDesc d{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const size_t off_desc = take(sizeof(ProbDesc));
+    d.st = reinterpret_cast<ProbState*>(take(sizeof(ProbState)));
+    const size_t off_flags = take(sizeof(int32_t));
+    int tiles[ICP_MAX_LEVELS] = {}, max_vn[ICP_MAX_LEVELS] = {}, max_mp[ICP_MAX_LEVELS] = {},
+        max_q[ICP_MAX_LEVELS] = {};
+    lay_out_problem(d, W, H, levels, params->tile_px, 1, tiles, max_vn, max_mp, max_q, take);
+    int max_tiles = 1;
+    for (int l = 0; l < levels; ++l) max_tiles = std::max(max_tiles, tiles[l]);
+    const size_t off_owner = take(sizeof(int32_t) * max_tiles);  // every tile belongs to problem 0
+    if (off > kStaticScratchBytes) return ICP_ENOMEM;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return ICP_EDEVICE;
+    }
+    char* base = nullptr;
+    if ((rc = static_scratch(dev, &base))) return rc;
+    bind_problem(d, q, levels, params->depth_filter, base);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t* owner = reinterpret_cast<int32_t*>(base + off_owner);
+    HIP_TRY(nullptr, icpk::launch_put_desc(d, reinterpret_cast<ProbDesc*>(base + off_desc), s));
+    HIP_TRY(nullptr, icpk::launch_fill_i32(owner, max_tiles, 0, s));
+    Launches G{};
+    G.d_desc = reinterpret_cast<const ProbDesc*>(base + off_desc);
+    G.need2 = reinterpret_cast<int32_t*>(base + off_flags);
+    for (int l = 0; l < levels; ++l) {
+        G.owner[l] = owner;
+        G.tiles[l] = tiles[l];
+        G.px[l] = d.lv[l].npx;
+    }
+    G.max_vn = max_vn;
+    G.max_mp = max_mp;
+    G.max_q = max_q;
+    return launch_registration(nullptr, 1, params, G, result_dev, s);
 }
 
 // ------------------------------------------------------------------ stages

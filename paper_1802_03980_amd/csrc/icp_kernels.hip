@@ -1235,6 +1235,18 @@ __global__ void k_stage_solve(MomArg M, int64_t n, PoseArg pose, KParams kp, dou
     out[18] = (double)status;
 }
 
+// ------------------------------------------------------------------ descriptor upload
+// A problem descriptor passed by value (a kernel argument) written to device
+// memory, and a fill of an int array: set-up without host-to-device copies.
+__global__ void k_put_desc(ProbDesc d, ProbDesc* dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = d;
+}
+
+__global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // ------------------------------------------------------------------ launchers
 
 static inline unsigned blocks_for(int n) { return (unsigned)((n + ICP_WG - 1) / ICP_WG); }
@@ -1331,6 +1343,16 @@ hipError_t launch_pass2(const ProbDesc* probs, const int* owner, int tiles, Iter
 
 hipError_t launch_solve(const ProbDesc* probs, int n, IterCtl ctl, const KParams& kp, hipStream_t s) {
     hipLaunchKernelGGL(k_solve, dim3(n), dim3(ICP_WG), 0, s, probs, ctl, kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_put_desc(const ProbDesc& d, ProbDesc* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n)), dim3(ICP_WG), 0, s, p, n, v);
     return hipGetLastError();
 }
 
