@@ -131,6 +131,20 @@ def default_params(**over):
     return p
 
 
+def params_like(p):
+    """Oracle parameters with the values of any object that has the same
+    field names (e.g. the GPU library's icp_params)."""
+    q = Params()
+    lib().or_params_default(C.byref(q))
+    for name, _ in Params._fields_:
+        if name == "iters":
+            for j in range(MAX_LEVELS):
+                q.iters[j] = int(p.iters[j])
+        else:
+            setattr(q, name, getattr(p, name))
+    return q
+
+
 def num_threads():
     return int(lib().or_num_threads())
 
@@ -361,3 +375,75 @@ def register(depth, vtx, nrm, K, imu_R, init_pose, params=None, trace_cap=64):
 def register_problem(prob, params=None, trace_cap=64):
     return register(prob.live_depth, prob.model_vtx, prob.model_nrm, prob.K, prob.imu_R, prob.init_pose,
                     params, trace_cap)
+
+
+# ---------------------------------------------------------------- analysis helpers
+
+def levels_of(prob, p):
+    """The pyramids of a problem with the front end of parameters p (oracle or
+    icp parameters: the same field names), as or_icp_register builds them."""
+    D = prob.live_depth
+    if p.depth_filter:
+        D = bilateral(D, p.filter_radius, p.filter_sigma_px, p.filter_sigma_m)
+    MV, MN = model_l0(prob.model_vtx, prob.model_nrm)
+    out = []
+    for lvl in range(p.levels):
+        if lvl:
+            D = depth_down(D)
+            MV, MN = model_down(MV, MN)
+        Kl = level_intrinsics(prob.K, lvl)
+        if p.normal_mode == 1:
+            LV, LN = live_vn_box(D, Kl, p.normal_radius)
+        else:
+            LV, LN = live_vn(D, Kl)
+        out.append(dict(D=D, LV=LV, LN=LN, MV=MV, MN=MN, K=Kl))
+    return out
+
+
+def seed_pose(prob, p):
+    """The pose a registration starts from: [imu_R | t_init] with the IMU seed, else init_pose."""
+    T = np.array(prob.init_pose, dtype=np.float64).reshape(4, 4).copy()
+    if p.use_imu_seed:
+        T[:3, :3] = prob.imu_R
+    return T
+
+
+def _rot_angle(R):
+    c = (np.trace(R) - 1.0) / 2.0
+    s = 0.5 * np.linalg.norm([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]])
+    return float(np.arctan2(s, c))
+
+
+def sensitivity(prob, p, rel=1e-6, seeds=(0, 1)):
+    """How far the final pose moves when every iteration's moments are
+    perturbed by `rel` relative (the size of an FP32 reduction's rounding):
+    the largest (rotation rad, translation m) change over the seeds, with the
+    fixed cadence of p.  A registration whose pose moves by more than a
+    comparison tolerance under this perturbation is ill-conditioned (too few
+    constraints for its regularisation): its result depends on rounding."""
+    lv = levels_of(prob, p)
+
+    def run(seed):
+        rng = np.random.default_rng(seed)
+        T = seed_pose(prob, p)
+        for lvl in range(p.levels - 1, -1, -1):
+            for _ in range(p.iters[lvl]):
+                _, _, _, hist = associate(lv[lvl], T, p.dist_max, p.cos_angle_max)
+                N, kmed, klo, khi = band(hist, p.use_median_filter, p.band_beta)
+                M, n = moments(lv[lvl], T, klo, khi, p.dist_max, p.cos_angle_max)
+                if seed is not None:
+                    M = M * (1.0 + rel * rng.standard_normal(28))
+                st, T1, _ = solve_update(M, n, T, p.lambda_mode, p.lambda_c, p.min_corr, p.ill_cond_eps,
+                                         prob.imu_R if p.anchor_to_imu else None)
+                if st != LEVEL_OK:
+                    break
+                T = T1
+        return T
+
+    base = run(None)
+    worst = (0.0, 0.0)
+    for sd in seeds:
+        T = run(sd)
+        worst = (max(worst[0], _rot_angle(T[:3, :3] @ base[:3, :3].T)),
+                 max(worst[1], float(np.linalg.norm(T[:3, 3] - base[:3, 3]))))
+    return worst

@@ -19,42 +19,16 @@ POSE_TOL = 1e-5
 
 def oracle_params(p):
     """Oracle parameters equal to an icp_params."""
-    return oracle.default_params(levels=p.levels, iters=list(p.iters), dist_max=p.dist_max,
-                                 cos_angle_max=p.cos_angle_max, band_beta=p.band_beta,
-                                 use_median_filter=p.use_median_filter, use_imu_seed=p.use_imu_seed,
-                                 lambda_mode=p.lambda_mode, lambda_c=p.lambda_c, min_corr=p.min_corr,
-                                 ill_cond_eps=p.ill_cond_eps, converge_window=p.converge_window,
-                                 depth_filter=p.depth_filter, filter_radius=p.filter_radius,
-                                 filter_sigma_px=p.filter_sigma_px, filter_sigma_m=p.filter_sigma_m,
-                                 normal_mode=p.normal_mode, normal_radius=p.normal_radius,
-                                 anchor_to_imu=p.anchor_to_imu)
+    return oracle.params_like(p)
 
 
 def oracle_levels(prob, p):
     """The oracle's pyramids of a problem with the front end of params p."""
-    D = prob.live_depth
-    if p.depth_filter:
-        D = oracle.bilateral(D, p.filter_radius, p.filter_sigma_px, p.filter_sigma_m)
-    MV, MN = oracle.model_l0(prob.model_vtx, prob.model_nrm)
-    out = []
-    for lvl in range(p.levels):
-        if lvl:
-            D = oracle.depth_down(D)
-            MV, MN = oracle.model_down(MV, MN)
-        Kl = oracle.level_intrinsics(prob.K, lvl)
-        if p.normal_mode == 1:
-            LV, LN = oracle.live_vn_box(D, Kl, p.normal_radius)
-        else:
-            LV, LN = oracle.live_vn(D, Kl)
-        out.append(dict(D=D, LV=LV, LN=LN, MV=MV, MN=MN, K=Kl))
-    return out
+    return oracle.levels_of(prob, p)
 
 
 def _seed_pose(prob, p):
-    T = np.array(prob.init_pose, dtype=np.float64).reshape(4, 4).copy()
-    if p.use_imu_seed:
-        T[:3, :3] = prob.imu_R
-    return T
+    return oracle.seed_pose(prob, p)
 
 
 def entering_poses(prob, p, trace):
@@ -113,35 +87,7 @@ def assert_registration_matches(prob, p, Tg, sg, tag="", ref=None):
 
 
 def oracle_sensitivity(prob, p, rel=1e-6, seeds=(0, 1)):
-    """How far the oracle's own final pose moves when every iteration's
-    moments are perturbed by `rel` relative (the size of an FP32 reduction's
-    rounding): the largest (rotation, translation) change over the seeds.
-    An ill-conditioned registration (few constraints, no regularisation)
-    amplifies rounding without bound; a comparison with the GPU at POSE_TOL
-    is only meaningful when this stays well below it."""
-    levels = oracle_levels(prob, p)
-
-    def run(seed):
-        rng = np.random.default_rng(seed)
-        T = _seed_pose(prob, p)
-        for lvl in range(p.levels - 1, -1, -1):
-            for _ in range(p.iters[lvl]):
-                _, _, _, hist = oracle.associate(levels[lvl], T, p.dist_max, p.cos_angle_max)
-                N, kmed, klo, khi = oracle.band(hist, p.use_median_filter, p.band_beta)
-                M, n = oracle.moments(levels[lvl], T, klo, khi, p.dist_max, p.cos_angle_max)
-                if seed is not None:
-                    M = M * (1.0 + rel * rng.standard_normal(28))
-                st, T1, _ = oracle.solve_update(M, n, T, p.lambda_mode, p.lambda_c, p.min_corr, p.ill_cond_eps,
-                                                prob.imu_R if p.anchor_to_imu else None)
-                if st != oracle.LEVEL_OK:
-                    break
-                T = T1
-                # the convergence rule is not replayed: a fixed cadence is what is perturbed
-        return T
-
-    base = run(None)
-    worst = (0.0, 0.0)
-    for sd in seeds:
-        a, d = pose_err(run(sd), base)
-        worst = (max(worst[0], a), max(worst[1], d))
-    return worst
+    """The oracle's own pose change under FP32-sized moment perturbations
+    (oracle.sensitivity): a comparison with the GPU at POSE_TOL is only
+    meaningful when this stays well below it."""
+    return oracle.sensitivity(prob, p, rel, seeds)
