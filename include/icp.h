@@ -111,9 +111,10 @@ typedef struct {
     int32_t converge_window;        /* 0: fixed cadence; k >= 1: a level stops once the median
                                        bin is unchanged on k successive iterations (Sec. 3.4) */
     int32_t reduce_mode;            /* 0: FP32 moment reduction; 1: rows centred on the live
-                                       centroid, split into FP16 hi + lo and reduced with
-                                       MFMA (FP32 accumulation), un-centred in FP64 (uses two
-                                       passes) */
+                                       centroid moved by the pose, split into FP16 hi + lo and
+                                       reduced with MFMA (FP32 accumulation), un-centred in FP64;
+                                       in single-pass mode the rows inside the band-edge window
+                                       are summed per bin in FP32 (the same centred rows) */
     int32_t pass_mode;              /* 0: single pass over the maps when the band edge falls in a
                                        window around the previous iteration's edge (two passes
                                        otherwise; needs band_beta >= 1 or no median filter);
@@ -364,13 +365,15 @@ int icp_stage_moments(icp_ctx* ctx, int level, const double* pose12, const icp_p
    below it, sums the partials up to the edge into the moments.  iter = 0 takes
    the full 48-bin window (a level's first iteration); iter > 0 a window of
    2 pred_hw bins (pred_hw 1..24).  pred_hi = -1: no prediction, no window.
+   With reduce_mode 1 the rows below the window are reduced by the split
+   FP16 hi + lo MFMA, and the moments are returned un-centred.
    The window is [pred_hi - hw, pred_hi + hw) clamped into 0..1023.
    Outputs (host): band {N, k_med, k_lo, k_hi}; window {h0, width} (h0 = -1:
    none); *hit = 1 when the moments came from the partials, else 0 (the
    registration would then run pass 2), with moments and *n zeroed; moments
    (28 doubles, as icp_stage_moments) and *n otherwise.  Needs a prepared stage
-   problem, reduce_mode 0 and band_beta >= 1 or no median filter (else
-   ICP_EINVAL).  Synchronises. */
+   problem and band_beta >= 1 or no median filter (else ICP_EINVAL).
+   Synchronises. */
 int icp_stage_single_pass(icp_ctx* ctx, int level, const double* pose12, const icp_params* params, int iter,
                           int pred_hi, int pred_hw, int64_t* band, int32_t* window, int* hit, double* moments,
                           int64_t* n, void* stream);

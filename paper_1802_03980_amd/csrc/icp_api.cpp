@@ -520,17 +520,15 @@ int launch_registration(icp_ctx* ctx, int n, const icp_params* prm, const Launch
     HIP_TRY(ctx, icpk::launch_init(d_desc, n, prm->use_imu_seed, kp.need2, s));
     if ((rc = begin(ICP_TIME_FRONT_END, G.px[0]))) return rc;
     HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, G.max_vn, G.max_mp, G.max_q, false, front_end(prm), s));
-    if (prm->reduce_mode == 1) HIP_TRY(ctx, icpk::launch_centroid(d_desc, n, prm->levels, s));
+    if (prm->reduce_mode == 1) HIP_TRY(ctx, icpk::launch_centroid(d_desc, n, prm->levels, G.owner, G.tiles, s));
     if ((rc = end())) return rc;
-    // single pass needs the band's lower edge at bin 0 and the FP32 reduction
-    const int fused = prm->pass_mode == 0 && prm->reduce_mode == 0 &&
-                              (!prm->use_median_filter || prm->band_beta >= 1.0)
-                          ? 1
-                          : 0;
-    // one problem in single-pass mode: most iterations end in the band kernel,
-    // so the solve launch is folded into pass 2 (whose last work-group solves
-    // the iterations the window missed) and one launch per iteration goes
-    kp.fold_solve = fused && n == 1 ? 1 : 0;
+    // single pass needs the band's lower edge at bin 0
+    const int fused = prm->pass_mode == 0 && (!prm->use_median_filter || prm->band_beta >= 1.0) ? 1 : 0;
+    // one problem in single-pass mode with the FP32 reduction: most iterations
+    // end in the band kernel, so the solve launch is folded into pass 2 (whose
+    // last work-group solves the iterations the window missed) and one launch
+    // per iteration goes
+    kp.fold_solve = fused && n == 1 && prm->reduce_mode == 0 ? 1 : 0;
     for (int l = prm->levels - 1; l >= 0; --l) {
         const int* owner = G.owner[l];
         const int64_t px = G.px[l];
@@ -1119,7 +1117,7 @@ int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const
     HIP_TRY(ctx, icpk::launch_init(ctx->d_desc, 1, 0, nullptr, s));
     HIP_TRY(ctx, icpk::launch_prepare(ctx->d_desc, 1, levels, P.max_vn, P.max_mp, P.max_q, true,
                                       front_end(prm), s));
-    HIP_TRY(ctx, icpk::launch_centroid(ctx->d_desc, 1, levels, s));
+    HIP_TRY(ctx, icpk::launch_centroid(ctx->d_desc, 1, levels, ctx->d_owner, ctx->tiles, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     ctx->stage_ready = true;
     return ICP_OK;
@@ -1221,8 +1219,8 @@ int icp_stage_single_pass(icp_ctx* ctx, int level, const double* pose12, const i
     if (rc) return rc;
     if (!pose12 || !band || !window || !hit || !moments || !n) return fail(ctx, ICP_EINVAL, "NULL argument");
     if ((rc = check_params(ctx, params))) return rc;
-    if (params->reduce_mode != 0 || (params->use_median_filter && params->band_beta < 1.0))
-        return fail(ctx, ICP_EINVAL, "the single pass needs reduce_mode 0 and band_beta >= 1 (or no median filter)");
+    if (params->use_median_filter && params->band_beta < 1.0)
+        return fail(ctx, ICP_EINVAL, "the single pass needs band_beta >= 1 (or no median filter)");
     if (iter < 0 || pred_hi < -1 || pred_hi >= ICP_HIST_BINS || (iter > 0 && (pred_hw < 1 || pred_hw > ICP_WIN / 2)))
         return fail(ctx, ICP_EINVAL, "iter >= 0, pred_hi in -1..1023 and (iter > 0) pred_hw in 1..24");
     HIP_TRY(ctx, hipSetDevice(ctx->device));

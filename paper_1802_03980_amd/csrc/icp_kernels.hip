@@ -503,18 +503,23 @@ __global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restric
     }
 }
 
-// Centroid of the valid live vertices of one level (one work-group per
-// problem and level, grid.y = level): the centring point of the split-
-// precision reduction.  Deterministic FP64 sums.
-__global__ __launch_bounds__(ICP_WG) void k_centroid(const ProbDesc* __restrict__ probs) {
+// Centroid of the valid live vertices of one level: the centring point of the
+// split-precision reduction.  Each tile of the level sums its valid vertices
+// (x = z (u - cx)/fx, y likewise, rounded to FP32 as the vertex map stores
+// them) in FP64 into its pass-2 partial slot (free during the front end); one
+// work-group per problem then adds the tiles in tile order.  Deterministic.
+__global__ __launch_bounds__(ICP_WG) void k_centroid_tiles(const ProbDesc* __restrict__ probs,
+                                                           const int* __restrict__ owner, int level) {
     __shared__ double sh[ICP_WG][4];
-    const ProbDesc& P = probs[blockIdx.x];
-    const int level = blockIdx.y;
+    const int g = blockIdx.x;
+    const ProbDesc& P = probs[owner[g]];
     const LevelDesc& L = P.lv[level];
+    const int tile = g - L.tile_base;
     const int tid = threadIdx.x;
+    const int base = tile * L.tile_px, end = min(base + L.tile_px, L.npx);
     double sx = 0.0, sy = 0.0, sz = 0.0, n = 0.0;
     const ICP_GLOBAL float* D = gconst(L.D);
-    for (int i = tid; i < L.npx; i += ICP_WG) {
+    for (int i = base + tid; i < end; i += ICP_WG) {
         const float z = D[i];
         if (depth_ok(z)) {
             const int v = i / L.W, u = i - v * L.W;
@@ -534,9 +539,29 @@ __global__ __launch_bounds__(ICP_WG) void k_centroid(const ProbDesc* __restrict_
             for (int k = 0; k < 4; ++k) sh[tid][k] += sh[tid + w][k];
         __syncthreads();
     }
+    if (tid < 4) reinterpret_cast<double*>(L.part + (size_t)tile * ICP_PART_STRIDE)[tid] = sh[0][tid];
+}
+
+__global__ __launch_bounds__(64) void k_centroid_sum(const ProbDesc* __restrict__ probs) {
+    __shared__ double sh[64];
+    const ProbDesc& P = probs[blockIdx.x];
+    const int level = blockIdx.y;
+    const LevelDesc& L = P.lv[level];
+    const int tid = threadIdx.x, k = tid & 3, c = tid >> 2;  // component k, chunk c of 16
+    const int per = (L.n_tiles + 15) / 16, t0 = c * per, t1 = min(t0 + per, L.n_tiles);
+    double s = 0.0;
+    for (int t = t0; t < t1; ++t) s += reinterpret_cast<const double*>(L.part + (size_t)t * ICP_PART_STRIDE)[k];
+    sh[tid] = s;
+    __syncthreads();
+    if (tid < 4) {
+        double tot = 0.0;
+        for (int q = 0; q < 16; ++q) tot += sh[4 * q + tid];
+        sh[tid] = tot;  // chunk 0's slot: read again by thread 0 below after the barrier
+    }
+    __syncthreads();
     if (tid == 0) {
         ProbState* st = P.st;
-        for (int k = 0; k < 3; ++k) st->cen[level][k] = sh[0][3] > 0.0 ? sh[0][k] / sh[0][3] : 0.0;
+        for (int a = 0; a < 3; ++a) st->cen[level][a] = sh[3] > 0.0 ? sh[a] / sh[3] : 0.0;
     }
 }
 
@@ -648,7 +673,85 @@ __device__ __forceinline__ void window_add(bool inwin, int bin_off, const float 
     }
 }
 
-template <bool kDebug, bool kFused>
+// Split-precision reduction (reduce_mode 1): a row r = [(p' - c) x n, n, b, 1]
+// (centred on the pose-moved live centroid c), scaled per column by a power of
+// two, is split into FP16 hi = fp16(r) and lo = fp16(r - hi); X = [hi | lo]
+// (rows x 16) goes through v_mfma_f32_16x16x32_f16 as X^T X with FP32
+// accumulation, whose four 8 x 8 blocks sum to the rows' Gram matrix.
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr float kScaleRot = 8.0f;     // |(p' - c) x n| stays well inside FP16 range
+constexpr float kScaleB = 1024.0f;    // |b| < dist_max <= 0.125 m; lifts b's lo part out of FP16 subnormals
+
+// The 8 split-precision columns of a kept row (zeros for a row not kept).
+__device__ __forceinline__ void split_row(bool keep, const float (&pc)[3], const float (&d)[3], const float (&n)[3],
+                                          _Float16 (&hi)[8], _Float16 (&lo)[8]) {
+    float r[7];
+    make_row(pc, d, n, r);
+    const float v[8] = {r[0] * kScaleRot, r[1] * kScaleRot, r[2] * kScaleRot, r[3], r[4], r[5], r[6] * kScaleB, 1.0f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const _Float16 h = (_Float16)v[c];
+        hi[c] = keep ? h : (_Float16)0.0f;
+        lo[c] = keep ? (_Float16)(v[c] - (float)h) : (_Float16)0.0f;
+    }
+}
+
+// Add the kept rows of this round (one per lane) to the wave's MFMA
+// accumulator: each half of the wave stages its 32 rows column-major in the
+// wave's 16 x 32 FP16 area (zeros where a lane keeps nothing), then one
+// 16x16x32 MFMA takes X^T X of them.  Halves without a kept row are skipped
+// (uniform).
+__device__ __forceinline__ void mfma_rows(bool keep, const float (&pc)[3], const float (&d)[3], const float (&n)[3],
+                                          _Float16 (*sx)[32], f4v& acc) {
+    const uint64_t m = __ballot(keep);
+    if (!m) return;
+    const int lane = threadIdx.x & 63;
+    _Float16 hi[8], lo[8];
+    split_row(keep, pc, d, n, hi, lo);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (!((m >> (32 * h)) & 0xffffffffull)) continue;
+        if ((lane >> 5) == h) {
+            const int row = lane & 31;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                sx[c][row] = hi[c];
+                sx[8 + c][row] = lo[c];
+            }
+        }
+        wave_sync();
+        const h8v a = *(const h8v*)&sx[lane & 15][8 * (lane >> 4)];
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, a, acc, 0, 0, 0);
+        wave_sync();
+    }
+}
+
+// The 28 moments (and the count) of a wave's MFMA accumulator, unscaled, in
+// lane 0 (zeros elsewhere): D[4 (l / 16) + t][l % 16] is written to the wave's
+// staging area (16 x 16 floats, exactly its size), then the four 8 x 8 blocks
+// hi'hi + hi'lo + lo'hi + lo'lo are added.
+__device__ __forceinline__ void mfma_moments(const f4v& acc, _Float16 (*sx)[32], float (&mom)[ICP_NMOM], float& cnt) {
+    const int lane = threadIdx.x & 63;
+    float* sd = reinterpret_cast<float*>(&sx[0][0]);
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) sd[(4 * (lane >> 4) + t) * 16 + (lane & 15)] = acc[t];
+    wave_sync();
+    int k = 0;
+    for (int a = 0; a < 7; ++a)
+        for (int b = a; b < 7; ++b) {
+            const float g = (sd[a * 16 + b] + sd[a * 16 + 8 + b]) + (sd[(8 + a) * 16 + b] + sd[(8 + a) * 16 + 8 + b]);
+            const float sa = a < 3 ? kScaleRot : (a == 6 ? kScaleB : 1.0f);
+            const float sb = b < 3 ? kScaleRot : (b == 6 ? kScaleB : 1.0f);
+            mom[k++] = lane == 0 ? g / (sa * sb) : 0.0f;
+        }
+    cnt = lane == 0 ? (sd[7 * 16 + 7] + sd[7 * 16 + 15]) + (sd[15 * 16 + 7] + sd[15 * 16 + 15]) : 0.0f;
+}
+
+template <bool kDebug, bool kFused, bool kSplit>
 __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) void k_pass1(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
                                                   IterCtl ctl, KParams kp, uint8_t* __restrict__ dbg_code,
                                                   int32_t* __restrict__ dbg_bin) {
@@ -656,6 +759,7 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
     __shared__ float sh_win[kFused ? ICP_WAVES : 1][kFused ? ICP_WIN : 1][ICP_NMOM + 1];
     __shared__ float sh_stage[kFused ? ICP_WAVES : 1][kFused ? ICP_STAGE : 1][8];
     __shared__ float sh_red[ICP_WAVES][ICP_PART_STRIDE];
+    __shared__ _Float16 sh_x[kSplit ? ICP_WAVES : 1][16][32];  // split precision: a half-wave's rows, column-major
     const int g = blockIdx.x;
     const ProbDesc& P = probs[owner[g]];
     const LevelDesc& L = P.lv[ctl.level];
@@ -674,9 +778,21 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
 #pragma unroll
     for (int k = 0; k < ICP_NMOM; ++k) acc[k] = 0.0f;
     float cnt = 0.0f;
+    f4v macc = {0.0f, 0.0f, 0.0f, 0.0f};  // split precision: the wave's X^T X
     {
         const Pose T = load_pose(st);
         const Lvl Lv = load_level(L);
+        // split precision: rows are centred on the level's live centroid moved
+        // by the pose of this iteration (the centring point of the two-pass
+        // variant, formed with the same FP64 expression, then rounded)
+        float cc[3] = {0.0f, 0.0f, 0.0f};
+        if (kSplit) {
+            const ICP_GLOBAL double* cen = gconst(st->cen[ctl.level]);
+            const double e0 = uniform(cen[0]), e1 = uniform(cen[1]), e2 = uniform(cen[2]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                cc[i] = (float)(((T.r[3 * i] * e0 + T.r[3 * i + 1] * e1) + T.r[3 * i + 2] * e2) + T.t[i]);
+        }
         const int base = tile * L.tile_px;
         const int end = min(base + L.tile_px, L.npx);
         // Every lane of the block runs the same rounds (the queue and window
@@ -703,12 +819,18 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
                 const bool gated = q.code == kGated;
                 if (gated) atomicAdd(&sh_hist[q.bin], 1u);
                 if (kFused && h0 >= 0) {
-                    if (gated && q.bin < h0) {
-                        accumulate_row(q.p, q.d, q.n, acc);
-                        cnt += 1.0f;
-                    }
                     const bool inwin = gated && q.bin >= h0 && q.bin < h0 + win.w;
-                    window_add(inwin, q.bin - h0, q.p, q.d, q.n, sh_win[wave], sh_stage[wave]);
+                    if (kSplit) {
+                        const float pc[3] = {q.p[0] - cc[0], q.p[1] - cc[1], q.p[2] - cc[2]};
+                        mfma_rows(gated && q.bin < h0, pc, q.d, q.n, sh_x[wave], macc);
+                        window_add(inwin, q.bin - h0, pc, q.d, q.n, sh_win[wave], sh_stage[wave]);
+                    } else {
+                        if (gated && q.bin < h0) {
+                            accumulate_row(q.p, q.d, q.n, acc);
+                            cnt += 1.0f;
+                        }
+                        window_add(inwin, q.bin - h0, q.p, q.d, q.n, sh_win[wave], sh_stage[wave]);
+                    }
                 }
             });
             cur = nxt;
@@ -722,6 +844,7 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
     }
     if (kFused && h0 >= 0) {
         float* part = L.part1 + (size_t)tile * ICP_WIN_SLOTS * ICP_PART_STRIDE;
+        if (kSplit) mfma_moments(macc, sh_x[wave], acc, cnt);
         block_reduce_row(acc, cnt, sh_red, part);
         // slot b+1 holds the prefix sum over window bins 0..b (b < w), so the
         // band kernel needs two slots per tile whatever the band edge.  The 48 bins
@@ -916,6 +1039,42 @@ __device__ __forceinline__ void set_centre(ProbState* st, int level) {
                        st->t[i];
 }
 
+// Back from centred rows: with a = [ (p' - c) x n + c x n, n ] = J a~,
+// J = [[I, [c]x], [0, I]], the moments are J M~ J^T and J g~ (FP64).
+__device__ void uncentre(double* M, const double* c) {
+    double A[6][6], g[6];
+    for (int i = 0; i < 6; ++i) {
+        for (int j = i; j < 6; ++j) A[i][j] = A[j][i] = M[tri7(i, j)];
+        g[i] = M[tri7(i, 6)];
+    }
+    const double C[3][3] = {{0.0, -c[2], c[1]}, {c[2], 0.0, -c[0]}, {-c[1], c[0], 0.0}};
+    double J[6][6] = {};
+    for (int i = 0; i < 6; ++i) J[i][i] = 1.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) J[i][3 + j] = C[i][j];
+    double T[6][6], B[6][6], h[6];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += J[i][k] * A[k][j];
+            T[i][j] = s;
+        }
+    for (int i = 0; i < 6; ++i) {
+        for (int j = 0; j < 6; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += T[i][k] * J[j][k];
+            B[i][j] = s;
+        }
+        double s = 0.0;
+        for (int k = 0; k < 6; ++k) s += J[i][k] * g[k];
+        h[i] = s;
+    }
+    for (int i = 0; i < 6; ++i) {
+        for (int j = i; j < 6; ++j) M[tri7(i, j)] = B[i][j];
+        M[tri7(i, 6)] = h[i];
+    }
+}
+
 // One work-group per problem: the band; in single-pass mode, when the band
 // edge fell inside the predicted window, the kept rows' moments are summed
 // from the pass-1 partials and the iteration is completed here.
@@ -932,11 +1091,16 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     }
     const Win win = fused ? band_window(pred, pred_hw, ctl.iter) : Win{-1, 0};
     const int h0 = win.h0;
+    // split precision: the centring point of this iteration (before any update)
+    if (kp.reduce_mode == 1 && threadIdx.x == 0) set_centre(st, ctl.level);
     const Band b = median_band(st, kp, dbg_hist);
     const bool hit = h0 >= 0 && b.N > 0 && b.k_lo == 0 && b.k_hi >= h0 - 1 && b.k_hi <= h0 + win.w - 1;
     if (hit) {
         sum_partials(L.part1, L.n_tiles, ICP_WIN_SLOTS * ICP_PART_STRIDE, b.k_hi - h0 + 1, sh_M);
-        if (threadIdx.x == 0) solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
+        if (threadIdx.x == 0) {
+            if (kp.reduce_mode == 1) uncentre(sh_M, st->cur_c);
+            solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
+        }
     }
     if (threadIdx.x == 0) {
         st->fused_done = hit ? 1 : 0;
@@ -948,7 +1112,6 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
         // with the solve folded into pass 2, an iteration finished here also
         // closes the level (pass 2 skips this problem: fused_done is set)
         if (kp.fold_solve && hit && ctl.last_of_level) level_reset(st);
-        if (kp.reduce_mode == 1) set_centre(st, ctl.level);
     }
 }
 
@@ -1023,12 +1186,6 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(4))) voi
 // of eight rows to both operands, so the product does not depend on how the
 // hardware orders the k slots.  Rows are staged through LDS: each round a
 // wave's 256 pixels form eight groups of 32.
-typedef _Float16 h8v __attribute__((ext_vector_type(8)));
-typedef _Float16 h4v __attribute__((ext_vector_type(4)));
-typedef float f4v __attribute__((ext_vector_type(4)));
-
-constexpr float kScaleRot = 8.0f;     // |(p' - c) x n| stays well inside FP16 range
-constexpr float kScaleB = 1024.0f;    // |b| < dist_max <= 0.125 m; lifts b's lo part out of FP16 subnormals
 
 __global__ __launch_bounds__(ICP_WG) void k_pass2_mfma(const ProbDesc* __restrict__ probs,
                                                        const int* __restrict__ owner, IterCtl ctl, KParams kp) {
@@ -1112,42 +1269,6 @@ __global__ __launch_bounds__(ICP_WG) void k_pass2_mfma(const ProbDesc* __restric
         cnt = lane == 0 ? (sh_d[wave][7][7] + sh_d[wave][7][15]) + (sh_d[wave][15][7] + sh_d[wave][15][15]) : 0.0f;
     }
     block_reduce_row(mom, cnt, sh_red, L.part + (size_t)tile * ICP_PART_STRIDE);
-}
-
-// Back from centred rows: with a = [ (p' - c) x n + c x n, n ] = J a~,
-// J = [[I, [c]x], [0, I]], the moments are J M~ J^T and J g~ (FP64).
-__device__ void uncentre(double* M, const double* c) {
-    double A[6][6], g[6];
-    for (int i = 0; i < 6; ++i) {
-        for (int j = i; j < 6; ++j) A[i][j] = A[j][i] = M[tri7(i, j)];
-        g[i] = M[tri7(i, 6)];
-    }
-    const double C[3][3] = {{0.0, -c[2], c[1]}, {c[2], 0.0, -c[0]}, {-c[1], c[0], 0.0}};
-    double J[6][6] = {};
-    for (int i = 0; i < 6; ++i) J[i][i] = 1.0;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) J[i][3 + j] = C[i][j];
-    double T[6][6], B[6][6], h[6];
-    for (int i = 0; i < 6; ++i)
-        for (int j = 0; j < 6; ++j) {
-            double s = 0.0;
-            for (int k = 0; k < 6; ++k) s += J[i][k] * A[k][j];
-            T[i][j] = s;
-        }
-    for (int i = 0; i < 6; ++i) {
-        for (int j = 0; j < 6; ++j) {
-            double s = 0.0;
-            for (int k = 0; k < 6; ++k) s += T[i][k] * J[j][k];
-            B[i][j] = s;
-        }
-        double s = 0.0;
-        for (int k = 0; k < 6; ++k) s += J[i][k] * g[k];
-        h[i] = s;
-    }
-    for (int i = 0; i < 6; ++i) {
-        for (int j = i; j < 6; ++j) M[tri7(i, j)] = B[i][j];
-        M[tri7(i, 6)] = h[i];
-    }
 }
 
 // One work-group per problem: FP64 sum of the pass-2 partials in tile order,
@@ -1256,8 +1377,11 @@ hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, int32_t* 
     return hipGetLastError();
 }
 
-hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, hipStream_t s) {
-    hipLaunchKernelGGL(k_centroid, dim3(n, levels), dim3(ICP_WG), 0, s, probs);
+hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, const int* const* owner, const int* tiles,
+                           hipStream_t s) {
+    for (int l = 0; l < levels; ++l)
+        hipLaunchKernelGGL(k_centroid_tiles, dim3(tiles[l]), dim3(ICP_WG), 0, s, probs, owner[l], l);
+    hipLaunchKernelGGL(k_centroid_sum, dim3(n, levels), dim3(64), 0, s, probs);
     return hipGetLastError();
 }
 
@@ -1318,12 +1442,15 @@ hipError_t launch_depth_to_maps(const MapsDesc* jobs, int n, int max_blocks, hip
 
 hipError_t launch_pass1(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp, int fused,
                         hipStream_t s) {
-    if (fused)
-        hipLaunchKernelGGL((k_pass1<false, true>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp, nullptr,
-                           nullptr);
+    if (fused && kp.reduce_mode == 1)
+        hipLaunchKernelGGL((k_pass1<false, true, true>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp,
+                           nullptr, nullptr);
+    else if (fused)
+        hipLaunchKernelGGL((k_pass1<false, true, false>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp,
+                           nullptr, nullptr);
     else
-        hipLaunchKernelGGL((k_pass1<false, false>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp, nullptr,
-                           nullptr);
+        hipLaunchKernelGGL((k_pass1<false, false, false>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp,
+                           nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -1369,8 +1496,12 @@ hipError_t launch_stage_set(const ProbDesc* probs, PoseArg pose, int k_lo, int k
 
 hipError_t launch_stage_single(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
                                int32_t* window, hipStream_t s) {
-    hipLaunchKernelGGL((k_pass1<false, true>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp, nullptr,
-                       nullptr);
+    if (kp.reduce_mode == 1)
+        hipLaunchKernelGGL((k_pass1<false, true, true>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp,
+                           nullptr, nullptr);
+    else
+        hipLaunchKernelGGL((k_pass1<false, true, false>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp,
+                           nullptr, nullptr);
     hipLaunchKernelGGL(k_stage_window, dim3(1), dim3(64), 0, s, probs, ctl, window);
     hipLaunchKernelGGL(k_band, dim3(1), dim3(ICP_WG), 0, s, probs, ctl, kp, 1, nullptr);
     return hipGetLastError();
@@ -1378,7 +1509,8 @@ hipError_t launch_stage_single(const ProbDesc* probs, const int* owner, int tile
 
 hipError_t launch_stage_pass1(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
                               uint8_t* code, int32_t* bin, uint32_t* hist, hipStream_t s) {
-    hipLaunchKernelGGL((k_pass1<true, false>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp, code, bin);
+    hipLaunchKernelGGL((k_pass1<true, false, false>), dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp, code,
+                       bin);
     hipLaunchKernelGGL(k_band, dim3(1), dim3(ICP_WG), 0, s, probs, ctl, kp, 0, hist);
     return hipGetLastError();
 }

@@ -18,8 +18,11 @@ struct MomArg {
 // per problem: seed the pose (IMU rotation or the initial pose), clear the
 // histogram, tickets, flags and statistics; clear the batch's pass-2 flag
 hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, int32_t* need2, hipStream_t s);
-// centroid of every level's valid live vertices (split-precision reduction)
-hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, hipStream_t s);
+// centroid of every level's valid live vertices (split-precision reduction):
+// per-tile FP64 sums over the level's flat tiles (owner[l], tiles[l]), then
+// per problem in tile order; uses the pass-2 partials as scratch
+hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, const int* const* owner, const int* tiles,
+                           hipStream_t s);
 // interleaved vertex / normal maps of n depth images (grid: max_blocks x n)
 hipError_t launch_depth_to_maps(const MapsDesc* jobs, int n, int max_blocks, hipStream_t s);
 // live-map work-groups of a W x H level (one per 64 x 4 pixels)

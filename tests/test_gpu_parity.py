@@ -267,17 +267,20 @@ def _check_single_pass(ctx, prob, gpu_lv, level, T, params, cases, tag):
     return hits
 
 
-def test_s3_single_pass_window_moments(ctx):
+@pytest.mark.parametrize("reduce_mode", [0, 1])
+def test_s3_single_pass_window_moments(ctx, reduce_mode):
     """The reduction the registration runs by default: rows below the
-    predicted band-edge window summed per tile, rows inside it per bin, and
-    the band kernel's FP64 sum of the partials up to the band edge.  Per entry
-    against the oracle's FP64 moments over the same band, with the edge just
-    below the window, inside it, on its last bin, and missed from above and
-    below (the band kernel must then decline), on VGA room levels."""
+    predicted band-edge window summed per tile (FP32 per lane, or the FP16
+    hi+lo split MFMA on centred rows), rows inside it per bin, and the band
+    kernel's FP64 sum of the partials up to the band edge (un-centred for the
+    split reduction).  Per entry against the oracle's FP64 moments over the
+    same band, with the edge just below the window, inside it, on its last
+    bin, and missed from above and below (the band kernel must then decline),
+    on VGA room levels."""
     seq = synth.RoomSequence(0, n_frames=3)
     prob = seq.problem(1)
     gpu_lv = _gpu_levels(ctx, prob)
-    params = icp.icp_params_default()
+    params = icp.icp_params_default(reduce_mode=reduce_mode)
     hits = 0
     for T in _poses_for(prob)[:2]:
         for level in range(3):
@@ -286,12 +289,13 @@ def test_s3_single_pass_window_moments(ctx):
     assert hits >= 6 * 6  # six of the nine placements hit when the window is not clamped
 
 
-def test_s3_single_pass_window_clamped_at_either_end(ctx):
+@pytest.mark.parametrize("reduce_mode", [0, 1])
+def test_s3_single_pass_window_clamped_at_either_end(ctx, reduce_mode):
     """Windows clamped into the histogram: noise-free identical frames put the
     band edge at bin 1 or 2 with the window from bin 0; model maps 9 cm behind
     the live frame put it at the last bin with the window at 976..1023."""
     same = synth.pair_problem(8, trans_m=0.0, rot_deg=0.0, imu_deg=0.0, noise=False)
-    params = icp.icp_params_default()
+    params = icp.icp_params_default(reduce_mode=reduce_mode)
     gpu_lv = _gpu_levels(ctx, same)
     T = np.eye(4)
     for level in range(3):
@@ -304,7 +308,7 @@ def test_s3_single_pass_window_clamped_at_either_end(ctx):
     mv[..., 2] += 0.09
     q = synth.Problem(live_depth=p.live_depth, model_vtx=mv, model_nrm=p.model_nrm, K=p.K, imu_R=p.imu_R,
                       init_pose=p.init_pose, T_gt=p.T_gt, name="shifted-9cm")
-    params = icp.icp_params_default(dist_max=0.125)
+    params = icp.icp_params_default(dist_max=0.125, reduce_mode=reduce_mode)
     gpu_lv = _gpu_levels(ctx, q)
     _, band = _check_associate(ctx, q, gpu_lv, 0, T, params)
     assert band[3] == 1023
