@@ -336,6 +336,7 @@ FrontEnd front_end(const icp_params* p) {
     fe.normal_mode = p->normal_mode;
     fe.normal_radius = p->normal_radius;
     fe.sigma_m = p->filter_sigma_m;
+    fe.inv_sigma_m = 1.0 / p->filter_sigma_m;
     if (p->depth_filter) {
         const int r = p->filter_radius, n = 2 * r + 1;
         const double sp = p->filter_sigma_px;

@@ -56,6 +56,7 @@ struct LevelDesc {
 struct FrontEnd {
     int32_t depth_filter, filter_radius, normal_mode, normal_radius;
     double sigma_m;
+    double inv_sigma_m;         // 1 / sigma_m, correctly rounded (an IEEE division on the host)
     double ws[(2 * ICP_FILTER_MAX_R + 1) * (2 * ICP_FILTER_MAX_R + 1)];
 };
 

@@ -146,6 +146,11 @@ __device__ __forceinline__ void live_px(const ICP_GLOBAL float* D, int W, int H,
 // over the (2r+1)^2 window in row-major order, valid neighbours within the
 // range cut-off add ws * (1 - (dz/c)^2)^2 to the weight sum and that times z
 // to the weighted sum (FP64); out = sum(w z) / sum(w); invalid pixels stay 0.
+// The quotient dz/c is the correctly rounded one without a division: with
+// y = RN(1/c) (from the host), q = RN(dz y) is within an ulp of dz/c, and one
+// correction RN(q + RN(dz - c q) y) (the remainder exact by FMA) rounds
+// correctly -- Markstein's theorem for division by a correctly rounded
+// reciprocal.
 // A work-group takes an FE_TX x FE_TY tile whose depth and R-pixel halo are
 // staged in LDS (0, an invalid depth, outside the image).
 constexpr int kBoxW = FE_TX + 2 * ICP_FILTER_MAX_R, kBoxH = FE_TY + 2 * ICP_FILTER_MAX_R;
@@ -187,7 +192,8 @@ __global__ __launch_bounds__(ICP_WG) void k_bilateral(const ProbDesc* __restrict
                     if (!depth_ok(zq)) continue;
                     const double dz = (double)zq - (double)z;
                     if (!(fabs(dz) < fe.sigma_m)) continue;
-                    const double t = dz / fe.sigma_m;
+                    const double q = dz * fe.inv_sigma_m;
+                    const double t = __builtin_fma(__builtin_fma(-q, fe.sigma_m, dz), fe.inv_sigma_m, q);
                     const double a = 1.0 - t * t;
                     const double w = fe.ws[(dv + R) * N + (du + R)] * (a * a);
                     sw += w;

@@ -707,3 +707,43 @@ def test_band_keeps_about_three_quarters_of_the_pairs():
         _, st, _ = oracle.register_problem(seq.problem(k))
         fracs.append(st[0]["n_kept"] / st[0]["n_gated"])
     assert all(0.6 < f < 0.9 for f in fracs), fracs
+
+
+def test_division_by_a_correctly_rounded_reciprocal(tmp_path):
+    """The bilateral filter's range quotient dz / c is formed on the GPU as
+    q = RN(dz y), t = RN(q + RN(dz - c q) y) with y = RN(1/c) (Markstein's
+    correction); it must equal the IEEE quotient for the filter's inputs.  A
+    plain C check over a million FP32 depth differences within the cut-off,
+    for several cut-offs (including ones whose reciprocal is inexact)."""
+    import subprocess
+    src = tmp_path / "m.c"
+    src.write_text(r'''
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+static uint64_t s = 88172645463325252ull;
+static uint64_t xr(void) { s ^= s << 13; s ^= s >> 7; s ^= s << 17; return s; }
+static double u01(void) { return (xr() >> 11) * 0x1.0p-53; }
+int main(void) {
+    const double cs[] = {0.05, 0.03, 0.1, 0.0123456789, 1.0 / 3.0};
+    long bad = 0, n = 0;
+    for (int ci = 0; ci < 5; ++ci) {
+        const double c = cs[ci], y = 1.0 / c;
+        for (long k = 0; k < 200000; ++k) {
+            const float z = (float)(0.3 + 9.7 * u01());
+            float zq = (k & 1) ? nextafterf(z, (k & 2) ? 100.0f : 0.0f) : (float)(z + (2.0 * u01() - 1.0) * c);
+            const double dz = (double)zq - (double)z;
+            if (!(fabs(dz) < c)) continue;
+            const double q = dz * y;
+            ++n;
+            bad += fma(fma(-q, c, dz), y, q) != dz / c;
+        }
+    }
+    printf("%ld %ld\n", n, bad);
+    return 0;
+}
+''')
+    exe = tmp_path / "m"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-o", str(exe), str(src), "-lm"], check=True)
+    n, bad = (int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split())
+    assert n > 500000 and bad == 0
