@@ -216,6 +216,27 @@ __global__ __launch_bounds__(ICP_WG) void k_bilateral(const ProbDesc* __restrict
 // an R-pixel halo are formed once into LDS (the same live_vertex of the same
 // depth and quotients, NaN outside the image), then every pixel sums its box
 // from LDS in row-major order.
+// Correctly rounded reciprocals 1/k of the box counts k = 1 .. r (2r + 1)
+// (constant evaluation rounds to nearest, as an IEEE division does), and s / k
+// from them with Markstein's correction (as in the bilateral filter): the
+// IEEE quotient without a division.
+constexpr int kMaxBoxCount = ICP_FILTER_MAX_R * (2 * ICP_FILTER_MAX_R + 1);
+struct RecipTable {
+    double v[kMaxBoxCount + 1];
+};
+constexpr RecipTable make_recips() {
+    RecipTable t{};
+    for (int k = 1; k <= kMaxBoxCount; ++k) t.v[k] = 1.0 / (double)k;
+    return t;
+}
+__constant__ RecipTable kBoxRecip = make_recips();
+
+__device__ __forceinline__ double div_count(double s, int k) {
+    const double y = kBoxRecip.v[k];
+    const double q = s * y;
+    return __builtin_fma(__builtin_fma(-q, (double)k, s), y, q);
+}
+
 template <int R>
 __global__ __launch_bounds__(ICP_WG) void k_live_n_box(const ProbDesc* __restrict__ probs, int level) {
     static_assert(R >= 1 && R <= ICP_FILTER_MAX_R, "box radius");
@@ -275,8 +296,8 @@ __global__ __launch_bounds__(ICP_WG) void k_live_n_box(const ProbDesc* __restric
             if (nr >= need && nl >= need && nd >= need && nu >= need) {
                 double h[3], g[3];
                 for (int k = 0; k < 3; ++k) {
-                    h[k] = sr[k] / nr - sl[k] / nl;
-                    g[k] = sd[k] / nd - su[k] / nu;
+                    h[k] = div_count(sr[k], nr) - div_count(sl[k], nl);
+                    g[k] = div_count(sd[k], nd) - div_count(su[k], nu);
                 }
                 const double c0 = h[1] * g[2] - h[2] * g[1];
                 const double c1 = h[2] * g[0] - h[0] * g[2];
