@@ -731,7 +731,10 @@ def sweep_main(args):
 
 # ----------------------------------------------------------------- serving
 
-SERVE_TILES = (4096, 2048, 1024, 0)  # fixed per level: a frame's result does not depend on its batch-mates
+SERVE_TILES = (2048, 1024, 1024, 0)  # fixed per level: a frame's result does not depend on its batch-mates
+SERVE_FEEDERS = 4  # client threads submitting frames (cameras deliver independently; each takes every 4th stream)
+SERVE_FRAMES_IN_FLIGHT = 4  # consecutive frames of one stream a batch may take
+SERVE_MAX_BATCH = 128
 
 
 def _make_stream_frames(job):
@@ -742,8 +745,9 @@ def _make_stream_frames(job):
 
 
 def _serve_run(icp, streams, rate_hz, n_frames, params, max_batch, seed):
-    """Poisson arrivals at rate_hz per stream; returns per-frame latencies and
-    the served rate."""
+    """Poisson arrivals at rate_hz per stream, submitted by SERVE_FEEDERS
+    client threads (stream i by thread i mod SERVE_FEEDERS); returns per-frame
+    latencies and the served rate."""
     import threading
     rng = np.random.default_rng(seed)
     sched = []
@@ -751,7 +755,8 @@ def _serve_run(icp, streams, rate_hz, n_frames, params, max_batch, seed):
         t = np.cumsum(rng.exponential(1.0 / rate_hz, size=n_frames))
         sched += [(float(t[k]), i, k) for k in range(n_frames)]
     sched.sort()
-    srv = icp.Server(icp.icp_server_config_default(params=params, max_batch=max_batch, slots=2))
+    srv = icp.Server(icp.icp_server_config_default(params=params, max_batch=max_batch, slots=2,
+                                                   frames_in_flight=SERVE_FRAMES_IN_FLIGHT))
     ids = [srv.open_stream(st["W"], st["H"], st["K"]) for st in streams]
     total = len(sched)
     lat, bsz = [], []
@@ -760,9 +765,11 @@ def _serve_run(icp, streams, rate_hz, n_frames, params, max_batch, seed):
     lock = threading.Lock()
     start = icp.icp_server_clock() + 0.05
 
-    def feeder():
+    def feeder(f):
         try:
             for t, i, k in sched:
+                if i % SERVE_FEEDERS != f:
+                    continue
                 due = start + t
                 while True:
                     d = due - icp.icp_server_clock()
@@ -779,15 +786,16 @@ def _serve_run(icp, streams, rate_hz, n_frames, params, max_batch, seed):
         except Exception as e:  # surfaced below
             errors.append(e)
 
-    th = threading.Thread(target=feeder)
-    th.start()
+    ths = [threading.Thread(target=feeder, args=(f,)) for f in range(SERVE_FEEDERS)]
+    for th in ths:
+        th.start()
     got = 0
     t_first = t_last = None
     quiet_since = time.time()
     while got < total:
         res = srv.poll(1024, timeout_ms=200)
         if not res:
-            if time.time() - quiet_since > 30.0 or (errors and not th.is_alive()):
+            if time.time() - quiet_since > 30.0 or (errors and not any(th.is_alive() for th in ths)):
                 break
             continue
         quiet_since = time.time()
@@ -801,7 +809,8 @@ def _serve_run(icp, streams, rate_hz, n_frames, params, max_batch, seed):
             t_first = r["t_done"] if t_first is None else min(t_first, r["t_done"])
             t_last = r["t_done"] if t_last is None else max(t_last, r["t_done"])
         got += len(res)
-    th.join()
+    for th in ths:
+        th.join()
     ctr = srv.counters()
     srv.close()
     if errors:
@@ -843,14 +852,14 @@ def serve_main(args):
     params = icp.icp_params_default(tile_px=SERVE_TILES)
     px_frame = sum(st["W"] * st["H"] for st in streams) / len(streams)
     log("warm-up")
-    _serve_run(icp, streams, 30.0, 3, params, 64, args.seed)
+    _serve_run(icp, streams, 30.0, 3, params, SERVE_MAX_BATCH, args.seed)
     log(f"serving {args.serve_frames} frames per stream at 30 Hz per stream")
-    base = _serve_run(icp, streams, 30.0, args.serve_frames, params, 64, args.seed)
+    base = _serve_run(icp, streams, 30.0, args.serve_frames, params, SERVE_MAX_BATCH, args.seed)
     log(f"  {base}")
     sweep = []
     for m in [float(x) for x in args.serve_sweep.split(",") if x]:
         n = max(30, min(args.serve_frames, int(30 * m * 4)))  # about 4 s of arrivals, at least 30 frames
-        r = _serve_run(icp, streams, 30.0 * m, n, params, 64, args.seed + 1)
+        r = _serve_run(icp, streams, 30.0 * m, n, params, SERVE_MAX_BATCH, args.seed + 1)
         log(f"  x{m:g}: {r}")
         sweep.append(r)
     out = {
@@ -861,7 +870,9 @@ def serve_main(args):
         "config": {"workload": "32 streams: 7 x 320x240, 13 x 640x480, 6 x 848x480, 6 x 1280x720; "
                                f"{args.serve_frames} frames each ({args.serve_period} distinct, periodic path); "
                                "Poisson arrivals at 30 Hz per stream; frame-to-frame; 3 levels {10,5,4}",
-                   "mean_px_per_frame": round(px_frame), "tiles": list(SERVE_TILES[:3])},
+                   "mean_px_per_frame": round(px_frame), "tiles": list(SERVE_TILES[:3]),
+                   "server": {"slots": 2, "max_batch": SERVE_MAX_BATCH, "frames_in_flight": SERVE_FRAMES_IN_FLIGHT,
+                              "use_graphs": 1, "client_threads": SERVE_FEEDERS}},
         "latency_ms": {"p50": base["p50_ms"], "p99": base["p99_ms"], "from": "arrival to result on the host"},
         "at_30hz": base, "saturation_sweep": sweep,
     }

@@ -199,7 +199,8 @@ void icp_ctx_destroy(icp_ctx* ctx);
 /* Replay registrations as HIP graphs (1, the default) or launch every kernel
    eagerly (0).  With graphs, the launches of a registration are captured
    once per combination of problem sizes, parameters and workspace and
-   replayed on later calls; calls with kernel timing enabled launch eagerly. */
+   replayed on later calls (a context keeps the eight most recently used
+   graphs); calls with kernel timing enabled launch eagerly. */
 int icp_ctx_set_graphs(icp_ctx* ctx, int enable);
 
 /* Bytes of device workspace the context currently holds. */
@@ -494,7 +495,7 @@ typedef struct {
     int32_t device;
     int32_t max_batch;          /* most frames per batch, 1..4096 (default 64) */
     int32_t slots;              /* batches in flight at once, 1..4 (default 2) */
-    int32_t use_graphs;         /* replay repeated batch shapes as HIP graphs (default 0) */
+    int32_t use_graphs;         /* replay repeated batch shapes as HIP graphs (default 1) */
     int32_t frames_in_flight;   /* most consecutive frames of one stream in one batch, 1..7 (default 2);
                                    a stream holds frames_in_flight + 1 frame slots on the device */
     int32_t pad;

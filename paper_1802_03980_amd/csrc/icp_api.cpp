@@ -52,9 +52,14 @@ struct icp_ctx {
     std::vector<int64_t> owners_key;    // plan whose tile owners are in device memory
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;   // private stream used only for capture
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    std::vector<int64_t> graph_key;
+    struct GraphEntry {
+        std::vector<int64_t> key;       // plan, workspace and parameters it was captured with
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        uint64_t used = 0;              // last use (for least-recently-used eviction)
+    };
+    std::vector<GraphEntry> graphs;     // at most kGraphCache
+    uint64_t graph_clock = 0;
     void* plan_mem = nullptr;  // the cached Plan (see ctx_plan)
     MapsDesc* d_jobs = nullptr;  // icp_live_maps job descriptor (device)
 };
@@ -246,12 +251,16 @@ std::vector<int64_t> plan_signature(int n, const icp_problem* probs, int levels,
     return k;
 }
 
-void drop_graph(icp_ctx* ctx) {
-    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
-    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
-    ctx->graph_exec = nullptr;
-    ctx->graph = nullptr;
-    ctx->graph_key.clear();
+void destroy_graph(icp_ctx::GraphEntry& g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g.exec = nullptr;
+    g.graph = nullptr;
+}
+
+void drop_graphs(icp_ctx* ctx) {
+    for (auto& g : ctx->graphs) destroy_graph(g);
+    ctx->graphs.clear();
 }
 
 template <typename T>
@@ -271,7 +280,7 @@ int ensure_workspace(icp_ctx* ctx, size_t bytes, bool exact = false) {
         ctx->stage_ready = false;
     }
     ctx->owners_key.clear();
-    drop_graph(ctx);
+    drop_graphs(ctx);
     // growth margin so that slightly larger batches reuse the allocation; none
     // when the caller sized the request itself
     size_t want = exact ? bytes : bytes + bytes / 4;
@@ -573,7 +582,11 @@ int run_batch(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, icp_result* r
 
 // Launch the whole registration of a staged batch on s, results into the
 // workspace's result array.  Without timing, the launches are captured once
-// per (plan, parameters, workspace) into a HIP graph and replayed.
+// per (plan, parameters, workspace) into a HIP graph and replayed; the context
+// keeps the kGraphCache most recently used graphs (a frame server's batches
+// cycle through a few shapes).
+constexpr size_t kGraphCache = 8;
+
 int execute(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, hipStream_t s) {
     char* base = static_cast<char*>(ctx->ws);
     icp_result* d_res = reinterpret_cast<icp_result*>(base + P.off_res);
@@ -582,26 +595,44 @@ int execute(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, hipStream_t s) 
     key.push_back(reinterpret_cast<int64_t>(ctx->ws));
     const int64_t* pw = reinterpret_cast<const int64_t*>(prm);
     for (size_t k = 0; k < sizeof(icp_params) / sizeof(int64_t); ++k) key.push_back(pw[k]);
-    if (key != ctx->graph_key) {
-        // an asynchronous call may still be running the old graph: it is
-        // destroyed only after the previous call's work has finished
-        if (ctx->graph_exec && ctx->done_valid) HIP_TRY(ctx, hipEventSynchronize(ctx->ev_done));
-        drop_graph(ctx);
+    icp_ctx::GraphEntry* hit = nullptr;
+    for (auto& g : ctx->graphs)
+        if (g.key == key) {
+            hit = &g;
+            break;
+        }
+    if (!hit) {
+        if (ctx->graphs.size() >= kGraphCache) {
+            // an asynchronous call may still be running the evicted graph: it
+            // is destroyed only after the previous call's work has finished
+            // (every earlier call's work is ordered before that)
+            if (ctx->done_valid) HIP_TRY(ctx, hipEventSynchronize(ctx->ev_done));
+            auto lru = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                        [](const auto& a, const auto& b) { return a.used < b.used; });
+            destroy_graph(*lru);
+            ctx->graphs.erase(lru);
+        }
         if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
         HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
         int rc = run_batch(ctx, n, prm, P, d_res, ctx->cap_stream);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
-        if (rc) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
+        icp_ctx::GraphEntry g;
+        hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g.graph);
+        if (rc || e != hipSuccess) {
+            destroy_graph(g);
+            return rc ? rc : hip_fail(ctx, e, "hipStreamEndCapture");
         }
-        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
-        ctx->graph = g;
-        HIP_TRY(ctx, hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
-        ctx->graph_key = key;
+        e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            g.exec = nullptr;
+            destroy_graph(g);
+            return hip_fail(ctx, e, "hipGraphInstantiate");
+        }
+        g.key = std::move(key);
+        ctx->graphs.push_back(std::move(g));
+        hit = &ctx->graphs.back();
     }
-    HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, s));
+    hit->used = ++ctx->graph_clock;
+    HIP_TRY(ctx, hipGraphLaunch(hit->exec, s));
     return ICP_OK;
 }
 
@@ -736,7 +767,7 @@ void icp_ctx_destroy(icp_ctx* ctx) {
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-    drop_graph(ctx);
+    drop_graphs(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete static_cast<Plan*>(ctx->plan_mem);
     if (ctx->d_jobs) (void)hipFree(ctx->d_jobs);

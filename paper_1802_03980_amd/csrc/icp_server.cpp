@@ -386,7 +386,7 @@ void icp_server_config_default(icp_server_config* cfg) {
     cfg->device = 0;
     cfg->max_batch = 64;
     cfg->slots = 2;
-    cfg->use_graphs = 0;
+    cfg->use_graphs = 1;
     cfg->frames_in_flight = 2;
     cfg->hbm_budget_bytes = 0;
     icp_params_default(&cfg->params);

@@ -450,6 +450,28 @@ def test_graph_replays_match_eager(ctx, reduce_mode):
         icp.icp_ctx_set_graphs(ctx, True)
 
 
+def test_graph_cache_evicts_and_recaptures(ctx):
+    """More batch shapes than the context keeps graphs for (ten batch sizes,
+    twice over, then the first two again): every replay, whether from a
+    cached graph or one captured after an eviction, equals the eager run bit
+    for bit."""
+    probs = [synth.pair_problem(k % 3) for k in range(10)]
+    data = [upload(p) for p in probs]
+    items = [dict(live_depth=d, model_vtx=mv, model_nrm=mn, K=p.K, imu_R=p.imu_R, init_pose=p.init_pose)
+             for p, (d, mv, mn) in zip(probs, data)]
+    params = icp.icp_params_default()
+    icp.icp_ctx_set_graphs(ctx, False)
+    sizes = list(range(10, 0, -1))  # largest first: the workspace does not grow under the graphs
+    eager = {n: icp.icp_register_batch(ctx, items[:n], params) for n in sizes}
+    icp.icp_ctx_set_graphs(ctx, True)
+    try:
+        for n in sizes + sizes + [10, 9]:
+            for (Tg, sg), (Te, se) in zip(icp.icp_register_batch(ctx, items[:n], params), eager[n]):
+                assert np.array_equal(Tg, Te) and sg == se, n
+    finally:
+        icp.icp_ctx_set_graphs(ctx, True)
+
+
 def test_edge_cases(ctx):
     prob = synth.pair_problem(0)
     params = icp.icp_params_default()
