@@ -107,8 +107,37 @@ __device__ __forceinline__ void frustum_terms(const Cull& c, int i, int j, int k
     q[4] = (c.b_hi * z + m * (1.0f + fabsf(c.b_hi))) - y;
 }
 
-// One voxel: pre-test, then the exact FP64 update.
-__device__ __forceinline__ void integrate_voxel(const Geo& g, const Cull& c, double mu, double maxw,
+// a / b rounded correctly from y = RN(1/b): q = RN(a y) lies within an ulp
+// of a / b, so the remainder a - b q is exact in one FMA, and one more FMA
+// with y gives the correctly rounded quotient (Markstein's theorem; it needs
+// no underflow or overflow in a y and the remainder, which the callers'
+// ranges guarantee: moderate a, and b at least 2^-900).
+__device__ __forceinline__ double div_by_recip(double a, double b, double y) {
+    const double q = a * y;
+    return __builtin_fma(__builtin_fma(-q, b, a), y, q);
+}
+
+constexpr double kRecipMinDivisor = 0x1p-900;
+
+// 1/k for the running average's integer weight counts k = 1..kMaxCount,
+// each correctly rounded (IEEE divisions at compile time).
+constexpr int kMaxCount = 256;
+struct CountRecip {
+    double v[kMaxCount + 1];
+};
+constexpr CountRecip make_count_recips() {
+    CountRecip t{};
+    for (int k = 1; k <= kMaxCount; ++k) t.v[k] = 1.0 / (double)k;
+    return t;
+}
+__constant__ CountRecip kCountRecip = make_count_recips();
+
+// One voxel: pre-test, then the exact FP64 update.  The quotients are the
+// IEEE quotients of the definition, formed from correctly rounded
+// reciprocals: one division for both projection quotients (a shared
+// divisor), 1/mu from the host, and a table for the weight count (an IEEE
+// division for counts that are not small integers).
+__device__ __forceinline__ void integrate_voxel(const Geo& g, const Cull& c, double mu, double inv_mu, double maxw,
                                                 const float* __restrict__ depth, int W, int H, double fx, double fy,
                                                 double cx, double cy, const double* P, int i, int j, int k,
                                                 int& d_neg) {
@@ -126,20 +155,35 @@ __device__ __forceinline__ void integrate_voxel(const Geo& g, const Cull& c, dou
     const double xc1 = (P[1] * d0 + P[5] * d1) + P[9] * d2;
     const double xc2 = (P[2] * d0 + P[6] * d1) + P[10] * d2;
     if (!(xc2 > 0.0)) return;
-    const double uu = floor(fx * (xc0 / xc2) + cx + 0.5);
-    const double vv = floor(fy * (xc1 / xc2) + cy + 0.5);
+    double q0, q1;
+    if (xc2 >= kRecipMinDivisor) {
+        const double y = 1.0 / xc2;
+        q0 = div_by_recip(xc0, xc2, y);
+        q1 = div_by_recip(xc1, xc2, y);
+    } else {
+        q0 = xc0 / xc2;
+        q1 = xc1 / xc2;
+    }
+    const double uu = floor(fx * q0 + cx + 0.5);
+    const double vv = floor(fy * q1 + cy + 0.5);
     if (!(uu >= 0.0 && uu <= (double)(W - 1) && vv >= 0.0 && vv <= (double)(H - 1))) return;
     const float z = depth[(size_t)vv * W + (size_t)uu];
     if (!depth_valid(z)) return;
     const double sdf = (double)z - xc2;
     if (sdf < -mu) return;
-    double f = sdf / mu;
+    double f = mu >= kRecipMinDivisor ? div_by_recip(sdf, mu, inv_mu) : sdf / mu;
     if (f > 1.0) f = 1.0;
     float2* p = g.vox + (((size_t)k * g.dim + j) * g.dim + i);
     const float2 cur = *p;
     const double w = (double)cur.y;
     const double wn = w + 1.0;
-    const float tn = (float)(((double)cur.x * w + f) / wn);
+    const double a = (double)cur.x * w + f;
+    double avg;
+    if (wn >= 1.0 && wn <= (double)kMaxCount && wn == floor(wn))
+        avg = div_by_recip(a, wn, kCountRecip.v[(int)wn]);
+    else
+        avg = a / wn;
+    const float tn = (float)avg;
     *p = make_float2(tn, (float)(wn < maxw ? wn : maxw));
     d_neg += (tn <= 0.0f ? 1 : 0) - (cur.y > 0.0f && cur.x <= 0.0f ? 1 : 0);
 }
@@ -147,7 +191,7 @@ __device__ __forceinline__ void integrate_voxel(const Geo& g, const Cull& c, dou
 // grid (ceil(dim/64), ceil(dim/4), ceil(dim/kIntegrateZ)), block 64 x 4; a
 // thread takes kIntegrateZ voxels along z (fewer, longer work-groups: one
 // voxel per thread left the launch rate, not the arithmetic, as the limit)
-__global__ void __launch_bounds__(256) k_tsdf_integrate(Geo g, Cull c, double mu, double maxw,
+__global__ void __launch_bounds__(256) k_tsdf_integrate(Geo g, Cull c, double mu, double inv_mu, double maxw,
                                                         const float* __restrict__ depth, int W, int H, double fx,
                                                         double fy, double cx, double cy, PoseArg T) {
     const int i = blockIdx.x * 64 + threadIdx.x;
@@ -169,7 +213,7 @@ __global__ void __launch_bounds__(256) k_tsdf_integrate(Geo g, Cull c, double mu
     if (__ballot(active) == 0) return;  // nothing to update or count in this wave
     int a_neg = 0;
     for (int k = k0; k < k1; ++k) {
-        if (active) integrate_voxel(g, c, mu, maxw, depth, W, H, fx, fy, cx, cy, T.v, i, j, k, a_neg);
+        if (active) integrate_voxel(g, c, mu, inv_mu, maxw, depth, W, H, fx, fy, cx, cy, T.v, i, j, k, a_neg);
         if (g.cnt && ((k & 7) == 7 || k + 1 == k1)) {
             // the 8 lanes sharing i >> 3 cover one brick row: one atomic per brick and row
 #pragma unroll
@@ -511,8 +555,9 @@ hipError_t launch_tsdf_integrate(const TsdfDesc& d, const float* depth, int W, i
     dim3 grid((unsigned)((d.dim + 63) / 64), (unsigned)((d.dim + 3) / 4),
               (unsigned)((d.dim + kIntegrateZ - 1) / kIntegrateZ));
     const Geo g = make_geo(d);
-    hipLaunchKernelGGL(k_tsdf_integrate, grid, dim3(64, 4), 0, s, g, c, d.mu, d.max_weight, depth, W, H, K[0], K[1],
-                       K[2], K[3], T);
+    const double inv_mu = 1.0 / d.mu;  // correctly rounded (IEEE division)
+    hipLaunchKernelGGL(k_tsdf_integrate, grid, dim3(64, 4), 0, s, g, c, d.mu, inv_mu, d.max_weight, depth, W, H, K[0],
+                       K[1], K[2], K[3], T);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !d.bricks) return e;
     return launch_flags(g, s);

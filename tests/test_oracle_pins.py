@@ -747,3 +747,55 @@ int main(void) {
     subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-o", str(exe), str(src), "-lm"], check=True)
     n, bad = (int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split())
     assert n > 500000 and bad == 0
+
+
+def test_reciprocal_division_over_the_tsdf_ranges(tmp_path):
+    """The TSDF integration forms its quotients the same way: x/z and y/z
+    share y = RN(1/z) (z from 2^-900 to 20 m, numerators up to 20 m in
+    magnitude down to 1e-12), sdf/mu uses RN(1/mu), and the running average
+    divides by an integer count k = 1..256 through a table of RN(1/k).  A
+    plain C check that every such quotient equals the IEEE one."""
+    import subprocess
+    src = tmp_path / "t.c"
+    src.write_text(r"""
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+static uint64_t s = 0x9E3779B97F4A7C15ull;
+static uint64_t xr(void) { s ^= s << 13; s ^= s >> 7; s ^= s << 17; return s; }
+static double u01(void) { return (xr() >> 11) * 0x1.0p-53; }
+static double mq(double a, double b, double y) { const double q = a * y; return fma(fma(-q, b, a), y, q); }
+int main(void) {
+    long bad = 0, n = 0;
+    for (long t = 0; t < 2000000; ++t) {          /* projection: shared divisor */
+        const double b = (t & 1) ? 0.01 + 20.0 * u01() : ldexp(1.0 + u01(), -(int)(900.0 * u01()));
+        const double a = (2.0 * u01() - 1.0) * ((t & 2) ? 20.0 : ldexp(1.0, -(int)(40.0 * u01())));
+        const double y = 1.0 / b;
+        ++n; bad += mq(a, b, y) != a / b;
+    }
+    const double mus[] = {0.05, 0.0125 * 4, 0.03, 0.1, 1.0 / 3.0, 0.0173};
+    for (int m = 0; m < 6; ++m) {                  /* sdf / mu */
+        const double mu = mus[m], y = 1.0 / mu;
+        for (long t = 0; t < 300000; ++t) {
+            const double z = (double)(float)(0.3 + 9.7 * u01()), xc = 0.3 + 9.7 * u01();
+            const double sdf = z - xc;
+            if (sdf < -mu) continue;
+            ++n; bad += mq(sdf, mu, y) != sdf / mu;
+        }
+    }
+    for (int k = 1; k <= 256; ++k) {               /* running average by the count */
+        const double y = 1.0 / (double)k;
+        for (long t = 0; t < 20000; ++t) {
+            const double w = (double)(k - 1);
+            const double a = (double)(float)(2.0 * u01() - 1.0) * w + (2.0 * u01() - 1.0);
+            ++n; bad += mq(a, (double)k, y) != a / (double)k;
+        }
+    }
+    printf("%ld %ld\n", n, bad);
+    return 0;
+}
+""")
+    exe = tmp_path / "t"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-o", str(exe), str(src), "-lm"], check=True)
+    n, bad = (int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split())
+    assert n > 7000000 and bad == 0
