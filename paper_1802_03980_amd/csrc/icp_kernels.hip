@@ -627,7 +627,7 @@ __device__ __forceinline__ int next_half_width(int k_hi, int pred_hi, int iter) 
 // Sum the 28 accumulators and the count over the work-group into `out`
 // (29 floats); every thread calls it.
 __device__ __forceinline__ void block_reduce_row(float (&acc)[ICP_NMOM], float cnt, float (*sh_red)[ICP_PART_STRIDE],
-                                                 float* out) {
+                                                 ICP_GLOBAL float* out) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int k = 0; k < ICP_NMOM; ++k) acc[k] = wave_sum(acc[k]);
@@ -793,9 +793,29 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
     const ProbState* st = P.st;
     const int tid = threadIdx.x;
     const int tile = g - L.tile_base;
-    if (st->level_done) return;  // uniform: the level has ended for this problem
-    const Win win = kFused ? band_window(st->pred_hi, st->pred_hw, ctl.iter) : Win{-1, 0};
+    const Lvl Lv = load_level(L);
+    const int base = tile * L.tile_px;
+    const int end = min(base + L.tile_px, L.npx);
+    // Every lane of the block runs the same rounds (the queue and window
+    // steps work across the wave); a lane past the tile's end loads the
+    // round's first pixels and treats its own as invalid.
+    constexpr int kRound = ICP_WG * ICP_PASS1_PX;  // pixels per round
+    auto ld_index = [&](int r) {
+        const int i = r + ICP_PASS1_PX * tid;
+        return i < end ? i : r;
+    };
+    // The first round's live data depend on the level alone: they are loaded
+    // before the problem's state, so that their latency overlaps the state's
+    // and the pose's (a work-group of a coarse level runs only a few rounds).
+    // (The state is read through a global pointer, as scalar loads, so that
+    // waiting for it does not also wait for the live loads.)
+    LiveIn<ICP_PASS1_PX> cur;
+    if (base < end) cur = load_live<ICP_PASS1_PX>(Lv, ld_index(base));
+    const ICP_GLOBAL ProbState* gst = gconst(st);
+    if (gst->level_done) return;  // uniform: the level has ended for this problem
+    const Win win = kFused ? band_window(gst->pred_hi, gst->pred_hw, ctl.iter) : Win{-1, 0};
     const int h0 = win.h0;
+    const Pose T = load_pose(st);
     for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) sh_hist[b] = 0u;
     if (kFused && h0 >= 0)
         for (int b = tid; b < ICP_WAVES * ICP_WIN * (ICP_NMOM + 1); b += ICP_WG) (&sh_win[0][0][0])[b] = 0.0f;
@@ -807,8 +827,6 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
     float cnt = 0.0f;
     f4v macc = {0.0f, 0.0f, 0.0f, 0.0f};  // split precision: the wave's X^T X
     {
-        const Pose T = load_pose(st);
-        const Lvl Lv = load_level(L);
         // split precision: rows are centred on the level's live centroid moved
         // by the pose of this iteration (the centring point of the two-pass
         // variant, formed with the same FP64 expression, then rounded)
@@ -820,18 +838,6 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
             for (int i = 0; i < 3; ++i)
                 cc[i] = (float)(((T.r[3 * i] * e0 + T.r[3 * i + 1] * e1) + T.r[3 * i + 2] * e2) + T.t[i]);
         }
-        const int base = tile * L.tile_px;
-        const int end = min(base + L.tile_px, L.npx);
-        // Every lane of the block runs the same rounds (the queue and window
-        // steps work across the wave); a lane past the tile's end loads the
-        // round's first pixels and treats its own as invalid.
-        constexpr int kRound = ICP_WG * ICP_PASS1_PX;  // pixels per round
-        auto ld_index = [&](int r) {
-            const int i = r + ICP_PASS1_PX * tid;
-            return i < end ? i : r;
-        };
-        LiveIn<ICP_PASS1_PX> cur;
-        if (base < end) cur = load_live<ICP_PASS1_PX>(Lv, ld_index(base));
         for (int r = base; r < end; r += kRound) {
             const int i = r + ICP_PASS1_PX * tid;
             // the next round's live planes are in flight while this round runs
@@ -864,13 +870,11 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
         }
     }
     __syncthreads();
-    unsigned int* hist = P.st->hist;
-    for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) {
-        const uint32_t c = sh_hist[b];
-        if (c) atomicAdd(&hist[b], c);
-    }
+    // (Partials are stored and the histogram added through global pointers:
+    // a generic-pointer store or atomic also counts as an LDS access, so each
+    // later LDS wait would wait for it to reach memory.)
     if (kFused && h0 >= 0) {
-        float* part = L.part1 + (size_t)tile * ICP_WIN_SLOTS * ICP_PART_STRIDE;
+        ICP_GLOBAL float* part = gmut(L.part1) + (size_t)tile * ICP_WIN_SLOTS * ICP_PART_STRIDE;
         if (kSplit) mfma_moments(macc, sh_x[wave], acc, cnt);
         block_reduce_row(acc, cnt, sh_red, part);
         // slot b+1 holds the prefix sum over window bins 0..b (b < w), so the
@@ -904,6 +908,12 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
                 if (cj * kPer + q < win.w) part[(cj * kPer + q + 1) * ICP_PART_STRIDE + mj] = off + pre[q];
         }
     }
+    // the tile's histogram, last: nothing after it waits for the adds
+    ICP_GLOBAL unsigned int* hist = gmut(P.st->hist);
+    for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) {
+        const uint32_t c = sh_hist[b];
+        if (c) __hip_atomic_fetch_add(hist + b, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // ------------------------------------------------------------------ epilogues
@@ -916,41 +926,71 @@ __device__ __forceinline__ void level_reset(ProbState* st) {
 }
 
 // Regularised solve (Eq. (5)), pose update and per-level bookkeeping of one
-// problem; thread 0 only.
-__device__ void solve_epilogue(ProbState* st, const double* M, int64_t n, const IterCtl& ctl, const KParams& kp,
+// problem; thread 0 only.  Every state field it reads is loaded first and
+// every one it writes is stored last, through a global pointer: a load after
+// a store waits for the store, so interleaving them would cost a memory
+// round trip each.
+__device__ void solve_epilogue(ProbState* st_in, const double* M, int64_t n, const IterCtl& ctl, const KParams& kp,
                                const double* imu_R) {
-    if (st->level_done) return;
-    for (int k = 0; k < ICP_NMOM; ++k) st->M[k] = M[k];
-    st->n_last = n;
-    if (ctl.no_update) return;
+    ICP_GLOBAL ProbState* st = gmut(st_in);
+    const int32_t done = st->level_done;
+    double R[9], t[3];
+    for (int k = 0; k < 9; ++k) R[k] = st->R[k];
+    for (int k = 0; k < 3; ++k) t[k] = st->t[k];
+    const uint32_t N = st->N;
+    const int32_t k_med = st->k_med, last_kmed = st->last_kmed, settled = st->settled;
+    const int32_t iters_total = st->stats.iters_total, first_status = st->stats.status;
+    // (an empty statement that takes the loaded values: the loads are issued
+    // here, before the early returns, and waited for once)
+    __asm__ volatile("" ::"v"(R[0]), "v"(R[1]), "v"(R[2]), "v"(R[3]), "v"(R[4]), "v"(R[5]), "v"(R[6]), "v"(R[7]),
+                     "v"(R[8]), "v"(t[0]), "v"(t[1]), "v"(t[2]), "v"(N), "v"(k_med), "v"(last_kmed), "v"(settled),
+                     "v"(iters_total), "v"(first_status));
+    if (done) return;
+    if (ctl.no_update) {
+        for (int k = 0; k < ICP_NMOM; ++k) st->M[k] = M[k];
+        st->n_last = n;
+        return;
+    }
     double x[6];
-    const int status = solve_regularised(M, n, kp, st->R, imu_R, x);
-    if (status == ICP_LEVEL_OK) compose_exp(x, st->R, st->t);
-    for (int k = 0; k < 6; ++k) st->x[k] = x[k];
-    st->last_status = status;
-    icp_level_stats& S = st->stats.level[ctl.level];
-    S.iters_run = ctl.iter + 1;
-    S.status = status;
-    S.n_gated = st->N;
-    S.n_kept = n;
-    S.k_med = st->k_med;
-    S.rmse = n > 0 ? sqrt(M[ICP_NMOM - 1] / (double)n) : 0.0;
-    st->stats.iters_total += 1;
+    const int status = solve_regularised(M, n, kp, R, imu_R, x);
+    if (status == ICP_LEVEL_OK) compose_exp(x, R, t);
+    int32_t level_done = 0, new_settled = settled, new_last = last_kmed, total_status = first_status;
     if (status != ICP_LEVEL_OK) {
-        st->level_done = 1;
-        if (st->stats.status == ICP_LEVEL_OK) st->stats.status = status;
+        level_done = 1;
+        if (first_status == ICP_LEVEL_OK) total_status = status;
     } else if (kp.converge_window > 0) {
         // Sec. 3.4: a level has converged once its median bin stays put
-        st->settled = (st->k_med == st->last_kmed) ? st->settled + 1 : 1;
-        st->last_kmed = st->k_med;
-        if (st->settled >= kp.converge_window) st->level_done = 1;
+        new_settled = (k_med == last_kmed) ? settled + 1 : 1;
+        new_last = k_med;
+        if (new_settled >= kp.converge_window) level_done = 1;
     }
+    for (int k = 0; k < ICP_NMOM; ++k) st->M[k] = M[k];
+    st->n_last = n;
+    if (status == ICP_LEVEL_OK) {
+        for (int k = 0; k < 9; ++k) st->R[k] = R[k];
+        for (int k = 0; k < 3; ++k) st->t[k] = t[k];
+    }
+    for (int k = 0; k < 6; ++k) st->x[k] = x[k];
+    st->last_status = status;
+    ICP_GLOBAL icp_level_stats& S = st->stats.level[ctl.level];
+    S.iters_run = ctl.iter + 1;
+    S.status = status;
+    S.n_gated = N;
+    S.n_kept = n;
+    S.k_med = k_med;
+    S.rmse = n > 0 ? sqrt(M[ICP_NMOM - 1] / (double)n) : 0.0;
+    st->stats.iters_total = iters_total + 1;
+    st->stats.status = total_status;
+    st->settled = new_settled;
+    st->last_kmed = new_last;
+    if (level_done) st->level_done = 1;
 }
 
 // Deterministic FP64 sums over the tiles (in tile order) of slot 0 plus, if
 // slot2 > 0, slot `slot2` of every tile partial into sh_out[0..28]; whole
 // work-group.
-__device__ void sum_partials(const float* part, int n_tiles, int tile_stride, int slot2, double* sh_out) {
+__device__ void sum_partials(const float* part_in, int n_tiles, int tile_stride, int slot2, double* sh_out) {
+    const ICP_GLOBAL float* part = gconst(part_in);
     __shared__ double sh_sum[ICP_NMOM + 1][8];
     const int tid = threadIdx.x;
     const int j = tid >> 3, c = tid & 7;
@@ -969,7 +1009,7 @@ __device__ void sum_partials(const float* part, int n_tiles, int tile_stride, in
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int tt = min(t + u, t1 - 1);  // past the end: a valid tile, not added
-                const float* q = part + (size_t)tt * tile_stride + j;
+                const ICP_GLOBAL float* q = part + (size_t)tt * tile_stride + j;
                 a[u] = q[0];
                 b[u] = q[off2];
             }
@@ -993,19 +1033,30 @@ struct Band {
     int32_t k_med, k_lo, k_hi;
 };
 
-// Median bin k_med = min{k : C_k >= ceil(N/2)} of the CDF and the kept band
-// (Sec. 3.3), stored in the state and returned to every thread through LDS;
-// the histogram is cleared for the next iteration.  Whole work-group.
-__device__ Band median_band(ProbState* st, const KParams& kp, uint32_t* dbg_hist) {
+// The histogram entries 4 tid .. 4 tid + 3 a thread of the band kernel owns
+// (loaded together with the rest of the state the kernel starts from).
+__device__ __forceinline__ void load_hist4(const ProbState* st, uint32_t (&h)[4]) {
+    const ICP_GLOBAL uint32_t* hist = gconst(st->hist);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) h[k] = hist[4 * threadIdx.x + k];
+}
+
+// Cleared for the next iteration, through a global pointer so that no later
+// LDS wait waits for the stores.
+__device__ __forceinline__ void clear_hist4(ProbState* st) {
+    ICP_GLOBAL uint32_t* hist = gmut(st->hist);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hist[4 * threadIdx.x + k] = 0u;
+}
+
+// Median bin k_med = min{k : C_k >= ceil(N/2)} of the CDF of the histogram
+// h (each thread's four entries) and the kept band (Sec. 3.3), stored in the
+// state and returned to every thread through LDS.  Whole work-group.
+__device__ Band median_band(ProbState* st, const uint32_t (&h)[4], const KParams& kp, uint32_t* dbg_hist) {
     __shared__ uint32_t sh_wsum[ICP_WAVES];
     __shared__ int32_t sh_kmed;
     __shared__ Band sh_band;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint32_t h[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) h[k] = st->hist[4 * tid + k];  // all four loads before any store
-#pragma unroll
-    for (int k = 0; k < 4; ++k) st->hist[4 * tid + k] = 0u;
     if (dbg_hist)
         for (int k = 0; k < 4; ++k) dbg_hist[4 * tid + k] = h[k];
     const uint32_t own = (h[0] + h[1]) + (h[2] + h[3]);
@@ -1047,10 +1098,11 @@ __device__ Band median_band(ProbState* st, const KParams& kp, uint32_t* dbg_hist
                 hi = ICP_HIST_BINS - 1;
             }
         }
-        st->N = total;
-        st->k_med = km;
-        st->k_lo = lo;
-        st->k_hi = hi;
+        ICP_GLOBAL ProbState* gw = gmut(st);  // (a global store: the barrier below does not wait for it)
+        gw->N = total;
+        gw->k_med = km;
+        gw->k_lo = lo;
+        gw->k_hi = hi;
         sh_band = Band{total, km, lo, hi};
     }
     __syncthreads();
@@ -1059,11 +1111,12 @@ __device__ Band median_band(ProbState* st, const KParams& kp, uint32_t* dbg_hist
 
 // Centring point of the split-precision reduction: the level's live centroid
 // moved by the current pose.
-__device__ __forceinline__ void set_centre(ProbState* st, int level) {
-    for (int i = 0; i < 3; ++i)
-        st->cur_c[i] = ((st->R[3 * i] * st->cen[level][0] + st->R[3 * i + 1] * st->cen[level][1]) +
-                        st->R[3 * i + 2] * st->cen[level][2]) +
-                       st->t[i];
+__device__ __forceinline__ void set_centre(ProbState* st_in, int level) {
+    ICP_GLOBAL ProbState* st = gmut(st_in);
+    const double R[9] = {st->R[0], st->R[1], st->R[2], st->R[3], st->R[4], st->R[5], st->R[6], st->R[7], st->R[8]};
+    const double t[3] = {st->t[0], st->t[1], st->t[2]};
+    const double c[3] = {st->cen[level][0], st->cen[level][1], st->cen[level][2]};
+    for (int i = 0; i < 3; ++i) st->cur_c[i] = ((R[3 * i] * c[0] + R[3 * i + 1] * c[1]) + R[3 * i + 2] * c[2]) + t[i];
 }
 
 // Back from centred rows: with a = [ (p' - c) x n + c x n, n ] = J a~,
@@ -1111,8 +1164,15 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     const ProbDesc& P = probs[blockIdx.x];
     const LevelDesc& L = P.lv[ctl.level];
     ProbState* st = P.st;
-    const int done = st->level_done, pred = st->pred_hi, pred_hw = st->pred_hw;  // loads in flight together
-    if (done) {
+    // the state the kernel starts from, loaded together: one wait, not three
+    const ICP_GLOBAL ProbState* gst = gconst(st);
+    uint32_t h[4];
+    load_hist4(st, h);
+    const int done = gst->level_done, pred = gst->pred_hi, pred_hw = gst->pred_hw;
+    // (an empty statement that takes the loaded values, so that the compiler
+    // issues every load above before the early return and waits once)
+    __asm__ volatile("" ::"v"(h[0]), "v"(h[1]), "v"(h[2]), "v"(h[3]), "s"(pred), "s"(pred_hw));
+    if (done) {  // (pass 1 added nothing: the histogram is still clear)
         if (kp.fold_solve && ctl.last_of_level && threadIdx.x == 0) level_reset(st);
         return;
     }
@@ -1120,7 +1180,8 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     const int h0 = win.h0;
     // split precision: the centring point of this iteration (before any update)
     if (kp.reduce_mode == 1 && threadIdx.x == 0) set_centre(st, ctl.level);
-    const Band b = median_band(st, kp, dbg_hist);
+    const Band b = median_band(st, h, kp, dbg_hist);
+    clear_hist4(st);
     const bool hit = h0 >= 0 && b.N > 0 && b.k_lo == 0 && b.k_hi >= h0 - 1 && b.k_hi <= h0 + win.w - 1;
     if (hit) {
         sum_partials(L.part1, L.n_tiles, ICP_WIN_SLOTS * ICP_PART_STRIDE, b.k_hi - h0 + 1, sh_M);
@@ -1179,7 +1240,7 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(4))) voi
             });
         }
     }
-    block_reduce_row(acc, cnt, sh_red, L.part + (size_t)tile * ICP_PART_STRIDE);
+    block_reduce_row(acc, cnt, sh_red, gmut(L.part) + (size_t)tile * ICP_PART_STRIDE);
     if (!kp.fold_solve) return;
     // The solve folded into pass 2 (one problem): every thread's stores are
     // made visible device-wide before the barrier, thread 0 takes a ticket,
@@ -1295,7 +1356,7 @@ __global__ __launch_bounds__(ICP_WG) void k_pass2_mfma(const ProbDesc* __restric
             }
         cnt = lane == 0 ? (sh_d[wave][7][7] + sh_d[wave][7][15]) + (sh_d[wave][15][7] + sh_d[wave][15][15]) : 0.0f;
     }
-    block_reduce_row(mom, cnt, sh_red, L.part + (size_t)tile * ICP_PART_STRIDE);
+    block_reduce_row(mom, cnt, sh_red, gmut(L.part) + (size_t)tile * ICP_PART_STRIDE);
 }
 
 // One work-group per problem: FP64 sum of the pass-2 partials in tile order,
@@ -1305,7 +1366,9 @@ __global__ __launch_bounds__(ICP_WG) void k_solve(const ProbDesc* __restrict__ p
     const ProbDesc& P = probs[blockIdx.x];
     const LevelDesc& L = P.lv[ctl.level];
     ProbState* st = P.st;
-    if (!st->fused_done && !st->level_done) {
+    const ICP_GLOBAL ProbState* gst = gconst(st);
+    const int32_t fused_done = gst->fused_done, done = gst->level_done;  // loaded together
+    if (!fused_done && !done) {
         sum_partials(L.part, L.n_tiles, ICP_PART_STRIDE, 0, sh_M);
         if (threadIdx.x == 0) {
             if (kp.reduce_mode == 1) uncentre(sh_M, st->cur_c);
