@@ -111,6 +111,7 @@ struct Lvl {
     int W, H, npx, ps;
     float invW;
     double fx, fy, cx, cy, umax, vmax;
+    double rfx, rfy;  // RN(1/fx), RN(1/fy)
 };
 
 __device__ __forceinline__ Lvl load_level(const LevelDesc& L) {
@@ -132,7 +133,21 @@ __device__ __forceinline__ Lvl load_level(const LevelDesc& L) {
     v.cy = L.cy;
     v.umax = (double)(L.W - 1);
     v.vmax = (double)(L.H - 1);
+    v.rfx = uniform(1.0 / L.fx);
+    v.rfy = uniform(1.0 / L.fy);
     return v;
+}
+
+// The back-projection quotient (t - c)/f of the front end's tables, rounded
+// as the IEEE FP64 division rounds it, without a division: with y = RN(1/f)
+// and a = RN(t - c), q = RN(a y) is within an ulp of a/f, and one correction
+// RN(q + RN(a - f q) y) (the remainder exact by FMA) is the correctly rounded
+// quotient (Markstein's theorem for division by a correctly rounded
+// reciprocal).  Saves the pixel passes a dependent table load per pixel.
+__device__ __forceinline__ double bp_quot(int t, double c, double f, double y) {
+    const double a = (double)t - c;
+    const double q = a * y;
+    return __builtin_fma(__builtin_fma(-q, f, a), y, q);
 }
 
 // Association result of one pixel handed to the caller: the code, the bin
@@ -256,7 +271,7 @@ __device__ __forceinline__ void associate_px(const Lvl& L, int i, int lim, const
     for (int k = 0; k < NPX; ++k) {
         int u, v;
         pixel_uv(L, min(i + k, L.npx - 1), u, v);
-        live_vertex(lq.z[k], L.XQ[u], L.YQ[v], V[k]);
+        live_vertex(lq.z[k], bp_quot(u, L.cx, L.fx, L.rfx), bp_quot(v, L.cy, L.fy, L.rfy), V[k]);
         N[k][0] = lq.n[k][0];
         N[k][1] = lq.n[k][1];
         N[k][2] = lq.n[k][2];

@@ -749,6 +749,54 @@ int main(void) {
     assert n > 500000 and bad == 0
 
 
+def test_back_projection_quotients_without_division(tmp_path):
+    """The pixel passes form the back-projection quotient (t - c)/f of the
+    front end's tables (t a pixel column or row, c the level's principal
+    point, f its focal length) as RN(q + RN(a - f q) y), q = RN(a y),
+    y = RN(1/f), a = RN(t - c).  A plain C check that this equals the IEEE
+    quotient for every column and row of the benchmark geometries' levels and
+    for random focal lengths and principal points."""
+    import subprocess
+    src = tmp_path / "b.c"
+    src.write_text(r"""
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+static uint64_t s = 0xD1B54A32D192ED03ull;
+static uint64_t xr(void) { s ^= s << 13; s ^= s >> 7; s ^= s << 17; return s; }
+static double u01(void) { return (xr() >> 11) * 0x1.0p-53; }
+static long n = 0, bad = 0;
+static void run(double f, double c, int T) {
+    const double y = 1.0 / f;
+    for (int t = 0; t <= T; ++t) {
+        const double a = (double)t - c, q = a * y;
+        ++n; bad += fma(fma(-q, f, a), y, q) != a / f;
+    }
+}
+int main(void) {
+    const double fs[] = {525.0, 130.0, 570.3, 1000.0, 481.2};
+    const int Ws[] = {160, 320, 640, 848, 1280, 120, 240, 480, 720};
+    for (int fi = 0; fi < 5; ++fi)
+        for (int l = 0; l < 5; ++l)
+            for (int wi = 0; wi < 9; ++wi) {
+                const double p = (double)(1 << l);
+                run(fs[fi] / p, ((Ws[wi] - 1) * 0.5 + 0.5) / p - 0.5, (Ws[wi] >> l) + 1);
+            }
+    for (long k = 0; k < 40000; ++k) {
+        const double p = (double)(1 << (int)(xr() % 5));
+        const double c0 = 2000.0 * u01();
+        run((20.0 + 3000.0 * u01()) / p, (k & 1) ? c0 : (c0 + 0.5) / p - 0.5, (int)(1300 / p));
+    }
+    printf("%ld %ld\n", n, bad);
+    return 0;
+}
+""")
+    exe = tmp_path / "b"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-o", str(exe), str(src), "-lm"], check=True)
+    n, bad = (int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split())
+    assert n > 10000000 and bad == 0
+
+
 def test_reciprocal_division_over_the_tsdf_ranges(tmp_path):
     """The TSDF integration forms its quotients the same way: x/z and y/z
     share y = RN(1/z) (z from 2^-900 to 20 m, numerators up to 20 m in
