@@ -385,6 +385,10 @@ void bind_problem(ProbDesc& d, const icp_problem& q, int levels, int depth_filte
         L.fy = q.K.fy * s2;
         L.cx = (q.K.cx + 0.5) * s2 - 0.5;
         L.cy = (q.K.cy + 0.5) * s2 - 0.5;
+        L.rfx = 1.0 / L.fx;
+        L.rfy = 1.0 / L.fy;
+        L.umax = (double)(L.W - 1);
+        L.vmax = (double)(L.H - 1);
         L.Dw = rebase(L.Dw, base);
         L.D = (l > 0 || depth_filter) ? L.Dw : q.live_depth;
         L.LV = rebase(L.LV, base);

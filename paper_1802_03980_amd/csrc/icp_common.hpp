@@ -35,6 +35,8 @@ struct LevelDesc {
     int32_t n_tiles;            // ceil(npx / tile_px)
     int32_t tile_base;          // first flat tile of this problem at this level
     double fx, fy, cx, cy;      // intrinsics of the level
+    double rfx, rfy;            // 1/fx, 1/fy (IEEE FP64 divisions)
+    double umax, vmax;          // W - 1, H - 1
     const float* D;             // depth (level 0: caller input)
     float* Dw;                  // writable depth (levels >= 1), same as D there
     float* LV;                  // live vertex, 3 planes

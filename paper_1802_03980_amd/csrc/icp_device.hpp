@@ -131,10 +131,10 @@ __device__ __forceinline__ Lvl load_level(const LevelDesc& L) {
     v.fy = L.fy;
     v.cx = L.cx;
     v.cy = L.cy;
-    v.umax = (double)(L.W - 1);
-    v.vmax = (double)(L.H - 1);
-    v.rfx = uniform(1.0 / L.fx);
-    v.rfy = uniform(1.0 / L.fy);
+    v.umax = L.umax;
+    v.vmax = L.vmax;
+    v.rfx = L.rfx;
+    v.rfy = L.rfy;
     return v;
 }
 
@@ -160,21 +160,14 @@ struct PixelOut {
     float n[3];
 };
 
-// Projective association of live pixels i..i+3 (i a multiple of 4, paper
-// Sec. 3): move each live point by the current pose, project it into the
-// model image, round to the nearest pixel, fetch the model point and normal
-// there, then gate on validity, distance and normal agreement.
-//
-// Written as straight-line code: every quantity is computed for every pixel
-// (NaN inputs propagate and fail every comparison) and the code is selected
-// at the end in the order the checks are defined, so a wavefront runs one
-// path.  The live maps store an invalid pixel as NaN in all three components,
-// so one component decides their validity.  The live vertices arrive as one
-// 16-byte load per plane; the model gathers (12 contiguous bytes per map) of
-// the pixels are issued together.  The live vertex of each pixel is rebuilt
-// from the level's depth with the front end's arithmetic and its normal is
-// read from the stored normal planes: 16 bytes of live data per pixel instead
-// of 24.
+// The association (paper Sec. 3) is written as straight-line code: every
+// quantity is computed for every pixel (NaN inputs propagate and fail every
+// comparison) and the code is selected at the end in the order the checks
+// are defined, so a wavefront runs one path.  The live maps store an invalid
+// pixel as NaN in all three components, so one component decides their
+// validity.  The live vertex of each pixel is rebuilt from the level's depth
+// with the front end's arithmetic and its normal is read from the stored
+// normal planes: 16 bytes of live data per pixel instead of 24.
 typedef float vf4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bool depth_ok(float z) { return __builtin_isfinite(z) && z > 0.0f; }
@@ -237,109 +230,140 @@ __device__ __forceinline__ void pixel_uv(const Lvl& L, int i, int& u, int& v) {
     u = i - v * L.W;
 }
 
-// What a pixel's live vertex and normal come from: its depth (the vertex is
-// rebuilt from it with the front end's arithmetic) and its stored normal (the
-// normal needs two neighbours and a square root and three divisions: cheaper
-// to read than to rebuild every iteration).  A loop loads the next round's
-// before running this one.
+// What a pixel's live vertex comes from: its depth (the vertex is rebuilt
+// from it with the front end's arithmetic).  Its normal is read from the
+// stored normal planes with the model gather (the normal needs two
+// neighbours, a square root and three divisions: cheaper to read than to
+// rebuild every iteration).  A loop loads the depths rounds ahead.
 template <int NPX>
 struct LiveIn {
-    float z[NPX], n[NPX][3];
+    float z[NPX];
 };
 
 template <int NPX>
 __device__ __forceinline__ LiveIn<NPX> load_live(const Lvl& L, int i) {
     LiveIn<NPX> q;
 #pragma unroll
-    for (int k = 0; k < NPX; ++k) {
-        const int j = min(i + k, L.npx - 1);  // pixels past the end read the last one (and count as invalid)
-        q.z[k] = L.D[j];
-        q.n[k][0] = L.LN[j];
-        q.n[k][1] = L.LN[L.ps + j];
-        q.n[k][2] = L.LN[2 * L.ps + j];
-    }
+    for (int k = 0; k < NPX; ++k) q.z[k] = L.D[min(i + k, L.npx - 1)];  // past the end: the last pixel (invalid)
     return q;
 }
 
+// The association of a pixel in three phases, so that a loop can issue one
+// round's model gathers before it decides the previous round's pixels:
+// projection (live point moved by the pose, projected and rounded to a model
+// pixel), gather (the model point and normal there), decision (gates, bin and
+// the row's inputs).
+template <int NPX>
+struct Proj {
+    double P[NPX][3];  // p' = R p + t
+    int j[NPX];        // model pixel gathered (0 when nothing is looked up)
+    bool vok[NPX], front[NPX], inside[NPX];
+};
+
+template <int NPX>
+struct Gath {
+    float Q[NPX][3], M[NPX][3];  // model point and normal at the projection
+    float N[NPX][3];             // live normal (rotated at the decision)
+};
+
 // Pixels at or beyond `lim` count as invalid live pixels (their planes may
 // be any in-bounds data).
-template <int NPX, class Emit>
-__device__ __forceinline__ void associate_px(const Lvl& L, int i, int lim, const LiveIn<NPX>& lq, const Pose& T,
-                                             double d2max, double cos_max, Emit&& emit) {
-    float V[NPX][3], N[NPX][3];
+template <int NPX>
+__device__ __forceinline__ Proj<NPX> assoc_project(const Lvl& L, int i, int lim, const LiveIn<NPX>& lq,
+                                                   const Pose& T) {
+    Proj<NPX> a;
 #pragma unroll
     for (int k = 0; k < NPX; ++k) {
         int u, v;
         pixel_uv(L, min(i + k, L.npx - 1), u, v);
-        live_vertex(lq.z[k], bp_quot(u, L.cx, L.fx, L.rfx), bp_quot(v, L.cy, L.fy, L.rfy), V[k]);
-        N[k][0] = lq.n[k][0];
-        N[k][1] = lq.n[k][1];
-        N[k][2] = lq.n[k][2];
-    }
-    double P[NPX][3];
-    int j[NPX];
-    bool vok[NPX], front[NPX], inside[NPX];
-#pragma unroll
-    for (int k = 0; k < NPX; ++k) {
-        vok[k] = (i + k < lim) && fin(V[k][2]);
-        const double px = V[k][0], py = V[k][1], pz = V[k][2];
+        float V[3];
+        live_vertex(lq.z[k], bp_quot(u, L.cx, L.fx, L.rfx), bp_quot(v, L.cy, L.fy, L.rfy), V);
+        a.vok[k] = (i + k < lim) && fin(V[2]);
+        const double px = V[0], py = V[1], pz = V[2];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            P[k][c] = ((T.r[3 * c] * px + T.r[3 * c + 1] * py) + T.r[3 * c + 2] * pz) + T.t[c];
-        front[k] = P[k][2] > 0.0;
+            a.P[k][c] = ((T.r[3 * c] * px + T.r[3 * c + 1] * py) + T.r[3 * c + 2] * pz) + T.t[c];
+        a.front[k] = a.P[k][2] > 0.0;
         double uu, vv;
-        project_round(P[k][0], P[k][2], L.fx, L.cx, P[k][1], L.fy, L.cy, vok[k] && front[k], uu, vv);
-        inside[k] = uu >= 0.0 && uu <= L.umax && vv >= 0.0 && vv <= L.vmax;
-        const bool look = vok[k] && front[k] && inside[k];
-        j[k] = look ? (int)vv * L.W + (int)uu : 0;
+        project_round(a.P[k][0], a.P[k][2], L.fx, L.cx, a.P[k][1], L.fy, L.cy, a.vok[k] && a.front[k], uu, vv);
+        a.inside[k] = uu >= 0.0 && uu <= L.umax && vv >= 0.0 && vv <= L.vmax;
+        const bool look = a.vok[k] && a.front[k] && a.inside[k];
+        a.j[k] = look ? (int)vv * L.W + (int)uu : 0;
     }
-    float Q[NPX][3], M[NPX][3];
+    return a;
+}
+
+template <int NPX>
+__device__ __forceinline__ Gath<NPX> assoc_gather(const Lvl& L, int i, const Proj<NPX>& a) {
+    Gath<NPX> g;
 #pragma unroll
     for (int k = 0; k < NPX; ++k) {
+        const int li = min(i + k, L.npx - 1);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Q[k][c] = L.MV[3 * j[k] + c];
-            M[k][c] = L.MN[3 * j[k] + c];
+            g.Q[k][c] = L.MV[3 * a.j[k] + c];
+            g.M[k][c] = L.MN[3 * a.j[k] + c];
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g.N[k][c] = L.LN[c * L.ps + li];
     }
+    return g;
+}
+
+template <int NPX, class Emit>
+__device__ __forceinline__ void assoc_decide(const Proj<NPX>& a, const Gath<NPX>& g, const Pose& T, double d2max,
+                                             double cos_max, Emit&& emit) {
 #pragma unroll
     for (int k = 0; k < NPX; ++k) {
-        const bool nok = fin(N[k][2]);
+        const float(&Q)[3] = g.Q[k];
+        const float(&M)[3] = g.M[k];
+        const double(&P)[3] = a.P[k];
+        const bool nok = fin(g.N[k][2]);
         // the caller's level-0 model maps may be partly NaN: all six decide
-        const bool mok = fin(Q[k][0]) && fin(Q[k][1]) && fin(Q[k][2]) && fin(M[k][0]) && fin(M[k][1]) &&
-                         fin(M[k][2]);
-        const double d0 = (double)Q[k][0] - P[k][0];
-        const double d1 = (double)Q[k][1] - P[k][1];
-        const double d2 = (double)Q[k][2] - P[k][2];
+        const bool mok = fin(Q[0]) && fin(Q[1]) && fin(Q[2]) && fin(M[0]) && fin(M[1]) && fin(M[2]);
+        const double d0 = (double)Q[0] - P[0];
+        const double d1 = (double)Q[1] - P[1];
+        const double d2 = (double)Q[2] - P[2];
         const double dd = (d0 * d0 + d1 * d1) + d2 * d2;
         const bool near = dd < d2max;
-        const double nxd = N[k][0], nyd = N[k][1], nzd = N[k][2];
+        const double nxd = g.N[k][0], nyd = g.N[k][1], nzd = g.N[k][2];
         const double r0 = (T.r[0] * nxd + T.r[1] * nyd) + T.r[2] * nzd;
         const double r1 = (T.r[3] * nxd + T.r[4] * nyd) + T.r[5] * nzd;
         const double r2 = (T.r[6] * nxd + T.r[7] * nyd) + T.r[8] * nzd;
-        const double cv = (r0 * (double)M[k][0] + r1 * (double)M[k][1]) + r2 * (double)M[k][2];
+        const double cv = (r0 * (double)M[0] + r1 * (double)M[1]) + r2 * (double)M[2];
         const bool agree = cv >= cos_max;
         int code = kGated;
         code = agree ? code : kAngle;
         code = near ? code : kFar;
         code = mok ? code : kInvalidModel;
-        code = inside[k] ? code : kOutside;
-        code = front[k] ? code : kBehind;
-        code = (vok[k] && nok) ? code : kInvalidLive;
+        code = a.inside[k] ? code : kOutside;
+        code = a.front[k] ? code : kBehind;
+        code = (a.vok[k] && nok) ? code : kInvalidLive;
         PixelOut o;
         o.code = code;
         o.bin = code == kGated ? dist_bin(dd) : -1;
-        o.p[0] = (float)P[k][0];
-        o.p[1] = (float)P[k][1];
-        o.p[2] = (float)P[k][2];
+        o.p[0] = (float)P[0];
+        o.p[1] = (float)P[1];
+        o.p[2] = (float)P[2];
         o.d[0] = (float)d0;
         o.d[1] = (float)d1;
         o.d[2] = (float)d2;
-        o.n[0] = M[k][0];
-        o.n[1] = M[k][1];
-        o.n[2] = M[k][2];
+        o.n[0] = M[0];
+        o.n[1] = M[1];
+        o.n[2] = M[2];
         emit(k, o);
     }
+}
+
+// Projective association of live pixels i..i+NPX-1 (paper Sec. 3): move each
+// live point by the current pose, project it into the model image, round to
+// the nearest pixel, fetch the model point and normal there, then gate on
+// validity, distance and normal agreement.
+template <int NPX, class Emit>
+__device__ __forceinline__ void associate_px(const Lvl& L, int i, int lim, const LiveIn<NPX>& lq, const Pose& T,
+                                             double d2max, double cos_max, Emit&& emit) {
+    const Proj<NPX> a = assoc_project<NPX>(L, i, lim, lq, T);
+    assoc_decide<NPX>(a, assoc_gather<NPX>(L, i, a), T, d2max, cos_max, emit);
 }
 
 // Four pixels i..i+3 of one level, every pixel below npx valid.

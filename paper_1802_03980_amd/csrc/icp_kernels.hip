@@ -778,8 +778,11 @@ __device__ __forceinline__ void mfma_moments(const f4v& acc, _Float16 (*sx)[32],
     cnt = lane == 0 ? (sd[7 * 16 + 7] + sd[7 * 16 + 15]) + (sd[15 * 16 + 7] + sd[15 * 16 + 15]) : 0.0f;
 }
 
+#ifndef ICP_PASS1_WAVES
+#define ICP_PASS1_WAVES 5
+#endif
 template <bool kDebug, bool kFused, bool kSplit>
-__global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) void k_pass1(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
+__global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(ICP_PASS1_WAVES))) void k_pass1(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
                                                   IterCtl ctl, KParams kp, uint8_t* __restrict__ dbg_code,
                                                   int32_t* __restrict__ dbg_bin) {
     __shared__ uint32_t sh_hist[ICP_HIST_BINS];
@@ -838,13 +841,21 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
             for (int i = 0; i < 3; ++i)
                 cc[i] = (float)(((T.r[3 * i] * e0 + T.r[3 * i + 1] * e1) + T.r[3 * i + 2] * e2) + T.t[i]);
         }
+        // Software pipeline over the rounds: while a round's pixels are
+        // decided, the next round's model gathers and the live planes of the
+        // round after it are in flight.  Past the tile's end every lane's
+        // projection is invalid (a gather of model pixel 0) and the live loads
+        // repeat the last round's pixels (no branch: the waits stay exact).
+        auto next_r = [&](int r) { return r + kRound < end ? r + kRound : r; };
+        Proj<ICP_PASS1_PX> pa = assoc_project<ICP_PASS1_PX>(Lv, base + ICP_PASS1_PX * tid, end, cur, T);
+        Gath<ICP_PASS1_PX> ga = assoc_gather<ICP_PASS1_PX>(Lv, base + ICP_PASS1_PX * tid, pa);
+        LiveIn<ICP_PASS1_PX> nxt = load_live<ICP_PASS1_PX>(Lv, ld_index(next_r(base)));
         for (int r = base; r < end; r += kRound) {
             const int i = r + ICP_PASS1_PX * tid;
-            // the next round's live planes are in flight while this round runs
-            // (the last round reloads its own pixels: no branch, so the wait
-            // for this round's data does not also wait for the next round's)
-            const LiveIn<ICP_PASS1_PX> nxt = load_live<ICP_PASS1_PX>(Lv, ld_index(r + kRound < end ? r + kRound : r));
-            associate_px<ICP_PASS1_PX>(Lv, i, end, cur, T, kp.d2max, kp.cos_max, [&](int k, const PixelOut& q) {
+            const LiveIn<ICP_PASS1_PX> nn = load_live<ICP_PASS1_PX>(Lv, ld_index(next_r(next_r(r))));
+            const Proj<ICP_PASS1_PX> pb = assoc_project<ICP_PASS1_PX>(Lv, r + kRound + ICP_PASS1_PX * tid, end, nxt, T);
+            const Gath<ICP_PASS1_PX> gb = assoc_gather<ICP_PASS1_PX>(Lv, r + kRound + ICP_PASS1_PX * tid, pb);
+            assoc_decide<ICP_PASS1_PX>(pa, ga, T, kp.d2max, kp.cos_max, [&](int k, const PixelOut& q) {
                 if (kDebug && i + k < end) {
                     if (dbg_code) dbg_code[i + k] = (uint8_t)q.code;
                     if (dbg_bin) dbg_bin[i + k] = q.bin;
@@ -866,7 +877,9 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(5))) voi
                     }
                 }
             });
-            cur = nxt;
+            pa = pb;
+            ga = gb;
+            nxt = nn;
         }
     }
     __syncthreads();
