@@ -138,16 +138,21 @@ __device__ __forceinline__ Lvl load_level(const LevelDesc& L) {
     return v;
 }
 
-// The back-projection quotient (t - c)/f of the front end's tables, rounded
-// as the IEEE FP64 division rounds it, without a division: with y = RN(1/f)
-// and a = RN(t - c), q = RN(a y) is within an ulp of a/f, and one correction
-// RN(q + RN(a - f q) y) (the remainder exact by FMA) is the correctly rounded
-// quotient (Markstein's theorem for division by a correctly rounded
-// reciprocal).  Saves the pixel passes a dependent table load per pixel.
-__device__ __forceinline__ double bp_quot(int t, double c, double f, double y) {
-    const double a = (double)t - c;
+// a/b rounded as the IEEE FP64 division rounds it, given y = RN(1/b): q =
+// RN(a y) is within an ulp of a/b, and one correction RN(q + RN(a - b q) y)
+// (the remainder exact by FMA) is the correctly rounded quotient (Markstein's
+// theorem for division by a correctly rounded reciprocal; no operand here
+// comes near the underflow or overflow range).
+__device__ __forceinline__ double div_rn(double a, double b, double y) {
     const double q = a * y;
-    return __builtin_fma(__builtin_fma(-q, f, a), y, q);
+    return __builtin_fma(__builtin_fma(-q, b, a), y, q);
+}
+
+// The back-projection quotient (t - c)/f of the front end's tables, without
+// a division (y = RN(1/f) from the descriptor): saves the pixel passes a
+// dependent table load per pixel.
+__device__ __forceinline__ double bp_quot(int t, double c, double f, double y) {
+    return div_rn((double)t - c, f, y);
 }
 
 // Association result of one pixel handed to the caller: the code, the bin
@@ -208,7 +213,8 @@ __device__ __forceinline__ void live_from_depth(float z, float zr, float zb, boo
         const double len2 = (c0 * c0 + c1 * c1) + c2 * c2;
         if (len2 > 0.0 && __builtin_isfinite(len2)) {
             const double len = sqrt(len2);
-            double m0 = c0 / len, m1 = c1 / len, m2 = c2 / len;
+            const double y = 1.0 / len;  // one division, then c / len for each component
+            double m0 = div_rn(c0, len, y), m1 = div_rn(c1, len, y), m2 = div_rn(c2, len, y);
             const double side = (m0 * (double)p[0] + m1 * (double)p[1]) + m2 * (double)p[2];
             if (side > 0.0) {
                 m0 = -m0;

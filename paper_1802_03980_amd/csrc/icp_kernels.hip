@@ -435,8 +435,8 @@ __device__ __forceinline__ void model_px(const float (&cv)[4][3], const float (&
     }
     const double len2 = (s[0] * s[0] + s[1] * s[1]) + s[2] * s[2];
     if (len2 > 0.0) {
-        const double len = sqrt(len2);
-        for (int k = 0; k < 3; ++k) no[k] = (float)(s[k] / len);
+        const double len = sqrt(len2), y = 1.0 / len;  // one division, then s / len per component
+        for (int k = 0; k < 3; ++k) no[k] = (float)div_rn(s[k], len, y);
     } else {
         vo[0] = vo[1] = vo[2] = qnan;
     }

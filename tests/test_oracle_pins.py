@@ -797,6 +797,47 @@ int main(void) {
     assert n > 10000000 and bad == 0
 
 
+def test_normalisation_by_one_division(tmp_path):
+    """The live normals and the model pyramid's normals divide each component
+    c_k of a vector by its length len = sqrt((c0 c0 + c1 c1) + c2 c2) as
+    RN(q + RN(c_k - len q) y), q = RN(c_k y), with the one division
+    y = RN(1/len).  A plain C check that this equals the IEEE quotient for
+    vectors over 80 binades, with components down to 1e-6 of the others and
+    exact zeros."""
+    import subprocess
+    src = tmp_path / "n.c"
+    src.write_text(r"""
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+static uint64_t s = 0x853c49e6748fea9bull;
+static uint64_t xr(void) { s ^= s << 13; s ^= s >> 7; s ^= s << 17; return s; }
+static double u01(void) { return (xr() >> 11) * 0x1.0p-53; }
+int main(void) {
+    long n = 0, bad = 0;
+    for (long t = 0; t < 4000000; ++t) {
+        const double sc = ldexp(1.0, (int)(xr() % 80) - 60);
+        double c[3];
+        for (int k = 0; k < 3; ++k) c[k] = (2.0 * u01() - 1.0) * sc * ((xr() & 7) == 0 ? 1e-6 : 1.0);
+        if (t & 1) c[xr() % 3] = 0.0;
+        const double len2 = (c[0] * c[0] + c[1] * c[1]) + c[2] * c[2];
+        if (!(len2 > 0.0) || !isfinite(len2)) continue;
+        const double len = sqrt(len2), y = 1.0 / len;
+        for (int k = 0; k < 3; ++k) {
+            const double q = c[k] * y;
+            ++n; bad += fma(fma(-q, len, c[k]), y, q) != c[k] / len;
+        }
+    }
+    printf("%ld %ld\n", n, bad);
+    return 0;
+}
+""")
+    exe = tmp_path / "n"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-o", str(exe), str(src), "-lm"], check=True)
+    n, bad = (int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split())
+    assert n > 10000000 and bad == 0
+
+
 def test_reciprocal_division_over_the_tsdf_ranges(tmp_path):
     """The TSDF integration forms its quotients the same way: x/z and y/z
     share y = RN(1/z) (z from 2^-900 to 20 m, numerators up to 20 m in
