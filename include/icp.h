@@ -120,7 +120,10 @@ typedef struct {
                                        otherwise; needs band_beta >= 1 or no median filter);
                                        1: always two passes */
     int32_t tile_px[ICP_MAX_LEVELS];/* pixels per work-group tile per level (multiple of 1024,
-                                       at most 65536); 0 = chosen by the library */
+                                       at most 65536); 0 = chosen by the library (about 8192
+                                       tiles over the batch, 1024..16384 pixels, and at least
+                                       4096 at a level whose batch still gives every pass-1
+                                       work-group slot of the GPU such a tile) */
     /* live front end (Sec. 3.3: normals by an integral-image method on smoothed depth) */
     int32_t depth_filter;           /* 1: bilateral smoothing of the level-0 depth before the pyramid:
                                        weights exp(-(du^2+dv^2)/(2 s^2)) (s = filter_sigma_px) times

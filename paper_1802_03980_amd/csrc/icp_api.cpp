@@ -149,12 +149,25 @@ int check_problem(icp_ctx* ctx, const icp_problem& q, int levels, int use_imu_se
 }
 
 // Tile size: aim for ~8192 work-groups per pass over the batch (32 per CU).
-int pick_tile(int npx, int nprob, int req) {
+// Pass-1 work-groups the GPU holds at once: five 256-thread work-groups per
+// compute unit (96 VGPRs, 28 KB of LDS each) on 256 compute units.
+constexpr int64_t kPass1Slots = 1280;
+
+// Tile of a level: about 8192 tiles over the batch (at least one 1024-pixel
+// quantum, at most 16384 pixels).  A work-group spends about four rounds'
+// time starting up (first loads, the pipeline's first gathers, LDS clears)
+// and finishing (tile sums, window scan, histogram merge), so a level whose
+// tiles would run fewer than 16 rounds takes 4096-pixel tiles instead while
+// that still gives every work-group slot a tile (the coarse levels of large
+// batches).  `level_px` is the batch's pixel count at the level.
+int pick_tile(int npx, int nprob, int req, int64_t level_px) {
     if (req > 0) return req;
     const long target = std::max(1L, 8192L / std::max(1, nprob));
     long t = (npx + target - 1) / target;
     t = (t + ICP_TILE_QUANTUM - 1) / ICP_TILE_QUANTUM * ICP_TILE_QUANTUM;
-    return (int)std::min(16384L, std::max((long)ICP_TILE_QUANTUM, t));
+    t = std::min(16384L, std::max((long)ICP_TILE_QUANTUM, t));
+    if (t < 4096 && level_px / 4096 >= kPass1Slots) t = 4096;
+    return (int)t;
 }
 
 // Workspace layout of a batch; offsets are relative to the workspace base.
@@ -173,15 +186,15 @@ struct Plan {
 // the buffers' offsets come from take(bytes), its tiles are appended to the
 // flat tile ranges tiles[l], and the largest launch sizes are kept.
 template <class Take>
-void lay_out_problem(ProbDesc& d, int32_t W, int32_t H, int levels, const int32_t* tile_req, int nprob, int* tiles,
-                     int* max_vn, int* max_mp, int* max_q, Take&& take) {
+void lay_out_problem(ProbDesc& d, int32_t W, int32_t H, int levels, const int32_t* tile_req, int nprob,
+                     const int64_t* level_px, int* tiles, int* max_vn, int* max_mp, int* max_q, Take&& take) {
     for (int l = 0; l < levels; ++l) {
         LevelDesc& L = d.lv[l];
         L.W = W >> l;
         L.H = H >> l;
         L.npx = L.W * L.H;
         L.ps = (L.npx + ICP_PLANE_ALIGN - 1) / ICP_PLANE_ALIGN * ICP_PLANE_ALIGN;
-        L.tile_px = pick_tile(L.npx, nprob, tile_req ? tile_req[l] : 0);
+        L.tile_px = pick_tile(L.npx, nprob, tile_req ? tile_req[l] : 0, level_px[l]);
         L.n_tiles = (L.npx + L.tile_px - 1) / L.tile_px;
         L.tile_base = tiles[l];
         tiles[l] += L.n_tiles;
@@ -222,10 +235,13 @@ void make_plan(int n, const int32_t* W, const int32_t* H, int levels, const int3
         P.max_q[l] = 0;
         P.owner[l].clear();
     }
+    int64_t level_px[ICP_MAX_LEVELS] = {};
+    for (int p = 0; p < n; ++p)
+        for (int l = 0; l < levels; ++l) level_px[l] += (int64_t)(W[p] >> l) * (H[p] >> l);
     for (int p = 0; p < n; ++p) {
         ProbDesc& d = P.desc[p];
         d.st = reinterpret_cast<ProbState*>(P.off_state + sizeof(ProbState) * p);
-        lay_out_problem(d, W[p], H[p], levels, tile_req, n, P.tiles, P.max_vn, P.max_mp, P.max_q, take);
+        lay_out_problem(d, W[p], H[p], levels, tile_req, n, level_px, P.tiles, P.max_vn, P.max_mp, P.max_q, take);
         for (int l = 0; l < levels; ++l)
             for (int t = 0; t < d.lv[l].n_tiles; ++t) P.owner[l].push_back(p);
     }
@@ -1088,7 +1104,9 @@ int icp_register_noalloc(const float* live_depth, int W, int H, const float* mod
     const size_t off_flags = take(sizeof(int32_t));
     int tiles[ICP_MAX_LEVELS] = {}, max_vn[ICP_MAX_LEVELS] = {}, max_mp[ICP_MAX_LEVELS] = {},
         max_q[ICP_MAX_LEVELS] = {};
-    lay_out_problem(d, W, H, levels, params->tile_px, 1, tiles, max_vn, max_mp, max_q, take);
+    int64_t level_px[ICP_MAX_LEVELS] = {};
+    for (int l = 0; l < levels; ++l) level_px[l] = (int64_t)(W >> l) * (H >> l);
+    lay_out_problem(d, W, H, levels, params->tile_px, 1, level_px, tiles, max_vn, max_mp, max_q, take);
     int max_tiles = 1;
     for (int l = 0; l < levels; ++l) max_tiles = std::max(max_tiles, tiles[l]);
     const size_t off_owner = take(sizeof(int32_t) * max_tiles);  // every tile belongs to problem 0
