@@ -286,8 +286,9 @@ def main():
         sp_s = time.perf_counter() - ts
         split = {"registrations_per_s": round(n * sp_steps / sp_s, 2), "steps": sp_steps,
                  "ms_per_step": round(sp_s / sp_steps * 1e3, 3),
-                 "note": "moment reduction as FP16 hi+lo split MFMA with FP32 accumulation on centred rows; "
-                         "solve and pose update in FP64; two passes per iteration"}
+                 "note": "moment reduction as FP16 hi+lo split MFMA with FP32 accumulation on centred rows "
+                         "(single pass with the band-edge window; the MFMA second pass where it misses); "
+                         "solve and pose update in FP64; synchronous calls, as synchronous_call_registrations_per_s"}
         log(f"split precision: {split['registrations_per_s']} registrations/s")
 
     # ------------------------------------------------------------- plain path
@@ -312,7 +313,8 @@ def main():
     avg_ms = d["total_ms"] / d["launches"]
     bytes_per_launch = BYTES_PER_PX_IT * d["pixels"] / d["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    tr = read_traffic(dom)
+    # (the committed counters were taken on the raw front end's data)
+    tr = read_traffic(dom) if args.front_end == "kinfu" else None
     traffic = None if tr is None else tr * d["pixels"] / d["launches"]
     roofline = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
