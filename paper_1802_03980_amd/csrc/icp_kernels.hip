@@ -624,6 +624,31 @@ __device__ __forceinline__ int next_half_width(int k_hi, int pred_hi, int iter) 
     return hw < 6 ? 6 : (hw > ICP_WIN / 2 ? ICP_WIN / 2 : hw);
 }
 
+// Rows of the histogram whose CDF is `cdf` that a window of half-width hw
+// around k_hi (placed as band_window places it) would hold.
+__device__ __forceinline__ uint32_t window_rows(const uint32_t* cdf, int k_hi, int hw) {
+    int h0 = k_hi - hw;
+    const int hmax = ICP_HIST_BINS - 2 * hw;
+    h0 = h0 < 0 ? 0 : (h0 > hmax ? hmax : h0);
+    return cdf[h0 + 2 * hw - 1] - (h0 > 0 ? cdf[h0 - 1] : 0u);
+}
+
+// Rows inside the window take the slow per-bin path (staged through LDS, one
+// moment per lane), at several times the cost of a pixel's whole pass; a
+// missed window costs one more pass over the problem's pixels.  So where the
+// pairs are dense around the edge (smoothed depth: most pixels are gated in)
+// the window is narrowed, down to six bins either side, until this
+// iteration's histogram puts at most 1/ICP_WIN_ROW_CAP of the level's pixels
+// in it.
+#ifndef ICP_WIN_ROW_CAP
+#define ICP_WIN_ROW_CAP 40
+#endif
+__device__ __forceinline__ int capped_half_width(const uint32_t* cdf, int k_hi, int hw, int npx) {
+    const uint32_t cap = (uint32_t)(npx / ICP_WIN_ROW_CAP);
+    while (hw > 6 && window_rows(cdf, k_hi, hw) > cap) --hw;
+    return hw;
+}
+
 // Sum the 28 accumulators and the count over the work-group into `out`
 // (29 floats); every thread calls it.
 __device__ __forceinline__ void block_reduce_row(float (&acc)[ICP_NMOM], float cnt, float (*sh_red)[ICP_PART_STRIDE],
@@ -1064,8 +1089,10 @@ __device__ __forceinline__ void clear_hist4(ProbState* st) {
 
 // Median bin k_med = min{k : C_k >= ceil(N/2)} of the CDF of the histogram
 // h (each thread's four entries) and the kept band (Sec. 3.3), stored in the
-// state and returned to every thread through LDS.  Whole work-group.
-__device__ Band median_band(ProbState* st, const uint32_t (&h)[4], const KParams& kp, uint32_t* dbg_hist) {
+// state and returned to every thread through LDS; the CDF is left in sh_cdf
+// (ICP_HIST_BINS entries; set when N > 0).  Whole work-group.
+__device__ Band median_band(ProbState* st, const uint32_t (&h)[4], const KParams& kp, uint32_t* dbg_hist,
+                            uint32_t* sh_cdf) {
     __shared__ uint32_t sh_wsum[ICP_WAVES];
     __shared__ int32_t sh_kmed;
     __shared__ Band sh_band;
@@ -1094,6 +1121,7 @@ __device__ Band median_band(ProbState* st, const uint32_t (&h)[4], const KParams
         for (int k = 0; k < 4; ++k) {
             const uint32_t prev = c;
             c += h[k];
+            sh_cdf[4 * tid + k] = c;
             if (prev < target && c >= target) sh_kmed = 4 * tid + k;
         }
     }
@@ -1193,7 +1221,8 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     const int h0 = win.h0;
     // split precision: the centring point of this iteration (before any update)
     if (kp.reduce_mode == 1 && threadIdx.x == 0) set_centre(st, ctl.level);
-    const Band b = median_band(st, h, kp, dbg_hist);
+    __shared__ uint32_t sh_cdf[ICP_HIST_BINS];
+    const Band b = median_band(st, h, kp, dbg_hist, sh_cdf);
     clear_hist4(st);
     const bool hit = h0 >= 0 && b.N > 0 && b.k_lo == 0 && b.k_hi >= h0 - 1 && b.k_hi <= h0 + win.w - 1;
     if (hit) {
@@ -1207,7 +1236,7 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
         st->fused_done = hit ? 1 : 0;
         if (!hit && kp.need2) atomicExch(kp.need2, 1);  // pass 2 has work this iteration
         if (b.N > 0) {
-            st->pred_hw = next_half_width(b.k_hi, pred, ctl.iter);
+            st->pred_hw = capped_half_width(sh_cdf, b.k_hi, next_half_width(b.k_hi, pred, ctl.iter), L.npx);
             st->pred_hi = b.k_hi;
         }
         // with the solve folded into pass 2, an iteration finished here also
