@@ -1024,17 +1024,50 @@ __device__ void solve_epilogue(ProbState* st_in, const double* M, int64_t n, con
     if (level_done) st->level_done = 1;
 }
 
+// The tile partials a thread of the band kernel adds: thread (j, c) takes
+// entry j (j <= ICP_NMOM) of tiles t0 .. t1 - 1, the c-th of eight equal runs.
+struct TileRun {
+    int j, t0, t1;
+    bool on;
+};
+
+__device__ __forceinline__ TileRun tile_run(int n_tiles) {
+    const int tid = threadIdx.x;
+    TileRun r;
+    r.j = tid >> 3;
+    const int c = tid & 7;
+    const int per = (n_tiles + 7) / 8;
+    r.t0 = c * per;
+    r.t1 = min(r.t0 + per, n_tiles);
+    r.on = r.j <= ICP_NMOM;
+    return r;
+}
+
+// Slot 0 of the first sixteen tiles of the thread's run (loaded before the
+// band is known: it does not depend on it).
+constexpr int kSumBatch = 16;
+__device__ __forceinline__ void load_slot0(const float* part_in, int tile_stride, const TileRun& r,
+                                           float (&a)[kSumBatch]) {
+    const ICP_GLOBAL float* part = gconst(part_in);
+    const int j = min(r.j, ICP_NMOM);  // (threads past the entries load one and do not add it: no branch)
+#pragma unroll
+    for (int u = 0; u < kSumBatch; ++u) {
+        const int tt = max(0, min(r.t0 + u, r.t1 - 1));  // past the end: a valid tile, not added
+        a[u] = part[(size_t)tt * tile_stride + j];
+    }
+}
+
 // Deterministic FP64 sums over the tiles (in tile order) of slot 0 plus, if
 // slot2 > 0, slot `slot2` of every tile partial into sh_out[0..28]; whole
-// work-group.
-__device__ void sum_partials(const float* part_in, int n_tiles, int tile_stride, int slot2, double* sh_out) {
+// work-group.  a0 holds slot 0 of the first sixteen tiles of each thread's
+// run (load_slot0).
+__device__ void sum_partials(const float* part_in, int n_tiles, int tile_stride, int slot2, const float (&a0)[kSumBatch],
+                             double* sh_out) {
     const ICP_GLOBAL float* part = gconst(part_in);
     __shared__ double sh_sum[ICP_NMOM + 1][8];
     const int tid = threadIdx.x;
-    const int j = tid >> 3, c = tid & 7;
-    if (j <= ICP_NMOM) {
-        const int per = (n_tiles + 7) / 8;
-        const int t0 = c * per, t1 = min(t0 + per, n_tiles);
+    const TileRun r = tile_run(n_tiles);
+    if (r.on) {
         // Sixteen tiles' loads are issued before their adds (the adds stay in
         // tile order): one memory latency per sixteen tiles, not per tile.  The
         // second slot is always loaded (slot 0 again when unused) and selected,
@@ -1042,20 +1075,31 @@ __device__ void sum_partials(const float* part_in, int n_tiles, int tile_stride,
         const bool two = slot2 > 0;
         const size_t off2 = two ? (size_t)slot2 * ICP_PART_STRIDE : 0;
         double s = 0.0;
-        for (int t = t0; t < t1; t += 16) {
-            float a[16], b[16];
+        {  // the first sixteen tiles: slot 0 is already in a0
+            float b[kSumBatch];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int tt = min(t + u, t1 - 1);  // past the end: a valid tile, not added
-                const ICP_GLOBAL float* q = part + (size_t)tt * tile_stride + j;
+            for (int u = 0; u < kSumBatch; ++u) {
+                const int tt = max(0, min(r.t0 + u, r.t1 - 1));
+                b[u] = part[(size_t)tt * tile_stride + r.j + off2];
+            }
+#pragma unroll
+            for (int u = 0; u < kSumBatch; ++u)
+                if (r.t0 + u < r.t1) s += two ? (double)a0[u] + (double)b[u] : (double)a0[u];
+        }
+        for (int t = r.t0 + kSumBatch; t < r.t1; t += kSumBatch) {
+            float a[kSumBatch], b[kSumBatch];
+#pragma unroll
+            for (int u = 0; u < kSumBatch; ++u) {
+                const int tt = min(t + u, r.t1 - 1);  // past the end: a valid tile, not added
+                const ICP_GLOBAL float* q = part + (size_t)tt * tile_stride + r.j;
                 a[u] = q[0];
                 b[u] = q[off2];
             }
 #pragma unroll
-            for (int u = 0; u < 16; ++u)
-                if (t + u < t1) s += two ? (double)a[u] + (double)b[u] : (double)a[u];
+            for (int u = 0; u < kSumBatch; ++u)
+                if (t + u < r.t1) s += two ? (double)a[u] + (double)b[u] : (double)a[u];
         }
-        sh_sum[j][c] = s;
+        sh_sum[r.j][tid & 7] = s;
     }
     __syncthreads();
     if (tid <= ICP_NMOM) {
@@ -1064,6 +1108,13 @@ __device__ void sum_partials(const float* part_in, int n_tiles, int tile_stride,
         sh_out[tid] = s;
     }
     __syncthreads();
+}
+
+__device__ __forceinline__ void sum_partials(const float* part, int n_tiles, int tile_stride, int slot2,
+                                             double* sh_out) {
+    float a0[kSumBatch];
+    load_slot0(part, tile_stride, tile_run(n_tiles), a0);
+    sum_partials(part, n_tiles, tile_stride, slot2, a0, sh_out);
 }
 
 struct Band {
@@ -1217,6 +1268,10 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
         if (kp.fold_solve && ctl.last_of_level && threadIdx.x == 0) level_reset(st);
         return;
     }
+    // slot 0 of the tile partials does not depend on the band: its loads are
+    // in flight while the band is found
+    float a0[kSumBatch];
+    if (fused) load_slot0(L.part1, ICP_WIN_SLOTS * ICP_PART_STRIDE, tile_run(L.n_tiles), a0);
     const Win win = fused ? band_window(pred, pred_hw, ctl.iter) : Win{-1, 0};
     const int h0 = win.h0;
     // split precision: the centring point of this iteration (before any update)
@@ -1226,7 +1281,7 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     clear_hist4(st);
     const bool hit = h0 >= 0 && b.N > 0 && b.k_lo == 0 && b.k_hi >= h0 - 1 && b.k_hi <= h0 + win.w - 1;
     if (hit) {
-        sum_partials(L.part1, L.n_tiles, ICP_WIN_SLOTS * ICP_PART_STRIDE, b.k_hi - h0 + 1, sh_M);
+        sum_partials(L.part1, L.n_tiles, ICP_WIN_SLOTS * ICP_PART_STRIDE, b.k_hi - h0 + 1, a0, sh_M);
         if (threadIdx.x == 0) {
             if (kp.reduce_mode == 1) uncentre(sh_M, st->cur_c);
             solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
