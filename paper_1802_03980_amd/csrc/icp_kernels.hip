@@ -443,87 +443,79 @@ __device__ __forceinline__ void model_px(const float (&cv)[4][3], const float (&
 }
 
 // Model level l from l - 1 and, with also_next, level l + 1 in the same
-// launch: one thread per 2 x 2 block of level-l pixels.  For each of the
-// block's rows it reads the two child rows below it as 12 consecutive floats
-// per map (three 16-byte loads when the maps are 16-byte aligned; any caller
-// buffer at level 0 is accepted: an unaligned one takes the scalar loads),
-// writes the level-l pixels and keeps them, and forms the level-(l+1) pixel
-// from the four it kept, so level l is never read back.  A block is partial
-// only at the right or bottom edge of an odd-sized level, and then it has no
-// level-(l+1) pixel (each level halves the size, rounding down).
+// launch: one thread per level-l pixel, the four lanes of a quad holding the
+// pixels of one 2 x 2 block.  Each thread reads its four children (two rows of
+// six consecutive floats per map), writes its level-l pixel and keeps it; the
+// quad's first lane gathers the block's four pixels from its neighbours (DPP
+// broadcasts within the quad) and forms the level-(l+1) pixel, so level l is
+// never read back.  A block is partial only at the right or bottom edge of an
+// odd-sized level, and then it has no level-(l+1) pixel (each level halves
+// the size, rounding down).
+template <int K>
+__device__ __forceinline__ float quad_bcast(float x) {
+    // quad_perm(K, K, K, K): every lane of a quad takes lane K's value
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x55 * K, 0xF, 0xF, false));
+}
+
 __global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restrict__ probs, int level,
                                                        int also_next) {
     const ProbDesc& P = probs[blockIdx.y];
     const LevelDesc& F = P.lv[level - 1];
     const LevelDesc& C = P.lv[level];
-    const int qw = (C.W + 1) >> 1;  // blocks per row
+    const int qw = (C.W + 1) >> 1, qh = (C.H + 1) >> 1;  // blocks per row, block rows
     const int t = blockIdx.x * ICP_WG + threadIdx.x;
-    if (t >= qw * ((C.H + 1) >> 1)) return;
-    const int vb = t / qw, u = 2 * (t % qw);
-    const bool two = u + 1 < C.W;
-    const int rows = 2 * vb + 1 < C.H ? 2 : 1;
+    const int blk = t >> 2, q = t & 3;
+    if (blk >= qw * qh) return;  // (whole quads)
+    const int bv = blk / qw, bu = blk - bv * qw;
+    const int u = 2 * bu + (q & 1), v = 2 * bv + (q >> 1);
+    const bool inside = u < C.W && v < C.H;
     const ICP_GLOBAL float* MV = gconst(F.MV);
     const ICP_GLOBAL float* MN = gconst(F.MN);
-    // 16-byte row loads need every row start aligned too: row r starts 3 r W
-    // floats in, a multiple of four for any r only when W is
-    const bool vec = two && (F.W & 3) == 0 &&
-                     ((reinterpret_cast<uintptr_t>(F.MV) | reinterpret_cast<uintptr_t>(F.MN)) & 15) == 0;
-    ICP_GLOBAL float* MVo = gmut(C.MVw);
-    ICP_GLOBAL float* MNo = gmut(C.MNw);
-    float kv[4][3], kn[4][3];  // the block's level-l values, row-major
-    for (int b = 0; b < rows; ++b) {
-        const int v = 2 * vb + b;
-        float rv[2][12], rn[2][12];  // [child row][4 children x 3 components]
-        for (int r = 0; r < 2; ++r) {
-            const int base = 3 * ((2 * v + r) * F.W + 2 * u);
-            if (vec) {
-                for (int q = 0; q < 3; ++q) {
-                    const vf4 a = *(const ICP_GLOBAL vf4*)(MV + base + 4 * q);
-                    const vf4 c = *(const ICP_GLOBAL vf4*)(MN + base + 4 * q);
-                    for (int k = 0; k < 4; ++k) {
-                        rv[r][4 * q + k] = a[k];
-                        rn[r][4 * q + k] = c[k];
-                    }
-                }
-            } else {
-                const int cnt = two ? 12 : 6;
-                for (int k = 0; k < 12; ++k) {
-                    rv[r][k] = k < cnt ? MV[base + k] : 0.0f;
-                    rn[r][k] = k < cnt ? MN[base + k] : 0.0f;
-                }
-            }
-        }
-        for (int o = 0; o < (two ? 2 : 1); ++o) {
-            float cv[4][3], cn[4][3];
-            for (int k = 0; k < 3; ++k) {
-                cv[0][k] = rv[0][6 * o + k];
-                cv[1][k] = rv[0][6 * o + 3 + k];
-                cv[2][k] = rv[1][6 * o + k];
-                cv[3][k] = rv[1][6 * o + 3 + k];
-                cn[0][k] = rn[0][6 * o + k];
-                cn[1][k] = rn[0][6 * o + 3 + k];
-                cn[2][k] = rn[1][6 * o + k];
-                cn[3][k] = rn[1][6 * o + 3 + k];
-            }
-            float vo[3], no[3];
-            model_px(cv, cn, vo, no);
-            const int i = v * C.W + u + o;
-            for (int k = 0; k < 3; ++k) {
-                MVo[3 * i + k] = vo[k];
-                MNo[3 * i + k] = no[k];
-                kv[2 * b + o][k] = vo[k];
-                kn[2 * b + o][k] = no[k];
-            }
+    // children (2u, 2v), (2u+1, 2v), (2u, 2v+1), (2u+1, 2v+1), row-major
+    float cv[4][3], cn[4][3];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int base = inside ? 3 * ((2 * v + r) * F.W + 2 * u) : 0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            cv[2 * r + k / 3][k % 3] = MV[base + k];
+            cn[2 * r + k / 3][k % 3] = MN[base + k];
         }
     }
-    if (!also_next || !two || rows != 2) return;
-    // a whole block: level l+1 (C.W >> 1 by C.H >> 1) has its pixel (u / 2, vb)
-    const LevelDesc& N = P.lv[level + 1];
     float vo[3], no[3];
+    model_px(cv, cn, vo, no);
+    if (inside) {
+        ICP_GLOBAL float* MVo = gmut(C.MVw);
+        ICP_GLOBAL float* MNo = gmut(C.MNw);
+        const int i = v * C.W + u;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            MVo[3 * i + k] = vo[k];
+            MNo[3 * i + k] = no[k];
+        }
+    }
+    if (!also_next) return;  // (uniform)
+    // every lane of the quad takes part in the broadcasts
+    float kv[4][3], kn[4][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        kv[0][k] = quad_bcast<0>(vo[k]);
+        kv[1][k] = quad_bcast<1>(vo[k]);
+        kv[2][k] = quad_bcast<2>(vo[k]);
+        kv[3][k] = quad_bcast<3>(vo[k]);
+        kn[0][k] = quad_bcast<0>(no[k]);
+        kn[1][k] = quad_bcast<1>(no[k]);
+        kn[2][k] = quad_bcast<2>(no[k]);
+        kn[3][k] = quad_bcast<3>(no[k]);
+    }
+    if (q != 0 || 2 * bu + 1 >= C.W || 2 * bv + 1 >= C.H) return;
+    // a whole block: level l+1 (C.W >> 1 by C.H >> 1) has its pixel (bu, bv)
+    const LevelDesc& N = P.lv[level + 1];
     model_px(kv, kn, vo, no);
-    const int i = vb * N.W + (u >> 1);
+    const int i = bv * N.W + bu;
     ICP_GLOBAL float* NVo = gmut(N.MVw);
     ICP_GLOBAL float* NNo = gmut(N.MNw);
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
         NVo[3 * i + k] = vo[k];
         NNo[3 * i + k] = no[k];
@@ -1617,7 +1609,7 @@ hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* m
         }
     }
     for (int l = 1; l < levels; l += 2)
-        hipLaunchKernelGGL(k_model_down, dim3(blocks_for(max_model_blocks[l]), n), dim3(ICP_WG), 0, s, probs, l,
+        hipLaunchKernelGGL(k_model_down, dim3(blocks_for(4 * max_model_blocks[l]), n), dim3(ICP_WG), 0, s, probs, l,
                            l + 1 < levels ? 1 : 0);
     return hipGetLastError();
 }
