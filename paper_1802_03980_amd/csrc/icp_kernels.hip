@@ -1296,7 +1296,14 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
 // Filter (kept iff gated and its bin lies in the band) and the 28-moment
 // reduction of the kept rows into one partial per tile.
 
-__global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(4))) void k_pass2(
+// kFold: the solve folded into the last work-group (one problem); its FP64
+// system needs registers the batch variant does without (four waves per SIMD
+// against five).
+#ifndef ICP_PASS2_WAVES
+#define ICP_PASS2_WAVES 5
+#endif
+template <bool kFold>
+__global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(kFold ? 4 : ICP_PASS2_WAVES))) void k_pass2(
     const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
                                                   IterCtl ctl, KParams kp) {
     // every problem of the batch finished its iteration in the band kernel
@@ -1320,17 +1327,34 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(4))) voi
         const int khi = __builtin_amdgcn_readfirstlane(st->k_hi);
         const int base = tile * L.tile_px;
         const int end = min(base + L.tile_px, L.npx);
-        for (int i = base + ICP_PX_PER_THREAD * tid; i < end; i += ICP_TILE_QUANTUM) {
-            associate4(Lv, i, T, kp.d2max, kp.cos_max, [&](int, const PixelOut& q) {
+        // one pixel per lane and round, software-pipelined as in pass 1: the
+        // next round's gathers are in flight while a round is decided
+        constexpr int kRound = ICP_WG;
+        auto ld_index = [&](int r) {
+            const int i = r + tid;
+            return i < end ? i : r;
+        };
+        auto next_r = [&](int r) { return r + kRound < end ? r + kRound : r; };
+        Proj<1> pa = assoc_project<1>(Lv, base + tid, end, load_live<1>(Lv, ld_index(base)), T);
+        Gath<1> ga = assoc_gather<1>(Lv, base + tid, pa);
+        LiveIn<1> nxt = load_live<1>(Lv, ld_index(next_r(base)));
+        for (int r = base; r < end; r += kRound) {
+            const LiveIn<1> nn = load_live<1>(Lv, ld_index(next_r(next_r(r))));
+            const Proj<1> pb = assoc_project<1>(Lv, r + kRound + tid, end, nxt, T);
+            const Gath<1> gb = assoc_gather<1>(Lv, r + kRound + tid, pb);
+            assoc_decide<1>(pa, ga, T, kp.d2max, kp.cos_max, [&](int, const PixelOut& q) {
                 if (q.code == kGated && q.bin >= klo && q.bin <= khi) {
                     accumulate_row(q.p, q.d, q.n, acc);
                     cnt += 1.0f;
                 }
             });
+            pa = pb;
+            ga = gb;
+            nxt = nn;
         }
     }
     block_reduce_row(acc, cnt, sh_red, gmut(L.part) + (size_t)tile * ICP_PART_STRIDE);
-    if (!kp.fold_solve) return;
+    if (!kFold) return;
     // The solve folded into pass 2 (one problem): every thread's stores are
     // made visible device-wide before the barrier, thread 0 takes a ticket,
     // and the work-group that finishes last sums the partials in tile order,
@@ -1642,8 +1666,10 @@ hipError_t launch_pass2(const ProbDesc* probs, const int* owner, int tiles, Iter
                         hipStream_t s) {
     if (kp.reduce_mode == 1)
         hipLaunchKernelGGL(k_pass2_mfma, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+    else if (kp.fold_solve)
+        hipLaunchKernelGGL(k_pass2<true>, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
     else
-        hipLaunchKernelGGL(k_pass2, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+        hipLaunchKernelGGL(k_pass2<false>, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
     return hipGetLastError();
 }
 
@@ -1699,7 +1725,7 @@ hipError_t launch_stage_pass2(const ProbDesc* probs, const int* owner, int tiles
     if (kp.reduce_mode == 1)
         hipLaunchKernelGGL(k_pass2_mfma, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
     else
-        hipLaunchKernelGGL(k_pass2, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+        hipLaunchKernelGGL(k_pass2<false>, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
     hipLaunchKernelGGL(k_solve, dim3(1), dim3(ICP_WG), 0, s, probs, ctl, kp);
     return hipGetLastError();
 }
