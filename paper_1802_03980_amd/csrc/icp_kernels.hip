@@ -159,7 +159,7 @@ template <int R>
 __global__ __launch_bounds__(ICP_WG) void k_bilateral(const ProbDesc* __restrict__ probs, FrontEnd fe) {
     static_assert(R >= 1 && R <= ICP_FILTER_MAX_R, "filter radius");
     constexpr int HW = FE_TX + 2 * R, HH = FE_TY + 2 * R, N = 2 * R + 1;
-    __shared__ float sz[kBoxH][kBoxW];
+    __shared__ double sz[kBoxH][kBoxW];  // (as FP64: no conversion per tap)
     const ProbDesc& P = probs[blockIdx.y];
     const LevelDesc& L = P.lv[0];
     const int tiles_x = (L.W + FE_TX - 1) / FE_TX;
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(ICP_WG) void k_bilateral(const ProbDesc* __restrict
     for (int t = threadIdx.x; t < HW * HH; t += ICP_WG) {
         const int ly = t / HW, lx = t - ly * HW;
         const int x = u0 - R + lx, y = v0 - R + ly;
-        sz[ly][lx] = (x >= 0 && x < L.W && y >= 0 && y < L.H) ? D[y * L.W + x] : 0.0f;
+        sz[ly][lx] = (x >= 0 && x < L.W && y >= 0 && y < L.H) ? (double)D[y * L.W + x] : 0.0;
     }
     __syncthreads();
     const int tx = threadIdx.x % FE_TX;
@@ -180,24 +180,29 @@ __global__ __launch_bounds__(ICP_WG) void k_bilateral(const ProbDesc* __restrict
     for (int ty = threadIdx.x / FE_TX; ty < FE_TY; ty += ICP_WG / FE_TX) {
         const int v = v0 + ty;
         if (v >= L.H) break;
-        const float z = sz[ty + R][tx + R];
+        const double z = sz[ty + R][tx + R];
         float out = 0.0f;
-        if (depth_ok(z)) {
+        if (__builtin_isfinite(z) && z > 0.0) {
             double sw = 0.0, swz = 0.0;
 #pragma unroll
             for (int dv = -R; dv <= R; ++dv)
 #pragma unroll
                 for (int du = -R; du <= R; ++du) {
-                    const float zq = sz[ty + R + dv][tx + R + du];
-                    if (!depth_ok(zq)) continue;
-                    const double dz = (double)zq - (double)z;
+                    const double zq = sz[ty + R + dv][tx + R + du];
+                    if (!(__builtin_isfinite(zq) && zq > 0.0)) continue;
+                    const double dz = zq - z;
                     if (!(fabs(dz) < fe.sigma_m)) continue;
                     const double q = dz * fe.inv_sigma_m;
                     const double t = __builtin_fma(__builtin_fma(-q, fe.sigma_m, dz), fe.inv_sigma_m, q);
                     const double a = 1.0 - t * t;
-                    const double w = fe.ws[(dv + R) * N + (du + R)] * (a * a);
+                    // the host's table is exp(-(du^2 + dv^2) / (2 s^2)): one entry per
+                    // distinct (max(|du|, |dv|), min(|du|, |dv|)) holds every value, so the
+                    // unrolled taps name only those (a few scalar registers, no spills)
+                    const int ea = (du < 0 ? -du : du) > (dv < 0 ? -dv : dv) ? (du < 0 ? -du : du) : (dv < 0 ? -dv : dv);
+                    const int eb = (du < 0 ? -du : du) > (dv < 0 ? -dv : dv) ? (dv < 0 ? -dv : dv) : (du < 0 ? -du : du);
+                    const double w = fe.ws[(ea + R) * N + (eb + R)] * (a * a);
                     sw += w;
-                    swz += w * (double)zq;
+                    swz += w * zq;
                 }
             out = (float)(swz / sw);
         }
@@ -304,8 +309,8 @@ __global__ __launch_bounds__(ICP_WG) void k_live_n_box(const ProbDesc* __restric
                 const double c2 = h[0] * g[1] - h[1] * g[0];
                 const double len2 = (c0 * c0 + c1 * c1) + c2 * c2;
                 if (len2 > 0.0 && __builtin_isfinite(len2)) {
-                    const double len = sqrt(len2);
-                    double m0 = c0 / len, m1 = c1 / len, m2 = c2 / len;
+                    const double len = sqrt(len2), y = 1.0 / len;  // one division, then c / len per component
+                    double m0 = div_rn(c0, len, y), m1 = div_rn(c1, len, y), m2 = div_rn(c2, len, y);
                     const double side = (m0 * (double)p[0] + m1 * (double)p[1]) + m2 * (double)p[2];
                     if (side > 0.0) {
                         m0 = -m0;
