@@ -1393,17 +1393,16 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(kFold ? 
 // hardware orders the k slots.  Rows are staged through LDS: each round a
 // wave's 256 pixels form eight groups of 32.
 
-__global__ __launch_bounds__(ICP_WG) void k_pass2_mfma(const ProbDesc* __restrict__ probs,
-                                                       const int* __restrict__ owner, IterCtl ctl, KParams kp) {
+__global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(6))) void k_pass2_mfma(
+    const ProbDesc* __restrict__ probs, const int* __restrict__ owner, IterCtl ctl, KParams kp) {
     if (kp.need2 && __builtin_amdgcn_readfirstlane(*kp.need2) == 0) return;  // nothing to do (see k_pass2)
-    __shared__ _Float16 sh_x[ICP_WAVES][8][16][32];  // [wave][group][column][row in group]
-    __shared__ float sh_d[ICP_WAVES][16][17];
+    __shared__ _Float16 sh_x[ICP_WAVES][16][32];  // a half-wave's rows, column-major
     __shared__ float sh_red[ICP_WAVES][ICP_PART_STRIDE];
     const int g = blockIdx.x;
     const ProbDesc& P = probs[owner[g]];
     const LevelDesc& L = P.lv[ctl.level];
     const ProbState* st = P.st;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, wave = tid >> 6;
     const int tile = g - L.tile_base;
     if (st->level_done || st->fused_done) return;  // uniform
     const float c0 = (float)st->cur_c[0], c1 = (float)st->cur_c[1], c2 = (float)st->cur_c[2];
@@ -1415,65 +1414,34 @@ __global__ __launch_bounds__(ICP_WG) void k_pass2_mfma(const ProbDesc* __restric
         const int khi = __builtin_amdgcn_readfirstlane(st->k_hi);
         const int base = tile * L.tile_px;
         const int end = min(base + L.tile_px, L.npx);
-        const int grp = lane >> 3, q0 = 4 * (lane & 7);
-        // every wave runs the same number of rounds so the wave-level steps stay uniform
-        for (int r0 = base; r0 < end; r0 += ICP_TILE_QUANTUM) {
-            const int i = r0 + ICP_PX_PER_THREAD * tid;
-            _Float16 hv[8][4], lv[8][4];
-#pragma unroll
-            for (int c = 0; c < 8; ++c)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) hv[c][k] = lv[c][k] = (_Float16)0.0f;
-            if (i < end) {
-                associate4(Lv, i, T, kp.d2max, kp.cos_max, [&](int k, const PixelOut& q) {
-                    if (!(q.code == kGated && q.bin >= klo && q.bin <= khi)) return;
-                    const float pc[3] = {q.p[0] - c0, q.p[1] - c1, q.p[2] - c2};
-                    float r[7];
-                    make_row(pc, q.d, q.n, r);
-                    float v[8] = {r[0] * kScaleRot, r[1] * kScaleRot, r[2] * kScaleRot, r[3], r[4], r[5],
-                                  r[6] * kScaleB, 1.0f};
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        const _Float16 h = (_Float16)v[c];
-                        hv[c][k] = h;
-                        lv[c][k] = (_Float16)(v[c] - (float)h);
-                    }
-                });
-            }
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const h4v hh = {hv[c][0], hv[c][1], hv[c][2], hv[c][3]};
-                const h4v ll = {lv[c][0], lv[c][1], lv[c][2], lv[c][3]};
-                *(h4v*)&sh_x[wave][grp][c][q0] = hh;
-                *(h4v*)&sh_x[wave][grp][8 + c][q0] = ll;
-            }
-            wave_sync();
-#pragma unroll
-            for (int G = 0; G < 8; ++G) {
-                const h8v a = *(const h8v*)&sh_x[wave][G][lane & 15][8 * (lane >> 4)];
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, a, acc, 0, 0, 0);
-            }
-            wave_sync();
+        // pass 2's software pipeline; every lane of the work-group runs the
+        // same rounds (the MFMA staging works across the wave)
+        constexpr int kRound = ICP_WG;
+        auto ld_index = [&](int r) {
+            const int i = r + tid;
+            return i < end ? i : r;
+        };
+        auto next_r = [&](int r) { return r + kRound < end ? r + kRound : r; };
+        Proj<1> pa = assoc_project<1>(Lv, base + tid, end, load_live<1>(Lv, ld_index(base)), T);
+        Gath<1> ga = assoc_gather<1>(Lv, base + tid, pa);
+        LiveIn<1> nxt = load_live<1>(Lv, ld_index(next_r(base)));
+        for (int r = base; r < end; r += kRound) {
+            const LiveIn<1> nn = load_live<1>(Lv, ld_index(next_r(next_r(r))));
+            const Proj<1> pb = assoc_project<1>(Lv, r + kRound + tid, end, nxt, T);
+            const Gath<1> gb = assoc_gather<1>(Lv, r + kRound + tid, pb);
+            assoc_decide<1>(pa, ga, T, kp.d2max, kp.cos_max, [&](int, const PixelOut& q) {
+                const bool keep = q.code == kGated && q.bin >= klo && q.bin <= khi;
+                const float pc[3] = {q.p[0] - c0, q.p[1] - c1, q.p[2] - c2};
+                mfma_rows(keep, pc, q.d, q.n, sh_x[wave], acc);
+            });
+            pa = pb;
+            ga = gb;
+            nxt = nn;
         }
     }
-    // D[4 (l / 16) + t][l % 16] -> LDS, then the 8x8 Gram blocks summed
-#pragma unroll
-    for (int t = 0; t < 4; ++t) sh_d[wave][4 * (lane >> 4) + t][lane & 15] = acc[t];
-    wave_sync();
     float mom[ICP_NMOM];
     float cnt = 0.0f;
-    {
-        int k = 0;
-        for (int a = 0; a < 7; ++a)
-            for (int b = a; b < 7; ++b) {
-                const float gsum = (sh_d[wave][a][b] + sh_d[wave][a][8 + b]) +
-                                   (sh_d[wave][8 + a][b] + sh_d[wave][8 + a][8 + b]);
-                const float sa = a < 3 ? kScaleRot : (a == 6 ? kScaleB : 1.0f);
-                const float sb = b < 3 ? kScaleRot : (b == 6 ? kScaleB : 1.0f);
-                mom[k++] = lane == 0 ? gsum / (sa * sb) : 0.0f;
-            }
-        cnt = lane == 0 ? (sh_d[wave][7][7] + sh_d[wave][7][15]) + (sh_d[wave][15][7] + sh_d[wave][15][15]) : 0.0f;
-    }
+    mfma_moments(acc, sh_x[wave], mom, cnt);
     block_reduce_row(mom, cnt, sh_red, gmut(L.part) + (size_t)tile * ICP_PART_STRIDE);
 }
 
