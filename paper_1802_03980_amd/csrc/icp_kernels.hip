@@ -543,14 +543,29 @@ __global__ __launch_bounds__(ICP_WG) void k_centroid_tiles(const ProbDesc* __res
     const int base = tile * L.tile_px, end = min(base + L.tile_px, L.npx);
     double sx = 0.0, sy = 0.0, sz = 0.0, n = 0.0;
     const ICP_GLOBAL float* D = gconst(L.D);
-    for (int i = base + tid; i < end; i += ICP_WG) {
-        const float z = D[i];
-        if (depth_ok(z)) {
-            const int v = i / L.W, u = i - v * L.W;
-            sx += (double)(float)((double)z * L.XQ[u]);
-            sy += (double)(float)((double)z * L.YQ[v]);
-            sz += (double)z;
-            n += 1.0;
+    const Lvl Lv = load_level(L);
+    // four of the thread's pixels per step, their depths loaded together; the
+    // vertices use the pixel passes' quotients (the table values), and the
+    // sums take the pixels in the same order as one at a time
+    constexpr int kStep = 4;
+    for (int i0 = base + tid; i0 < end; i0 += kStep * ICP_WG) {
+        float z[kStep];
+#pragma unroll
+        for (int k = 0; k < kStep; ++k) {
+            const int i = i0 + k * ICP_WG;
+            z[k] = D[i < end ? i : i0];
+        }
+#pragma unroll
+        for (int k = 0; k < kStep; ++k) {
+            const int i = i0 + k * ICP_WG;
+            if (i < end && depth_ok(z[k])) {
+                int u, v;
+                pixel_uv(Lv, i, u, v);
+                sx += (double)(float)((double)z[k] * bp_quot(u, Lv.cx, Lv.fx, Lv.rfx));
+                sy += (double)(float)((double)z[k] * bp_quot(v, Lv.cy, Lv.fy, Lv.rfy));
+                sz += (double)z[k];
+                n += 1.0;
+            }
         }
     }
     sh[tid][0] = sx;
