@@ -858,7 +858,9 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(ICP_PASS
     const Pose T = load_pose(st);
     for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) sh_hist[b] = 0u;
     if (kFused && h0 >= 0)
-        for (int b = tid; b < ICP_WAVES * ICP_WIN * (ICP_NMOM + 1); b += ICP_WG) (&sh_win[0][0][0])[b] = 0.0f;
+        // only the window's w bins of each wave's sums are cleared (and later read)
+        for (int wv = 0; wv < ICP_WAVES; ++wv)
+            for (int b = tid; b < win.w * (ICP_NMOM + 1); b += ICP_WG) (&sh_win[wv][0][0])[b] = 0.0f;
     __syncthreads();
     const int wave = tid >> 6;
     float acc[ICP_NMOM];
@@ -944,7 +946,7 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(ICP_PASS
 #pragma unroll
             for (int q = 0; q < kPer; ++q) {
                 const int b = cj * kPer + q;
-                run += (sh_win[0][b][mj] + sh_win[1][b][mj]) + (sh_win[2][b][mj] + sh_win[3][b][mj]);
+                if (b < win.w) run += (sh_win[0][b][mj] + sh_win[1][b][mj]) + (sh_win[2][b][mj] + sh_win[3][b][mj]);
                 pre[q] = run;
             }
             sh_tot[cj * (ICP_NMOM + 1) + mj] = run;
