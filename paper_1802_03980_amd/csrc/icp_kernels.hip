@@ -822,7 +822,7 @@ template <bool kDebug, bool kFused, bool kSplit>
 __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(ICP_PASS1_WAVES))) void k_pass1(const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
                                                   IterCtl ctl, KParams kp, uint8_t* __restrict__ dbg_code,
                                                   int32_t* __restrict__ dbg_bin) {
-    __shared__ uint32_t sh_hist[ICP_HIST_BINS];
+    __shared__ __attribute__((aligned(16))) uint32_t sh_hist[ICP_HIST_BINS];
     __shared__ float sh_win[kFused ? ICP_WAVES : 1][kFused ? ICP_WIN : 1][ICP_NMOM + 1];
     __shared__ float sh_stage[kFused ? ICP_WAVES : 1][kFused ? ICP_STAGE : 1][8];
     __shared__ float sh_red[ICP_WAVES][ICP_PART_STRIDE];
@@ -856,7 +856,9 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(ICP_PASS
     const Win win = kFused ? band_window(gst->pred_hi, gst->pred_hw, ctl.iter) : Win{-1, 0};
     const int h0 = win.h0;
     const Pose T = load_pose(st);
-    for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) sh_hist[b] = 0u;
+    static_assert(ICP_HIST_BINS == 4 * ICP_WG, "four histogram bins per thread");
+    typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+    reinterpret_cast<u4v*>(sh_hist)[tid] = u4v{0u, 0u, 0u, 0u};
     if (kFused && h0 >= 0)
         // only the window's w bins of each wave's sums are cleared (and later read)
         for (int wv = 0; wv < ICP_WAVES; ++wv)
@@ -962,10 +964,10 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(ICP_PASS
     }
     // the tile's histogram, last: nothing after it waits for the adds
     ICP_GLOBAL unsigned int* hist = gmut(P.st->hist);
-    for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) {
-        const uint32_t c = sh_hist[b];
-        if (c) __hip_atomic_fetch_add(hist + b, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    const u4v hc = reinterpret_cast<const u4v*>(sh_hist)[tid];  // bins 4 tid .. 4 tid + 3
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (hc[k]) __hip_atomic_fetch_add(hist + 4 * tid + k, hc[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ------------------------------------------------------------------ epilogues
