@@ -964,10 +964,14 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(ICP_PASS
     }
     // the tile's histogram, last: nothing after it waits for the adds
     ICP_GLOBAL unsigned int* hist = gmut(P.st->hist);
-    const u4v hc = reinterpret_cast<const u4v*>(sh_hist)[tid];  // bins 4 tid .. 4 tid + 3
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (hc[k]) __hip_atomic_fetch_add(hist + 4 * tid + k, hc[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // (lane-consecutive bins: each atomic instruction of a wave covers 256
+    // contiguous bytes; four bins per thread would spread it over four times
+    // as many cache lines, which a one-problem registration's 300 work-groups,
+    // all adding into one histogram, pay in latency)
+    for (int b = tid; b < ICP_HIST_BINS; b += ICP_WG) {
+        const uint32_t c = sh_hist[b];
+        if (c) __hip_atomic_fetch_add(hist + b, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // ------------------------------------------------------------------ epilogues
