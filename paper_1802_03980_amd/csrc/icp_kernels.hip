@@ -983,26 +983,42 @@ __device__ __forceinline__ void level_reset(ProbState* st) {
     st->last_kmed = -2;
 }
 
-// Regularised solve (Eq. (5)), pose update and per-level bookkeeping of one
-// problem; thread 0 only.  Every state field it reads is loaded first and
-// every one it writes is stored last, through a global pointer: a load after
-// a store waits for the store, so interleaving them would cost a memory
-// round trip each.
-__device__ void solve_epilogue(ProbState* st_in, const double* M, int64_t n, const IterCtl& ctl, const KParams& kp,
-                               const double* imu_R) {
-    ICP_GLOBAL ProbState* st = gmut(st_in);
-    const int32_t done = st->level_done;
+// The state a solve starts from.  Loaded before the work that precedes the
+// solve (with the kernel's other loads), so that the solve itself waits for
+// no memory.
+struct EpiIn {
     double R[9], t[3];
-    for (int k = 0; k < 9; ++k) R[k] = st->R[k];
-    for (int k = 0; k < 3; ++k) t[k] = st->t[k];
-    const uint32_t N = st->N;
-    const int32_t k_med = st->k_med, last_kmed = st->last_kmed, settled = st->settled;
-    const int32_t iters_total = st->stats.iters_total, first_status = st->stats.status;
-    // (an empty statement that takes the loaded values: the loads are issued
-    // here, before the early returns, and waited for once)
-    __asm__ volatile("" ::"v"(R[0]), "v"(R[1]), "v"(R[2]), "v"(R[3]), "v"(R[4]), "v"(R[5]), "v"(R[6]), "v"(R[7]),
-                     "v"(R[8]), "v"(t[0]), "v"(t[1]), "v"(t[2]), "v"(N), "v"(k_med), "v"(last_kmed), "v"(settled),
-                     "v"(iters_total), "v"(first_status));
+    int32_t done, last_kmed, settled, iters_total, first_status;
+};
+
+__device__ __forceinline__ EpiIn load_epi(const ProbState* st_in) {
+    const ICP_GLOBAL ProbState* st = gconst(st_in);
+    EpiIn e;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) e.R[k] = st->R[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e.t[k] = st->t[k];
+    e.done = st->level_done;
+    e.last_kmed = st->last_kmed;
+    e.settled = st->settled;
+    e.iters_total = st->stats.iters_total;
+    e.first_status = st->stats.status;
+    return e;
+}
+
+// Regularised solve (Eq. (5)), pose update and per-level bookkeeping of one
+// problem; thread 0 only.  It starts from e (load_epi) and the iteration's
+// gated count N and median bin k_med, and stores every field it writes
+// through a global pointer, after all of its arithmetic.
+__device__ void solve_epilogue(ProbState* st_in, const EpiIn& e, uint32_t N, int32_t k_med, const double* M,
+                               int64_t n, const IterCtl& ctl, const KParams& kp, const double* imu_R) {
+    ICP_GLOBAL ProbState* st = gmut(st_in);
+    const int32_t done = e.done;
+    double R[9], t[3];
+    for (int k = 0; k < 9; ++k) R[k] = e.R[k];
+    for (int k = 0; k < 3; ++k) t[k] = e.t[k];
+    const int32_t last_kmed = e.last_kmed, settled = e.settled;
+    const int32_t iters_total = e.iters_total, first_status = e.first_status;
     if (done) return;
     if (ctl.no_update) {
         for (int k = 0; k < ICP_NMOM; ++k) st->M[k] = M[k];
@@ -1044,95 +1060,107 @@ __device__ void solve_epilogue(ProbState* st_in, const double* M, int64_t n, con
     if (level_done) st->level_done = 1;
 }
 
-// The tile partials a thread of the band kernel adds: thread (j, c) takes
-// entry j (j <= ICP_NMOM) of tiles t0 .. t1 - 1, the c-th of eight equal runs.
+// The tile partials a thread of a summing work-group adds: thread (g, c)
+// takes entries 4g .. 4g + 3 (one 16-byte load per tile) of tiles
+// t0 .. t1 - 1, the c-th of kRuns equal runs of consecutive tiles.  Eight
+// lanes cover one tile's 32 floats, so a wave reads eight whole partials per
+// load instruction.
+constexpr int kGroups = ICP_PART_STRIDE / 4;
+constexpr int kRuns = ICP_WG / kGroups;
+static_assert(kGroups * 4 == ICP_PART_STRIDE && kGroups * kRuns == ICP_WG && ICP_NMOM < ICP_PART_STRIDE,
+              "partial sum layout");
 struct TileRun {
-    int j, t0, t1;
-    bool on;
+    int g, t0, t1;
 };
 
 __device__ __forceinline__ TileRun tile_run(int n_tiles) {
     const int tid = threadIdx.x;
     TileRun r;
-    r.j = tid >> 3;
-    const int c = tid & 7;
-    const int per = (n_tiles + 7) / 8;
+    r.g = tid % kGroups;
+    const int c = tid / kGroups;
+    const int per = (n_tiles + kRuns - 1) / kRuns;
     r.t0 = c * per;
     r.t1 = min(r.t0 + per, n_tiles);
-    r.on = r.j <= ICP_NMOM;
     return r;
 }
 
-// Slot 0 of the first sixteen tiles of the thread's run (loaded before the
-// band is known: it does not depend on it).
-constexpr int kSumBatch = 16;
+typedef float pf4 __attribute__((ext_vector_type(4)));
+
+// Slot 0 of the first kSumBatch tiles of the thread's run (loaded before the
+// band is known: it does not depend on it).  Past the run's end a valid tile
+// is loaded and not added, so no branch separates the loads.
+constexpr int kSumBatch = 12;
 __device__ __forceinline__ void load_slot0(const float* part_in, int tile_stride, const TileRun& r,
-                                           float (&a)[kSumBatch]) {
+                                           pf4 (&a)[kSumBatch]) {
     const ICP_GLOBAL float* part = gconst(part_in);
-    const int j = min(r.j, ICP_NMOM);  // (threads past the entries load one and do not add it: no branch)
 #pragma unroll
     for (int u = 0; u < kSumBatch; ++u) {
-        const int tt = max(0, min(r.t0 + u, r.t1 - 1));  // past the end: a valid tile, not added
-        a[u] = part[(size_t)tt * tile_stride + j];
+        const int tt = max(0, min(r.t0 + u, r.t1 - 1));
+        a[u] = *reinterpret_cast<const ICP_GLOBAL pf4*>(part + (size_t)tt * tile_stride + 4 * r.g);
     }
 }
 
-// Deterministic FP64 sums over the tiles (in tile order) of slot 0 plus, if
-// slot2 > 0, slot `slot2` of every tile partial into sh_out[0..28]; whole
-// work-group.  a0 holds slot 0 of the first sixteen tiles of each thread's
-// run (load_slot0).
-__device__ void sum_partials(const float* part_in, int n_tiles, int tile_stride, int slot2, const float (&a0)[kSumBatch],
+// Deterministic FP64 sums over the tiles of slot 0 plus, if slot2 > 0, slot
+// `slot2` of every tile partial into sh_out[0..28]; whole work-group.  Each
+// run adds its tiles in order and the runs are added in order.  a0 holds slot
+// 0 of the first kSumBatch tiles of each thread's run (load_slot0).
+__device__ void sum_partials(const float* part_in, int n_tiles, int tile_stride, int slot2, const pf4 (&a0)[kSumBatch],
                              double* sh_out) {
     const ICP_GLOBAL float* part = gconst(part_in);
-    __shared__ double sh_sum[ICP_NMOM + 1][8];
+    __shared__ double sh_sum[ICP_PART_STRIDE][kRuns + 1];
     const int tid = threadIdx.x;
     const TileRun r = tile_run(n_tiles);
-    if (r.on) {
-        // Sixteen tiles' loads are issued before their adds (the adds stay in
-        // tile order): one memory latency per sixteen tiles, not per tile.  The
-        // second slot is always loaded (slot 0 again when unused) and selected,
-        // so no branch separates the loads.
-        const bool two = slot2 > 0;
-        const size_t off2 = two ? (size_t)slot2 * ICP_PART_STRIDE : 0;
-        double s = 0.0;
-        {  // the first sixteen tiles: slot 0 is already in a0
-            float b[kSumBatch];
+    // kSumBatch tiles' loads are issued before their adds (the adds stay in
+    // tile order): one memory latency per batch, not per tile.  The second
+    // slot is always loaded (slot 0 again when unused) and selected.
+    const bool two = slot2 > 0;
+    const size_t off2 = two ? (size_t)slot2 * ICP_PART_STRIDE : 0;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    auto add = [&](const pf4& x, const pf4& y) {
+        s[0] += two ? (double)x.x + (double)y.x : (double)x.x;
+        s[1] += two ? (double)x.y + (double)y.y : (double)x.y;
+        s[2] += two ? (double)x.z + (double)y.z : (double)x.z;
+        s[3] += two ? (double)x.w + (double)y.w : (double)x.w;
+    };
+    {  // the first batch: slot 0 is already in a0
+        pf4 b[kSumBatch];
 #pragma unroll
-            for (int u = 0; u < kSumBatch; ++u) {
-                const int tt = max(0, min(r.t0 + u, r.t1 - 1));
-                b[u] = part[(size_t)tt * tile_stride + r.j + off2];
-            }
-#pragma unroll
-            for (int u = 0; u < kSumBatch; ++u)
-                if (r.t0 + u < r.t1) s += two ? (double)a0[u] + (double)b[u] : (double)a0[u];
+        for (int u = 0; u < kSumBatch; ++u) {
+            const int tt = max(0, min(r.t0 + u, r.t1 - 1));
+            b[u] = *reinterpret_cast<const ICP_GLOBAL pf4*>(part + (size_t)tt * tile_stride + 4 * r.g + off2);
         }
-        for (int t = r.t0 + kSumBatch; t < r.t1; t += kSumBatch) {
-            float a[kSumBatch], b[kSumBatch];
 #pragma unroll
-            for (int u = 0; u < kSumBatch; ++u) {
-                const int tt = min(t + u, r.t1 - 1);  // past the end: a valid tile, not added
-                const ICP_GLOBAL float* q = part + (size_t)tt * tile_stride + r.j;
-                a[u] = q[0];
-                b[u] = q[off2];
-            }
-#pragma unroll
-            for (int u = 0; u < kSumBatch; ++u)
-                if (t + u < r.t1) s += two ? (double)a[u] + (double)b[u] : (double)a[u];
-        }
-        sh_sum[r.j][tid & 7] = s;
+        for (int u = 0; u < kSumBatch; ++u)
+            if (r.t0 + u < r.t1) add(a0[u], b[u]);
     }
+    for (int t = r.t0 + kSumBatch; t < r.t1; t += kSumBatch) {
+        pf4 a[kSumBatch], b[kSumBatch];
+#pragma unroll
+        for (int u = 0; u < kSumBatch; ++u) {
+            const int tt = min(t + u, r.t1 - 1);
+            const ICP_GLOBAL float* q = part + (size_t)tt * tile_stride + 4 * r.g;
+            a[u] = *reinterpret_cast<const ICP_GLOBAL pf4*>(q);
+            b[u] = *reinterpret_cast<const ICP_GLOBAL pf4*>(q + off2);
+        }
+#pragma unroll
+        for (int u = 0; u < kSumBatch; ++u)
+            if (t + u < r.t1) add(a[u], b[u]);
+    }
+    const int c = tid / kGroups;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh_sum[4 * r.g + k][c] = s[k];
     __syncthreads();
     if (tid <= ICP_NMOM) {
-        double s = 0.0;
-        for (int q = 0; q < 8; ++q) s += sh_sum[tid][q];
-        sh_out[tid] = s;
+        double v = 0.0;
+        for (int q = 0; q < kRuns; ++q) v += sh_sum[tid][q];
+        sh_out[tid] = v;
     }
     __syncthreads();
 }
 
 __device__ __forceinline__ void sum_partials(const float* part, int n_tiles, int tile_stride, int slot2,
                                              double* sh_out) {
-    float a0[kSumBatch];
+    pf4 a0[kSumBatch];
     load_slot0(part, tile_stride, tile_run(n_tiles), a0);
     sum_partials(part, n_tiles, tile_stride, slot2, a0, sh_out);
 }
@@ -1281,16 +1309,18 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     uint32_t h[4];
     load_hist4(st, h);
     const int done = gst->level_done, pred = gst->pred_hi, pred_hw = gst->pred_hw;
+    const EpiIn epi = load_epi(st);
     // (an empty statement that takes the loaded values, so that the compiler
     // issues every load above before the early return and waits once)
-    __asm__ volatile("" ::"v"(h[0]), "v"(h[1]), "v"(h[2]), "v"(h[3]), "s"(pred), "s"(pred_hw));
+    __asm__ volatile("" ::"v"(h[0]), "v"(h[1]), "v"(h[2]), "v"(h[3]), "s"(pred), "s"(pred_hw), "v"(epi.R[0]),
+                     "v"(epi.t[2]), "v"(epi.iters_total), "v"(epi.first_status));
     if (done) {  // (pass 1 added nothing: the histogram is still clear)
         if (kp.fold_solve && ctl.last_of_level && threadIdx.x == 0) level_reset(st);
         return;
     }
     // slot 0 of the tile partials does not depend on the band: its loads are
     // in flight while the band is found
-    float a0[kSumBatch];
+    pf4 a0[kSumBatch];
     if (fused) load_slot0(L.part1, ICP_WIN_SLOTS * ICP_PART_STRIDE, tile_run(L.n_tiles), a0);
     const Win win = fused ? band_window(pred, pred_hw, ctl.iter) : Win{-1, 0};
     const int h0 = win.h0;
@@ -1304,7 +1334,7 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
         sum_partials(L.part1, L.n_tiles, ICP_WIN_SLOTS * ICP_PART_STRIDE, b.k_hi - h0 + 1, a0, sh_M);
         if (threadIdx.x == 0) {
             if (kp.reduce_mode == 1) uncentre(sh_M, st->cur_c);
-            solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
+            solve_epilogue(st, epi, b.N, b.k_med, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
         }
     }
     if (threadIdx.x == 0) {
@@ -1395,10 +1425,13 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(kFold ? 
     __syncthreads();
     if (!sh_last) return;
     __threadfence();
+    const EpiIn epi = load_epi(P.st);
+    const uint32_t N = gconst(P.st)->N;
+    const int32_t k_med = gconst(P.st)->k_med;
     sum_partials(L.part, L.n_tiles, ICP_PART_STRIDE, 0, sh_M);
     if (tid == 0) {
         ProbState* sw = P.st;
-        solve_epilogue(sw, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
+        solve_epilogue(sw, epi, N, k_med, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
         sw->ticket = 0;
         sw->fused_done = 0;
         *kp.need2 = 0;
@@ -1478,10 +1511,13 @@ __global__ __launch_bounds__(ICP_WG) void k_solve(const ProbDesc* __restrict__ p
     const ICP_GLOBAL ProbState* gst = gconst(st);
     const int32_t fused_done = gst->fused_done, done = gst->level_done;  // loaded together
     if (!fused_done && !done) {
+        const EpiIn epi = load_epi(st);
+        const uint32_t N = gst->N;
+        const int32_t k_med = gst->k_med;
         sum_partials(L.part, L.n_tiles, ICP_PART_STRIDE, 0, sh_M);
         if (threadIdx.x == 0) {
             if (kp.reduce_mode == 1) uncentre(sh_M, st->cur_c);
-            solve_epilogue(st, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
+            solve_epilogue(st, epi, N, k_med, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
         }
     }
     if (threadIdx.x == 0) {
