@@ -554,26 +554,31 @@ int launch_registration(icp_ctx* ctx, int n, const icp_params* prm, const Launch
     if ((rc = end())) return rc;
     // single pass needs the band's lower edge at bin 0
     const int fused = prm->pass_mode == 0 && (!prm->use_median_filter || prm->band_beta >= 1.0) ? 1 : 0;
-    // one problem in single-pass mode with the FP32 reduction: most iterations
-    // end in the band kernel, so the solve launch is folded into pass 2 (whose
-    // last work-group solves the iterations the window missed) and one launch
-    // per iteration goes
+    // one problem in single-pass mode with the FP32 reduction: the band, pass 2
+    // and the solve are one launch (k_band_pass2), two launches per iteration
     kp.fold_solve = fused && n == 1 && prm->reduce_mode == 0 ? 1 : 0;
+    int gidx = 0;  // iterations so far, over all levels
     for (int l = prm->levels - 1; l >= 0; --l) {
         const int* owner = G.owner[l];
         const int64_t px = G.px[l];
-        for (int it = 0; it < prm->iters[l]; ++it) {
-            IterCtl ctl{l, it, it == prm->iters[l] - 1 ? 1 : 0, 0};
+        for (int it = 0; it < prm->iters[l]; ++it, ++gidx) {
+            // (k_band_pass2 alternates the histogram and the window prediction)
+            IterCtl ctl{l, it, it == prm->iters[l] - 1 ? 1 : 0, 0, kp.fold_solve ? gidx & 1 : 0};
             if ((rc = begin(ICP_TIME_PASS1, px))) return rc;
             HIP_TRY(ctx, icpk::launch_pass1(d_desc, owner, G.tiles[l], ctl, kp, fused, s));
             if ((rc = end())) return rc;
+            if (kp.fold_solve) {
+                if ((rc = begin(ICP_TIME_PASS2, px))) return rc;
+                HIP_TRY(ctx, icpk::launch_band_pass2(d_desc, G.tiles[l], ctl, kp, s));
+                if ((rc = end())) return rc;
+                continue;
+            }
             if ((rc = begin(ICP_TIME_BAND, 0))) return rc;
             HIP_TRY(ctx, icpk::launch_band(d_desc, n, ctl, kp, fused, s));
             if ((rc = end())) return rc;
             if ((rc = begin(ICP_TIME_PASS2, px))) return rc;
             HIP_TRY(ctx, icpk::launch_pass2(d_desc, owner, G.tiles[l], ctl, kp, s));
             if ((rc = end())) return rc;
-            if (kp.fold_solve) continue;
             if ((rc = begin(ICP_TIME_SOLVE, 0))) return rc;
             HIP_TRY(ctx, icpk::launch_solve(d_desc, n, ctl, kp, s));
             if ((rc = end())) return rc;

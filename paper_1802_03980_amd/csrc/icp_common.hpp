@@ -87,17 +87,17 @@ struct ProbState {
     double M[ICP_NMOM];         // last reduced moments (FP64 sums of tile partials)
     double x[6];                // last increment
     int64_t n_last;             // kept pairs of the last reduction
-    uint32_t hist[ICP_HIST_BINS];
+    uint32_t hist[2][ICP_HIST_BINS];  // distance histogram; IterCtl::par selects the one in use
     uint32_t N;                 // gated pairs of the current iteration
     int32_t k_med, k_lo, k_hi;  // median bin and kept band of the current iteration
-    int32_t pred_hi;            // band upper edge predicted for the next iteration (-1: none)
-    int32_t pred_hw;            // half-width of the window around it, in bins (at most ICP_WIN / 2)
+    int32_t pred_hi[2];         // band upper edge predicted for an iteration (-1: none), by IterCtl::par
+    int32_t pred_hw[2];         // half-width of the window around it, in bins (at most ICP_WIN / 2)
     int32_t fused_done;         // this iteration was completed from the single-pass partials
     int32_t level_done;         // the current level has ended (status or convergence)
     int32_t settled;            // successive iterations with an unchanged median
     int32_t last_kmed;
     int32_t last_status;        // status of the last solve
-    int32_t ticket;             // pass-2 tiles finished this iteration (solve folded into pass 2)
+    int32_t ticket;             // work-groups of k_band_pass2 finished this iteration
     icp_stats stats;
     double cen[ICP_MAX_LEVELS][3];  // centroid of each level's valid live vertices
     double cur_c[3];            // centring point of the current iteration (model frame)
@@ -117,6 +117,8 @@ struct IterCtl {
     int32_t iter;               // iteration index within the level
     int32_t last_of_level;      // this is the level's last scheduled iteration
     int32_t no_update;          // stage calls: reduce only, keep the pose
+    int32_t par;                // histogram and window prediction in use (0, or the global iteration's
+                                //   parity where k_band_pass2 runs: its launch reads one and writes the other)
 };
 
 struct KParams {
@@ -132,6 +134,6 @@ struct KParams {
     int32_t reduce_mode;        // 0: FP32 rows; 1: FP16 hi+lo split MFMA on centred rows
     int32_t* need2;             // batch flag: some problem needs pass 2 this iteration (NULL: always run it)
     int32_t anchor_to_imu;      // the damping acts on the deviation from the IMU rotation
-    int32_t fold_solve;         // one problem, single pass: no solve launch; the band kernel keeps the level's
-                                //   books and pass 2's last work-group solves an iteration the window missed
+    int32_t fold_solve;         // one problem, single pass, FP32 reduction: band, pass 2 and solve in one
+                                //   launch per iteration (k_band_pass2)
 };

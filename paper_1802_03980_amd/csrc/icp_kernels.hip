@@ -26,7 +26,7 @@ __global__ __launch_bounds__(ICP_WG) void k_init(const ProbDesc* __restrict__ pr
     const ProbDesc& P = probs[blockIdx.x];
     ProbState* st = P.st;
     if (need2 && blockIdx.x == 0 && threadIdx.x == 0) *need2 = 0;
-    for (int b = threadIdx.x; b < ICP_HIST_BINS; b += ICP_WG) st->hist[b] = 0u;
+    for (int b = threadIdx.x; b < ICP_HIST_BINS; b += ICP_WG) st->hist[0][b] = st->hist[1][b] = 0u;
     if (threadIdx.x == 0) {
         // Sec. 3: the live points are pre-oriented by the IMU rotation
         for (int i = 0; i < 3; ++i) {
@@ -40,8 +40,8 @@ __global__ __launch_bounds__(ICP_WG) void k_init(const ProbDesc* __restrict__ pr
         st->k_med = -1;
         st->k_lo = 0;
         st->k_hi = -1;
-        st->pred_hi = -1;
-        st->pred_hw = ICP_WIN / 2;
+        st->pred_hi[0] = st->pred_hi[1] = -1;
+        st->pred_hw[0] = st->pred_hw[1] = ICP_WIN / 2;
         st->fused_done = 0;
         st->ticket = 0;
         st->level_done = 0;
@@ -853,7 +853,7 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(ICP_PASS
     if (base < end) cur = load_live<ICP_PASS1_PX>(Lv, ld_index(base));
     const ICP_GLOBAL ProbState* gst = gconst(st);
     if (gst->level_done) return;  // uniform: the level has ended for this problem
-    const Win win = kFused ? band_window(gst->pred_hi, gst->pred_hw, ctl.iter) : Win{-1, 0};
+    const Win win = kFused ? band_window(gst->pred_hi[ctl.par], gst->pred_hw[ctl.par], ctl.iter) : Win{-1, 0};
     const int h0 = win.h0;
     const Pose T = load_pose(st);
     static_assert(ICP_HIST_BINS == 4 * ICP_WG, "four histogram bins per thread");
@@ -963,7 +963,7 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(ICP_PASS
         }
     }
     // the tile's histogram, last: nothing after it waits for the adds
-    ICP_GLOBAL unsigned int* hist = gmut(P.st->hist);
+    ICP_GLOBAL unsigned int* hist = gmut(P.st->hist[ctl.par]);
     // (lane-consecutive bins: each atomic instruction of a wave covers 256
     // contiguous bytes; four bins per thread would spread it over four times
     // as many cache lines, which a one-problem registration's 300 work-groups,
@@ -1172,26 +1172,25 @@ struct Band {
 
 // The histogram entries 4 tid .. 4 tid + 3 a thread of the band kernel owns
 // (loaded together with the rest of the state the kernel starts from).
-__device__ __forceinline__ void load_hist4(const ProbState* st, uint32_t (&h)[4]) {
-    const ICP_GLOBAL uint32_t* hist = gconst(st->hist);
+__device__ __forceinline__ void load_hist4(const ProbState* st, int par, uint32_t (&h)[4]) {
+    const ICP_GLOBAL uint32_t* hist = gconst(st->hist[par]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) h[k] = hist[4 * threadIdx.x + k];
 }
 
 // Cleared for the next iteration, through a global pointer so that no later
 // LDS wait waits for the stores.
-__device__ __forceinline__ void clear_hist4(ProbState* st) {
-    ICP_GLOBAL uint32_t* hist = gmut(st->hist);
+__device__ __forceinline__ void clear_hist4(ProbState* st, int par) {
+    ICP_GLOBAL uint32_t* hist = gmut(st->hist[par]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) hist[4 * threadIdx.x + k] = 0u;
 }
 
 // Median bin k_med = min{k : C_k >= ceil(N/2)} of the CDF of the histogram
-// h (each thread's four entries) and the kept band (Sec. 3.3), stored in the
-// state and returned to every thread through LDS; the CDF is left in sh_cdf
-// (ICP_HIST_BINS entries; set when N > 0).  Whole work-group.
-__device__ Band median_band(ProbState* st, const uint32_t (&h)[4], const KParams& kp, uint32_t* dbg_hist,
-                            uint32_t* sh_cdf) {
+// h (each thread's four entries) and the kept band (Sec. 3.3), returned to
+// every thread through LDS; the CDF is left in sh_cdf (ICP_HIST_BINS
+// entries; set when N > 0).  Whole work-group; it writes no state.
+__device__ Band find_band(const uint32_t (&h)[4], const KParams& kp, uint32_t* dbg_hist, uint32_t* sh_cdf) {
     __shared__ uint32_t sh_wsum[ICP_WAVES];
     __shared__ int32_t sh_kmed;
     __shared__ Band sh_band;
@@ -1238,15 +1237,20 @@ __device__ Band median_band(ProbState* st, const uint32_t (&h)[4], const KParams
                 hi = ICP_HIST_BINS - 1;
             }
         }
-        ICP_GLOBAL ProbState* gw = gmut(st);  // (a global store: the barrier below does not wait for it)
-        gw->N = total;
-        gw->k_med = km;
-        gw->k_lo = lo;
-        gw->k_hi = hi;
         sh_band = Band{total, km, lo, hi};
     }
     __syncthreads();
     return sh_band;
+}
+
+// The band of the iteration into the problem's state (one thread), through a
+// global pointer: no later barrier or LDS wait waits for the stores.
+__device__ __forceinline__ void store_band(ProbState* st, const Band& b) {
+    ICP_GLOBAL ProbState* gw = gmut(st);
+    gw->N = b.N;
+    gw->k_med = b.k_med;
+    gw->k_lo = b.k_lo;
+    gw->k_hi = b.k_hi;
 }
 
 // Centring point of the split-precision reduction: the level's live centroid
@@ -1307,17 +1311,14 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     // the state the kernel starts from, loaded together: one wait, not three
     const ICP_GLOBAL ProbState* gst = gconst(st);
     uint32_t h[4];
-    load_hist4(st, h);
-    const int done = gst->level_done, pred = gst->pred_hi, pred_hw = gst->pred_hw;
+    load_hist4(st, ctl.par, h);
+    const int done = gst->level_done, pred = gst->pred_hi[ctl.par], pred_hw = gst->pred_hw[ctl.par];
     const EpiIn epi = load_epi(st);
     // (an empty statement that takes the loaded values, so that the compiler
     // issues every load above before the early return and waits once)
     __asm__ volatile("" ::"v"(h[0]), "v"(h[1]), "v"(h[2]), "v"(h[3]), "s"(pred), "s"(pred_hw), "v"(epi.R[0]),
                      "v"(epi.t[2]), "v"(epi.iters_total), "v"(epi.first_status));
-    if (done) {  // (pass 1 added nothing: the histogram is still clear)
-        if (kp.fold_solve && ctl.last_of_level && threadIdx.x == 0) level_reset(st);
-        return;
-    }
+    if (done) return;  // (pass 1 added nothing: the histogram is still clear)
     // slot 0 of the tile partials does not depend on the band: its loads are
     // in flight while the band is found
     pf4 a0[kSumBatch];
@@ -1327,8 +1328,9 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
     // split precision: the centring point of this iteration (before any update)
     if (kp.reduce_mode == 1 && threadIdx.x == 0) set_centre(st, ctl.level);
     __shared__ uint32_t sh_cdf[ICP_HIST_BINS];
-    const Band b = median_band(st, h, kp, dbg_hist, sh_cdf);
-    clear_hist4(st);
+    const Band b = find_band(h, kp, dbg_hist, sh_cdf);
+    if (threadIdx.x == 0) store_band(st, b);
+    clear_hist4(st, ctl.par);
     const bool hit = h0 >= 0 && b.N > 0 && b.k_lo == 0 && b.k_hi >= h0 - 1 && b.k_hi <= h0 + win.w - 1;
     if (hit) {
         sum_partials(L.part1, L.n_tiles, ICP_WIN_SLOTS * ICP_PART_STRIDE, b.k_hi - h0 + 1, a0, sh_M);
@@ -1341,12 +1343,9 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
         st->fused_done = hit ? 1 : 0;
         if (!hit && kp.need2) atomicExch(kp.need2, 1);  // pass 2 has work this iteration
         if (b.N > 0) {
-            st->pred_hw = capped_half_width(sh_cdf, b.k_hi, next_half_width(b.k_hi, pred, ctl.iter), L.npx);
-            st->pred_hi = b.k_hi;
+            st->pred_hw[ctl.par] = capped_half_width(sh_cdf, b.k_hi, next_half_width(b.k_hi, pred, ctl.iter), L.npx);
+            st->pred_hi[ctl.par] = b.k_hi;
         }
-        // with the solve folded into pass 2, an iteration finished here also
-        // closes the level (pass 2 skips this problem: fused_done is set)
-        if (kp.fold_solve && hit && ctl.last_of_level) level_reset(st);
     }
 }
 
@@ -1354,16 +1353,47 @@ __global__ __launch_bounds__(ICP_WG) void k_band(const ProbDesc* __restrict__ pr
 // Filter (kept iff gated and its bin lies in the band) and the 28-moment
 // reduction of the kept rows into one partial per tile.
 
-// kFold: the solve folded into the last work-group (one problem); its FP64
-// system needs registers the batch variant does without (four waves per SIMD
-// against five).
 #ifndef ICP_PASS2_WAVES
 #define ICP_PASS2_WAVES 5
 #endif
-template <bool kFold>
-__global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(kFold ? 4 : ICP_PASS2_WAVES))) void k_pass2(
-    const ProbDesc* __restrict__ probs, const int* __restrict__ owner,
-                                                  IterCtl ctl, KParams kp) {
+
+// Pass 2 over one tile: the rows kept by the band [klo, khi] reduced into
+// acc and cnt (one pixel per lane and round, software-pipelined as in pass 1:
+// the next round's gathers are in flight while a round is decided).
+__device__ __forceinline__ void pass2_tile(const LevelDesc& L, const ProbState* st, int tile, int klo, int khi,
+                                           const KParams& kp, float (&acc)[ICP_NMOM], float& cnt) {
+    const int tid = threadIdx.x;
+    const Pose T = load_pose(st);
+    const Lvl Lv = load_level(L);
+    const int base = tile * L.tile_px;
+    const int end = min(base + L.tile_px, L.npx);
+    constexpr int kRound = ICP_WG;
+    auto ld_index = [&](int r) {
+        const int i = r + tid;
+        return i < end ? i : r;
+    };
+    auto next_r = [&](int r) { return r + kRound < end ? r + kRound : r; };
+    Proj<1> pa = assoc_project<1>(Lv, base + tid, end, load_live<1>(Lv, ld_index(base)), T);
+    Gath<1> ga = assoc_gather<1>(Lv, base + tid, pa);
+    LiveIn<1> nxt = load_live<1>(Lv, ld_index(next_r(base)));
+    for (int r = base; r < end; r += kRound) {
+        const LiveIn<1> nn = load_live<1>(Lv, ld_index(next_r(next_r(r))));
+        const Proj<1> pb = assoc_project<1>(Lv, r + kRound + tid, end, nxt, T);
+        const Gath<1> gb = assoc_gather<1>(Lv, r + kRound + tid, pb);
+        assoc_decide<1>(pa, ga, T, kp.d2max, kp.cos_max, [&](int, const PixelOut& q) {
+            if (q.code == kGated && q.bin >= klo && q.bin <= khi) {
+                accumulate_row(q.p, q.d, q.n, acc);
+                cnt += 1.0f;
+            }
+        });
+        pa = pb;
+        ga = gb;
+        nxt = nn;
+    }
+}
+
+__global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(ICP_PASS2_WAVES))) void k_pass2(
+    const ProbDesc* __restrict__ probs, const int* __restrict__ owner, IterCtl ctl, KParams kp) {
     // every problem of the batch finished its iteration in the band kernel
     if (kp.need2 && __builtin_amdgcn_readfirstlane(*kp.need2) == 0) return;
     __shared__ float sh_red[ICP_WAVES][ICP_PART_STRIDE];
@@ -1371,72 +1401,116 @@ __global__ __launch_bounds__(ICP_WG) __attribute__((amdgpu_waves_per_eu(kFold ? 
     const ProbDesc& P = probs[owner[g]];
     const LevelDesc& L = P.lv[ctl.level];
     const ProbState* st = P.st;
-    const int tid = threadIdx.x;
     const int tile = g - L.tile_base;
     if (st->level_done || st->fused_done) return;  // uniform
     float acc[ICP_NMOM];
 #pragma unroll
     for (int k = 0; k < ICP_NMOM; ++k) acc[k] = 0.0f;
     float cnt = 0.0f;
-    {
-        const Pose T = load_pose(st);
-        const Lvl Lv = load_level(L);
-        const int klo = __builtin_amdgcn_readfirstlane(st->k_lo);
-        const int khi = __builtin_amdgcn_readfirstlane(st->k_hi);
-        const int base = tile * L.tile_px;
-        const int end = min(base + L.tile_px, L.npx);
-        // one pixel per lane and round, software-pipelined as in pass 1: the
-        // next round's gathers are in flight while a round is decided
-        constexpr int kRound = ICP_WG;
-        auto ld_index = [&](int r) {
-            const int i = r + tid;
-            return i < end ? i : r;
-        };
-        auto next_r = [&](int r) { return r + kRound < end ? r + kRound : r; };
-        Proj<1> pa = assoc_project<1>(Lv, base + tid, end, load_live<1>(Lv, ld_index(base)), T);
-        Gath<1> ga = assoc_gather<1>(Lv, base + tid, pa);
-        LiveIn<1> nxt = load_live<1>(Lv, ld_index(next_r(base)));
-        for (int r = base; r < end; r += kRound) {
-            const LiveIn<1> nn = load_live<1>(Lv, ld_index(next_r(next_r(r))));
-            const Proj<1> pb = assoc_project<1>(Lv, r + kRound + tid, end, nxt, T);
-            const Gath<1> gb = assoc_gather<1>(Lv, r + kRound + tid, pb);
-            assoc_decide<1>(pa, ga, T, kp.d2max, kp.cos_max, [&](int, const PixelOut& q) {
-                if (q.code == kGated && q.bin >= klo && q.bin <= khi) {
-                    accumulate_row(q.p, q.d, q.n, acc);
-                    cnt += 1.0f;
-                }
-            });
-            pa = pb;
-            ga = gb;
-            nxt = nn;
-        }
-    }
+    pass2_tile(L, st, tile, __builtin_amdgcn_readfirstlane(st->k_lo), __builtin_amdgcn_readfirstlane(st->k_hi), kp,
+               acc, cnt);
     block_reduce_row(acc, cnt, sh_red, gmut(L.part) + (size_t)tile * ICP_PART_STRIDE);
-    if (!kFold) return;
-    // The solve folded into pass 2 (one problem): every thread's stores are
-    // made visible device-wide before the barrier, thread 0 takes a ticket,
-    // and the work-group that finishes last sums the partials in tile order,
-    // solves and keeps the level's books, as the solve kernel would.
-    __shared__ int sh_last;
+}
+
+// One problem in single-pass mode (FP32 reduction): the band kernel, pass 2
+// and the solve in one launch over the problem's tiles.  Every work-group
+// finds the band from the histogram pass 1 left (the same arithmetic on the
+// same counts, so the same band in each).  When the band edge fell inside the
+// predicted window (or nothing was gated, or the level has ended) no pixel is
+// revisited, and work-group 0 completes the iteration alone: the window's
+// sums, the solve, the level's books.  Otherwise each work-group filters and
+// reduces its own tile as pass 2 does, publishes its partial and takes a
+// ticket; the one that takes the last completes the iteration from pass 2's
+// partials.
+//
+// What a work-group decides from (histogram, window prediction, level_done)
+// is never changed in a way that changes a decision while the launch runs:
+// the histogram and the prediction in use are the ones IterCtl::par selects,
+// and the iteration's writes go to the others (the next iteration's
+// prediction, and the clear of the histogram the previous launch read, which
+// the next pass 1 fills); level_done changes only where the band was a hit
+// or the level had ended, where every work-group has nothing to do whatever
+// it reads (a level reset leaves the histogram in use clear: N = 0).
+// (Occupancy does not matter for one problem: the registers are not limited.)
+__device__ __forceinline__ void band_pass2_finish(ProbState* st, const ProbDesc& P, const LevelDesc& L,
+                                                  const IterCtl& ctl, const KParams& kp, const EpiIn& epi,
+                                                  const Band& b, bool done, int pred, int pred_hw,
+                                                  const double* sh_M, const uint32_t* sh_cdf) {
+    const int par = ctl.par;
+    if (threadIdx.x == 0) {
+        ICP_GLOBAL ProbState* sw = gmut(st);
+        if (!done) {
+            store_band(st, b);
+            solve_epilogue(st, epi, b.N, b.k_med, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
+        }
+        const bool upd = !done && b.N > 0;
+        sw->pred_hw[1 - par] =
+            upd ? capped_half_width(sh_cdf, b.k_hi, next_half_width(b.k_hi, pred, ctl.iter), L.npx) : pred_hw;
+        sw->pred_hi[1 - par] = upd ? b.k_hi : pred;
+        if (ctl.last_of_level) level_reset(st);
+    }
+    clear_hist4(st, 1 - par);
+}
+
+__global__ __launch_bounds__(ICP_WG) void k_band_pass2(const ProbDesc* __restrict__ probs, IterCtl ctl, KParams kp) {
     __shared__ double sh_M[ICP_NMOM + 1];
-    __threadfence();
+    __shared__ uint32_t sh_cdf[ICP_HIST_BINS];
+    __shared__ float sh_red[ICP_WAVES][ICP_PART_STRIDE];
+    __shared__ int sh_last;
+    const ProbDesc& P = probs[0];
+    const LevelDesc& L = P.lv[ctl.level];
+    ProbState* st = P.st;
+    const ICP_GLOBAL ProbState* gst = gconst(st);
+    const int tid = threadIdx.x, tile = blockIdx.x;
+    uint32_t h[4];
+    load_hist4(st, ctl.par, h);
+    const int done = gst->level_done, pred = gst->pred_hi[ctl.par], pred_hw = gst->pred_hw[ctl.par];
+    // work-group 0 completes most iterations: its solve state and slot 0 of
+    // the window partials are loaded with the histogram
+    EpiIn epi;
+    pf4 a0[kSumBatch];
+    if (tile == 0) {
+        epi = load_epi(st);
+        load_slot0(L.part1, ICP_WIN_SLOTS * ICP_PART_STRIDE, tile_run(L.n_tiles), a0);
+    }
+    __asm__ volatile("" ::"v"(h[0]), "v"(h[1]), "v"(h[2]), "v"(h[3]), "s"(done), "s"(pred), "s"(pred_hw));
+    const Win win = band_window(pred, pred_hw, ctl.iter);
+    Band b{0u, -1, 0, -1};
+    bool hit = false, need2 = false;
+    if (!done) {  // uniform; when done, pass 1 added nothing
+        b = find_band(h, kp, nullptr, sh_cdf);
+        hit = win.h0 >= 0 && b.N > 0 && b.k_lo == 0 && b.k_hi >= win.h0 - 1 && b.k_hi <= win.h0 + win.w - 1;
+        need2 = b.N > 0 && !hit;
+    }
+    if (!need2) {
+        if (tile != 0) return;
+        if (hit) {
+            sum_partials(L.part1, L.n_tiles, ICP_WIN_SLOTS * ICP_PART_STRIDE, b.k_hi - win.h0 + 1, a0, sh_M);
+        } else {  // nothing gated (or the level has ended): every moment is zero
+            if (tid <= ICP_NMOM) sh_M[tid] = 0.0;
+            __syncthreads();
+        }
+        band_pass2_finish(st, P, L, ctl, kp, epi, b, done, pred, pred_hw, sh_M, sh_cdf);
+        return;
+    }
+    {
+        float acc[ICP_NMOM];
+#pragma unroll
+        for (int k = 0; k < ICP_NMOM; ++k) acc[k] = 0.0f;
+        float cnt = 0.0f;
+        pass2_tile(L, st, tile, b.k_lo, b.k_hi, kp, acc, cnt);
+        block_reduce_row(acc, cnt, sh_red, gmut(L.part) + (size_t)tile * ICP_PART_STRIDE);
+    }
+    __threadfence();  // the partial is visible device-wide before the ticket
     __syncthreads();
-    if (tid == 0) sh_last = atomicAdd(&P.st->ticket, 1) == L.n_tiles - 1;
+    if (tid == 0) sh_last = atomicAdd(&st->ticket, 1) == L.n_tiles - 1;
     __syncthreads();
     if (!sh_last) return;
     __threadfence();
-    const EpiIn epi = load_epi(P.st);
-    const uint32_t N = gconst(P.st)->N;
-    const int32_t k_med = gconst(P.st)->k_med;
+    epi = load_epi(st);
     sum_partials(L.part, L.n_tiles, ICP_PART_STRIDE, 0, sh_M);
-    if (tid == 0) {
-        ProbState* sw = P.st;
-        solve_epilogue(sw, epi, N, k_med, sh_M, (int64_t)sh_M[ICP_NMOM], ctl, kp, P.imu_R);
-        sw->ticket = 0;
-        sw->fused_done = 0;
-        *kp.need2 = 0;
-        if (ctl.last_of_level) level_reset(sw);
-    }
+    band_pass2_finish(st, P, L, ctl, kp, epi, b, false, pred, pred_hw, sh_M, sh_cdf);
+    if (tid == 0) gmut(st)->ticket = 0;
 }
 
 // Split-precision variant of pass 2 (reduce_mode 1): each kept row
@@ -1548,7 +1622,7 @@ __global__ void k_finalize(const ProbDesc* __restrict__ probs, int n, icp_result
 __global__ void k_stage_set(const ProbDesc* __restrict__ probs, PoseArg pose, int k_lo, int k_hi, int level,
                             int pred_hi, int pred_hw) {
     ProbState* st = probs[0].st;
-    for (int b = threadIdx.x; b < ICP_HIST_BINS; b += blockDim.x) st->hist[b] = 0u;
+    for (int b = threadIdx.x; b < ICP_HIST_BINS; b += blockDim.x) st->hist[0][b] = 0u;  // (stage calls use par 0)
     if (threadIdx.x == 0) {
         for (int i = 0; i < 3; ++i) {
             for (int j = 0; j < 3; ++j) st->R[3 * i + j] = pose.v[4 * i + j];
@@ -1556,8 +1630,8 @@ __global__ void k_stage_set(const ProbDesc* __restrict__ probs, PoseArg pose, in
         }
         st->k_lo = k_lo;
         st->k_hi = k_hi;
-        st->pred_hi = pred_hi;
-        st->pred_hw = pred_hw;
+        st->pred_hi[0] = pred_hi;
+        st->pred_hw[0] = pred_hw;
         st->fused_done = 0;
         st->level_done = 0;
         set_centre(st, level);
@@ -1569,7 +1643,7 @@ __global__ void k_stage_set(const ProbDesc* __restrict__ probs, PoseArg pose, in
 __global__ void k_stage_window(const ProbDesc* __restrict__ probs, IterCtl ctl, int32_t* out) {
     if (threadIdx.x != 0) return;
     const ProbState* st = probs[0].st;
-    const Win w = band_window(st->pred_hi, st->pred_hw, ctl.iter);
+    const Win w = band_window(st->pred_hi[ctl.par], st->pred_hw[ctl.par], ctl.iter);
     out[0] = w.h0;
     out[1] = w.w;
 }
@@ -1698,10 +1772,13 @@ hipError_t launch_pass2(const ProbDesc* probs, const int* owner, int tiles, Iter
                         hipStream_t s) {
     if (kp.reduce_mode == 1)
         hipLaunchKernelGGL(k_pass2_mfma, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
-    else if (kp.fold_solve)
-        hipLaunchKernelGGL(k_pass2<true>, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
     else
-        hipLaunchKernelGGL(k_pass2<false>, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+        hipLaunchKernelGGL(k_pass2, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_pass2(const ProbDesc* probs, int tiles, IterCtl ctl, const KParams& kp, hipStream_t s) {
+    hipLaunchKernelGGL(k_band_pass2, dim3(tiles), dim3(ICP_WG), 0, s, probs, ctl, kp);
     return hipGetLastError();
 }
 
@@ -1757,7 +1834,7 @@ hipError_t launch_stage_pass2(const ProbDesc* probs, const int* owner, int tiles
     if (kp.reduce_mode == 1)
         hipLaunchKernelGGL(k_pass2_mfma, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
     else
-        hipLaunchKernelGGL(k_pass2<false>, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
+        hipLaunchKernelGGL(k_pass2, dim3(tiles), dim3(ICP_WG), 0, s, probs, owner, ctl, kp);
     hipLaunchKernelGGL(k_solve, dim3(1), dim3(ICP_WG), 0, s, probs, ctl, kp);
     return hipGetLastError();
 }

@@ -46,6 +46,8 @@ hipError_t launch_band(const ProbDesc* probs, int n, IterCtl ctl, const KParams&
 hipError_t launch_pass2(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp,
                         hipStream_t s);
 hipError_t launch_solve(const ProbDesc* probs, int n, IterCtl ctl, const KParams& kp, hipStream_t s);
+// one problem, single pass, FP32 reduction: band, pass 2 and solve in one launch
+hipError_t launch_band_pass2(const ProbDesc* probs, int tiles, IterCtl ctl, const KParams& kp, hipStream_t s);
 // write one problem descriptor (a kernel argument) to dst; fill n ints with v
 hipError_t launch_put_desc(const ProbDesc& d, ProbDesc* dst, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s);
