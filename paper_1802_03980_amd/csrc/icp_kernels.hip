@@ -76,13 +76,14 @@ __device__ __forceinline__ float depth_px(float a, float b, float c, float d) {
     return (float)(((((double)a + (double)b) + (double)c) + (double)d) * 0.25);
 }
 
-__global__ __launch_bounds__(ICP_WG) void k_depth_down(const ProbDesc* __restrict__ probs, int level,
-                                                       int also_next) {
+// (bx: the work-group's index within the launch's range for this step)
+__device__ __forceinline__ void depth_down_block(const ProbDesc* __restrict__ probs, int level, int also_next,
+                                                 int bx) {
     const ProbDesc& P = probs[blockIdx.y];
     const LevelDesc& F = P.lv[level - 1];
     const LevelDesc& C = P.lv[level];
     const int qw = (C.W + 1) >> 1;  // blocks per row
-    const int t = blockIdx.x * ICP_WG + threadIdx.x;
+    const int t = bx * ICP_WG + threadIdx.x;
     if (t >= qw * ((C.H + 1) >> 1)) return;
     const int vb = t / qw, u = 2 * (t % qw);
     const bool two = u + 1 < C.W;
@@ -112,6 +113,11 @@ __global__ __launch_bounds__(ICP_WG) void k_depth_down(const ProbDesc* __restric
     if (!also_next || !two || rows != 2) return;
     const LevelDesc& N = P.lv[level + 1];  // C.W >> 1 by C.H >> 1
     gmut(N.Dw)[vb * N.W + (u >> 1)] = depth_px(kept[0], kept[1], kept[2], kept[3]);
+}
+
+__global__ __launch_bounds__(ICP_WG) void k_depth_down(const ProbDesc* __restrict__ probs, int level,
+                                                       int also_next) {
+    depth_down_block(probs, level, also_next, blockIdx.x);
 }
 
 // Live vertex map and forward-difference normal map (flipped to face the
@@ -342,11 +348,12 @@ __global__ __launch_bounds__(ICP_WG) void k_quotients(const ProbDesc* __restrict
         gmut(L.YQ)[t - L.W - 1] = ((double)(t - L.W - 1) - L.cy) / L.fy;
 }
 
-__global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__ probs, int level, int with_vertex) {
+__device__ __forceinline__ void live_vn_block(const ProbDesc* __restrict__ probs, int level, int with_vertex,
+                                              int blk) {
     __shared__ double sx[FE_TX + 1], sy[FE_TY + 1];
     const LevelDesc& L = probs[blockIdx.y].lv[level];
     const int tiles_x = (L.W + FE_TX - 1) / FE_TX;
-    const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+    const int bx = blk % tiles_x, by = blk / tiles_x;
     const int u0 = bx * FE_TX, v0 = by * FE_TY;
     if (v0 >= L.H) return;  // uniform: grids cover the largest level of the batch
     fe_quotients(sx, sy, u0, v0, L.fx, L.fy, L.cx, L.cy);
@@ -390,6 +397,10 @@ __global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__
         LN[S + i] = n[1];
         LN[2 * S + i] = n[2];
     }
+}
+
+__global__ __launch_bounds__(ICP_WG) void k_live_vn(const ProbDesc* __restrict__ probs, int level, int with_vertex) {
+    live_vn_block(probs, level, with_vertex, blockIdx.x);
 }
 
 // The same vertex and normal maps of full-resolution depth images, written
@@ -462,13 +473,13 @@ __device__ __forceinline__ float quad_bcast(float x) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x55 * K, 0xF, 0xF, false));
 }
 
-__global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restrict__ probs, int level,
-                                                       int also_next) {
+__device__ __forceinline__ void model_down_block(const ProbDesc* __restrict__ probs, int level, int also_next,
+                                                 int bx) {
     const ProbDesc& P = probs[blockIdx.y];
     const LevelDesc& F = P.lv[level - 1];
     const LevelDesc& C = P.lv[level];
     const int qw = (C.W + 1) >> 1, qh = (C.H + 1) >> 1;  // blocks per row, block rows
-    const int t = blockIdx.x * ICP_WG + threadIdx.x;
+    const int t = bx * ICP_WG + threadIdx.x;
     const int blk = t >> 2, q = t & 3;
     if (blk >= qw * qh) return;  // (whole quads)
     const int bv = blk / qw, bu = blk - bv * qw;
@@ -525,6 +536,37 @@ __global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restric
         NVo[3 * i + k] = vo[k];
         NNo[3 * i + k] = no[k];
     }
+}
+
+__global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restrict__ probs, int level,
+                                                       int also_next) {
+    model_down_block(probs, level, also_next, blockIdx.x);
+}
+
+// The raw-depth front end of two or three levels in two launches.  The model
+// pyramid, the depth pyramid and level 0's live maps depend only on the
+// inputs, so one launch runs all three, each on its own range of the grid's
+// work-groups (the model pyramid's memory traffic then overlaps the normals'
+// FP64 arithmetic); the coarser levels' live maps, which need the depth
+// pyramid, follow in a second launch.
+__global__ __launch_bounds__(ICP_WG) void k_front_inputs(const ProbDesc* __restrict__ probs, int nb_model,
+                                                         int nb_depth, int also_next, int with_vertex) {
+    const int b = blockIdx.x;  // (each range is whole work-groups: the branches are uniform)
+    if (b < nb_model)
+        model_down_block(probs, 1, also_next, b);
+    else if (b < nb_model + nb_depth)
+        depth_down_block(probs, 1, also_next, b - nb_model);
+    else
+        live_vn_block(probs, 0, with_vertex, b - nb_model - nb_depth);
+}
+
+__global__ __launch_bounds__(ICP_WG) void k_front_coarse(const ProbDesc* __restrict__ probs, int nb_level1,
+                                                         int with_vertex) {
+    const int b = blockIdx.x;
+    if (b < nb_level1)
+        live_vn_block(probs, 1, with_vertex, b);
+    else
+        live_vn_block(probs, 2, with_vertex, b - nb_level1);
 }
 
 // Centroid of the valid live vertices of one level: the centring point of the
@@ -1714,11 +1756,24 @@ hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* m
             default: return hipErrorInvalidValue;
         }
     }
+    if (!fe.depth_filter && fe.normal_mode == 0 && (levels == 2 || levels == 3)) {
+        const int nb_model = (int)blocks_for(4 * max_model_blocks[1]), nb_depth = (int)blocks_for(max_model_blocks[1]);
+        const int next = levels == 3 ? 1 : 0, wv = with_live_maps ? 1 : 0;
+        hipLaunchKernelGGL(k_front_inputs, dim3(nb_model + nb_depth + max_vn_blocks[0], n), dim3(ICP_WG), 0, s,
+                           probs, nb_model, nb_depth, next, wv);
+        if (levels == 3)
+            hipLaunchKernelGGL(k_front_coarse, dim3(max_vn_blocks[1] + max_vn_blocks[2], n), dim3(ICP_WG), 0, s,
+                               probs, max_vn_blocks[1], wv);
+        else
+            hipLaunchKernelGGL(k_live_vn, dim3(max_vn_blocks[1], n), dim3(ICP_WG), 0, s, probs, 1, wv);
+        return hipGetLastError();
+    }
     for (int l = 1; l < levels; l += 2)  // two levels per launch, as for the model maps
         hipLaunchKernelGGL(k_depth_down, dim3(blocks_for(max_model_blocks[l]), n), dim3(ICP_WG), 0, s, probs, l,
                            l + 1 < levels ? 1 : 0);
-    for (int l = 0; l < levels; ++l)
-        hipLaunchKernelGGL(k_quotients, dim3(blocks_for(max_quot[l]), n), dim3(ICP_WG), 0, s, probs, l);
+    if (fe.normal_mode == 1)  // (the quotient tables are read by the box normals only)
+        for (int l = 0; l < levels; ++l)
+            hipLaunchKernelGGL(k_quotients, dim3(blocks_for(max_quot[l]), n), dim3(ICP_WG), 0, s, probs, l);
     for (int l = 0; l < levels; ++l) {
         // live vertex planes (stage access) and forward-difference normals
         if (with_live_maps || fe.normal_mode == 0)
