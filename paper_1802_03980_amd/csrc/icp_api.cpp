@@ -547,9 +547,9 @@ int launch_registration(icp_ctx* ctx, int n, const icp_params* prm, const Launch
     const bool timed = ctx && ctx->timing;
     auto begin = [&](int kind, int64_t px) { return timed ? time_begin(ctx, s, r, kind, px) : ICP_OK; };
     auto end = [&]() { return timed ? time_end(ctx, s, r) : ICP_OK; };
-    HIP_TRY(ctx, icpk::launch_init(d_desc, n, prm->use_imu_seed, kp.need2, s));
     if ((rc = begin(ICP_TIME_FRONT_END, G.px[0]))) return rc;
-    HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, G.max_vn, G.max_mp, G.max_q, false, front_end(prm), s));
+    HIP_TRY(ctx, icpk::launch_prepare(d_desc, n, prm->levels, G.max_vn, G.max_mp, G.max_q, false, front_end(prm),
+                                      prm->use_imu_seed, kp.need2, s));
     if (prm->reduce_mode == 1) HIP_TRY(ctx, icpk::launch_centroid(d_desc, n, prm->levels, G.owner, G.tiles, s));
     if ((rc = end())) return rc;
     // single pass needs the band's lower edge at bin 0
@@ -1173,9 +1173,8 @@ int icp_stage_prepare(icp_ctx* ctx, const float* live_depth, int W, int H, const
     ctx->d_scratch = reinterpret_cast<double*>(base + P.off_scratch);
     ctx->stage_desc = P.desc[0];
     ctx->stage_levels = levels;
-    HIP_TRY(ctx, icpk::launch_init(ctx->d_desc, 1, 0, nullptr, s));
     HIP_TRY(ctx, icpk::launch_prepare(ctx->d_desc, 1, levels, P.max_vn, P.max_mp, P.max_q, true,
-                                      front_end(prm), s));
+                                      front_end(prm), 0, nullptr, s));
     HIP_TRY(ctx, icpk::launch_centroid(ctx->d_desc, 1, levels, ctx->d_owner, ctx->tiles, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     ctx->stage_ready = true;

@@ -21,11 +21,12 @@ namespace icpk {
 
 // ------------------------------------------------------------------ init
 
-__global__ __launch_bounds__(ICP_WG) void k_init(const ProbDesc* __restrict__ probs, int use_imu_seed,
-                                                 int32_t* need2) {
-    const ProbDesc& P = probs[blockIdx.x];
+// The state of problem p at the start of a registration (one work-group).
+__device__ __forceinline__ void init_block(const ProbDesc* __restrict__ probs, int p, int use_imu_seed,
+                                           int32_t* need2) {
+    const ProbDesc& P = probs[p];
     ProbState* st = P.st;
-    if (need2 && blockIdx.x == 0 && threadIdx.x == 0) *need2 = 0;
+    if (need2 && p == 0 && threadIdx.x == 0) *need2 = 0;
     for (int b = threadIdx.x; b < ICP_HIST_BINS; b += ICP_WG) st->hist[0][b] = st->hist[1][b] = 0u;
     if (threadIdx.x == 0) {
         // Sec. 3: the live points are pre-oriented by the IMU rotation
@@ -61,6 +62,11 @@ __global__ __launch_bounds__(ICP_WG) void k_init(const ProbDesc* __restrict__ pr
         st->stats.status = ICP_LEVEL_OK;
         st->stats.iters_total = 0;
     }
+}
+
+__global__ __launch_bounds__(ICP_WG) void k_init(const ProbDesc* __restrict__ probs, int use_imu_seed,
+                                                 int32_t* need2) {
+    init_block(probs, blockIdx.x, use_imu_seed, need2);
 }
 
 // ------------------------------------------------------------------ front end
@@ -544,20 +550,23 @@ __global__ __launch_bounds__(ICP_WG) void k_model_down(const ProbDesc* __restric
 }
 
 // The raw-depth front end of two or three levels in two launches.  The model
-// pyramid, the depth pyramid and level 0's live maps depend only on the
-// inputs, so one launch runs all three, each on its own range of the grid's
-// work-groups (the model pyramid's memory traffic then overlaps the normals'
-// FP64 arithmetic); the coarser levels' live maps, which need the depth
-// pyramid, follow in a second launch.
+// pyramid, the depth pyramid, level 0's live maps and the problem's initial
+// state depend only on the inputs, so one launch does all four, each on its
+// own range of the grid's work-groups (the model pyramid's memory traffic then
+// overlaps the normals' FP64 arithmetic); the coarser levels' live maps, which
+// need the depth pyramid, follow in a second launch.
 __global__ __launch_bounds__(ICP_WG) void k_front_inputs(const ProbDesc* __restrict__ probs, int nb_model,
-                                                         int nb_depth, int also_next, int with_vertex) {
+                                                         int nb_depth, int nb_vn, int also_next, int with_vertex,
+                                                         int use_imu_seed, int32_t* need2) {
     const int b = blockIdx.x;  // (each range is whole work-groups: the branches are uniform)
     if (b < nb_model)
         model_down_block(probs, 1, also_next, b);
     else if (b < nb_model + nb_depth)
         depth_down_block(probs, 1, also_next, b - nb_model);
-    else
+    else if (b < nb_model + nb_depth + nb_vn)
         live_vn_block(probs, 0, with_vertex, b - nb_model - nb_depth);
+    else
+        init_block(probs, blockIdx.y, use_imu_seed, need2);
 }
 
 __global__ __launch_bounds__(ICP_WG) void k_front_coarse(const ProbDesc* __restrict__ probs, int nb_level1,
@@ -1723,11 +1732,6 @@ __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
 
 static inline unsigned blocks_for(int n) { return (unsigned)((n + ICP_WG - 1) / ICP_WG); }
 
-hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, int32_t* need2, hipStream_t s) {
-    hipLaunchKernelGGL(k_init, dim3(n), dim3(ICP_WG), 0, s, probs, use_imu_seed, need2);
-    return hipGetLastError();
-}
-
 hipError_t launch_centroid(const ProbDesc* probs, int n, int levels, const int* const* owner, const int* tiles,
                            hipStream_t s) {
     for (int l = 0; l < levels; ++l)
@@ -1742,7 +1746,7 @@ int model_blocks(int W, int H) { return ((W + 1) / 2) * ((H + 1) / 2); }
 
 hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_vn_blocks,
                           const int* max_model_blocks, const int* max_quot, bool with_live_maps, const FrontEnd& fe,
-                          hipStream_t s) {
+                          int use_imu_seed, int32_t* need2, hipStream_t s) {
     if (fe.depth_filter) {
         const dim3 grid(max_vn_blocks[0], n);
         switch (fe.filter_radius) {
@@ -1759,8 +1763,8 @@ hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* m
     if (!fe.depth_filter && fe.normal_mode == 0 && (levels == 2 || levels == 3)) {
         const int nb_model = (int)blocks_for(4 * max_model_blocks[1]), nb_depth = (int)blocks_for(max_model_blocks[1]);
         const int next = levels == 3 ? 1 : 0, wv = with_live_maps ? 1 : 0;
-        hipLaunchKernelGGL(k_front_inputs, dim3(nb_model + nb_depth + max_vn_blocks[0], n), dim3(ICP_WG), 0, s,
-                           probs, nb_model, nb_depth, next, wv);
+        hipLaunchKernelGGL(k_front_inputs, dim3(nb_model + nb_depth + max_vn_blocks[0] + 1, n), dim3(ICP_WG), 0, s,
+                           probs, nb_model, nb_depth, max_vn_blocks[0], next, wv, use_imu_seed, need2);
         if (levels == 3)
             hipLaunchKernelGGL(k_front_coarse, dim3(max_vn_blocks[1] + max_vn_blocks[2], n), dim3(ICP_WG), 0, s,
                                probs, max_vn_blocks[1], wv);
@@ -1768,6 +1772,7 @@ hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* m
             hipLaunchKernelGGL(k_live_vn, dim3(max_vn_blocks[1], n), dim3(ICP_WG), 0, s, probs, 1, wv);
         return hipGetLastError();
     }
+    hipLaunchKernelGGL(k_init, dim3(n), dim3(ICP_WG), 0, s, probs, use_imu_seed, need2);
     for (int l = 1; l < levels; l += 2)  // two levels per launch, as for the model maps
         hipLaunchKernelGGL(k_depth_down, dim3(blocks_for(max_model_blocks[l]), n), dim3(ICP_WG), 0, s, probs, l,
                            l + 1 < levels ? 1 : 0);

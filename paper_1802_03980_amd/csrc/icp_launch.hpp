@@ -15,9 +15,6 @@ struct MomArg {
     double m[ICP_NMOM];
 };
 
-// per problem: seed the pose (IMU rotation or the initial pose), clear the
-// histogram, tickets, flags and statistics; clear the batch's pass-2 flag
-hipError_t launch_init(const ProbDesc* probs, int n, int use_imu_seed, int32_t* need2, hipStream_t s);
 // centroid of every level's valid live vertices (split-precision reduction):
 // per-tile FP64 sums over the level's flat tiles (owner[l], tiles[l]), then
 // per problem in tile order; uses the pass-2 partials as scratch
@@ -29,15 +26,19 @@ hipError_t launch_depth_to_maps(const MapsDesc* jobs, int n, int max_blocks, hip
 int live_vn_blocks(int W, int H);
 // depth- and model-pyramid threads of a W x H level (one per 2 x 2 block)
 int model_blocks(int W, int H);
-// Front end of every problem: optional bilateral filter of the caller's depth
-// into the level-0 workspace plane, depth pyramid, back-projection quotient
-// tables, live normal planes (forward differences or box gradients), model
-// pyramid (two levels per launch), and (with_live_maps) the live vertex
-// planes, which only the stage-access calls read (the pixel passes rebuild
-// the vertices from depth).
+// Start of every problem's registration: its initial state (pose seeded by
+// the IMU rotation or the initial pose; histograms, tickets, flags and
+// statistics cleared; the batch's pass-2 flag cleared), then the front end:
+// optional bilateral filter of the caller's depth into the level-0 workspace
+// plane, depth pyramid, back-projection quotient tables (box normals only),
+// live normal planes (forward differences or box gradients), model pyramid
+// (two levels per launch), and (with_live_maps) the live vertex planes, which
+// only the stage-access calls read (the pixel passes rebuild the vertices from
+// depth).  Raw depth with forward-difference normals over two or three levels
+// takes two launches.
 hipError_t launch_prepare(const ProbDesc* probs, int n, int levels, const int* max_vn_blocks,
                           const int* max_model_blocks, const int* max_quot, bool with_live_maps, const FrontEnd& fe,
-                          hipStream_t s);
+                          int use_imu_seed, int32_t* need2, hipStream_t s);
 // one ICP iteration at ctl.level: pass 1 over `tiles` flat tiles of all
 // problems, the per-problem band, pass 2 over the tiles, the per-problem solve
 hipError_t launch_pass1(const ProbDesc* probs, const int* owner, int tiles, IterCtl ctl, const KParams& kp, int fused,
