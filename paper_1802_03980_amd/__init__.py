@@ -226,7 +226,8 @@ def _f64(a, n, name):
 
 
 def _np_ptr(a):
-    return a.ctypes.data_as(C.c_void_p)
+    """Address of a numpy array's data (the caller keeps `a` alive for the call)."""
+    return C.c_void_p(a.ctypes.data)
 
 
 def _check(ctx, rc):
