@@ -288,8 +288,12 @@ int ensure_workspace(icp_ctx* ctx, size_t bytes, bool exact = false) {
     if (ctx->budget && bytes > ctx->budget)
         return fail(ctx, ICP_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes exceeds the HBM budget");
     if (bytes <= ctx->ws_cap) return ICP_OK;
+    const icpi::RelaxedCaptureScope relaxed;
     if (ctx->ws) {
-        HIP_TRY(ctx, hipDeviceSynchronize());
+        // the old workspace is free once this context's last call has ended
+        // (each call waits for the one before); no device-wide wait, which
+        // would also wait on a graph another thread may be capturing
+        if (ctx->done_valid) HIP_TRY(ctx, hipEventSynchronize(ctx->ev_done));
         HIP_TRY(ctx, hipFree(ctx->ws));
         ctx->ws = nullptr;
         ctx->ws_cap = 0;
@@ -344,6 +348,7 @@ int ensure_stage(icp_ctx* ctx, size_t bytes) {
         ctx->ev_pending = false;
     }
     if (bytes <= ctx->hstage_cap) return ICP_OK;
+    const icpi::RelaxedCaptureScope relaxed;
     if (ctx->hstage) HIP_TRY(ctx, hipHostFree(ctx->hstage));
     ctx->hstage = nullptr;
     ctx->hstage_cap = 0;
@@ -638,13 +643,22 @@ int execute(icp_ctx* ctx, int n, const icp_params* prm, Plan& P, hipStream_t s) 
             ctx->graphs.erase(lru);
         }
         if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
-        HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        // (relaxed: allocations that other threads make meanwhile, such as a
+        // frame server's clients, must not invalidate the capture; this
+        // thread makes none until it ends)
+        HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
         int rc = run_batch(ctx, n, prm, P, d_res, ctx->cap_stream);
         icp_ctx::GraphEntry g;
         hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g.graph);
         if (rc || e != hipSuccess) {
             destroy_graph(g);
-            return rc ? rc : hip_fail(ctx, e, "hipStreamEndCapture");
+            // A device-wide call that another thread makes meanwhile (a
+            // synchronisation, a free) can spoil a capture in progress.  This
+            // call's launches then go straight to its stream (a genuine error
+            // shows there again); the next call with this shape captures anew.
+            (void)hipGetLastError();
+            ctx->err.clear();
+            return run_batch(ctx, n, prm, P, d_res, s);
         }
         e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
@@ -782,7 +796,11 @@ int icp_ctx_create(int device, size_t hbm_budget_bytes, icp_ctx** out) {
 void icp_ctx_destroy(icp_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
-    (void)hipDeviceSynchronize();
+    const icpi::RelaxedCaptureScope relaxed;
+    // this context's work has ended once its last call's event has (see
+    // ensure_workspace); a context may die while another thread captures
+    if (ctx->done_valid) (void)hipEventSynchronize(ctx->ev_done);
+    if (ctx->ev_pending) (void)hipEventSynchronize(ctx->ev_upload);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->hstage) (void)hipHostFree(ctx->hstage);
     if (ctx->ev_upload) (void)hipEventDestroy(ctx->ev_upload);

@@ -23,6 +23,18 @@ int validate_params(icp_ctx* ctx, const icp_params* params);
 // The context's last error message.
 const char* error(icp_ctx* ctx);
 
+// For its lifetime, this thread's allocation and free calls run in relaxed
+// stream-capture mode, so that they cannot invalidate a graph another thread
+// is capturing (a frame server captures on its scheduler thread while clients
+// submit frames and open streams).
+struct RelaxedCaptureScope {
+    hipStreamCaptureMode prev = hipStreamCaptureModeRelaxed;
+    RelaxedCaptureScope() { (void)hipThreadExchangeStreamCaptureMode(&prev); }
+    ~RelaxedCaptureScope() { (void)hipThreadExchangeStreamCaptureMode(&prev); }
+    RelaxedCaptureScope(const RelaxedCaptureScope&) = delete;
+    RelaxedCaptureScope& operator=(const RelaxedCaptureScope&) = delete;
+};
+
 // Largest |(R^T R - I)_ij| a rotation passed to the library may show.
 constexpr double kRotTol = 1e-6;
 

@@ -154,6 +154,7 @@ size_t stream_bytes(int W, int H, int ring) {
 }
 
 void free_stream(Stream* st) {
+    const icpi::RelaxedCaptureScope relaxed;
     for (int r = 0; r < kMaxRing; ++r) {
         if (st->d_depth[r]) (void)hipFree(st->d_depth[r]);
         if (st->d_mv[r]) (void)hipFree(st->d_mv[r]);
@@ -492,6 +493,7 @@ int icp_server_open_stream(icp_server* S, int W, int H, const icp_intrinsics* K,
                             std::to_string(S->cfg.hbm_budget_bytes));
     }
     (void)hipSetDevice(S->cfg.device);
+    const icpi::RelaxedCaptureScope relaxed;
     const size_t px = (size_t)W * H;
     for (int r = 0; r < st->ring; ++r)
         if (hipMalloc(&st->d_depth[r], px * 4) != hipSuccess || hipMalloc(&st->d_mv[r], px * 12) != hipSuccess ||
@@ -547,6 +549,7 @@ int icp_server_submit(icp_server* S, int id, const float* depth_host, const doub
     }
     if (!buf) {
         (void)hipSetDevice(S->cfg.device);
+        const icpi::RelaxedCaptureScope relaxed;
         if (hipHostMalloc(&buf, bytes) != hipSuccess) return srv_fail(S, ICP_ENOMEM, "pinned depth buffer");
     }
     std::memcpy(buf, depth_host, bytes);
@@ -554,6 +557,7 @@ int icp_server_submit(icp_server* S, int id, const float* depth_host, const doub
         std::lock_guard<std::mutex> lk(S->mu);
         Stream* st = (id < (int)S->streams.size()) ? S->streams[id] : nullptr;
         if (!st || st->closing) {
+            const icpi::RelaxedCaptureScope relaxed;
             (void)hipHostFree(buf);
             return srv_fail(S, ICP_EINVAL, "stream closed during submit");
         }

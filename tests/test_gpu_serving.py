@@ -142,6 +142,49 @@ def test_server_alone_vs_mix(ctx, in_flight):
             assert np.allclose(r["pose_world"], world, rtol=0, atol=1e-12)
 
 
+def test_server_survives_context_churn(ctx):
+    """Contexts created, used and destroyed by the client thread while the
+    server's scheduler captures its batch graphs: a context's destruction (and
+    a workspace growth) waits for that context's own work only, and a capture
+    that another thread's device-wide call spoils still runs its batch (its
+    launches go straight to the stream), so every frame comes back and equals
+    the alone run bit for bit."""
+    import gc
+    params = _params()
+    streams = [CameraStream(4, 160, 120, period=8), CameraStream(5, 320, 240, period=8)]
+    n_frames = 5
+    frames = [[s.depth(k) for k in range(n_frames)] for s in streams]
+    q = CameraStream(6, 160, 120, period=8)
+    qd = torch.from_numpy(q.depth(1)).cuda()
+    qmv, qmn = icp.icp_live_maps(ctx, torch.from_numpy(q.depth(0)).cuda(), q.K)
+    srv = icp.Server(icp.icp_server_config_default(params=params, max_batch=8, slots=2, frames_in_flight=1))
+    results = []
+    try:
+        ids = [srv.open_stream(s.W, s.H, s.K) for s in streams]
+        for k in range(n_frames):
+            for i, s in enumerate(streams):
+                R = np.eye(3) if k == 0 else s.imu_rel(k)
+                srv.submit(ids[i], frames[i][k], R, tag=1000 * i + k)
+                c = icp.icp_ctx_create(0)
+                icp.icp_register(c, qd, qmv, qmn, q.K, q.imu_rel(1), np.eye(4), params)
+                del c
+                gc.collect()
+                results += srv.poll(256, timeout_ms=0)
+        while len(results) < len(streams) * n_frames:
+            got = srv.poll(256, timeout_ms=20000)
+            assert got, "server stalled"
+            results += got
+    finally:
+        srv.close()
+    by = {(r["stream_id"], r["frame"]): r for r in results}
+    for i, s in enumerate(streams):
+        for k in range(1, n_frames):
+            r = by[(ids[i], k)]
+            assert r["status"] == icp.OK
+            T, _ = _alone(ctx, s, k, params)
+            assert np.array_equal(r["pose_rel"], T), (i, k)
+
+
 def test_server_matches_oracle_sample(ctx):
     params = _params()
     streams = [CameraStream(7, 320, 240, period=6), CameraStream(8, 160, 120, period=6)]
