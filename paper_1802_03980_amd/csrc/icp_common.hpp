@@ -21,7 +21,9 @@
 #define ICP_WAVES (ICP_WG / 64)
 #define ICP_PART_STRIDE 32      // floats per tile partial: 28 moments, count, pad
 #define ICP_NMOM 28
+#ifndef ICP_PX_PER_THREAD
 #define ICP_PX_PER_THREAD 4
+#endif
 #define ICP_PASS1_PX 1          // pixels per thread and round in the single-pass kernel
 #define ICP_TILE_QUANTUM (ICP_WG * ICP_PX_PER_THREAD)
 #define ICP_PLANE_ALIGN 64      // floats
