@@ -12,6 +12,9 @@ calls and the context's workspace accounting.
     launches give the same pose as the untraced ones.
   * The context holds at least the workspace icp_workspace_bytes names for
     the batch it ran.
+  * A one-problem registration (which alternates two histograms and window
+    predictions between iterations) gives the same pose, bit for bit, after
+    stage calls and a batch have used the same context's state.
 """
 import ctypes as C
 
@@ -154,3 +157,23 @@ def test_context_workspace_covers_the_batch(ctx):
     icp.icp_register_batch(ctx, items, icp.icp_params_default())
     need = icp.icp_workspace_bytes([(p.live_depth.shape[1], p.live_depth.shape[0]) for p in probs])
     assert need > 0 and ctx.workspace_bytes() >= need
+
+
+def test_state_does_not_leak_between_calls(ctx):
+    a = synth.RoomSequence(1, n_frames=3).problem(1)
+    b = synth.pair_problem(0)
+    da, db = upload(a), upload(b)
+    params = icp.icp_params_default()
+    T1, s1 = icp.icp_register(ctx, *da, a.K, a.imu_R, a.init_pose, params)
+    # stage calls on another problem leave their histogram and prediction behind
+    icp.icp_stage_prepare(ctx, *db, b.K, levels=params.levels, params=params)
+    for level in range(params.levels):
+        T = np.eye(4)
+        icp.icp_stage_single_pass(ctx, level, T, 3, 700, 6, params)
+    items = [dict(live_depth=d[0], model_vtx=d[1], model_nrm=d[2], K=p.K, imu_R=p.imu_R, init_pose=p.init_pose)
+             for p, d in ((a, da), (b, db))]
+    batch = icp.icp_register_batch(ctx, items, params)
+    T2, s2 = icp.icp_register(ctx, *da, a.K, a.imu_R, a.init_pose, params)
+    assert np.array_equal(T1, T2)
+    assert s1 == s2
+    assert np.array_equal(batch[0][0], T1)  # (the same 1024-pixel tiles alone and in this batch)
